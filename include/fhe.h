@@ -1,0 +1,160 @@
+/*
+ * fhe.h -- C ABI of the MI355X (gfx950) RNS-CKKS library.
+ *
+ * The operations follow the setting of Jain et al., "Efficient CNN Building
+ * Blocks for Encrypted Data": the end user holds the secret key and encrypts
+ * both the images and (through the model owner) the weights under its public
+ * key; the untrusted cloud evaluates ciphertext-ciphertext and
+ * ciphertext-plaintext additions and multiplications, rotations and the CNN
+ * layers built from them; the user decrypts the class scores (Sec. 1,
+ * Fig. 1; Sec. 2.1 "Homomorphic Encryption"; Sec. 3, Eq. (enc_conv),
+ * Eq. (approxReLU), Eq. (ActPool); Sec. 4.3).  The paper uses CKKS as a black
+ * box; the arithmetic is full-RNS CKKS with hybrid key switching.
+ *
+ * Conventions for every entry point
+ *   - Ciphertext, plaintext and key buffers are DEVICE memory owned by the
+ *     caller, 64-bit residues, limb-major [polys][limbs][N], evaluation (NTT)
+ *     domain in the library's internal order.  The context owns only its
+ *     precomputed tables and its scratch memory.
+ *   - Arrays documented as "host" are host memory; everything else is device.
+ *   - All work is enqueued on the HIP stream given to fhe_ctx_create (or
+ *     fhe_set_stream) and is asynchronous, except calls that return host data
+ *     (fhe_keygen_secret, fhe_decode, fhe_export_limbs), which synchronise it.
+ *   - Output buffers may alias inputs for the element-wise operations,
+ *     rescale, relinearisation and rotation.
+ *   - Errors are negative fhe_status codes; fhe_last_error() returns a
+ *     thread-local message.  On error no output buffer has been written.
+ */
+#ifndef FHE_H
+#define FHE_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fhe_status;
+#define FHE_OK 0
+#define FHE_EINVAL (-1)   /* null pointer, shape or size mismatch */
+#define FHE_ELEVEL (-2)   /* limb-count mismatch, or rescale at one limb */
+#define FHE_ESCALE (-3)   /* add of operands whose scales differ by more than 2^-20 relative */
+#define FHE_ENOKEY (-4)   /* evaluation key does not match the requested rotation */
+#define FHE_EPARAM (-5)   /* invalid parameter set */
+#define FHE_ENOMEM (-6)   /* the context's HBM budget would be exceeded */
+#define FHE_EDEVICE (-7)  /* HIP runtime error */
+
+/* Parameter set (all arrays host memory, copied by fhe_ctx_create).
+ * Requirements: 10 <= log_n <= 16; every prime is distinct, below 2^50 and
+ * = 1 mod 2N; n_q + n_p <= 64; 1 <= dnum <= n_q.  The key-switching digit
+ * size is alpha = ceil(n_q / dnum).  cdt holds the cumulative thresholds of
+ * the error distribution: |e| = #{i : cdt[i] <= u} for a uniform 64-bit u. */
+typedef struct {
+    uint32_t log_n;
+    uint32_t n_q;
+    uint32_t n_p;
+    uint32_t dnum;
+    const uint64_t *q;
+    const uint64_t *p;
+    const uint64_t *cdt;
+    uint32_t n_cdt;
+} fhe_params;
+
+typedef struct fhe_ctx fhe_ctx;
+
+/* Ciphertext: polys (2, or 3 after a tensor product) x limbs x N residues. */
+typedef struct {
+    uint64_t *d;
+    uint32_t limbs;
+    uint32_t polys;
+    double scale;
+} fhe_ct;
+
+/* Plaintext: limbs x N residues. */
+typedef struct {
+    uint64_t *d;
+    uint32_t limbs;
+    double scale;
+} fhe_pt;
+
+/* Key-switching key: [dnum][2][n_q + n_p][N]; galois = 0 for the
+ * relinearisation key, else the Galois element 5^r mod 2N of the rotation. */
+typedef struct {
+    uint64_t *d;
+    uint64_t galois;
+} fhe_evk;
+
+/* ---------------------------------------------------------------- context */
+fhe_status fhe_ctx_create(const fhe_params *params, void *hip_stream, uint64_t hbm_budget_bytes,
+                          fhe_ctx **out);
+void fhe_ctx_destroy(fhe_ctx *ctx);
+fhe_status fhe_set_stream(fhe_ctx *ctx, void *hip_stream);
+const char *fhe_last_error(void);
+uint32_t fhe_ring_degree(const fhe_ctx *ctx);
+uint64_t fhe_modulus(const fhe_ctx *ctx, uint32_t idx);          /* 0..n_q-1: q_i; n_q..: p_j */
+size_t fhe_evk_bytes(const fhe_ctx *ctx);
+uint64_t fhe_galois_elt(const fhe_ctx *ctx, int32_t step);        /* 5^(step mod N/2) mod 2N */
+uint64_t fhe_scratch_bytes(const fhe_ctx *ctx);                   /* scratch currently held */
+
+/* --------------------------------------------------- limb transforms / IO
+ * Residue limbs are identified by a host list of modulus indices, one per
+ * limb (e.g. 0..l-1 repeated per polynomial of a ciphertext at l limbs).
+ * fhe_ntt / fhe_intt transform nlimbs consecutive limbs of d in place
+ * (negacyclic NTT, the evaluation at the odd powers of a 2N-th root).
+ * fhe_export_limbs writes the canonical coefficient-domain residues in
+ * [0, q) to host memory (d is left unchanged); fhe_import_limbs reads them
+ * from host memory and leaves the evaluation form in d. */
+fhe_status fhe_ntt(fhe_ctx *ctx, uint64_t *d, uint32_t nlimbs, const uint32_t *modidx);
+fhe_status fhe_intt(fhe_ctx *ctx, uint64_t *d, uint32_t nlimbs, const uint32_t *modidx);
+fhe_status fhe_export_limbs(fhe_ctx *ctx, const uint64_t *d, uint32_t nlimbs, const uint32_t *modidx,
+                            uint64_t *host_out);
+fhe_status fhe_import_limbs(fhe_ctx *ctx, const uint64_t *host_in, uint32_t nlimbs, const uint32_t *modidx,
+                            uint64_t *d);
+
+/* -------------------------------------------------------- client side
+ * The only calls that take the secret key s (host, N ternary coefficients).
+ * Random polynomials come from Philox4x64-10 with key (seed, stream tag) and
+ * counter (coefficient, modulus index, polynomial id, round); see the
+ * sampler notes in the library sources for the exact stream layout. */
+fhe_status fhe_keygen_secret(fhe_ctx *ctx, uint64_t seed, int8_t *s_host);
+fhe_status fhe_keygen_pk(fhe_ctx *ctx, const int8_t *s_host, uint64_t seed, fhe_ct *pk);   /* polys 2, limbs n_q */
+fhe_status fhe_keygen_relin(fhe_ctx *ctx, const int8_t *s_host, uint64_t seed, fhe_evk *out);
+fhe_status fhe_keygen_rot(fhe_ctx *ctx, const int8_t *s_host, int32_t step, uint64_t seed, fhe_evk *out);
+/* Slots (host re/im, im may be NULL; n <= N/2) -> round(scale * inverse
+ * canonical embedding) -> residues on limbs 0..limbs-1. */
+fhe_status fhe_encode(fhe_ctx *ctx, const double *re, const double *im, uint32_t n, double scale,
+                      fhe_pt *out);
+/* Integer coefficients (host, N values) -> plaintext on out->limbs limbs. */
+fhe_status fhe_encode_coeffs(fhe_ctx *ctx, const int64_t *coeff_host, fhe_pt *out);
+fhe_status fhe_encrypt(fhe_ctx *ctx, const fhe_ct *pk, const fhe_pt *m, uint64_t seed, fhe_ct *out);
+fhe_status fhe_decrypt(fhe_ctx *ctx, const int8_t *s_host, const fhe_ct *ct, fhe_pt *out);
+/* Plaintext -> n slots (host re/im, im may be NULL), dividing by pt->scale. */
+fhe_status fhe_decode(fhe_ctx *ctx, const fhe_pt *pt, double *re, double *im, uint32_t n);
+
+/* --------------------------------------------------------- server side */
+fhe_status fhe_add(fhe_ctx *ctx, const fhe_ct *a, const fhe_ct *b, fhe_ct *out);
+fhe_status fhe_sub(fhe_ctx *ctx, const fhe_ct *a, const fhe_ct *b, fhe_ct *out);
+fhe_status fhe_add_pt(fhe_ctx *ctx, const fhe_ct *a, const fhe_pt *p, fhe_ct *out);
+fhe_status fhe_mul_pt(fhe_ctx *ctx, const fhe_ct *a, const fhe_pt *p, fhe_ct *out);
+/* Multiply by the integer round(value * const_scale); out->scale = a->scale * const_scale. */
+fhe_status fhe_mul_const(fhe_ctx *ctx, const fhe_ct *a, double value, double const_scale, fhe_ct *out);
+/* Tensor product (a0 b0, a0 b1 + a1 b0, a1 b1); out has 3 polys. */
+fhe_status fhe_mul(fhe_ctx *ctx, const fhe_ct *a, const fhe_ct *b, fhe_ct *out3);
+/* acc3 = sum_t a[t] (x) b[t]; a, b: host arrays of n descriptors. */
+fhe_status fhe_mul_acc(fhe_ctx *ctx, const fhe_ct *a, const fhe_ct *b, uint32_t n, fhe_ct *acc3);
+fhe_status fhe_relin(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *in3, fhe_ct *out2);
+fhe_status fhe_rescale(fhe_ctx *ctx, const fhe_ct *in, fhe_ct *out);
+fhe_status fhe_drop_level(fhe_ctx *ctx, const fhe_ct *in, uint32_t limbs, fhe_ct *out);
+/* Left rotation by step slots with the Galois key of that step. */
+fhe_status fhe_rotate(fhe_ctx *ctx, const fhe_evk *gk, const fhe_ct *in, int32_t step, fhe_ct *out);
+/* Hybrid key switch of d (limbs x N, evaluation form): out = (ks0, ks1), polys 2. */
+fhe_status fhe_keyswitch(fhe_ctx *ctx, const fhe_evk *evk, const uint64_t *d, uint32_t limbs, fhe_ct *out);
+/* Batched key switch: n independent inputs d[t] (each limbs x N) with keys evk[t];
+ * d, evk, out are host arrays of n entries.  One launch sequence for all. */
+fhe_status fhe_keyswitch_batch(fhe_ctx *ctx, const fhe_evk *evk, const uint64_t *const *d, uint32_t limbs,
+                               uint32_t n, fhe_ct *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

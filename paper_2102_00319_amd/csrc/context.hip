@@ -1,0 +1,406 @@
+// context.hip -- parameter validation, precomputed tables, scratch memory,
+// limb transforms and coefficient-domain import/export.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "fhe_internal.h"
+
+typedef unsigned __int128 u128;
+
+namespace {
+thread_local std::string g_err;
+
+uint64_t hmul(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+uint64_t hpow(uint64_t a, uint64_t e, uint64_t m)
+{
+    uint64_t r = 1 % m;
+    a %= m;
+    for (; e; e >>= 1, a = hmul(a, a, m))
+        if (e & 1) r = hmul(r, a, m);
+    return r;
+}
+uint64_t hinv(uint64_t a, uint64_t m) { return hpow(a % m, m - 2, m); }
+
+bool miller_rabin(uint64_t n)
+{
+    if (n < 2) return false;
+    static const uint64_t w[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    for (uint64_t p : w)
+        if (n % p == 0) return n == p;
+    uint64_t d = n - 1;
+    int s = 0;
+    while (!(d & 1)) { d >>= 1; ++s; }
+    for (uint64_t a : w) {
+        uint64_t x = hpow(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool composite = true;
+        for (int i = 1; i < s && composite; ++i) {
+            x = hmul(x, x, n);
+            if (x == n - 1) composite = false;
+        }
+        if (composite) return false;
+    }
+    return true;
+}
+
+// Any element of order exactly 2N (N a power of two): w = g^((q-1)/2N) with w^N = -1.
+uint64_t root_2n(uint64_t q, uint32_t N)
+{
+    for (uint64_t g = 2; g < 1000000; ++g) {
+        uint64_t w = hpow(g, (q - 1) / (2ull * N), q);
+        if (hpow(w, N, q) == q - 1) return w;
+    }
+    return 0;
+}
+uint32_t brv(uint32_t x, uint32_t bits)
+{
+    uint32_t r = 0;
+    for (uint32_t i = 0; i < bits; ++i, x >>= 1) r = (r << 1) | (x & 1);
+    return r;
+}
+template <typename T>
+fhe_status dev_alloc(fhe_ctx *c, T **p, size_t count)
+{
+    size_t bytes = count * sizeof(T);
+    if (c->used + bytes > c->budget) return fhe_fail(FHE_ENOMEM, "context tables exceed the HBM budget");
+    HIPCHK(hipMalloc((void **)p, bytes ? bytes : 8));
+    c->used += bytes;
+    return FHE_OK;
+}
+template <typename T>
+fhe_status upload(fhe_ctx *c, T **p, const std::vector<T> &v)
+{
+    fhe_status s = dev_alloc(c, p, v.size());
+    if (s) return s;
+    HIPCHK(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return FHE_OK;
+}
+}  // namespace
+
+fhe_status fhe_fail(fhe_status code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+fhe_status fhe_hip_check(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return FHE_EDEVICE;
+}
+
+extern "C" const char *fhe_last_error(void) { return g_err.c_str(); }
+
+static void ctx_free_all(fhe_ctx *c)
+{
+    void *ptrs[] = {c->d_mod, c->d_tw, c->d_itw, c->d_ninv, c->d_cdt, c->d_cos, c->d_sin, c->d_g5,
+                    c->d_bconv, c->d_pinv, c->d_phalf, c->d_pmod, c->d_qlinv, c->scratch, c->d_ptrs, c->d_big};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->h_ptrs) {
+        (void)hipHostFree(c->h_ptrs);
+        for (int i = 0; i < PTR_SLOTS; ++i) (void)hipEventDestroy(c->ptr_ev[i]);
+    }
+    delete[] c->modup;
+    delete[] c->moddown;
+    delete c;
+}
+
+extern "C" fhe_status fhe_ctx_create(const fhe_params *pp, void *hip_stream, uint64_t hbm_budget, fhe_ctx **out)
+{
+    if (!pp || !out || !pp->q || (pp->n_p && !pp->p) || (pp->n_cdt && !pp->cdt))
+        return fhe_fail(FHE_EINVAL, "fhe_ctx_create: null argument");
+    *out = nullptr;
+    const uint32_t logN = pp->log_n, L = pp->n_q, K = pp->n_p;
+    if (logN < 10 || logN > 16) return fhe_fail(FHE_EPARAM, "log_n must be in [10, 16]");
+    if (L < 1 || L + K > FHE_MAXMOD || pp->dnum < 1 || pp->dnum > L)
+        return fhe_fail(FHE_EPARAM, "need 1 <= n_q, n_q + n_p <= 64, 1 <= dnum <= n_q");
+    const uint32_t N = 1u << logN;
+    fhe_ctx *c = new fhe_ctx();
+    std::memset((void *)c, 0, sizeof(fhe_ctx));
+    c->logN = logN; c->N = N; c->L = L; c->K = K; c->dnum = pp->dnum;
+    c->alpha = (L + pp->dnum - 1) / pp->dnum;
+    c->stream = (hipStream_t)hip_stream;
+    c->budget = hbm_budget ? hbm_budget : ~0ull;
+    for (uint32_t i = 0; i < L; ++i) c->mod[i] = pp->q[i];
+    for (uint32_t j = 0; j < K; ++j) c->mod[L + j] = pp->p[j];
+    const uint32_t M = L + K;
+    for (uint32_t i = 0; i < M; ++i) {
+        uint64_t q = c->mod[i];
+        bool bad = q >= (1ull << 50) || q < 3 || (q - 1) % (2ull * N) != 0 || !miller_rabin(q);
+        for (uint32_t j = 0; j < i; ++j) bad |= c->mod[j] == q;
+        if (bad) {
+            delete c;
+            return fhe_fail(FHE_EPARAM, "modulus " + std::to_string(i) +
+                                            " is not a distinct prime below 2^50 congruent to 1 mod 2N");
+        }
+    }
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return fhe_fail(FHE_EDEVICE, "no HIP device"); }
+
+    fhe_status st = FHE_OK;
+    // per-modulus constants and twiddles
+    std::vector<ModQ> mq(M);
+    std::vector<double> tw((size_t)M * N), itw((size_t)M * N), ninv(M), phalf(M);
+    uint64_t Pm[FHE_MAXMOD];
+    for (uint32_t i = 0; i < M; ++i) {
+        uint64_t q = c->mod[i];
+        mq[i].q = (double)q;
+        mq[i].qinv = 1.0 / (double)q;
+        uint64_t psi = root_2n(q, N), ipsi = hinv(psi, q);
+        for (uint32_t k = 0; k < N; ++k) {
+            uint32_t e = brv(k, logN);
+            tw[(size_t)i * N + k] = (double)hpow(psi, e, q);
+            itw[(size_t)i * N + k] = (double)hpow(ipsi, e, q);
+        }
+        ninv[i] = (double)hinv(N % q, q);
+        uint64_t pm = 1;
+        for (uint32_t j = 0; j < K; ++j) pm = hmul(pm, c->mod[L + j] % q, q);
+        Pm[i] = pm;
+        phalf[i] = (double)hmul((pm + q - 1) % q, hinv(2, q), q);    // (P-1)/2 mod q
+    }
+    std::vector<double> pinv(L), pmod(L), qlinv((size_t)L * L, 0.0);
+    for (uint32_t i = 0; i < L; ++i) {
+        pinv[i] = (double)hinv(Pm[i], c->mod[i]);
+        pmod[i] = (double)Pm[i];
+    }
+    for (uint32_t l = 1; l < L; ++l)            // dropping limb l
+        for (uint32_t i = 0; i < l; ++i) qlinv[(size_t)l * L + i] = (double)hinv(c->mod[l] % c->mod[i], c->mod[i]);
+
+    // basis conversion tables
+    std::vector<double> bc;
+    auto make_bconv = [&](BconvTab &t, const std::vector<uint32_t> &src, const std::vector<uint32_t> &dst) {
+        t.nsrc = (uint32_t)src.size();
+        t.ndst = (uint32_t)dst.size();
+        t.off = (uint32_t)bc.size();
+        for (uint32_t a = 0; a < t.nsrc; ++a) t.src[a] = (uint8_t)src[a];
+        for (uint32_t a = 0; a < t.ndst; ++a) t.dst[a] = (uint8_t)dst[a];
+        for (uint32_t a = 0; a < t.nsrc; ++a) {
+            uint64_t bi = c->mod[src[a]], h = 1;
+            for (uint32_t o = 0; o < t.nsrc; ++o)
+                if (o != a) h = hmul(h, c->mod[src[o]] % bi, bi);
+            bc.push_back((double)hinv(h, bi));
+        }
+        for (uint32_t a = 0; a < t.nsrc; ++a) bc.push_back((double)c->mod[src[a]]);
+        for (uint32_t a = 0; a < t.nsrc; ++a) bc.push_back(1.0 / (double)c->mod[src[a]]);
+        for (uint32_t d = 0; d < t.ndst; ++d) bc.push_back((double)c->mod[dst[d]]);
+        for (uint32_t d = 0; d < t.ndst; ++d) bc.push_back(1.0 / (double)c->mod[dst[d]]);
+        for (uint32_t a = 0; a < t.nsrc; ++a)
+            for (uint32_t d = 0; d < t.ndst; ++d) {
+                uint64_t cm = c->mod[dst[d]], h = 1;
+                for (uint32_t o = 0; o < t.nsrc; ++o)
+                    if (o != a) h = hmul(h, c->mod[src[o]] % cm, cm);
+                bc.push_back((double)h);
+            }
+    };
+    c->modup = new BconvTab[(size_t)(L + 1) * c->dnum];
+    c->moddown = new BconvTab[L + 1];
+    std::memset((void *)c->modup, 0, sizeof(BconvTab) * (L + 1) * c->dnum);
+    std::memset((void *)c->moddown, 0, sizeof(BconvTab) * (L + 1));
+    for (uint32_t l = 1; l <= L; ++l) {
+        uint32_t nd = (l + c->alpha - 1) / c->alpha;
+        for (uint32_t j = 0; j < nd; ++j) {
+            uint32_t lo = j * c->alpha, hi = std::min(lo + c->alpha, l);
+            std::vector<uint32_t> src, dst;
+            for (uint32_t i = lo; i < hi; ++i) src.push_back(i);
+            for (uint32_t i = 0; i < l; ++i)
+                if (i < lo || i >= hi) dst.push_back(i);
+            for (uint32_t k = 0; k < K; ++k) dst.push_back(L + k);
+            make_bconv(c->modup[(size_t)l * c->dnum + j], src, dst);
+        }
+        if (K) {
+            std::vector<uint32_t> src, dst;
+            for (uint32_t k = 0; k < K; ++k) src.push_back(L + k);
+            for (uint32_t i = 0; i < l; ++i) dst.push_back(i);
+            make_bconv(c->moddown[l], src, dst);
+        }
+    }
+    // encoding tables
+    std::vector<double> cs(2 * N), sn(2 * N);
+    for (uint32_t e = 0; e < 2 * N; ++e) {
+        double ang = M_PI * (double)e / (double)N;
+        cs[e] = std::cos(ang);
+        sn[e] = std::sin(ang);
+    }
+    std::vector<uint32_t> g5(N / 2);
+    {
+        uint64_t g = 1;
+        for (uint32_t j = 0; j < N / 2; ++j) { g5[j] = (uint32_t)g; g = g * 5 % (2ull * N); }
+    }
+    std::vector<uint64_t> cdt(pp->cdt, pp->cdt + pp->n_cdt);
+    c->ncdt = pp->n_cdt;
+
+    if ((st = upload(c, &c->d_mod, mq)) || (st = upload(c, &c->d_tw, tw)) || (st = upload(c, &c->d_itw, itw)) ||
+        (st = upload(c, &c->d_ninv, ninv)) || (st = upload(c, &c->d_phalf, phalf)) ||
+        (st = upload(c, &c->d_pinv, pinv)) || (st = upload(c, &c->d_pmod, pmod)) ||
+        (st = upload(c, &c->d_qlinv, qlinv)) || (st = upload(c, &c->d_bconv, bc)) ||
+        (st = upload(c, &c->d_cos, cs)) || (st = upload(c, &c->d_sin, sn)) || (st = upload(c, &c->d_g5, g5)) ||
+        (st = upload(c, &c->d_cdt, cdt.empty() ? std::vector<uint64_t>{0} : cdt))) {
+        ctx_free_all(c);
+        return st;
+    }
+    *out = c;
+    return FHE_OK;
+}
+
+extern "C" void fhe_ctx_destroy(fhe_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    ctx_free_all(c);
+}
+extern "C" fhe_status fhe_set_stream(fhe_ctx *c, void *s)
+{
+    if (!c) return fhe_fail(FHE_EINVAL, "null context");
+    c->stream = (hipStream_t)s;
+    return FHE_OK;
+}
+extern "C" uint32_t fhe_ring_degree(const fhe_ctx *c) { return c ? c->N : 0; }
+extern "C" uint64_t fhe_modulus(const fhe_ctx *c, uint32_t i) { return (c && i < c->L + c->K) ? c->mod[i] : 0; }
+extern "C" size_t fhe_evk_bytes(const fhe_ctx *c)
+{
+    return c ? (size_t)c->dnum * 2 * (c->L + c->K) * c->N * sizeof(uint64_t) : 0;
+}
+extern "C" uint64_t fhe_galois_elt(const fhe_ctx *c, int32_t step)
+{
+    if (!c) return 0;
+    int64_t n = c->N / 2, r = ((int64_t)step % n + n) % n;
+    uint64_t g = 1, m = 2ull * c->N, b = 5;
+    for (; r; r >>= 1, b = b * b % m)
+        if (r & 1) g = g * b % m;
+    return g;
+}
+extern "C" uint64_t fhe_scratch_bytes(const fhe_ctx *c) { return c ? c->scratch_bytes : 0; }
+
+fhe_status ctx_scratch(fhe_ctx *c, size_t bytes, uint8_t **out)
+{
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes > c->scratch_bytes) {
+        size_t grow = bytes - c->scratch_bytes;
+        if (c->used + grow > c->budget) return fhe_fail(FHE_ENOMEM, "scratch exceeds the HBM budget");
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->scratch) HIPCHK(hipFree(c->scratch));
+        c->scratch = nullptr;
+        c->used -= c->scratch_bytes;
+        c->scratch_bytes = 0;
+        HIPCHK(hipMalloc((void **)&c->scratch, bytes));
+        c->scratch_bytes = bytes;
+        c->used += bytes;
+    }
+    *out = c->scratch;
+    return FHE_OK;
+}
+
+// Upload a list of device pointers for the next launch(es) on the context's
+// stream.  Tables up to PTR_SLOT_CAP entries go through a ring of pinned
+// staging slots; a slot is refilled only after its previous copy completed.
+fhe_status ctx_ptr_table(fhe_ctx *c, const std::vector<uint64_t *> &ptrs, uint64_t ***dev)
+{
+    const size_t n = ptrs.size() ? ptrs.size() : 1;
+    if (!c->d_ptrs) {
+        HIPCHK(hipMalloc((void **)&c->d_ptrs, sizeof(uint64_t *) * PTR_SLOTS * PTR_SLOT_CAP));
+        HIPCHK(hipHostMalloc((void **)&c->h_ptrs, sizeof(uint64_t *) * PTR_SLOTS * PTR_SLOT_CAP));
+        for (int i = 0; i < PTR_SLOTS; ++i) HIPCHK(hipEventCreateWithFlags(&c->ptr_ev[i], hipEventDisableTiming));
+        for (int i = 0; i < PTR_SLOTS; ++i) HIPCHK(hipEventRecord(c->ptr_ev[i], c->stream));
+    }
+    if (n > PTR_SLOT_CAP) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (n > c->d_big_cap) {
+            if (c->d_big) HIPCHK(hipFree(c->d_big));
+            c->d_big = nullptr;
+            HIPCHK(hipMalloc((void **)&c->d_big, n * sizeof(uint64_t *)));
+            c->d_big_cap = n;
+        }
+        HIPCHK(hipMemcpy(c->d_big, ptrs.data(), ptrs.size() * sizeof(uint64_t *), hipMemcpyHostToDevice));
+        *dev = c->d_big;
+        return FHE_OK;
+    }
+    const uint32_t slot = c->ptr_next;
+    c->ptr_next = (c->ptr_next + 1) % PTR_SLOTS;
+    HIPCHK(hipEventSynchronize(c->ptr_ev[slot]));
+    uint64_t **h = c->h_ptrs + (size_t)slot * PTR_SLOT_CAP, **d = c->d_ptrs + (size_t)slot * PTR_SLOT_CAP;
+    std::memcpy(h, ptrs.data(), ptrs.size() * sizeof(uint64_t *));
+    HIPCHK(hipMemcpyAsync(d, h, ptrs.size() * sizeof(uint64_t *), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->ptr_ev[slot], c->stream));
+    *dev = d;
+    return FHE_OK;
+}
+
+LimbSet limbset_list(uint64_t *base, const uint32_t *mods, uint32_t period)
+{
+    LimbSet ls;
+    std::memset((void *)&ls, 0, sizeof(ls));
+    ls.base = base;
+    ls.period = period;
+    for (uint32_t i = 0; i < period && i < FHE_LIMBTAB; ++i) ls.mod[i] = (uint8_t)mods[i];
+    return ls;
+}
+// count limbs with moduli first_mod .. first_mod+period_mods-1, repeating
+LimbSet limbset_range(uint64_t *base, uint32_t first_mod, uint32_t count, uint32_t period_mods)
+{
+    (void)count;
+    uint32_t m[FHE_LIMBTAB];
+    for (uint32_t i = 0; i < period_mods; ++i) m[i] = first_mod + i;
+    return limbset_list(base, m, period_mods);
+}
+
+static fhe_status check_modlist(fhe_ctx *c, uint32_t nlimbs, const uint32_t *modidx)
+{
+    if (!modidx) return fhe_fail(FHE_EINVAL, "null modulus list");
+    if (nlimbs > FHE_LIMBTAB) return fhe_fail(FHE_EINVAL, "at most 128 limbs per call");
+    for (uint32_t i = 0; i < nlimbs; ++i)
+        if (modidx[i] >= c->L + c->K) return fhe_fail(FHE_EINVAL, "modulus index out of range");
+    return FHE_OK;
+}
+
+extern "C" fhe_status fhe_ntt(fhe_ctx *c, uint64_t *d, uint32_t nlimbs, const uint32_t *modidx)
+{
+    if (!c || !d) return fhe_fail(FHE_EINVAL, "fhe_ntt: null argument");
+    fhe_status s = check_modlist(c, nlimbs, modidx);
+    if (s) return s;
+    launch_ntt_fwd(c, limbset_list(d, modidx, nlimbs), nlimbs);
+    HIPCHK(hipGetLastError());
+    return FHE_OK;
+}
+extern "C" fhe_status fhe_intt(fhe_ctx *c, uint64_t *d, uint32_t nlimbs, const uint32_t *modidx)
+{
+    if (!c || !d) return fhe_fail(FHE_EINVAL, "fhe_intt: null argument");
+    fhe_status s = check_modlist(c, nlimbs, modidx);
+    if (s) return s;
+    launch_ntt_inv(c, limbset_list(d, modidx, nlimbs), nlimbs);
+    HIPCHK(hipGetLastError());
+    return FHE_OK;
+}
+extern "C" fhe_status fhe_export_limbs(fhe_ctx *c, const uint64_t *d, uint32_t nlimbs, const uint32_t *modidx,
+                                       uint64_t *host_out)
+{
+    if (!c || !d || !host_out) return fhe_fail(FHE_EINVAL, "fhe_export_limbs: null argument");
+    fhe_status s = check_modlist(c, nlimbs, modidx);
+    if (s) return s;
+    size_t bytes = (size_t)nlimbs * c->N * sizeof(uint64_t);
+    uint8_t *tmp;
+    if ((s = ctx_scratch(c, bytes, &tmp))) return s;
+    HIPCHK(hipMemcpyAsync(tmp, d, bytes, hipMemcpyDeviceToDevice, c->stream));
+    launch_ntt_inv(c, limbset_list((uint64_t *)tmp, modidx, nlimbs), nlimbs);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(host_out, tmp, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return FHE_OK;
+}
+extern "C" fhe_status fhe_import_limbs(fhe_ctx *c, const uint64_t *host_in, uint32_t nlimbs, const uint32_t *modidx,
+                                       uint64_t *d)
+{
+    if (!c || !d || !host_in) return fhe_fail(FHE_EINVAL, "fhe_import_limbs: null argument");
+    fhe_status s = check_modlist(c, nlimbs, modidx);
+    if (s) return s;
+    for (uint32_t i = 0; i < nlimbs; ++i)
+        for (uint32_t k = 0; k < c->N; ++k)
+            if (host_in[(size_t)i * c->N + k] >= c->mod[modidx[i]])
+                return fhe_fail(FHE_EINVAL, "import: residue not below its modulus");
+    size_t bytes = (size_t)nlimbs * c->N * sizeof(uint64_t);
+    HIPCHK(hipMemcpyAsync(d, host_in, bytes, hipMemcpyHostToDevice, c->stream));
+    launch_ntt_fwd(c, limbset_list(d, modidx, nlimbs), nlimbs);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return FHE_OK;
+}

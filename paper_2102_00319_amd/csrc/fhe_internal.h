@@ -1,0 +1,170 @@
+// fhe_internal.h -- shared definitions of the gfx950 RNS-CKKS library.
+//
+// Residue arithmetic runs on the FP64 vector ALU.  Every modulus is below
+// 2^50, so a residue is an integer held exactly in a double, and so is the
+// remainder of a product: for |a|, |b| with |a*b/q| < 2^52 the product
+// a*b = h + l is split exactly with one FMA, the quotient estimate
+// rint(h * (1/q)) is off by less than 2, and h - qt*q + l is computed
+// exactly (it is an integer below 2^53 in magnitude).  CDNA runs FP64 FMA at
+// the full vector rate, whereas 64-bit integer multiplies are built from
+// quarter-rate 32-bit ones, so this is the cheap form of modular arithmetic
+// on this GPU.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "fhe.h"
+
+#define FHE_MAXMOD 64
+#define FHE_LIMBTAB 128
+#define PTR_SLOTS 16
+#define PTR_SLOT_CAP 131072
+
+struct Consts64 {
+    double v[FHE_MAXMOD];
+};
+
+struct ModQ {
+    double q;
+    double qinv;   // 1/q rounded to nearest
+};
+
+// A batch of residue limbs.  Limb b lives at units[b / lpu] + (b % lpu) * N
+// (or base + b * N when units is null) and is reduced modulo
+// mods[mod[b % period]].
+struct LimbSet {
+    uint64_t *base;
+    uint64_t *const *units;
+    uint32_t lpu;
+    uint32_t period;
+    uint32_t b0;                  // limb number of blockIdx.y == 0 (large batches are split)
+    uint8_t mod[FHE_LIMBTAB];
+};
+
+// ------------------------------------------------------------------ device
+__device__ __forceinline__ double u64_to_f64(uint64_t x)   // x < 2^52
+{
+    return __hiloint2double((int)((uint32_t)(x >> 32) | 0x43300000u), (int)(uint32_t)x) -
+           4503599627370496.0;
+}
+__device__ __forceinline__ uint64_t f64_to_u64(double x)   // integer x in [0, 2^52)
+{
+    return (uint64_t)__double_as_longlong(x + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+}
+__device__ __forceinline__ double bits_to_f64(uint64_t x) { return __longlong_as_double((long long)x); }
+__device__ __forceinline__ uint64_t f64_to_bits(double x) { return (uint64_t)__double_as_longlong(x); }
+
+// a*b mod q, |result| < 2q, valid when |a*b/q| < 2^52 and |a|,|b| < 2^52.
+__device__ __forceinline__ double mulmod(double a, double b, double q, double qinv)
+{
+    double h = a * b;
+    double l = __fma_rn(a, b, -h);
+    double qt = __builtin_rint(h * qinv);
+    double r = __fma_rn(-qt, q, h);
+    return r + l;
+}
+// x mod q into [-q/2 - 1, q/2 + 1], valid for |x| < 2^52.
+__device__ __forceinline__ double redc(double x, double q, double qinv)
+{
+    return __fma_rn(-__builtin_rint(x * qinv), q, x);
+}
+// x mod q into [0, q), valid for |x| < 2^52.
+__device__ __forceinline__ double canon(double x, double q, double qinv)
+{
+    double r = redc(x, q, qinv);
+    return r < 0.0 ? r + q : r;
+}
+// x in (-q, 2q) into [0, q)
+__device__ __forceinline__ double fold(double x, double q)
+{
+    x = x < 0.0 ? x + q : x;
+    return x >= q ? x - q : x;
+}
+
+__device__ __forceinline__ uint64_t *limb_ptr(const LimbSet &ls, uint32_t b, uint32_t N)
+{
+    return ls.units ? ls.units[b / ls.lpu] + (size_t)(b % ls.lpu) * N : ls.base + (size_t)b * N;
+}
+__device__ __forceinline__ uint32_t limb_mod(const LimbSet &ls, uint32_t b) { return ls.mod[b % ls.period]; }
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ __forceinline__ void philox4x64_10(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1, uint64_t c2,
+                                              uint64_t c3, uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// --------------------------------------------------------------------- host
+struct BconvTab {                 // one fast basis conversion S -> T
+    uint32_t nsrc, ndst;
+    uint32_t off;                 // offset into ctx->d_bconv (doubles)
+    // layout at off: [nsrc] (B/b_i)^-1 mod b_i, [nsrc] b_i, [nsrc] 1/b_i, [ndst] c_t,
+    // [ndst] 1/c_t, then [nsrc][ndst] (B/b_i) mod c_t
+    uint8_t src[FHE_MAXMOD], dst[FHE_MAXMOD];
+};
+
+struct fhe_ctx {
+    uint32_t logN, N, L, K, dnum, alpha;
+    uint64_t mod[FHE_MAXMOD];
+    hipStream_t stream;
+    uint64_t budget, used;
+    int device;
+    // device tables
+    ModQ *d_mod;          // [L+K]
+    double *d_tw;         // [L+K][N]  psi^brv(i)
+    double *d_itw;        // [L+K][N]  psi^-brv(i)
+    double *d_ninv;       // [L+K]     N^-1 mod q
+    uint64_t *d_cdt;
+    uint32_t ncdt;
+    double *d_cos, *d_sin;   // [2N] cos/sin(pi e / N)
+    uint32_t *d_g5;          // [N/2] 5^j mod 2N
+    double *d_bconv;         // all basis-conversion constants
+    BconvTab *modup;         // [L+1][dnum] host: level l, digit j
+    BconvTab *moddown;       // [L+1] host: P -> Q_l
+    double *d_pinv;          // [L]      P^-1 mod q_i
+    double *d_phalf;         // [L+K]    (P-1)/2 mod m
+    double *d_pmod;          // [L]      P mod q_i
+    double *d_qlinv;         // [L][L]   q_l^-1 mod q_i  (row l)
+    // scratch (device), grown on demand within the budget
+    uint8_t *scratch;
+    size_t scratch_bytes;
+    // pointer tables for batched launches: a ring of slots, each a pinned host
+    // staging area and a device copy, reused once the slot's copy has completed
+    uint64_t **d_ptrs;       // [PTR_SLOTS][PTR_SLOT_CAP]
+    uint64_t **h_ptrs;       // pinned, same shape
+    hipEvent_t ptr_ev[16];
+    uint32_t ptr_next;
+    uint64_t **d_big;        // oversize table (synchronous path)
+    size_t d_big_cap;
+};
+
+// error handling
+fhe_status fhe_fail(fhe_status code, const std::string &msg);
+fhe_status fhe_hip_check(hipError_t e, const char *what);
+#define HIPCHK(x)                                                                  \
+    do {                                                                           \
+        hipError_t _e = (x);                                                       \
+        if (_e != hipSuccess) return fhe_hip_check(_e, #x);                        \
+    } while (0)
+
+// scratch / pointer tables
+fhe_status ctx_scratch(fhe_ctx *c, size_t bytes, uint8_t **out);
+fhe_status ctx_ptr_table(fhe_ctx *c, const std::vector<uint64_t *> &ptrs, uint64_t ***dev);
+
+// launchers (ntt.hip)
+void launch_ntt_fwd(fhe_ctx *c, const LimbSet &ls, uint32_t nlimbs);
+void launch_ntt_inv(fhe_ctx *c, const LimbSet &ls, uint32_t nlimbs);
+LimbSet limbset_range(uint64_t *base, uint32_t first_mod, uint32_t count, uint32_t period_mods);
+LimbSet limbset_list(uint64_t *base, const uint32_t *mods, uint32_t period);

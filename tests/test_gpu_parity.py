@@ -1,0 +1,265 @@
+"""GPU parity: every library operation, called through the C ABI, against the
+CPU oracle on the same seeded inputs.  Integer results must be bit-exact
+(canonical coefficient-domain residues); decoded slots are compared in FP64.
+
+Sizes: N = 2^12 (one NTT pass), 2^14 (one pass, 1024-thread groups), 2^15 and
+2^16 (column + row passes); levels include ragged last key-switching digits
+and the one-limb floor of rescale."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import OracleCtx, ckks
+
+pytestmark = pytest.mark.gpu
+
+
+def _fhe():
+    import paper_2102_00319_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def sets():
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            P = _fhe()
+            cache[name] = (P.Context.from_set(name), OracleCtx.from_set(name))
+        return cache[name]
+    return get
+
+
+def rand_ct(o, l, polys, seed):
+    return workloads.uniform_residues(seed, o.q[:l] * polys, o.N).reshape(polys, l, o.N)
+
+
+def eq(a, b):
+    a, b = np.asarray(a, dtype=np.uint64), np.asarray(b, dtype=np.uint64)
+    assert a.shape == b.shape
+    bad = np.argwhere(a != b)
+    assert bad.size == 0, "mismatch at %s (of %d)" % (bad[:5].tolist(), len(bad))
+
+
+# ------------------------------------------------------------------ NTT
+@pytest.mark.parametrize("name", ["c1_n12", "c2_n14", "c3_n15", "c4_n16"])
+def test_ntt_roundtrip_and_ring_product(sets, name):
+    g, o = sets(name)
+    l = min(o.L, 4)
+    x = rand_ct(o, l, 2, 1)
+    p = workloads.uniform_residues(2, o.q[:l], o.N)
+    cx = g.import_ct(x, 1.0)
+    eq(g.export_ct(cx), x)                          # iNTT(NTT(x)) == x
+    cp = g.import_limbs(p, list(range(l)))
+    prod = g.mul_pt(cx, _fhe().Plaintext(cp, 1.0))
+    want = o.mul_pt(ckks.Ct(x, 1.0), p, 1.0).data
+    eq(g.export_ct(prod), want)
+
+
+def test_ntt_special_primes_batch(sets):
+    g, o = sets("c4_n16")
+    mods = list(range(o.L, o.L + o.K)) * 3
+    x = workloads.uniform_residues(3, [o.moduli[m] for m in mods], o.N)
+    t = g.import_limbs(x, mods)
+    eq(g.export_limbs(t, mods), x)
+
+
+# -------------------------------------------------------------- samplers / keys
+def test_secret_and_public_key_parity(sets):
+    g, o = sets("c1_n12")
+    s = g.keygen_secret(workloads.SEED_SECRET)
+    so = o.keygen_secret(workloads.SEED_SECRET)
+    assert np.array_equal(s.astype(np.int64), so)
+    pk = g.keygen_pk(s, workloads.SEED_PK)
+    eq(g.export_ct(pk), o.keygen_pk(so, workloads.SEED_PK))
+
+
+@pytest.mark.parametrize("name", ["c1_n12", "c3_n13"])
+def test_relin_and_rotation_key_parity(sets, name):
+    g, o = sets(name)
+    s = g.keygen_secret(7)
+    so = s.astype(np.int64)
+    rlk = g.keygen_relin(s, 11)
+    eq(g.export_evk(rlk), o.keygen_relin(so, 11))
+    for step in [1, -3]:
+        gk = g.keygen_rot(s, step, 12)
+        assert gk.galois == o.galois_elt(step)
+        eq(g.export_evk(gk), o.keygen_rot(so, step, 12))
+
+
+# ------------------------------------------------------- encode / encrypt
+@pytest.mark.parametrize("name", ["c1_n12", "c2_n14"])
+def test_encode_parity(sets, name):
+    g, o = sets(name)
+    n = o.N // 2
+    re, im = workloads.complex_messages(3, n)
+    pt = g.encode(re, im, scale=o.scale, limbs=2)
+    got = g.export_limbs(pt.data, [0, 1])
+    want = o.encode_rns(re, o.scale, 2, im)
+    eq(got, want)
+    # fewer values than slots, real only
+    pt = g.encode(re[:100], None, scale=o.scale, limbs=1)
+    eq(g.export_limbs(pt.data, [0]), o.encode_rns(re[:100], o.scale, 1))
+
+
+def test_encrypt_decrypt_decode_parity(sets):
+    g, o = sets("c1_n12")
+    s = g.keygen_secret(1)
+    so = s.astype(np.int64)
+    pk = g.keygen_pk(s, 2)
+    pko = o.keygen_pk(so, 2)
+    n = o.N // 2
+    z = workloads.slot_messages(4, n)
+    coeff = o.encode(z, None, o.scale)
+    for l in [3, 1]:
+        pt = g.encode_coeffs(coeff, o.scale, limbs=l)
+        ct = g.encrypt(pk, pt, 99)
+        cto = o.encrypt(pko, o.small_to_rns(coeff, l), 99, o.scale)
+        eq(g.export_ct(ct), cto.data)
+        dec = g.decrypt(s, ct)
+        eq(g.export_limbs(dec.data, list(range(l))), o.decrypt(cto, so))
+        re, im = g.decode(dec)
+        ro, io = o.decode(o.decrypt(cto, so), o.scale)
+        assert np.array_equal(re, ro) and np.array_equal(im, io)
+        assert np.abs(re - z).max() < 1e-3
+
+
+# ------------------------------------------------------------ arithmetic
+def test_add_sub_mulconst_parity(sets):
+    g, o = sets("c1_n12")
+    a, b = rand_ct(o, 3, 2, 5), rand_ct(o, 3, 2, 6)
+    ga, gb = g.import_ct(a, 1.0), g.import_ct(b, 1.0)
+    eq(g.export_ct(g.add(ga, gb)), o.add(ckks.Ct(a, 1.0), ckks.Ct(b, 1.0)).data)
+    eq(g.export_ct(g.sub(ga, gb)), o.sub(ckks.Ct(a, 1.0), ckks.Ct(b, 1.0)).data)
+    got = g.mul_const(ga, -0.37, 2.0 ** 20)
+    eq(g.export_ct(got), o.mul_const(ckks.Ct(a, 1.0), round(-0.37 * 2 ** 20)).data)
+    p = workloads.uniform_residues(7, o.q, o.N)
+    gp = _fhe().Plaintext(g.import_limbs(p, [0, 1, 2]), 1.0)
+    eq(g.export_ct(g.add_pt(ga, gp)), o.add_pt(ckks.Ct(a, 1.0), p).data)
+
+
+@pytest.mark.parametrize("n", [1, 5, 25])
+def test_tensor_mac_parity(sets, n):
+    g, o = sets("c2_n14")
+    l = 5
+    As = [rand_ct(o, l, 2, 100 + i) for i in range(n)]
+    Bs = [rand_ct(o, l, 2, 200 + i) for i in range(n)]
+    got = g.mul_acc([g.import_ct(x, 1.0) for x in As], [g.import_ct(x, 1.0) for x in Bs])
+    want = o.mul_acc([ckks.Ct(x, 1.0) for x in As], [ckks.Ct(x, 1.0) for x in Bs])
+    eq(g.export_ct(got), want.data)
+
+
+@pytest.mark.parametrize("name,levels", [("c1_n12", [3, 2]), ("c2_n14", [8, 2]), ("c4_n16", [3])])
+def test_rescale_parity(sets, name, levels):
+    g, o = sets(name)
+    for l in levels:
+        for polys in [2, 3]:
+            x = rand_ct(o, l, polys, 10 + l)
+            got = g.rescale(g.import_ct(x, 2.0 ** 60))
+            want = o.rescale(ckks.Ct(x, 2.0 ** 60))
+            eq(g.export_ct(got), want.data)
+            assert got.scale == want.scale
+    # in place (output aliases the input buffer)
+    x = rand_ct(o, levels[0], 2, 3)
+    gx = g.import_ct(x, 1.0)
+    out = _fhe().Ciphertext(gx.data.view(-1)[: 2 * (levels[0] - 1) * o.N].view(2, levels[0] - 1, o.N), 1.0)
+    g.rescale(gx, out)
+    eq(g.export_ct(out), o.rescale(ckks.Ct(x, 1.0)).data)
+
+
+def test_rescale_floor_raises(sets):
+    g, o = sets("c1_n12")
+    P = _fhe()
+    x = g.import_ct(rand_ct(o, 1, 2, 1), 1.0)
+    with pytest.raises(P.FheError) as e:
+        g.rescale(x, g.new_ct(1))
+    assert e.value.code == P.fhe.FHE_ELEVEL
+
+
+# ----------------------------------------------------------- key switching
+@pytest.mark.parametrize("name,levels", [("c1_n12", [3, 2, 1]), ("c2_n14", [8, 5]), ("c3_n15", [16, 7, 1])])
+def test_keyswitch_parity_random_key(sets, name, levels):
+    g, o = sets(name)
+    M = o.L + o.K
+    evk = workloads.uniform_residues(50, o.moduli * (2 * o.dnum), o.N).reshape(o.dnum, 2, M, o.N)
+    gk = g.import_evk(evk)
+    for l in levels:
+        d = workloads.uniform_residues(60 + l, o.q[:l], o.N)
+        gd = g.import_limbs(d, list(range(l)))
+        got = g.keyswitch(gk, gd)
+        eq(g.export_ct(got), o.keyswitch(d, evk))
+
+
+def test_keyswitch_batch_matches_single(sets):
+    g, o = sets("c3_n15")
+    M = o.L + o.K
+    keys, ds = [], []
+    for b in range(3):
+        evk = workloads.uniform_residues(70 + b, o.moduli * (2 * o.dnum), o.N)
+        keys.append(g.import_evk(evk))
+        ds.append(g.import_limbs(workloads.uniform_residues(80 + b, o.q[:9], o.N), list(range(9))))
+    outs = g.keyswitch_batch(keys, ds)
+    for b in range(3):
+        single = g.keyswitch(keys[b], ds[b])
+        assert np.array_equal(g.export_ct(outs[b]), g.export_ct(single))
+
+
+def test_relin_rotate_parity(sets):
+    g, o = sets("c1_n12")
+    s = g.keygen_secret(3)
+    so = s.astype(np.int64)
+    rlk = g.keygen_relin(s, 4)
+    rlko = o.keygen_relin(so, 4)
+    x3 = rand_ct(o, 3, 3, 21)
+    got = g.relin(rlk, g.import_ct(x3, 1.0))
+    eq(g.export_ct(got), o.relin(ckks.Ct(x3, 1.0), rlko).data)
+    for step in [1, -1, 5]:
+        gk = g.keygen_rot(s, step, 30 + step)
+        gko = o.keygen_rot(so, step, 30 + step)
+        for l in [3, 2]:
+            x = rand_ct(o, l, 2, 40 + l)
+            got = g.rotate(gk, g.import_ct(x, 1.0), step)
+            eq(g.export_ct(got), o.rotate(ckks.Ct(x, 1.0), step, gko).data)
+    P = _fhe()
+    with pytest.raises(P.FheError) as e:
+        g.rotate(gk, g.import_ct(rand_ct(o, 3, 2, 1), 1.0), 2)
+    assert e.value.code == P.fhe.FHE_ENOKEY
+
+
+def test_end_to_end_mult_rotate_c1(sets):
+    """Config 1: encode, encrypt, HMult + relin + rescale, rotate by 1, decrypt, decode."""
+    g, o = sets("c1_n12")
+    n = o.N // 2
+    s = g.keygen_secret(workloads.SEED_SECRET)
+    pk = g.keygen_pk(s, workloads.SEED_PK)
+    rlk = g.keygen_relin(s, workloads.SEED_EVK)
+    gk = g.keygen_rot(s, 1, workloads.SEED_EVK + 1)
+    a, b = workloads.slot_messages(1, n), workloads.slot_messages(2, n)
+    ca = g.encrypt(pk, g.encode(a, scale=o.scale), workloads.SEED_ENC)
+    cb = g.encrypt(pk, g.encode(b, scale=o.scale), workloads.SEED_ENC + 1)
+    m = g.mul_relin_rescale(rlk, ca, cb)
+    r = g.rotate(gk, m, 1)
+    # bit-exact against the oracle pipeline from the same seeds
+    so = s.astype(np.int64)
+    pko = o.keygen_pk(so, workloads.SEED_PK)
+    rlko = o.keygen_relin(so, workloads.SEED_EVK)
+    gko = o.keygen_rot(so, 1, workloads.SEED_EVK + 1)
+    cao = o.encrypt(pko, o.encode_rns(a, o.scale, o.L), workloads.SEED_ENC, o.scale)
+    cbo = o.encrypt(pko, o.encode_rns(b, o.scale, o.L), workloads.SEED_ENC + 1, o.scale)
+    ro = o.rotate(o.mul_relin_rescale(cao, cbo, rlko), 1, gko)
+    eq(g.export_ct(r), ro.data)
+    got, _ = g.decode(g.decrypt(s, r))
+    assert np.abs(got - np.roll(a * b, -1)).max() < 1e-2   # scale 2^20 after the rescale
+
+
+# ------------------------------------------- the key switch at N=2^16, l=24
+def test_keyswitch_parity_n16_full_level(sets):
+    g, o = sets("c4_n16")
+    M = o.L + o.K
+    evk = workloads.uniform_residues(90, o.moduli * (2 * o.dnum), o.N).reshape(o.dnum, 2, M, o.N)
+    gk = g.import_evk(evk)
+    for l in [24, 17]:
+        d = workloads.uniform_residues(91 + l, o.q[:l], o.N)
+        got = g.keyswitch(gk, g.import_limbs(d, list(range(l))))
+        eq(g.export_ct(got), o.keyswitch(d, evk))
