@@ -96,6 +96,16 @@ size_t fhe_evk_bytes(const fhe_ctx *ctx);
 uint64_t fhe_galois_elt(const fhe_ctx *ctx, int32_t step);        /* 5^(step mod N/2) mod 2N */
 uint64_t fhe_scratch_bytes(const fhe_ctx *ctx);                   /* scratch currently held */
 
+/* Kernel timing for measurement: after fhe_profile_enable(ctx, cat) every
+ * launch of kernel category cat ("*" = all; categories: ntt_fwd, ntt_inv,
+ * bconv_up, bconv_down, ks_inner, ks_final, ks_copy, automorph, rescale,
+ * tensor, elementwise) is bracketed by HIP events on the context's stream.
+ * fhe_profile_read synchronises the stream and returns the summed event time
+ * and launch count of a category since enabling.  fhe_profile_enable(ctx,
+ * NULL) switches timing off. */
+fhe_status fhe_profile_enable(fhe_ctx *ctx, const char *category);
+fhe_status fhe_profile_read(fhe_ctx *ctx, const char *category, double *total_ms, uint64_t *count);
+
 /* --------------------------------------------------- limb transforms / IO
  * Residue limbs are identified by a host list of modulus indices, one per
  * limb (e.g. 0..l-1 repeated per polynomial of a ciphertext at l limbs).
@@ -147,6 +157,10 @@ fhe_status fhe_rescale(fhe_ctx *ctx, const fhe_ct *in, fhe_ct *out);
 fhe_status fhe_drop_level(fhe_ctx *ctx, const fhe_ct *in, uint32_t limbs, fhe_ct *out);
 /* Left rotation by step slots with the Galois key of that step. */
 fhe_status fhe_rotate(fhe_ctx *ctx, const fhe_evk *gk, const fhe_ct *in, int32_t step, fhe_ct *out);
+/* n independent rotations in one launch sequence: out[t] = rotate(in[t], steps[t])
+ * with Galois key gk[t]; gk, in, steps, out are host arrays of n entries. */
+fhe_status fhe_rotate_batch(fhe_ctx *ctx, const fhe_evk *gk, const fhe_ct *in, const int32_t *steps, uint32_t n,
+                            fhe_ct *out);
 /* Hybrid key switch of d (limbs x N, evaluation form): out = (ks0, ks1), polys 2. */
 fhe_status fhe_keyswitch(fhe_ctx *ctx, const fhe_evk *evk, const uint64_t *d, uint32_t limbs, fhe_ct *out);
 /* Batched key switch: n independent inputs d[t] (each limbs x N) with keys evk[t];

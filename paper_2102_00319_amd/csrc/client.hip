@@ -199,6 +199,17 @@ __global__ void k_encode(const double *__restrict__ re, const double *__restrict
     }
     coeff[k] = (int64_t)v;
 }
+// Correctly rounded conversion of an unsigned 128-bit integer (hi, lo) to double:
+// the top 64 significant bits with the discarded bits folded into a sticky bit,
+// then one rounding of that 64-bit integer and an exact scaling by 2^s.
+__device__ __forceinline__ double u128_to_f64(uint64_t hi, uint64_t lo)
+{
+    if (hi == 0) return (double)lo;
+    const int s = 64 - __clzll(hi);
+    uint64_t m = (hi << (64 - s)) | (lo >> s);
+    if (lo & ((1ull << s) - 1)) m |= 1ull;
+    return ldexp((double)m, s);
+}
 // centered lift of the plaintext from limb 0 (l == 1) or limbs 0, 1 by CRT
 __global__ void k_lift(const uint64_t *__restrict__ m, uint32_t l, uint64_t q0, uint64_t q1, uint64_t q0inv_mod_q1,
                        double *out, uint32_t logN)
@@ -215,7 +226,12 @@ __global__ void k_lift(const uint64_t *__restrict__ m, uint32_t l, uint64_t q0, 
         const uint64_t d = (x1 + q1 - x0 % q1) % q1;
         const uint64_t t = (uint64_t)(((u128)d * q0inv_mod_q1) % q1);
         const u128 Q = (u128)q0 * q1, x = (u128)x0 + (u128)q0 * t;
-        out[k] = x > Q / 2 ? -(double)(Q - x) : (double)x;
+        if (x > Q / 2) {
+            const u128 y = Q - x;
+            out[k] = -u128_to_f64((uint64_t)(y >> 64), (uint64_t)y);
+        } else {
+            out[k] = u128_to_f64((uint64_t)(x >> 64), (uint64_t)x);
+        }
     }
 }
 // decoding: one thread per slot j

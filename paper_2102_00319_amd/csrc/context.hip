@@ -2,6 +2,7 @@
 // limb transforms and coefficient-domain import/export.
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -92,8 +93,87 @@ fhe_status fhe_hip_check(hipError_t e, const char *what)
 
 extern "C" const char *fhe_last_error(void) { return g_err.c_str(); }
 
+struct Prof {
+    std::string cat;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    std::vector<std::pair<int, std::string>> live;   // recorded (slot, category)
+    std::map<std::string, std::pair<double, uint64_t>> acc;
+};
+
+int prof_begin(fhe_ctx *c, const char *cat)
+{
+    Prof *p = c->prof;
+    if (!p || (p->cat != "*" && p->cat != cat)) return -1;
+    int slot = -1;
+    for (size_t i = 0; i < p->pool.size() && slot < 0; ++i) {
+        bool used = false;
+        for (auto &l : p->live) used |= l.first == (int)i;
+        if (!used) slot = (int)i;
+    }
+    if (slot < 0) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1;
+        p->pool.push_back({a, b});
+        slot = (int)p->pool.size() - 1;
+    }
+    p->live.push_back({slot, cat});
+    (void)hipEventRecord(p->pool[slot].first, c->stream);
+    return slot;
+}
+void prof_end(fhe_ctx *c, int slot) { (void)hipEventRecord(c->prof->pool[slot].second, c->stream); }
+
+static void prof_collect(fhe_ctx *c)
+{
+    Prof *p = c->prof;
+    if (!p) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &l : p->live) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p->pool[l.first].first, p->pool[l.first].second) == hipSuccess) {
+            auto &e = p->acc[l.second];
+            e.first += ms;
+            e.second += 1;
+        }
+    }
+    p->live.clear();
+}
+
+extern "C" fhe_status fhe_profile_enable(fhe_ctx *c, const char *category)
+{
+    if (!c) return fhe_fail(FHE_EINVAL, "null context");
+    if (!category) {
+        if (c->prof) {
+            prof_collect(c);
+            for (auto &e : c->prof->pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+            delete c->prof;
+            c->prof = nullptr;
+        }
+        return FHE_OK;
+    }
+    if (!c->prof) c->prof = new Prof();
+    prof_collect(c);
+    c->prof->cat = category;
+    c->prof->acc.clear();
+    return FHE_OK;
+}
+extern "C" fhe_status fhe_profile_read(fhe_ctx *c, const char *category, double *total_ms, uint64_t *count)
+{
+    if (!c || !category || !total_ms || !count) return fhe_fail(FHE_EINVAL, "fhe_profile_read: null argument");
+    *total_ms = 0.0;
+    *count = 0;
+    if (!c->prof) return FHE_OK;
+    prof_collect(c);
+    auto it = c->prof->acc.find(category);
+    if (it != c->prof->acc.end()) {
+        *total_ms = it->second.first;
+        *count = it->second.second;
+    }
+    return FHE_OK;
+}
+
 static void ctx_free_all(fhe_ctx *c)
 {
+    if (c->prof) (void)fhe_profile_enable(c, nullptr);
     void *ptrs[] = {c->d_mod, c->d_tw, c->d_itw, c->d_ninv, c->d_cdt, c->d_cos, c->d_sin, c->d_g5,
                     c->d_bconv, c->d_pinv, c->d_phalf, c->d_pmod, c->d_qlinv, c->scratch, c->d_ptrs, c->d_big};
     for (void *p : ptrs)
@@ -148,10 +228,16 @@ extern "C" fhe_status fhe_ctx_create(const fhe_params *pp, void *hip_stream, uin
         mq[i].q = (double)q;
         mq[i].qinv = 1.0 / (double)q;
         uint64_t psi = root_2n(q, N), ipsi = hinv(psi, q);
+        std::vector<uint64_t> pw(N), ipw(N);
+        pw[0] = ipw[0] = 1;
+        for (uint32_t e = 1; e < N; ++e) {
+            pw[e] = hmul(pw[e - 1], psi, q);
+            ipw[e] = hmul(ipw[e - 1], ipsi, q);
+        }
         for (uint32_t k = 0; k < N; ++k) {
             uint32_t e = brv(k, logN);
-            tw[(size_t)i * N + k] = (double)hpow(psi, e, q);
-            itw[(size_t)i * N + k] = (double)hpow(ipsi, e, q);
+            tw[(size_t)i * N + k] = (double)pw[e];
+            itw[(size_t)i * N + k] = (double)ipw[e];
         }
         ninv[i] = (double)hinv(N % q, q);
         uint64_t pm = 1;

@@ -148,6 +148,7 @@ struct fhe_ctx {
     uint32_t ptr_next;
     uint64_t **d_big;        // oversize table (synchronous path)
     size_t d_big_cap;
+    struct Prof *prof;       // kernel timing (HIP events), null until enabled
 };
 
 // error handling
@@ -162,6 +163,20 @@ fhe_status fhe_hip_check(hipError_t e, const char *what);
 // scratch / pointer tables
 fhe_status ctx_scratch(fhe_ctx *c, size_t bytes, uint8_t **out);
 fhe_status ctx_ptr_table(fhe_ctx *c, const std::vector<uint64_t *> &ptrs, uint64_t ***dev);
+
+// Kernel timing: when enabled for a category (or "*"), launches of that
+// category are bracketed by HIP events on the context's stream.
+int prof_begin(fhe_ctx *c, const char *cat);
+void prof_end(fhe_ctx *c, int slot);
+struct ProfScope {
+    fhe_ctx *c;
+    int slot;
+    ProfScope(fhe_ctx *cc, const char *cat) : c(cc), slot(cc->prof ? prof_begin(cc, cat) : -1) {}
+    ~ProfScope()
+    {
+        if (slot >= 0) prof_end(c, slot);
+    }
+};
 
 // launchers (ntt.hip)
 void launch_ntt_fwd(fhe_ctx *c, const LimbSet &ls, uint32_t nlimbs);

@@ -187,7 +187,8 @@ void launch_ntt_fwd(fhe_ctx *c, const LimbSet &ls, uint32_t nlimbs)
     if (!nlimbs) return;
     const uint32_t logN = c->logN;
     hipStream_t st = c->stream;
-    auto go = [&](auto kern, uint32_t gx, int wg, uint32_t sig0) {
+    auto go = [&](auto kern, uint32_t gx, int wg, uint32_t sig0, const char *cat) {
+        ProfScope ps(c, cat);
         for (uint32_t done = 0; done < nlimbs; done += 65535u) {
             LimbSet l2 = ls;
             l2.b0 = ls.b0 + done;
@@ -197,18 +198,18 @@ void launch_ntt_fwd(fhe_ctx *c, const LimbSet &ls, uint32_t nlimbs)
         }
     };
     switch (logN) {
-    case 10: go(k_ntt_fwd<10, 64, false, true, true>, 1, 64, 0); break;
-    case 11: go(k_ntt_fwd<11, 128, false, true, true>, 1, 128, 0); break;
-    case 12: go(k_ntt_fwd<12, 256, false, true, true>, 1, 256, 0); break;
-    case 13: go(k_ntt_fwd<13, 512, false, true, true>, 1, 512, 0); break;
-    case 14: go(k_ntt_fwd<14, 1024, false, true, true>, 1, 1024, 0); break;
+    case 10: go(k_ntt_fwd<10, 64, false, true, true>, 1, 64, 0, "ntt_fwd"); break;
+    case 11: go(k_ntt_fwd<11, 128, false, true, true>, 1, 128, 0, "ntt_fwd"); break;
+    case 12: go(k_ntt_fwd<12, 256, false, true, true>, 1, 256, 0, "ntt_fwd"); break;
+    case 13: go(k_ntt_fwd<13, 512, false, true, true>, 1, 512, 0, "ntt_fwd"); break;
+    case 14: go(k_ntt_fwd<14, 1024, false, true, true>, 1, 1024, 0, "ntt_fwd"); break;
     case 15:
-        go(k_ntt_fwd<7, 256, true, true, false>, (1u << 8) / 32, 256, 0);
-        go(k_ntt_fwd<8, 256, false, false, true>, (1u << 7) / 16, 256, 7);
+        go(k_ntt_fwd<7, 256, true, true, false>, (1u << 8) / 32, 256, 0, "ntt_fwd_col");
+        go(k_ntt_fwd<8, 256, false, false, true>, (1u << 7) / 16, 256, 7, "ntt_fwd_row");
         break;
     case 16:
-        go(k_ntt_fwd<8, 256, true, true, false>, (1u << 8) / 16, 256, 0);
-        go(k_ntt_fwd<8, 256, false, false, true>, (1u << 8) / 16, 256, 8);
+        go(k_ntt_fwd<8, 256, true, true, false>, (1u << 8) / 16, 256, 0, "ntt_fwd_col");
+        go(k_ntt_fwd<8, 256, false, false, true>, (1u << 8) / 16, 256, 8, "ntt_fwd_row");
         break;
     default: break;
     }
@@ -219,7 +220,8 @@ void launch_ntt_inv(fhe_ctx *c, const LimbSet &ls, uint32_t nlimbs)
     if (!nlimbs) return;
     const uint32_t logN = c->logN;
     hipStream_t st = c->stream;
-    auto go = [&](auto kern, uint32_t gx, int wg, uint32_t sig0) {
+    auto go = [&](auto kern, uint32_t gx, int wg, uint32_t sig0, const char *cat) {
+        ProfScope ps(c, cat);
         for (uint32_t done = 0; done < nlimbs; done += 65535u) {
             LimbSet l2 = ls;
             l2.b0 = ls.b0 + done;
@@ -229,18 +231,18 @@ void launch_ntt_inv(fhe_ctx *c, const LimbSet &ls, uint32_t nlimbs)
         }
     };
     switch (logN) {
-    case 10: go(k_ntt_inv<10, 64, false, true, true, true>, 1, 64, 0); break;
-    case 11: go(k_ntt_inv<11, 128, false, true, true, true>, 1, 128, 0); break;
-    case 12: go(k_ntt_inv<12, 256, false, true, true, true>, 1, 256, 0); break;
-    case 13: go(k_ntt_inv<13, 512, false, true, true, true>, 1, 512, 0); break;
-    case 14: go(k_ntt_inv<14, 1024, false, true, true, true>, 1, 1024, 0); break;
+    case 10: go(k_ntt_inv<10, 64, false, true, true, true>, 1, 64, 0, "ntt_inv"); break;
+    case 11: go(k_ntt_inv<11, 128, false, true, true, true>, 1, 128, 0, "ntt_inv"); break;
+    case 12: go(k_ntt_inv<12, 256, false, true, true, true>, 1, 256, 0, "ntt_inv"); break;
+    case 13: go(k_ntt_inv<13, 512, false, true, true, true>, 1, 512, 0, "ntt_inv"); break;
+    case 14: go(k_ntt_inv<14, 1024, false, true, true, true>, 1, 1024, 0, "ntt_inv"); break;
     case 15:
-        go(k_ntt_inv<8, 256, false, true, false, false>, (1u << 7) / 16, 256, 7);
-        go(k_ntt_inv<7, 256, true, false, true, true>, (1u << 8) / 32, 256, 0);
+        go(k_ntt_inv<8, 256, false, true, false, false>, (1u << 7) / 16, 256, 7, "ntt_inv_row");
+        go(k_ntt_inv<7, 256, true, false, true, true>, (1u << 8) / 32, 256, 0, "ntt_inv_col");
         break;
     case 16:
-        go(k_ntt_inv<8, 256, false, true, false, false>, (1u << 8) / 16, 256, 8);
-        go(k_ntt_inv<8, 256, true, false, true, true>, (1u << 8) / 16, 256, 0);
+        go(k_ntt_inv<8, 256, false, true, false, false>, (1u << 8) / 16, 256, 8, "ntt_inv_row");
+        go(k_ntt_inv<8, 256, true, false, true, true>, (1u << 8) / 16, 256, 0, "ntt_inv_col");
         break;
     default: break;
     }

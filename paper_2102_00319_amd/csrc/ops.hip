@@ -335,37 +335,55 @@ fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, 
     const uint32_t gx = blocks_for(N, TPB);
 
     // 1. coefficient-domain copy of the inputs
-    hipLaunchKernelGGL(k_copy_limbs, dim3(blocks_for((uint64_t)l * N, TPB), n), dim3(TPB), 0, st, dt, dc,
-                       (uint64_t)l * N);
+    {
+        ProfScope ps(c, "ks_copy");
+        hipLaunchKernelGGL(k_copy_limbs, dim3(blocks_for((uint64_t)l * N, TPB), n), dim3(TPB), 0, st, dt, dc,
+                           (uint64_t)l * N);
+    }
     {
         uint32_t m[FHE_LIMBTAB];
         for (uint32_t i = 0; i < l; ++i) m[i] = i;
         launch_ntt_inv(c, limbset_list(dc, m, l), n * l);
     }
     // 2. ModUp basis conversion, 3. NTT of the converted limbs
-    hipLaunchKernelGGL(k_bconv<false>, dim3(gx, nd, n), dim3(TPB), 0, st, (const uint64_t *)dc, up,
-                       (const double *)c->d_bconv, up_args, c->logN, (const double *)nullptr, (const double *)nullptr);
+    {
+        ProfScope ps(c, "bconv_up");
+        hipLaunchKernelGGL(k_bconv<false>, dim3(gx, nd, n), dim3(TPB), 0, st, (const uint64_t *)dc, up,
+                           (const double *)c->d_bconv, up_args, c->logN, (const double *)nullptr,
+                           (const double *)nullptr);
+    }
     launch_ntt_fwd(c, limbset_list(up, upmods, ups), n * ups);
     // 4. inner product with the key over Q_l u P
-    hipLaunchKernelGGL(k_ks_inner, dim3(gx, l + K, n), dim3(TPB), 0, st, (uint64_t *const *)dt,
-                       (uint64_t *const *)(dt + n), (const uint64_t *)up, uQ, uP, (const ModQ *)c->d_mod, dm, c->logN);
+    {
+        ProfScope ps(c, "ks_inner");
+        hipLaunchKernelGGL(k_ks_inner, dim3(gx, l + K, n), dim3(TPB), 0, st, (uint64_t *const *)dt,
+                           (uint64_t *const *)(dt + n), (const uint64_t *)up, uQ, uP, (const ModQ *)c->d_mod, dm,
+                           c->logN);
+    }
     // 5. ModDown: P limbs to coefficients, rounded conversion to Q_l, NTT, finish
     {
         uint32_t m[FHE_LIMBTAB];
         for (uint32_t k = 0; k < K; ++k) m[k] = L + k;
         launch_ntt_inv(c, limbset_list(uP, m, K), n * 2 * K);
     }
-    hipLaunchKernelGGL(k_bconv<true>, dim3(gx, 1, n * 2), dim3(TPB), 0, st, (const uint64_t *)uP, z,
-                       (const double *)c->d_bconv, dn_args, c->logN, (const double *)(c->d_phalf + L),
-                       (const double *)c->d_phalf);
+    {
+        ProfScope ps(c, "bconv_down");
+        hipLaunchKernelGGL(k_bconv<true>, dim3(gx, 1, n * 2), dim3(TPB), 0, st, (const uint64_t *)uP, z,
+                           (const double *)c->d_bconv, dn_args, c->logN, (const double *)(c->d_phalf + L),
+                           (const double *)c->d_phalf);
+    }
     {
         uint32_t m[FHE_LIMBTAB];
         for (uint32_t i = 0; i < l; ++i) m[i] = i;
         launch_ntt_fwd(c, limbset_list(z, m, l), n * 2 * l);
     }
-    hipLaunchKernelGGL(k_ks_final, dim3(gx, l, 2 * n), dim3(TPB), 0, st, (const uint64_t *)uQ, (const uint64_t *)z,
-                       (uint64_t *const *)(dt + 2 * n), add ? (uint64_t *const *)(dt + 3 * n) : nullptr,
-                       (const double *)c->d_pinv, (const ModQ *)c->d_mod, l, c->logN);
+    {
+        ProfScope ps(c, "ks_final");
+        hipLaunchKernelGGL(k_ks_final, dim3(gx, l, 2 * n), dim3(TPB), 0, st, (const uint64_t *)uQ,
+                           (const uint64_t *)z, (uint64_t *const *)(dt + 2 * n),
+                           add ? (uint64_t *const *)(dt + 3 * n) : nullptr, (const double *)c->d_pinv,
+                           (const ModQ *)c->d_mod, l, c->logN);
+    }
     HIPCHK(hipGetLastError());
     return FHE_OK;
 }
@@ -610,6 +628,47 @@ fhe_status fhe_rotate(fhe_ctx *c, const fhe_evk *gk, const fhe_ct *in, int32_t s
     const uint64_t *ad[1] = {perm};
     fhe_status r = ks_run(c, l, 1, dd, ek, oo, ad);
     out->scale = in->scale;
+    return r;
+}
+
+fhe_status fhe_rotate_batch(fhe_ctx *c, const fhe_evk *gk, const fhe_ct *in, const int32_t *steps, uint32_t n,
+                            fhe_ct *out)
+{
+    fhe_status s;
+    if (!c || !gk || !in || !steps || !out || !n) return fhe_fail(FHE_EINVAL, "fhe_rotate_batch: null or empty");
+    const uint32_t l = in[0].limbs;
+    for (uint32_t b = 0; b < n; ++b) {
+        if (!gk[b].d) return fhe_fail(FHE_EINVAL, "fhe_rotate_batch: null key");
+        if ((s = chk_ct(c, &in[b], "fhe_rotate_batch")) || (s = chk_ct(c, &out[b], "fhe_rotate_batch"))) return s;
+        if (in[b].limbs != l || in[b].polys != 2 || out[b].polys != 2 || out[b].limbs != l)
+            return fhe_fail(FHE_EINVAL, "fhe_rotate_batch: all inputs and outputs must be 2 x l");
+        if (gk[b].galois != fhe_galois_elt(c, steps[b]))
+            return fhe_fail(FHE_ENOKEY, "fhe_rotate_batch: Galois key is for another step");
+    }
+    const size_t per = (size_t)l * c->N;
+    const uint32_t nd = (l + c->alpha - 1) / c->alpha;
+    size_t ups = 0;
+    for (uint32_t j = 0; j < nd; ++j) ups += c->modup[(size_t)l * c->dnum + j].ndst;
+    const size_t ks_limbs = (size_t)n * (l + ups + 4 * (size_t)l + 2 * c->K);
+    uint8_t *scr;
+    if ((s = ctx_scratch(c, (ks_limbs + 2 * (size_t)n * l) * c->N * sizeof(uint64_t), &scr))) return s;
+    uint64_t *perm = (uint64_t *)scr + ks_limbs * c->N;
+    std::vector<const uint64_t *> dd(n), ek(n), ad(n);
+    std::vector<uint64_t *> oo(n);
+    {
+        ProfScope ps(c, "automorph");
+        for (uint32_t b = 0; b < n; ++b) {
+            uint64_t *pb = perm + (size_t)b * 2 * per;
+            hipLaunchKernelGGL(k_automorph, dim3(blocks_for(2 * per, TPB)), dim3(TPB), 0, c->stream,
+                               (const uint64_t *)in[b].d, pb, c->logN, (uint64_t)2 * l, (uint32_t)gk[b].galois);
+            dd[b] = pb + per;
+            ad[b] = pb;
+            ek[b] = gk[b].d;
+            oo[b] = out[b].d;
+        }
+    }
+    fhe_status r = ks_run(c, l, n, dd.data(), ek.data(), oo.data(), ad.data());
+    for (uint32_t b = 0; b < n; ++b) out[b].scale = in[b].scale;
     return r;
 }
 

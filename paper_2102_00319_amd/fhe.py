@@ -74,6 +74,9 @@ _sig = {
     "fhe_rotate": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), C.c_int32, C.POINTER(fhe_ct)],
     "fhe_keyswitch": [_P, C.POINTER(fhe_evk), _P, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_keyswitch_batch": [_P, C.POINTER(fhe_evk), _P, C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
+    "fhe_rotate_batch": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), _P, C.c_uint32, C.POINTER(fhe_ct)],
+    "fhe_profile_enable": [_P, C.c_char_p],
+    "fhe_profile_read": [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)],
 }
 for _n, _a in _sig.items():
     getattr(_lib, _n).argtypes = _a
@@ -415,6 +418,27 @@ class Context:
         O = (fhe_ct * n)(*[o.s() for o in outs])
         _check(_lib.fhe_keyswitch_batch(self._h, K, D, limbs, n, O))
         return outs
+
+    def rotate_batch(self, gks, cts, steps, outs=None):
+        n = len(cts)
+        outs = outs or [self.new_ct(cts[0].limbs, 2) for _ in range(n)]
+        K = (fhe_evk * n)(*[k.s() for k in gks])
+        I = (fhe_ct * n)(*[x.s() for x in cts])
+        S = (C.c_int32 * n)(*[int(x) for x in steps])
+        O = (fhe_ct * n)(*[o.s() for o in outs])
+        _check(_lib.fhe_rotate_batch(self._h, K, I, C.cast(S, C.c_void_p), n, O))
+        for i, o in enumerate(outs):
+            o.scale = O[i].scale
+        return outs
+
+    # ------------------------------------------------------- measurement
+    def profile_enable(self, category):
+        _check(_lib.fhe_profile_enable(self._h, None if category is None else category.encode()))
+
+    def profile_read(self, category):
+        ms, cnt = C.c_double(), C.c_uint64()
+        _check(_lib.fhe_profile_read(self._h, category.encode(), C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value
 
     def mul_relin_rescale(self, rlk, a, b):
         return self.rescale(self.relin(rlk, self.mul(a, b)))
