@@ -243,6 +243,7 @@ __global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ 
     o1[k] = f64_to_u64(canon(a1, q, qi));
 }
 // out_t[i] = (u_t[i] - z_t[i]) * P^-1 (+ add_t[i]) mod q_i.  blockIdx.y = limb i, blockIdx.z = 2*b + t.
+// addptr (optional) holds 2 pointers per item: the addend polynomials for t = 0, 1 (each may be null).
 __global__ __launch_bounds__(TPB) void k_ks_final(const uint64_t *__restrict__ uQ, const uint64_t *__restrict__ z,
                                                   uint64_t *const *__restrict__ outptr,
                                                   uint64_t *const *__restrict__ addptr, const double *__restrict__ pinv,
@@ -257,7 +258,8 @@ __global__ __launch_bounds__(TPB) void k_ks_final(const uint64_t *__restrict__ u
     double r = mulmod(u64_to_f64(uQ[e]) - u64_to_f64(z[e]), pinv[i], q, qi);
     r = fold(r, q);
     const size_t oe = ((size_t)t * l + i) * N + k;
-    if (addptr && addptr[b]) r = fold(r + u64_to_f64(addptr[b][oe]), q);
+    const uint64_t *ad = addptr ? addptr[2 * b + t] : nullptr;   // addend polynomial t of item b, or none
+    if (ad) r = fold(r + u64_to_f64(ad[(size_t)i * N + k]), q);
     outptr[b][oe] = f64_to_u64(r);
 }
 __global__ void k_copy_limbs(uint64_t *const *__restrict__ srcptr, uint64_t *__restrict__ dst, uint64_t per_item)
@@ -280,7 +282,8 @@ static fhe_status chk_ct(const fhe_ctx *c, const fhe_ct *a, const char *what)
 static bool scales_match(double a, double b) { return std::fabs(a / b - 1.0) <= 9.5367431640625e-07; }   // 2^-20
 
 // Host-side key switch driver: n inputs (each l limbs, NTT domain), keys, outputs
-// (2 polys, l limbs) and optional addends (2 polys) folded into the result.
+// (2 polys, l limbs) and optional addends folded into the result: add[2b + t] is
+// the polynomial (l limbs) added to output polynomial t of item b, or null.
 fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, const uint64_t *const *evk,
                   uint64_t *const *out, const uint64_t *const *add)
 {
@@ -328,7 +331,7 @@ fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, 
     for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)d[b]);
     for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)evk[b]);
     for (uint32_t b = 0; b < n; ++b) tab.push_back(out[b]);
-    for (uint32_t b = 0; b < n; ++b) tab.push_back(add ? (uint64_t *)add[b] : nullptr);
+    for (uint32_t b = 0; b < 2 * n; ++b) tab.push_back(add ? (uint64_t *)add[b] : nullptr);
     uint64_t **dt;
     if ((s = ctx_ptr_table(c, tab, &dt))) return s;
     hipStream_t st = c->stream;
@@ -596,7 +599,7 @@ fhe_status fhe_relin(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *in3, fhe_ct *
     const uint64_t *dd[1] = {in3->d + 2 * per};
     const uint64_t *ek[1] = {rlk->d};
     uint64_t *oo[1] = {out2->d};
-    const uint64_t *ad[1] = {in3->d};   // (d0, d1) are the first two polys of the input
+    const uint64_t *ad[2] = {in3->d, in3->d + per};   // (d0, d1) + (ks0, ks1)
     fhe_status r = ks_run(c, in3->limbs, 1, dd, ek, oo, ad);
     out2->scale = in3->scale;
     return r;
@@ -625,7 +628,7 @@ fhe_status fhe_rotate(fhe_ctx *c, const fhe_evk *gk, const fhe_ct *in, int32_t s
     const uint64_t *dd[1] = {perm + per};
     const uint64_t *ek[1] = {gk->d};
     uint64_t *oo[1] = {out->d};
-    const uint64_t *ad[1] = {perm};
+    const uint64_t *ad[2] = {perm, nullptr};   // (sigma_g(c0) + ks0, ks1)
     fhe_status r = ks_run(c, l, 1, dd, ek, oo, ad);
     out->scale = in->scale;
     return r;
@@ -653,7 +656,7 @@ fhe_status fhe_rotate_batch(fhe_ctx *c, const fhe_evk *gk, const fhe_ct *in, con
     uint8_t *scr;
     if ((s = ctx_scratch(c, (ks_limbs + 2 * (size_t)n * l) * c->N * sizeof(uint64_t), &scr))) return s;
     uint64_t *perm = (uint64_t *)scr + ks_limbs * c->N;
-    std::vector<const uint64_t *> dd(n), ek(n), ad(n);
+    std::vector<const uint64_t *> dd(n), ek(n), ad(2 * (size_t)n, nullptr);
     std::vector<uint64_t *> oo(n);
     {
         ProfScope ps(c, "automorph");
@@ -662,7 +665,7 @@ fhe_status fhe_rotate_batch(fhe_ctx *c, const fhe_evk *gk, const fhe_ct *in, con
             hipLaunchKernelGGL(k_automorph, dim3(blocks_for(2 * per, TPB)), dim3(TPB), 0, c->stream,
                                (const uint64_t *)in[b].d, pb, c->logN, (uint64_t)2 * l, (uint32_t)gk[b].galois);
             dd[b] = pb + per;
-            ad[b] = pb;
+            ad[2 * b] = pb;
             ek[b] = gk[b].d;
             oo[b] = out[b].d;
         }
