@@ -168,6 +168,39 @@ fhe_status fhe_keyswitch(fhe_ctx *ctx, const fhe_evk *evk, const uint64_t *d, ui
 fhe_status fhe_keyswitch_batch(fhe_ctx *ctx, const fhe_evk *evk, const uint64_t *const *d, uint32_t limbs,
                                uint32_t n, fhe_ct *out);
 
+/* Batched relinearisation and rescale of n ciphertexts (host descriptor arrays;
+ * one key; rescale outputs must not overlap their inputs). */
+fhe_status fhe_relin_batch(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *in3, uint32_t n, fhe_ct *out2);
+fhe_status fhe_rescale_batch(fhe_ctx *ctx, const fhe_ct *in, uint32_t n, fhe_ct *out);
+
+/* --------------------------------------------------------- CNN layers
+ * Slot packing (Sec. 3 "Convolution Operator", Fig. 2): each input ciphertext
+ * holds one pixel of every image of the batch; each weight ciphertext holds one
+ * weight replicated in all slots.  All arrays are host arrays of descriptors.
+ *
+ * fhe_conv2d_slot, Eq. (enc_conv) with stride and zero padding:
+ *   Y[co][i][j] = Rescale(Relin( sum over ci, p, q with (y, x) inside the image of
+ *                 X[ci][y][x] (x) W[co][ci][p][q] )),  y = i*stride + p - pad_t,
+ *                 x = j*stride + q - pad_l;  padded taps are skipped.
+ * Layouts: X[(ci*H + y)*W + x], W[((co*Cin + ci)*kh + p)*kw + q], Y[(co*Ho + i)*Wo + j].
+ * Inputs and weights at one level l >= 2, outputs (caller-allocated) at l - 1.
+ * fhe_fc_slot: y[o] = Rescale(Relin(sum_i x[i] (x) W[o*n_in + i])) (Sec. 2.3, Z = f(WX), no bias).
+ * fhe_square_act: y[i] = Rescale(Relin(x[i] (x) x[i])) (the x^2 activation). */
+fhe_status fhe_conv2d_slot(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *X, uint32_t H, uint32_t W, uint32_t Cin,
+                           const fhe_ct *Wt, uint32_t Cout, uint32_t kh, uint32_t kw, uint32_t stride, uint32_t pad_t,
+                           uint32_t pad_l, uint32_t Ho, uint32_t Wo, fhe_ct *Y);
+fhe_status fhe_fc_slot(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *x, uint32_t n_in, const fhe_ct *Wt,
+                       uint32_t n_out, fhe_ct *y);
+fhe_status fhe_square_act(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *x, uint32_t n, fhe_ct *y);
+/* Model owner: encrypt n weights, each replicated in every slot (a constant
+ * polynomial round(value * scale)), under the user's public key; per-weight
+ * seeds (host array); outputs at out[0].limbs limbs. */
+fhe_status fhe_encrypt_const_batch(fhe_ctx *ctx, const fhe_ct *pk, const double *values, uint32_t n, double scale,
+                                   const uint64_t *seeds, fhe_ct *out);
+/* Operation counters since the last call (then reset): ct-ct mult, ct-ct add,
+ * ct-pt mult, ct-pt add, relinearise, rescale, rotate, (reserved). */
+fhe_status fhe_op_counts(fhe_ctx *ctx, uint64_t out[8]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -101,6 +101,8 @@ def build_all():
                  "uneven batch N=2^15: q0 ~2^45, 15 primes nearest 2^40, 4 special, dnum 4"),
         make_set("c4_n16", 16, 50, 23, 49, 8, 50, 49, 3,
                  "key switch / deep CNN: q0 ~2^50, 23 primes nearest 2^49, 8 special, dnum 3"),
+        make_set("t_n12", 12, 40, 5, 30, 2, 41, 30, 3,
+                 "small CNN tests: q0 ~2^40, 5 primes nearest 2^30, 2 special ~2^41, dnum 3"),
         make_set("p_n15", 15, 50, 15, 40, 4, 50, 40, 4,
                  "the paper's ring (m = 2^16): q0 ~2^50, 15 primes nearest 2^40, 4 special"),
     ]

@@ -22,6 +22,8 @@
 #define PTR_SLOTS 16
 #define PTR_SLOT_CAP 131072
 
+enum { OP_CT_MULT = 0, OP_CT_ADD, OP_PT_MULT, OP_PT_ADD, OP_RELIN, OP_RESCALE, OP_ROTATE, OP_KEYSWITCH };
+
 struct Consts64 {
     double v[FHE_MAXMOD];
 };
@@ -149,6 +151,7 @@ struct fhe_ctx {
     uint64_t **d_big;        // oversize table (synchronous path)
     size_t d_big_cap;
     struct Prof *prof;       // kernel timing (HIP events), null until enabled
+    uint64_t ops[8];         // operation counters, see OP_* (read and reset by fhe_op_counts)
 };
 
 // error handling
@@ -177,6 +180,15 @@ struct ProfScope {
         if (slot >= 0) prof_end(c, slot);
     }
 };
+
+// shared drivers (ops.hip)
+size_t ks_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t n);
+fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, const uint64_t *const *evk,
+                  uint64_t *const *out, const uint64_t *const *add, uint8_t *scr);
+size_t rescale_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n);
+fhe_status rescale_run(fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n, const uint64_t *const *in,
+                       uint64_t *const *out, uint8_t *scr);
+void launch_automorph(fhe_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nlimbs, uint64_t g);
 
 // launchers (ntt.hip)
 void launch_ntt_fwd(fhe_ctx *c, const LimbSet &ls, uint32_t nlimbs);

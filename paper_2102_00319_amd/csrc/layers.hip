@@ -1,0 +1,423 @@
+// layers.hip -- encrypted CNN layers built from batched ciphertext operations.
+//
+// Slot packing of the paper (Sec. 3 "Convolution Operator", Fig. 2): one
+// ciphertext per pixel holding that pixel of every image of the batch in its
+// slots, and one ciphertext per weight with the weight replicated in every
+// slot.  A layer output is then an inner product of ciphertexts, Eq. (enc_conv):
+//   Y[o] = Rescale(Relin( sum_t X[a_t] (x) W[b_t] ))
+// computed for all outputs of a layer at once: one tensor multiply-accumulate
+// launch over a CSR list of (input, weight) pairs, one batched key switch, one
+// batched rescale, in chunks that bound the scratch memory.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "fhe_internal.h"
+
+namespace {
+
+constexpr int TPB = 256;
+inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
+constexpr uint64_t TAG_UNIFORM = 2, TAG_ERROR = 3, TAG_EPHEMERAL = 4;
+
+// Pointer table layout: [a: P][b: P][out: n_out][offsets: n_out + 1 (as integers)].
+// Output o accumulates pairs off[o] .. off[o+1]-1 into a 3-poly ciphertext.
+__global__ __launch_bounds__(TPB) void k_tensor_acc_csr(uint64_t *const *__restrict__ tab, uint32_t P, uint32_t o0,
+                                                        uint32_t n_out, const ModQ *__restrict__ mods, uint32_t logN,
+                                                        uint32_t limbs)
+{
+    const uint32_t N = 1u << logN;
+    const uint64_t e = (uint64_t)blockIdx.x * TPB + threadIdx.x;   // limb * N + k
+    if (e >= ((uint64_t)limbs << logN)) return;
+    const uint32_t o = o0 + blockIdx.y;
+    uint64_t *const *ap = tab, *const *bp = tab + P;
+    uint64_t *out = tab[2 * P + o];
+    const uint64_t *off = (const uint64_t *)(tab + 2 * P + n_out);
+    const uint32_t limb = (uint32_t)(e >> logN);
+    const uint64_t off1 = (uint64_t)limbs * N;
+    const double q = mods[limb].q, qi = mods[limb].qinv;
+    double d0 = 0, d1 = 0, d2 = 0;
+    const uint32_t t0 = (uint32_t)off[o], t1 = (uint32_t)off[o + 1];
+    uint32_t cnt = 0;
+    for (uint32_t t = t0; t < t1; ++t, ++cnt) {
+        const uint64_t *A = ap[t], *B = bp[t];
+        const double a0 = u64_to_f64(A[e]), a1 = u64_to_f64(A[e + off1]);
+        const double b0 = u64_to_f64(B[e]), b1 = u64_to_f64(B[e + off1]);
+        d0 += mulmod(a0, b0, q, qi);
+        d1 += mulmod(a0, b1, q, qi) + mulmod(a1, b0, q, qi);
+        d2 += mulmod(a1, b1, q, qi);
+        if ((cnt & 3) == 3) {
+            d0 = redc(d0, q, qi);
+            d1 = redc(d1, q, qi);
+            d2 = redc(d2, q, qi);
+        }
+    }
+    out[e] = f64_to_u64(canon(d0, q, qi));
+    out[e + off1] = f64_to_u64(canon(d1, q, qi));
+    out[e + 2 * off1] = f64_to_u64(canon(d2, q, qi));
+}
+
+// ---- batched encryption of constant (slot-replicated) plaintexts
+__global__ void k_small_batch(int64_t *out, const uint64_t *__restrict__ seeds, const uint64_t *__restrict__ cdt,
+                              uint32_t ncdt, uint32_t N)
+{
+    // per item: v (ternary, tag 4, poly 0), e0 (tag 3, poly 0), e1 (tag 3, poly 1) -> out [item][3][N]
+    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
+    if (k >= N) return;
+    const uint32_t item = blockIdx.y;
+    const uint64_t seed = seeds[item];
+    int64_t *o = out + (size_t)item * 3 * N;
+    {
+        const uint64_t lim = 3ull * (0x100000000ull / 3);
+        int64_t val = 0;
+        for (uint64_t round = 0; round < 64; ++round) {
+            uint64_t w[4];
+            philox4x64_10(seed, TAG_EPHEMERAL, k, 0, 0, round, w);
+            bool found = false;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint64_t u = w[i] & 0xffffffffull;
+                if (!found && u < lim) { val = (int64_t)(u % 3) - 1; found = true; }
+            }
+            if (found) break;
+        }
+        o[k] = val;
+    }
+    for (uint64_t pid = 0; pid < 2; ++pid) {
+        uint64_t w[4];
+        philox4x64_10(seed, TAG_ERROR, k, 0, pid, 0, w);
+        int64_t mag = 0;
+        for (uint32_t i = 0; i < ncdt; ++i) mag += cdt[i] <= w[0];
+        o[(size_t)(1 + pid) * N + k] = (mag != 0 && (w[1] & 1)) ? -mag : mag;
+    }
+}
+// signed values [item][3][N] -> residues [item][3][l][N]
+__global__ void k_small_batch_rns(const int64_t *__restrict__ in, uint64_t *out, const ModQ *__restrict__ mods,
+                                  uint32_t logN, uint32_t l)
+{
+    const uint32_t N = 1u << logN;
+    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
+    if (k >= N) return;
+    const uint32_t limb = blockIdx.y, row = blockIdx.z;   // row = item * 3 + which
+    const int64_t q = (int64_t)mods[limb].q;
+    int64_t r = in[(size_t)row * N + k] % q;
+    if (r < 0) r += q;
+    out[((size_t)row * l + limb) * N + k] = (uint64_t)r;
+}
+// c0 = v*b + e0 + m, c1 = v*a + e1 with m the constant polynomial cres[item] (same value at
+// every evaluation point); outp[item] is [2][l][N].
+__global__ void k_encrypt_const(const uint64_t *__restrict__ pk, uint32_t L, const uint64_t *__restrict__ vee,
+                                const int64_t *__restrict__ cvals, uint64_t *const *__restrict__ outp, uint32_t l,
+                                const ModQ *__restrict__ mods, uint32_t logN)
+{
+    const uint32_t N = 1u << logN;
+    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
+    if (k >= N) return;
+    const uint32_t i = blockIdx.y, item = blockIdx.z;
+    const double q = mods[i].q, qi = mods[i].qinv;
+    const uint64_t *base = vee + (size_t)item * 3 * l * N;
+    const double v = u64_to_f64(base[(size_t)i * N + k]);
+    const double e0 = u64_to_f64(base[((size_t)l + i) * N + k]);
+    const double e1 = u64_to_f64(base[((size_t)2 * l + i) * N + k]);
+    int64_t mv = cvals[item] % (int64_t)q;
+    if (mv < 0) mv += (int64_t)q;
+    const double b = u64_to_f64(pk[(size_t)i * N + k]), a = u64_to_f64(pk[((size_t)L + i) * N + k]);
+    const double c0 = mulmod(v, b, q, qi) + e0 + (double)mv;
+    const double c1 = mulmod(v, a, q, qi) + e1;
+    uint64_t *o = outp[item];
+    o[(size_t)i * N + k] = f64_to_u64(canon(c0, q, qi));
+    o[((size_t)l + i) * N + k] = f64_to_u64(canon(c1, q, qi));
+}
+
+}  // namespace
+
+// Y[o] = Rescale(Relin(sum over CSR pairs)) for every output; all inputs at l limbs, 2 polys.
+static fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const std::vector<uint64_t *> &A,
+                                    const std::vector<uint64_t *> &B, const std::vector<uint32_t> &off,
+                                    const std::vector<uint64_t *> &Y)
+{
+    const uint32_t n_out = (uint32_t)Y.size();
+    if (l < 2) return fhe_fail(FHE_ELEVEL, "layer: inputs need at least 2 limbs (one rescale)");
+    const size_t N = c->N, LB = N * sizeof(uint64_t);
+    // chunk size: bound the scratch of one chunk to about 2 GiB
+    const size_t per_out = ks_scratch_bytes(c, l, 1) + (3 * (size_t)l + 2 * (size_t)l) * LB +
+                           rescale_scratch_bytes(c, l, 2, 1);
+    uint32_t C = (uint32_t)std::max<size_t>(1, std::min<size_t>(n_out, ((size_t)2 << 30) / per_out));
+    C = std::min<uint32_t>(C, 4096);
+    uint8_t *scr;
+    fhe_status s;
+    if ((s = ctx_scratch(c, per_out * C, &scr))) return s;
+    uint8_t *ks_scr = scr;
+    uint64_t *acc3 = (uint64_t *)(scr + ks_scratch_bytes(c, l, C));
+    uint64_t *tmp2 = acc3 + (size_t)C * 3 * l * N;
+    uint8_t *rs_scr = (uint8_t *)(tmp2 + (size_t)C * 2 * l * N);
+    // one pointer table for the whole layer
+    const uint32_t P = (uint32_t)A.size();
+    std::vector<uint64_t *> tab;
+    tab.reserve(2 * (size_t)P + 2 * (size_t)n_out + 1);
+    tab.insert(tab.end(), A.begin(), A.end());
+    tab.insert(tab.end(), B.begin(), B.end());
+    for (uint32_t o = 0; o < n_out; ++o) tab.push_back(nullptr);   // filled per chunk below
+    for (uint32_t o = 0; o <= n_out; ++o) tab.push_back((uint64_t *)(uintptr_t)off[o]);
+    std::vector<const uint64_t *> kd(C), ke(C, rlk->d), ka(2 * (size_t)C);
+    std::vector<uint64_t *> ko(C), ro(C);
+    std::vector<const uint64_t *> ri(C);
+    for (uint32_t o0 = 0; o0 < n_out; o0 += C) {
+        const uint32_t cn = std::min(C, n_out - o0);
+        for (uint32_t t = 0; t < cn; ++t) tab[2 * (size_t)P + o0 + t] = acc3 + (size_t)t * 3 * l * N;
+        uint64_t **dt;
+        if ((s = ctx_ptr_table(c, tab, &dt))) return s;
+        {
+            ProfScope ps(c, "tensor");
+            hipLaunchKernelGGL(k_tensor_acc_csr, dim3(blocks_for((uint64_t)l * N, TPB), cn), dim3(TPB), 0, c->stream,
+                               (uint64_t *const *)dt, P, o0, n_out, (const ModQ *)c->d_mod, c->logN, l);
+        }
+        for (uint32_t t = 0; t < cn; ++t) {
+            uint64_t *a3 = acc3 + (size_t)t * 3 * l * N;
+            kd[t] = a3 + 2 * (size_t)l * N;
+            ka[2 * t] = a3;
+            ka[2 * t + 1] = a3 + (size_t)l * N;
+            ko[t] = tmp2 + (size_t)t * 2 * l * N;
+            ri[t] = ko[t];
+            ro[t] = Y[o0 + t];
+        }
+        if ((s = ks_run(c, l, cn, kd.data(), ke.data(), ko.data(), ka.data(), ks_scr))) return s;
+        if ((s = rescale_run(c, l, 2, cn, ri.data(), ro.data(), rs_scr))) return s;
+    }
+    c->ops[OP_CT_MULT] += P;
+    c->ops[OP_CT_ADD] += P - n_out;
+    c->ops[OP_RELIN] += n_out;
+    c->ops[OP_RESCALE] += n_out;
+    HIPCHK(hipGetLastError());
+    return FHE_OK;
+}
+
+static fhe_status chk_in(const fhe_ct *x, uint32_t l, const char *what)
+{
+    if (!x->d || x->polys != 2 || x->limbs != l)
+        return fhe_fail(FHE_EINVAL, std::string(what) + ": every input must be a 2-poly ciphertext at the same level");
+    return FHE_OK;
+}
+static bool same_scale(double a, double b) { return std::fabs(a / b - 1.0) <= 9.5367431640625e-07; }
+
+extern "C" {
+
+fhe_status fhe_op_counts(fhe_ctx *c, uint64_t out[8])
+{
+    if (!c || !out) return fhe_fail(FHE_EINVAL, "fhe_op_counts: null argument");
+    for (int i = 0; i < 8; ++i) out[i] = c->ops[i];
+    std::memset(c->ops, 0, sizeof(c->ops));
+    return FHE_OK;
+}
+
+fhe_status fhe_relin_batch(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *in3, uint32_t n, fhe_ct *out2)
+{
+    if (!c || !rlk || !rlk->d || !in3 || !out2 || !n) return fhe_fail(FHE_EINVAL, "fhe_relin_batch: null or empty");
+    if (rlk->galois != 0) return fhe_fail(FHE_ENOKEY, "fhe_relin_batch: needs the relinearisation key");
+    const uint32_t l = in3[0].limbs;
+    const size_t per = (size_t)l * c->N;
+    std::vector<const uint64_t *> d(n), e(n, rlk->d), a(2 * (size_t)n);
+    std::vector<uint64_t *> o(n);
+    for (uint32_t t = 0; t < n; ++t) {
+        if (!in3[t].d || in3[t].polys != 3 || in3[t].limbs != l || !out2[t].d || out2[t].polys != 2 ||
+            out2[t].limbs != l)
+            return fhe_fail(FHE_EINVAL, "fhe_relin_batch: need 3-poly inputs and 2-poly outputs at one level");
+        d[t] = in3[t].d + 2 * per;
+        a[2 * t] = in3[t].d;
+        a[2 * t + 1] = in3[t].d + per;
+        o[t] = out2[t].d;
+    }
+    const uint32_t C = (uint32_t)std::max<size_t>(1, std::min<size_t>(n, ((size_t)2 << 30) / ks_scratch_bytes(c, l, 1)));
+    uint8_t *scr;
+    fhe_status s;
+    if ((s = ctx_scratch(c, ks_scratch_bytes(c, l, C), &scr))) return s;
+    for (uint32_t t0 = 0; t0 < n; t0 += C) {
+        const uint32_t cn = std::min(C, n - t0);
+        if ((s = ks_run(c, l, cn, d.data() + t0, e.data() + t0, o.data() + t0, a.data() + 2 * t0, scr))) return s;
+    }
+    for (uint32_t t = 0; t < n; ++t) out2[t].scale = in3[t].scale;
+    c->ops[OP_RELIN] += n;
+    return FHE_OK;
+}
+
+fhe_status fhe_rescale_batch(fhe_ctx *c, const fhe_ct *in, uint32_t n, fhe_ct *out)
+{
+    if (!c || !in || !out || !n) return fhe_fail(FHE_EINVAL, "fhe_rescale_batch: null or empty");
+    const uint32_t l = in[0].limbs, P = in[0].polys;
+    if (l < 2) return fhe_fail(FHE_ELEVEL, "fhe_rescale_batch: one limb left");
+    std::vector<const uint64_t *> ip(n);
+    std::vector<uint64_t *> op(n);
+    for (uint32_t t = 0; t < n; ++t) {
+        if (!in[t].d || in[t].limbs != l || in[t].polys != P || !out[t].d || out[t].limbs != l - 1 ||
+            out[t].polys != P)
+            return fhe_fail(FHE_EINVAL, "fhe_rescale_batch: shapes differ");
+        const uint64_t *ib = in[t].d, *ie = ib + (size_t)P * l * c->N;
+        const uint64_t *ob = out[t].d, *oe = ob + (size_t)P * (l - 1) * c->N;
+        if (ob < ie && ib < oe) return fhe_fail(FHE_EINVAL, "fhe_rescale_batch: outputs must not overlap inputs");
+        ip[t] = in[t].d;
+        op[t] = out[t].d;
+    }
+    const uint32_t C = std::min<uint32_t>(65535 / P, (uint32_t)std::max<size_t>(
+                                                          1, ((size_t)2 << 30) / rescale_scratch_bytes(c, l, P, 1)));
+    uint8_t *scr;
+    fhe_status s;
+    if ((s = ctx_scratch(c, rescale_scratch_bytes(c, l, P, std::min(C, n)), &scr))) return s;
+    for (uint32_t t0 = 0; t0 < n; t0 += C) {
+        const uint32_t cn = std::min(C, n - t0);
+        if ((s = rescale_run(c, l, P, cn, ip.data() + t0, op.data() + t0, scr))) return s;
+    }
+    for (uint32_t t = 0; t < n; ++t) out[t].scale = in[t].scale / (double)c->mod[l - 1];
+    c->ops[OP_RESCALE] += n;
+    return FHE_OK;
+}
+
+fhe_status fhe_conv2d_slot(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *X, uint32_t H, uint32_t W, uint32_t Cin,
+                           const fhe_ct *Wt, uint32_t Cout, uint32_t kh, uint32_t kw, uint32_t stride, uint32_t pad_t,
+                           uint32_t pad_l, uint32_t Ho, uint32_t Wo, fhe_ct *Y)
+{
+    fhe_status s;
+    if (!c || !rlk || !rlk->d || !X || !Wt || !Y) return fhe_fail(FHE_EINVAL, "fhe_conv2d_slot: null argument");
+    if (!H || !W || !Cin || !Cout || !kh || !kw || !stride || !Ho || !Wo)
+        return fhe_fail(FHE_EINVAL, "fhe_conv2d_slot: zero dimension");
+    if (rlk->galois != 0) return fhe_fail(FHE_ENOKEY, "fhe_conv2d_slot: needs the relinearisation key");
+    const uint32_t l = X[0].limbs;
+    const double sx = X[0].scale, sw = Wt[0].scale;
+    for (uint32_t i = 0; i < H * W * Cin; ++i) {
+        if ((s = chk_in(&X[i], l, "fhe_conv2d_slot"))) return s;
+        if (!same_scale(X[i].scale, sx)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_slot: input scales differ");
+    }
+    for (uint32_t i = 0; i < Cout * Cin * kh * kw; ++i) {
+        if ((s = chk_in(&Wt[i], l, "fhe_conv2d_slot"))) return s;
+        if (!same_scale(Wt[i].scale, sw)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_slot: weight scales differ");
+    }
+    std::vector<uint64_t *> A, B, Yp;
+    std::vector<uint32_t> off{0};
+    for (uint32_t co = 0; co < Cout; ++co)
+        for (uint32_t i = 0; i < Ho; ++i)
+            for (uint32_t j = 0; j < Wo; ++j) {
+                for (uint32_t ci = 0; ci < Cin; ++ci)
+                    for (uint32_t p = 0; p < kh; ++p)
+                        for (uint32_t q = 0; q < kw; ++q) {
+                            const int64_t y = (int64_t)i * stride + p - pad_t, x = (int64_t)j * stride + q - pad_l;
+                            if (y < 0 || x < 0 || y >= (int64_t)H || x >= (int64_t)W) continue;   // zero padding
+                            A.push_back(X[((size_t)ci * H + y) * W + x].d);
+                            B.push_back(Wt[(((size_t)co * Cin + ci) * kh + p) * kw + q].d);
+                        }
+                if (A.size() == off.back()) return fhe_fail(FHE_EINVAL, "fhe_conv2d_slot: an output has no taps");
+                off.push_back((uint32_t)A.size());
+                fhe_ct &y = Y[((size_t)co * Ho + i) * Wo + j];
+                if (!y.d || y.polys != 2 || y.limbs != l - 1)
+                    return fhe_fail(FHE_EINVAL, "fhe_conv2d_slot: outputs must be 2 x (l-1)");
+                Yp.push_back(y.d);
+            }
+    if ((s = mac_relin_rescale(c, rlk, l, A, B, off, Yp))) return s;
+    const double so = sx * sw / (double)c->mod[l - 1];
+    for (uint32_t o = 0; o < Cout * Ho * Wo; ++o) Y[o].scale = so;
+    return FHE_OK;
+}
+
+fhe_status fhe_fc_slot(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_t n_in, const fhe_ct *Wt,
+                       uint32_t n_out, fhe_ct *y)
+{
+    fhe_status s;
+    if (!c || !rlk || !rlk->d || !x || !Wt || !y || !n_in || !n_out) return fhe_fail(FHE_EINVAL, "fhe_fc_slot: null");
+    if (rlk->galois != 0) return fhe_fail(FHE_ENOKEY, "fhe_fc_slot: needs the relinearisation key");
+    const uint32_t l = x[0].limbs;
+    for (uint32_t i = 0; i < n_in; ++i) {
+        if ((s = chk_in(&x[i], l, "fhe_fc_slot"))) return s;
+        if (!same_scale(x[i].scale, x[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_slot: input scales differ");
+    }
+    std::vector<uint64_t *> A, B, Yp;
+    std::vector<uint32_t> off{0};
+    for (uint32_t o = 0; o < n_out; ++o) {
+        for (uint32_t i = 0; i < n_in; ++i) {
+            const fhe_ct &w = Wt[(size_t)o * n_in + i];
+            if ((s = chk_in(&w, l, "fhe_fc_slot"))) return s;
+            if (!same_scale(w.scale, Wt[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_slot: weight scales differ");
+            A.push_back(x[i].d);
+            B.push_back(w.d);
+        }
+        off.push_back((uint32_t)A.size());
+        if (!y[o].d || y[o].polys != 2 || y[o].limbs != l - 1) return fhe_fail(FHE_EINVAL, "fhe_fc_slot: bad output");
+        Yp.push_back(y[o].d);
+    }
+    if ((s = mac_relin_rescale(c, rlk, l, A, B, off, Yp))) return s;
+    const double so = x[0].scale * Wt[0].scale / (double)c->mod[l - 1];
+    for (uint32_t o = 0; o < n_out; ++o) y[o].scale = so;
+    return FHE_OK;
+}
+
+fhe_status fhe_square_act(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_t n, fhe_ct *y)
+{
+    fhe_status s;
+    if (!c || !rlk || !rlk->d || !x || !y || !n) return fhe_fail(FHE_EINVAL, "fhe_square_act: null");
+    if (rlk->galois != 0) return fhe_fail(FHE_ENOKEY, "fhe_square_act: needs the relinearisation key");
+    const uint32_t l = x[0].limbs;
+    std::vector<uint64_t *> A, B, Yp;
+    std::vector<uint32_t> off{0};
+    for (uint32_t i = 0; i < n; ++i) {
+        if ((s = chk_in(&x[i], l, "fhe_square_act"))) return s;
+        if (!y[i].d || y[i].polys != 2 || y[i].limbs != l - 1) return fhe_fail(FHE_EINVAL, "fhe_square_act: bad output");
+        A.push_back(x[i].d);
+        B.push_back(x[i].d);
+        off.push_back(i + 1);
+        Yp.push_back(y[i].d);
+    }
+    if ((s = mac_relin_rescale(c, rlk, l, A, B, off, Yp))) return s;
+    for (uint32_t i = 0; i < n; ++i) y[i].scale = x[i].scale * x[i].scale / (double)c->mod[l - 1];
+    return FHE_OK;
+}
+
+fhe_status fhe_encrypt_const_batch(fhe_ctx *c, const fhe_ct *pk, const double *values, uint32_t n, double scale,
+                                   const uint64_t *seeds, fhe_ct *out)
+{
+    if (!c || !pk || !pk->d || !values || !seeds || !out || !n)
+        return fhe_fail(FHE_EINVAL, "fhe_encrypt_const_batch: null argument");
+    if (pk->polys != 2 || pk->limbs != c->L) return fhe_fail(FHE_EINVAL, "fhe_encrypt_const_batch: bad public key");
+    const uint32_t l = out[0].limbs, N = c->N;
+    if (l < 1 || l > c->L) return fhe_fail(FHE_ELEVEL, "fhe_encrypt_const_batch: level out of range");
+    for (uint32_t t = 0; t < n; ++t)
+        if (!out[t].d || out[t].polys != 2 || out[t].limbs != l)
+            return fhe_fail(FHE_EINVAL, "fhe_encrypt_const_batch: outputs must be 2 x limbs, all at one level");
+    const uint32_t C = std::min<uint32_t>(n, 1024);
+    const size_t LB = (size_t)N * 8;
+    // scratch: seeds [C], values [C], small [C][3][N] int64, residues [C][3][l][N]
+    uint8_t *scr;
+    fhe_status s;
+    if ((s = ctx_scratch(c, 16 * (size_t)C + 256 + (size_t)C * 3 * LB + (size_t)C * 3 * l * LB, &scr))) return s;
+    uint64_t *dseed = (uint64_t *)scr;
+    int64_t *dval = (int64_t *)(dseed + C);
+    int64_t *small = (int64_t *)(scr + ((16 * (size_t)C + 255) & ~(size_t)255));
+    uint64_t *res = (uint64_t *)(small + (size_t)C * 3 * N);
+    std::vector<int64_t> iv(C);
+    std::vector<uint64_t *> optr(C);
+    for (uint32_t t0 = 0; t0 < n; t0 += C) {
+        const uint32_t cn = std::min(C, n - t0);
+        for (uint32_t t = 0; t < cn; ++t) {
+            const double v = std::nearbyint(values[t0 + t] * scale);
+            if (!(std::fabs(v) < 4611686018427387904.0)) return fhe_fail(FHE_EINVAL, "constant out of range");
+            iv[t] = (int64_t)v;
+            optr[t] = out[t0 + t].d;
+        }
+        HIPCHK(hipMemcpyAsync(dseed, seeds + t0, cn * 8, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(dval, iv.data(), cn * 8, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));   // iv is reused by the next chunk
+        uint64_t **dt;
+        if ((s = ctx_ptr_table(c, std::vector<uint64_t *>(optr.begin(), optr.begin() + cn), &dt))) return s;
+        hipLaunchKernelGGL(k_small_batch, dim3(blocks_for(N, TPB), cn), dim3(TPB), 0, c->stream, small,
+                           (const uint64_t *)dseed, (const uint64_t *)c->d_cdt, c->ncdt, N);
+        hipLaunchKernelGGL(k_small_batch_rns, dim3(blocks_for(N, TPB), l, 3 * cn), dim3(TPB), 0, c->stream,
+                           (const int64_t *)small, res, (const ModQ *)c->d_mod, c->logN, l);
+        uint32_t m[FHE_LIMBTAB];
+        for (uint32_t i = 0; i < l; ++i) m[i] = i;
+        launch_ntt_fwd(c, limbset_list(res, m, l), 3 * cn * l);
+        hipLaunchKernelGGL(k_encrypt_const, dim3(blocks_for(N, TPB), l, cn), dim3(TPB), 0, c->stream,
+                           (const uint64_t *)pk->d, c->L, (const uint64_t *)res, (const int64_t *)dval,
+                           (uint64_t *const *)dt, l, (const ModQ *)c->d_mod, c->logN);
+        for (uint32_t t = 0; t < cn; ++t) out[t0 + t].scale = scale;
+    }
+    HIPCHK(hipGetLastError());
+    return FHE_OK;
+}
+
+}  // extern "C"

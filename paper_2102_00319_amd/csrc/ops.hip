@@ -99,45 +99,45 @@ __global__ void k_automorph(const uint64_t *__restrict__ in, uint64_t *__restric
     const uint32_t y = __brev((ey - 1u) >> 1) >> (32 - logN);
     out[i] = in[base + y];
 }
-// Rescale, step 1: copy the last limb of each polynomial (in: [polys][l][N]) to tmp [polys][N].
-__global__ void k_gather_last(const uint64_t *__restrict__ in, uint64_t *__restrict__ tmp, uint32_t logN, uint32_t l,
+// Rescale over a batch of ciphertexts given by pointer tables (item b = ciphertext).
+// Step 1: copy the last limb of every polynomial to tmp [n*P][N].
+__global__ void k_gather_last(uint64_t *const *__restrict__ inp, uint64_t *__restrict__ tmp, uint32_t logN, uint32_t l,
                               uint32_t polys)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * TPB + threadIdx.x;
-    if (i >= ((uint64_t)polys << logN)) return;
-    const uint32_t N = 1u << logN, p = (uint32_t)(i >> logN), k = (uint32_t)(i & (N - 1));
-    tmp[i] = in[((uint64_t)p * l + (l - 1)) * N + k];
+    const uint32_t N = 1u << logN;
+    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
+    if (k >= N) return;
+    const uint32_t item = blockIdx.y, b = item / polys, p = item % polys;
+    tmp[(size_t)item * N + k] = inp[b][((size_t)p * l + (l - 1)) * N + k];
 }
-// Rescale, step 2: r (coefficient domain, mod q_last) lifted to (-q_last/2, q_last/2],
-// reduced mod q_i for i < l-1: dst [polys][l-1][N].
+// Step 2: the last limb r (coefficient domain, mod q_last) lifted to (-q_last/2, q_last/2]
+// and reduced mod q_i for i < l-1: dst [n*P][l-1][N].
 __global__ void k_spread_centered(const uint64_t *__restrict__ r, uint64_t *__restrict__ dst,
-                                  const ModQ *__restrict__ mods, uint32_t logN, uint32_t l, uint32_t polys)
+                                  const ModQ *__restrict__ mods, uint32_t logN, uint32_t l)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * TPB + threadIdx.x;
-    const uint32_t lo = l - 1;
-    if (i >= ((uint64_t)polys * lo << logN)) return;
-    const uint32_t N = 1u << logN, k = (uint32_t)(i & (N - 1));
-    const uint32_t limb = (uint32_t)((i >> logN) % lo), p = (uint32_t)((i >> logN) / lo);
+    const uint32_t N = 1u << logN;
+    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
+    if (k >= N) return;
+    const uint32_t limb = blockIdx.y, item = blockIdx.z, lo = l - 1;
     const double ql = mods[l - 1].q;
-    double v = u64_to_f64(r[((uint64_t)p << logN) + k]);
+    double v = u64_to_f64(r[(size_t)item * N + k]);
     v = v > 0.5 * ql ? v - ql : v;   // centered lift (q_last odd: no ties)
     const double q = mods[limb].q, qi = mods[limb].qinv;
-    dst[i] = f64_to_u64(canon(v, q, qi));
+    dst[((size_t)item * lo + limb) * N + k] = f64_to_u64(canon(v, q, qi));
 }
-// Rescale, step 3: out = (c - s) * q_last^-1 mod q_i.
-__global__ void k_rescale_fin(const uint64_t *__restrict__ in, const uint64_t *__restrict__ s, uint64_t *out,
-                              const ModQ *__restrict__ mods, const double *__restrict__ qlinv_row, uint32_t logN,
-                              uint32_t l, uint32_t polys)
+// Step 3: out = (c - s) * q_last^-1 mod q_i.
+__global__ void k_rescale_fin(uint64_t *const *__restrict__ inp, const uint64_t *__restrict__ s,
+                              uint64_t *const *__restrict__ outp, const ModQ *__restrict__ mods,
+                              const double *__restrict__ qlinv_row, uint32_t logN, uint32_t l, uint32_t polys)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * TPB + threadIdx.x;
-    const uint32_t lo = l - 1;
-    if (i >= ((uint64_t)polys * lo << logN)) return;
-    const uint32_t N = 1u << logN, k = (uint32_t)(i & (N - 1));
-    const uint32_t limb = (uint32_t)((i >> logN) % lo), p = (uint32_t)((i >> logN) / lo);
+    const uint32_t N = 1u << logN;
+    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
+    if (k >= N) return;
+    const uint32_t limb = blockIdx.y, item = blockIdx.z, b = item / polys, p = item % polys, lo = l - 1;
     const double q = mods[limb].q, qi = mods[limb].qinv;
-    const double c = u64_to_f64(in[((uint64_t)p * l + limb) * N + k]);
-    const double r = mulmod(c - u64_to_f64(s[i]), qlinv_row[limb], q, qi);
-    out[i] = f64_to_u64(fold(r, q));
+    const double c = u64_to_f64(inp[b][((size_t)p * l + limb) * N + k]);
+    const double r = mulmod(c - u64_to_f64(s[((size_t)item * lo + limb) * N + k]), qlinv_row[limb], q, qi);
+    outp[b][((size_t)p * lo + limb) * N + k] = f64_to_u64(fold(r, q));
 }
 
 // ------------------------------------------------------------ key switching
@@ -284,8 +284,16 @@ static bool scales_match(double a, double b) { return std::fabs(a / b - 1.0) <= 
 // Host-side key switch driver: n inputs (each l limbs, NTT domain), keys, outputs
 // (2 polys, l limbs) and optional addends folded into the result: add[2b + t] is
 // the polynomial (l limbs) added to output polynomial t of item b, or null.
+size_t ks_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t n)
+{
+    const uint32_t nd = (l + c->alpha - 1) / c->alpha;
+    size_t ups = 0;
+    for (uint32_t j = 0; j < nd; ++j) ups += c->modup[(size_t)l * c->dnum + j].ndst;
+    return (size_t)n * (5 * (size_t)l + ups + 2 * (size_t)c->K) * c->N * sizeof(uint64_t);
+}
+
 fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, const uint64_t *const *evk,
-                  uint64_t *const *out, const uint64_t *const *add)
+                  uint64_t *const *out, const uint64_t *const *add, uint8_t *scr_in)
 {
     if (!c->K) return fhe_fail(FHE_EPARAM, "key switching needs special primes");
     const uint32_t N = c->N, K = c->K, L = c->L, alpha = c->alpha;
@@ -322,9 +330,9 @@ fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, 
     // scratch: dc [n][l], up [n][ups], uQ [n][2][l], uP [n][2][K], z [n][2][l]
     const size_t LB = (size_t)N * sizeof(uint64_t);
     const size_t n_dc = (size_t)n * l, n_up = (size_t)n * ups, n_uq = (size_t)n * 2 * l, n_up2 = (size_t)n * 2 * K;
-    uint8_t *scr;
-    fhe_status s = ctx_scratch(c, (n_dc + n_up + n_uq + n_up2 + n_uq) * LB, &scr);
-    if (s) return s;
+    uint8_t *scr = scr_in;
+    fhe_status s = FHE_OK;
+    if (!scr && (s = ctx_scratch(c, (n_dc + n_up + n_uq + n_up2 + n_uq) * LB, &scr))) return s;
     uint64_t *dc = (uint64_t *)scr, *up = dc + n_dc * N, *uQ = up + n_up * N, *uP = uQ + n_uq * N, *z = uP + n_up2 * N;
 
     std::vector<uint64_t *> tab;
@@ -391,6 +399,43 @@ fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, 
     return FHE_OK;
 }
 
+size_t rescale_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n)
+{
+    return (size_t)n * polys * ((size_t)l) * c->N * sizeof(uint64_t);   // last limbs + spread limbs
+}
+// Rescale n ciphertexts (polys each, l limbs) into outputs (l-1 limbs); outputs must not overlap inputs.
+fhe_status rescale_run(fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n, const uint64_t *const *in,
+                       uint64_t *const *out, uint8_t *scr)
+{
+    const size_t N = c->N;
+    fhe_status s;
+    std::vector<uint64_t *> tab;
+    for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)in[b]);
+    for (uint32_t b = 0; b < n; ++b) tab.push_back(out[b]);
+    uint64_t **dt;
+    if ((s = ctx_ptr_table(c, tab, &dt))) return s;
+    uint64_t *last = (uint64_t *)scr, *spread = last + (size_t)n * polys * N;
+    const uint32_t gx = blocks_for(N, TPB), items = n * polys;
+    if (items > 65535u) return fhe_fail(FHE_EINVAL, "rescale batch too large for one launch");
+    ProfScope ps(c, "rescale");
+    hipLaunchKernelGGL(k_gather_last, dim3(gx, items), dim3(TPB), 0, c->stream, (uint64_t *const *)dt, last, c->logN,
+                       l, polys);
+    uint32_t m1 = l - 1;
+    launch_ntt_inv(c, limbset_list(last, &m1, 1), items);
+    hipLaunchKernelGGL(k_spread_centered, dim3(gx, l - 1, items), dim3(TPB), 0, c->stream, (const uint64_t *)last,
+                       spread, (const ModQ *)c->d_mod, c->logN, l);
+    {
+        uint32_t m[FHE_LIMBTAB];
+        for (uint32_t i = 0; i < l - 1; ++i) m[i] = i;
+        launch_ntt_fwd(c, limbset_list(spread, m, l - 1), items * (l - 1));
+    }
+    hipLaunchKernelGGL(k_rescale_fin, dim3(gx, l - 1, items), dim3(TPB), 0, c->stream, (uint64_t *const *)dt,
+                       (const uint64_t *)spread, (uint64_t *const *)(dt + n), (const ModQ *)c->d_mod,
+                       (const double *)(c->d_qlinv + (size_t)(l - 1) * c->L), c->logN, l, polys);
+    HIPCHK(hipGetLastError());
+    return FHE_OK;
+}
+
 // ========================================================= C entry points
 extern "C" {
 
@@ -406,6 +451,7 @@ fhe_status fhe_add(fhe_ctx *c, const fhe_ct *a, const fhe_ct *b, fhe_ct *out)
     hipLaunchKernelGGL(k_addsub, dim3(blocks_for(total, TPB)), dim3(TPB), 0, c->stream, (const uint64_t *)a->d,
                        (const uint64_t *)b->d, out->d, (const ModQ *)c->d_mod, c->logN, a->limbs, total, 0);
     out->scale = a->scale;
+    c->ops[OP_CT_ADD] += 1;
     HIPCHK(hipGetLastError());
     return FHE_OK;
 }
@@ -435,6 +481,7 @@ fhe_status fhe_add_pt(fhe_ctx *c, const fhe_ct *a, const fhe_pt *p, fhe_ct *out)
     const uint64_t per = (uint64_t)a->limbs * c->N;
     hipLaunchKernelGGL(k_addsub, dim3(blocks_for(per, TPB)), dim3(TPB), 0, c->stream, (const uint64_t *)a->d,
                        (const uint64_t *)p->d, out->d, (const ModQ *)c->d_mod, c->logN, a->limbs, per, 0);
+    c->ops[OP_PT_ADD] += 1;
     if (out->d != a->d)
         HIPCHK(hipMemcpyAsync(out->d + per, a->d + per, (a->polys - 1) * per * sizeof(uint64_t),
                               hipMemcpyDeviceToDevice, c->stream));
@@ -453,6 +500,7 @@ fhe_status fhe_mul_pt(fhe_ctx *c, const fhe_ct *a, const fhe_pt *p, fhe_ct *out)
     hipLaunchKernelGGL(k_mulpt, dim3(blocks_for(total, TPB)), dim3(TPB), 0, c->stream, (const uint64_t *)a->d,
                        (const uint64_t *)p->d, out->d, (const ModQ *)c->d_mod, c->logN, a->limbs, total);
     out->scale = a->scale * p->scale;
+    c->ops[OP_PT_MULT] += 1;
     HIPCHK(hipGetLastError());
     return FHE_OK;
 }
@@ -475,6 +523,7 @@ fhe_status fhe_mul_const(fhe_ctx *c, const fhe_ct *a, double value, double const
     hipLaunchKernelGGL(k_mulconst, dim3(blocks_for(total, TPB)), dim3(TPB), 0, c->stream, (const uint64_t *)a->d,
                        out->d, cres, (const ModQ *)c->d_mod, c->logN, a->limbs, total);
     out->scale = a->scale * const_scale;
+    c->ops[OP_PT_MULT] += 1;
     HIPCHK(hipGetLastError());
     return FHE_OK;
 }
@@ -500,6 +549,8 @@ fhe_status fhe_mul_acc(fhe_ctx *c, const fhe_ct *a, const fhe_ct *b, uint32_t n,
                        (uint64_t *const *)dt, (uint64_t *const *)(dt + n), n, acc3->d, (const ModQ *)c->d_mod, c->logN,
                        l);
     acc3->scale = sc;
+    c->ops[OP_CT_MULT] += n;
+    c->ops[OP_CT_ADD] += n - 1;
     HIPCHK(hipGetLastError());
     return FHE_OK;
 }
@@ -535,30 +586,18 @@ fhe_status fhe_rescale(fhe_ctx *c, const fhe_ct *in, fhe_ct *out)
     // then write to scratch and copy back
     const uint64_t *ib = in->d, *ie = in->d + (size_t)P * l * N, *ob = out->d, *oe = out->d + (size_t)P * (l - 1) * N;
     const bool overlap = ob < ie && ib < oe;
+    const size_t need = rescale_scratch_bytes(c, l, P, 1);
     uint8_t *scr;
-    const size_t res = overlap ? (size_t)P * (l - 1) : 0;
-    if ((s = ctx_scratch(c, ((size_t)P + (size_t)P * (l - 1) + res) * N * sizeof(uint64_t), &scr))) return s;
-    uint64_t *last = (uint64_t *)scr, *spread = last + P * N, *dst = overlap ? spread + (size_t)P * (l - 1) * N : out->d;
-    hipStream_t st = c->stream;
-    hipLaunchKernelGGL(k_gather_last, dim3(blocks_for(P * N, TPB)), dim3(TPB), 0, st, (const uint64_t *)in->d, last,
-                       c->logN, l, P);
-    uint32_t m1 = l - 1;
-    launch_ntt_inv(c, limbset_list(last, &m1, 1), P);
-    hipLaunchKernelGGL(k_spread_centered, dim3(blocks_for((uint64_t)P * (l - 1) * N, TPB)), dim3(TPB), 0, st,
-                       (const uint64_t *)last, spread, (const ModQ *)c->d_mod, c->logN, l, P);
-    {
-        uint32_t m[FHE_LIMBTAB];
-        for (uint32_t i = 0; i < l - 1; ++i) m[i] = i;
-        launch_ntt_fwd(c, limbset_list(spread, m, l - 1), P * (l - 1));
-    }
-    hipLaunchKernelGGL(k_rescale_fin, dim3(blocks_for((uint64_t)P * (l - 1) * N, TPB)), dim3(TPB), 0, st,
-                       (const uint64_t *)in->d, (const uint64_t *)spread, dst, (const ModQ *)c->d_mod,
-                       (const double *)(c->d_qlinv + (size_t)(l - 1) * c->L), c->logN, l, P);
+    if ((s = ctx_scratch(c, need + (overlap ? (size_t)P * (l - 1) * N * 8 : 0), &scr))) return s;
+    uint64_t *dst = overlap ? (uint64_t *)(scr + need) : out->d;
+    const uint64_t *ip[1] = {in->d};
+    uint64_t *op[1] = {dst};
+    if ((s = rescale_run(c, l, P, 1, ip, op, scr))) return s;
     if (overlap)
         HIPCHK(hipMemcpyAsync(out->d, dst, (size_t)P * (l - 1) * N * sizeof(uint64_t), hipMemcpyDeviceToDevice,
                               c->stream));
     out->scale = in->scale / (double)c->mod[l - 1];
-    HIPCHK(hipGetLastError());
+    c->ops[OP_RESCALE] += 1;
     return FHE_OK;
 }
 fhe_status fhe_keyswitch(fhe_ctx *c, const fhe_evk *evk, const uint64_t *d, uint32_t limbs, fhe_ct *out)
@@ -570,7 +609,7 @@ fhe_status fhe_keyswitch(fhe_ctx *c, const fhe_evk *evk, const uint64_t *d, uint
     const uint64_t *dd[1] = {d};
     const uint64_t *ek[1] = {evk->d};
     uint64_t *oo[1] = {out->d};
-    return ks_run(c, limbs, 1, dd, ek, oo, nullptr);
+    return ks_run(c, limbs, 1, dd, ek, oo, nullptr, nullptr);
 }
 fhe_status fhe_keyswitch_batch(fhe_ctx *c, const fhe_evk *evk, const uint64_t *const *d, uint32_t limbs, uint32_t n,
                                fhe_ct *out)
@@ -585,7 +624,7 @@ fhe_status fhe_keyswitch_batch(fhe_ctx *c, const fhe_evk *evk, const uint64_t *c
         if (out[b].limbs != limbs || out[b].polys != 2) return fhe_fail(FHE_EINVAL, "fhe_keyswitch_batch: bad output");
         dd[b] = d[b]; ek[b] = evk[b].d; oo[b] = out[b].d;
     }
-    return ks_run(c, limbs, n, dd.data(), ek.data(), oo.data(), nullptr);
+    return ks_run(c, limbs, n, dd.data(), ek.data(), oo.data(), nullptr, nullptr);
 }
 fhe_status fhe_relin(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *in3, fhe_ct *out2)
 {
@@ -600,8 +639,9 @@ fhe_status fhe_relin(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *in3, fhe_ct *
     const uint64_t *ek[1] = {rlk->d};
     uint64_t *oo[1] = {out2->d};
     const uint64_t *ad[2] = {in3->d, in3->d + per};   // (d0, d1) + (ks0, ks1)
-    fhe_status r = ks_run(c, in3->limbs, 1, dd, ek, oo, ad);
+    fhe_status r = ks_run(c, in3->limbs, 1, dd, ek, oo, ad, nullptr);
     out2->scale = in3->scale;
+    c->ops[OP_RELIN] += 1;
     return r;
 }
 fhe_status fhe_rotate(fhe_ctx *c, const fhe_evk *gk, const fhe_ct *in, int32_t step, fhe_ct *out)
@@ -629,8 +669,9 @@ fhe_status fhe_rotate(fhe_ctx *c, const fhe_evk *gk, const fhe_ct *in, int32_t s
     const uint64_t *ek[1] = {gk->d};
     uint64_t *oo[1] = {out->d};
     const uint64_t *ad[2] = {perm, nullptr};   // (sigma_g(c0) + ks0, ks1)
-    fhe_status r = ks_run(c, l, 1, dd, ek, oo, ad);
+    fhe_status r = ks_run(c, l, 1, dd, ek, oo, ad, scr);
     out->scale = in->scale;
+    c->ops[OP_ROTATE] += 1;
     return r;
 }
 
@@ -670,8 +711,9 @@ fhe_status fhe_rotate_batch(fhe_ctx *c, const fhe_evk *gk, const fhe_ct *in, con
             oo[b] = out[b].d;
         }
     }
-    fhe_status r = ks_run(c, l, n, dd.data(), ek.data(), oo.data(), ad.data());
+    fhe_status r = ks_run(c, l, n, dd.data(), ek.data(), oo.data(), ad.data(), scr);
     for (uint32_t b = 0; b < n; ++b) out[b].scale = in[b].scale;
+    c->ops[OP_ROTATE] += n;
     return r;
 }
 

@@ -76,6 +76,16 @@ _sig = {
     "fhe_keyswitch_batch": [_P, C.POINTER(fhe_evk), _P, C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_rotate_batch": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), _P, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_profile_enable": [_P, C.c_char_p],
+    "fhe_op_counts": [_P, _P],
+    "fhe_relin_batch": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), C.c_uint32, C.POINTER(fhe_ct)],
+    "fhe_rescale_batch": [_P, C.POINTER(fhe_ct), C.c_uint32, C.POINTER(fhe_ct)],
+    "fhe_conv2d_slot": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), C.c_uint32, C.c_uint32, C.c_uint32,
+                        C.POINTER(fhe_ct), C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                        C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
+    "fhe_fc_slot": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), C.c_uint32, C.POINTER(fhe_ct), C.c_uint32,
+                    C.POINTER(fhe_ct)],
+    "fhe_square_act": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), C.c_uint32, C.POINTER(fhe_ct)],
+    "fhe_encrypt_const_batch": [_P, C.POINTER(fhe_ct), _P, C.c_uint32, C.c_double, _P, C.POINTER(fhe_ct)],
     "fhe_profile_read": [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)],
 }
 for _n, _a in _sig.items():
@@ -439,6 +449,71 @@ class Context:
         ms, cnt = C.c_double(), C.c_uint64()
         _check(_lib.fhe_profile_read(self._h, category.encode(), C.byref(ms), C.byref(cnt)))
         return ms.value, cnt.value
+
+    # ----------------------------------------------------------- batches
+    @staticmethod
+    def _arr(cts):
+        return (fhe_ct * len(cts))(*[x.s() for x in cts])
+
+    @staticmethod
+    def _back(arr, cts):
+        for i, x in enumerate(cts):
+            x.scale = arr[i].scale
+
+    def relin_batch(self, rlk, cts3, outs=None):
+        outs = outs or [self.new_ct(x.limbs, 2) for x in cts3]
+        k, I, O = rlk.s(), self._arr(cts3), self._arr(outs)
+        _check(_lib.fhe_relin_batch(self._h, C.byref(k), I, len(cts3), O))
+        self._back(O, outs)
+        return outs
+
+    def rescale_batch(self, cts, outs=None):
+        outs = outs or [self.new_ct(x.limbs - 1, x.polys) for x in cts]
+        I, O = self._arr(cts), self._arr(outs)
+        _check(_lib.fhe_rescale_batch(self._h, I, len(cts), O))
+        self._back(O, outs)
+        return outs
+
+    def op_counts(self):
+        """(ct_mult, ct_add, pt_mult, pt_add, relin, rescale, rotate) since the last call."""
+        out = (C.c_uint64 * 8)()
+        _check(_lib.fhe_op_counts(self._h, out))
+        return dict(zip(["ct_mult", "ct_add", "pt_mult", "pt_add", "relin", "rescale", "rotate"], list(out)[:7]))
+
+    # ------------------------------------------------------------ layers
+    def encrypt_const_batch(self, pk, values, scale, seeds, limbs):
+        values = np.ascontiguousarray(values, dtype=np.float64).ravel()
+        seeds = np.ascontiguousarray(seeds, dtype=np.uint64).ravel()
+        outs = [self.new_ct(limbs, 2, scale) for _ in range(len(values))]
+        O = self._arr(outs)
+        _check(_lib.fhe_encrypt_const_batch(self._h, C.byref(pk.s()), values.ctypes.data_as(C.c_void_p), len(values),
+                                            float(scale), seeds.ctypes.data_as(C.c_void_p), O))
+        self._back(O, outs)
+        return outs
+
+    def conv2d_slot(self, rlk, X, H, W, Cin, Wt, Cout, kh, kw, stride, pad_t, pad_l, Ho, Wo):
+        l = X[0].limbs
+        Y = [self.new_ct(l - 1, 2) for _ in range(Cout * Ho * Wo)]
+        XA, WA, YA = self._arr(X), self._arr(Wt), self._arr(Y)
+        _check(_lib.fhe_conv2d_slot(self._h, C.byref(rlk.s()), XA, H, W, Cin, WA, Cout, kh, kw, stride, pad_t, pad_l,
+                                    Ho, Wo, YA))
+        self._back(YA, Y)
+        return Y
+
+    def fc_slot(self, rlk, x, Wt, n_out):
+        l = x[0].limbs
+        y = [self.new_ct(l - 1, 2) for _ in range(n_out)]
+        XA, WA, YA = self._arr(x), self._arr(Wt), self._arr(y)
+        _check(_lib.fhe_fc_slot(self._h, C.byref(rlk.s()), XA, len(x), WA, n_out, YA))
+        self._back(YA, y)
+        return y
+
+    def square_act(self, rlk, x):
+        y = [self.new_ct(v.limbs - 1, 2) for v in x]
+        XA, YA = self._arr(x), self._arr(y)
+        _check(_lib.fhe_square_act(self._h, C.byref(rlk.s()), XA, len(x), YA))
+        self._back(YA, y)
+        return y
 
     def mul_relin_rescale(self, rlk, a, b):
         return self.rescale(self.relin(rlk, self.mul(a, b)))

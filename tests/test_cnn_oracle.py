@@ -1,0 +1,47 @@
+"""CPU checks of the CNN layer definitions used by the encrypted recipes:
+the op-count formula of the paper and the FP64 network shape arithmetic."""
+import numpy as np
+
+from oracle import cnn
+
+
+def test_conv_count_matches_paper_formula_without_padding():
+    # Sec. 3: (M-P+1)(N-Q+1)PQ CT-CT mults for an M x N image and P x Q kernel, stride 1, no padding
+    for (M, N, P, Q) in [(28, 28, 3, 3), (8, 6, 2, 3), (5, 5, 5, 5)]:
+        Ho, Wo = M - P + 1, N - Q + 1
+        assert cnn.conv_op_count(M, N, P, Q, 1, 0, 0, Ho, Wo, 1, 1) == (M - P + 1) * (N - Q + 1) * P * Q
+
+
+def test_paper_network_shapes():
+    # Sec. 4.3: 28x28 input, 3x3 conv without padding -> 26x26, 2x2 mean pool -> 13x13, 28 filters
+    assert 28 - 3 + 1 == 26 and 26 // 2 == 13 and 13 * 13 * 28 == 4732
+    # Table 1 / Sec. 4.3: one filter's conv is 26*26*9 = 6084 CT-CT mults
+    assert cnn.conv_op_count(28, 28, 3, 3, 1, 0, 0, 26, 26, 1, 1) == 6084
+
+
+def test_config2_conv_counts():
+    # 28x28, 5x5 stride 2, pad top/left 1 -> 13x13 x 5 channels = 845 outputs
+    H = W = 28
+    Ho = Wo = (H + 1 - 5) // 2 + 1
+    assert Ho == 13 and 13 * 13 * 5 == 845
+    n = cnn.conv_op_count(H, W, 5, 5, 2, 1, 1, Ho, Wo, 1, 5)
+    assert n == 20480   # in-bounds taps only
+
+
+def test_fp64_forward_matches_direct_sum():
+    rs = np.random.default_rng(0)
+    x = rs.uniform(0, 1, (3, 6, 6))
+    w = rs.normal(0, 0.1, (2, 1, 3, 3))
+    f1 = rs.normal(0, 0.1, (3, 18))
+    f2 = rs.normal(0, 0.1, (2, 3))
+    out = cnn.slot_cnn_fp64(x, w, f1, f2, 2, 1, 1, 3, 3)
+    # independent evaluation by explicit zero padding and slicing
+    xp = np.pad(x, ((0, 0), (1, 1), (1, 1)))
+    conv = np.zeros((3, 2, 3, 3))
+    for co in range(2):
+        for i in range(3):
+            for j in range(3):
+                conv[:, co, i, j] = (xp[:, 2 * i:2 * i + 3, 2 * j:2 * j + 3] * w[co, 0]).sum(axis=(1, 2))
+    h = (conv ** 2).reshape(3, -1)
+    ref = ((h @ f1.T) ** 2) @ f2.T
+    assert np.allclose(out, ref, rtol=1e-12, atol=1e-14)
