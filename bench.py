@@ -36,6 +36,10 @@ def parse():
     ap.add_argument("--batch", type=int, default=8, help="rotations (distinct keys) per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--param-set", default="c4_n16")
+    ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "cnn2"],
+                    help="keyswitch: the headline metric; cnn2: slot-packed encrypted CNN images/s")
+    ap.add_argument("--fc1", type=int, default=100, help="cnn2: FC1 width (100 = the full network)")
+    ap.add_argument("--unbatched", action="store_true", help="cnn2: also time the one-ciphertext-per-call form")
     return ap.parse_args()
 
 
@@ -71,11 +75,94 @@ def kernel_model(cat, N, l, K, alpha, B):
     return "bytes", 0
 
 
+def cnn2(args):
+    """Slot-packed encrypted CNN (8192 images per ciphertext): conv 5x5 stride 2 x 5
+    channels -> x^2 -> FC 845->fc1 -> x^2 -> FC fc1->10; images and weights encrypted."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from oracle import cnn
+    import paper_2102_00319_amd as P
+
+    torch.cuda.set_device(0)
+    g = P.Context.from_set("c2_n14")
+    D, L = g.scale, g.L
+    B, H, W, K, Cout, n1, n2 = g.N // 2, 28, 28, 5, 5, args.fc1, 10
+    Ho = Wo = 13
+    imgs = workloads.images(workloads.SEED_DATA, B, H, W)
+    cw = workloads.weights(workloads.SEED_DATA + 1, (Cout, 1, K, K))
+    f1 = workloads.weights(workloads.SEED_DATA + 2, (n1, Cout * Ho * Wo))
+    f2 = workloads.weights(workloads.SEED_DATA + 3, (n2, n1))
+    t_setup = time.perf_counter()
+    s = g.keygen_secret(workloads.SEED_SECRET)
+    pk = g.keygen_pk(s, workloads.SEED_PK)
+    rlk = g.keygen_relin(s, workloads.SEED_EVK)
+    X = [g.encrypt(pk, g.encode(imgs[:, y, x], scale=D), workloads.SEED_ENC + y * W + x)
+         for y in range(H) for x in range(W)]
+    Wc = g.encrypt_const_batch(pk, cw.ravel(), D, [workloads.SEED_ENC + 100000 + t for t in range(cw.size)], L)
+    W1 = g.encrypt_const_batch(pk, f1.ravel(), D, [workloads.SEED_ENC + 200000 + t for t in range(f1.size)], L - 2)
+    W2 = g.encrypt_const_batch(pk, f2.ravel(), D, [workloads.SEED_ENC + 300000 + t for t in range(f2.size)], L - 4)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+
+    def forward():
+        Y = g.conv2d_slot(rlk, X, H, W, 1, Wc, Cout, K, K, 2, 1, 1, Ho, Wo)
+        return g.fc_slot(rlk, g.square_act(rlk, g.fc_slot(rlk, g.square_act(rlk, Y), W1, n1)), W2, n2)
+
+    out = forward()
+    ref = cnn.slot_cnn_fp64(imgs, cw, f1, f2, 2, 1, 1, Ho, Wo)
+    err = max(float(np.abs(g.decode(g.decrypt(s, out[r]), n=B)[0] - ref[:, r]).max()) for r in range(n2))
+    for _ in range(args.warmup):
+        forward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = forward()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    rec = {"metric": "encrypted-CNN images/s (slot packing, batched layers)", "value": round(B / dt, 1),
+           "unit": "images/s", "ms_per_batch": round(dt * 1e3, 3), "images_per_batch": B, "steps": args.steps,
+           "max_abs_logit_error_vs_fp64": err, "setup_s": round(t_setup, 1),
+           "config": {"workload": "conv5x5s2x5 -> x^2 -> FC845x%d -> x^2 -> FC%dx10, N=2^14, 8 x ~40-bit primes, "
+                                  "scale 2^40" % (n1, n1), "weight_ciphertexts": int(cw.size + f1.size + f2.size)}}
+    if args.unbatched:
+        def forward_unbatched():
+            def mrr(pairs):
+                acc = g.mul_acc([a for a, _ in pairs], [b for _, b in pairs])
+                return g.rescale(g.relin(rlk, acc))
+            Y = []
+            for co in range(Cout):
+                for i in range(Ho):
+                    for j in range(Wo):
+                        pr = [(X[(i * 2 + p - 1) * W + (j * 2 + q - 1)], Wc[co * K * K + p * K + q])
+                              for p in range(K) for q in range(K)
+                              if 0 <= i * 2 + p - 1 < H and 0 <= j * 2 + q - 1 < W]
+                        Y.append(mrr(pr))
+            A = [mrr([(y, y)]) for y in Y]
+            Z = [mrr([(A[i], W1[r * len(A) + i]) for i in range(len(A))]) for r in range(n1)]
+            A2 = [mrr([(z, z)]) for z in Z]
+            return [mrr([(A2[i], W2[r * n1 + i]) for i in range(n1)]) for r in range(n2)]
+        ou = forward_unbatched()
+        same = all(np.array_equal(g.export_ct(a), g.export_ct(b)) for a, b in zip(ou, out))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        forward_unbatched()
+        torch.cuda.synchronize()
+        du = time.perf_counter() - t0
+        rec["unbatched_images_per_s"] = round(B / du, 1)
+        rec["unbatched_ms_per_batch"] = round(du * 1e3, 2)
+        rec["unbatched_equals_batched_bitwise"] = bool(same)
+    print(json.dumps(rec))
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "cnn2":
+        return cnn2(args)
     import numpy as np
     import torch
 
