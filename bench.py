@@ -43,36 +43,51 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_model(cat, N, l, K, alpha, B):
-    """Algorithmic work of one launch of a kernel category in one step:
-    (kind, amount) with kind 'bytes' (HBM) or 'flops' (FP64 ALU)."""
+def ks_shape(logN):
+    """Split of each transform in the key-switching path: a column pass of LOGA
+    stages and a row pass of LOGB <= 8 stages."""
+    logB = min(8, logN - 4)
+    return logN - logB, logB
+
+
+def kernel_model(cat, N, l, K, alpha, B, dnum, L):
+    """Algorithmic work of one step (B key switches) per kernel category:
+    (bytes moved to and from HBM by the algorithm, FP64 flops)."""
     limb = N * 8
+    logN = N.bit_length() - 1
     nd = (l + alpha - 1) // alpha
     ups = sum(l + K - min(alpha, l - j * alpha) for j in range(nd))
-    logN = N.bit_length() - 1
-    if cat.startswith("ntt_"):
-        half = logN // 2
-        if cat == "ntt_fwd_col" or cat == "ntt_inv_col":
-            stages = half
-        elif cat in ("ntt_fwd_row", "ntt_inv_row"):
-            stages = logN - half
-        else:
-            stages = logN
-        return None, stages
+    logA, logB = ks_shape(logN)
+    bfly = (N // 2) * FLOPS_PER_BUTTERFLY     # flops of one stage over one limb
+    if cat == "ntt_fwd_col":
+        n = B * (ups + 2 * l)
+        return 2 * n * limb, n * logA * bfly
+    if cat == "ntt_fwd_row":
+        n = B * ups
+        return 2 * n * limb, n * logB * bfly
+    if cat == "ntt_inv_col":
+        n = B * (l + 2 * K)
+        return 2 * n * limb, n * logA * bfly
+    if cat == "ntt_inv_row":
+        n = B * 2 * K
+        return 2 * n * limb, n * logB * bfly
+    if cat == "ks_intt_first":
+        n = B * l
+        return 2 * n * limb, n * logB * bfly
+    if cat == "ks_moddown_final":
+        n = B * 2 * l
+        # z in, u in, out; the rotation addend sigma_g(c0); one exact product per element
+        return (3 * n + B * l) * limb, n * logB * bfly + n * N * 8
     if cat == "ks_inner":
-        # read nd*(l+K) D limbs and 2*nd*(l+K) key limbs, write 2*(l+K) limbs, per key switch
-        return "bytes", B * (nd * (l + K) + 2 * nd * (l + K) + 2 * (l + K)) * limb
-    if cat == "ks_final":
-        return "bytes", B * (2 * l * 3 + 2 * l) * limb        # uQ, z, addend in; out
+        # D_j and both key polynomials per digit in, u out (2 products per element per digit)
+        return B * (3 * nd * (l + K) + 2 * (l + K)) * limb, B * 2 * nd * (l + K) * N * 9
     if cat == "bconv_up":
-        return "bytes", B * (l + ups) * limb
+        return B * (l + ups) * limb, B * ups * alpha * N * 9
     if cat == "bconv_down":
-        return "bytes", B * (2 * K + 2 * l) * limb
+        return B * (2 * K + 2 * l) * limb, B * 2 * l * K * N * 9
     if cat == "automorph":
-        return "bytes", B * 4 * l * limb
-    if cat == "ks_copy":
-        return "bytes", B * 2 * l * limb
-    return "bytes", 0
+        return B * 4 * l * limb, 0
+    return 0, 0
 
 
 def cnn2(args):
@@ -198,7 +213,7 @@ def main():
 
     # untimed profiling pass to find the dominant kernel category
     cats = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_col", "ntt_inv_row", "ntt_fwd", "ntt_inv", "bconv_up",
-            "bconv_down", "ks_inner", "ks_final", "ks_copy", "automorph"]
+            "bconv_down", "ks_intt_first", "ks_inner", "ks_moddown_final", "automorph"]
     g.profile_enable("*")
     for _ in range(3):
         step()
@@ -224,26 +239,21 @@ def main():
     ks_bytes = (l + g.dnum * 2 * (g.L + g.K) + 2 * l) * N * 8
     hbm_frac = ks_per_s * ks_bytes / (HBM_PEAK_GBS * 1e9)
 
-    kind, amount = kernel_model(dominant, N, l, K, alpha, B)
+    bytes_step, flops_step = kernel_model(dominant, N, l, K, alpha, B, g.dnum, g.L)
     avg_ms = dom_ms / max(dom_cnt, 1)
     launches_per_step = dom_cnt / args.steps
-    if kind is None:   # NTT pass: FP64 ALU work
-        stages = amount
-        # limbs per launch: derived from launches per step and the per-step limb count
-        nd = (l + alpha - 1) // alpha
-        ups = sum(l + K - min(alpha, l - j * alpha) for j in range(nd))
-        limbs_per_step = {"ntt_fwd": B * (ups + 2 * l), "ntt_inv": B * (l + 2 * K)}
-        key = "ntt_fwd" if dominant.startswith("ntt_fwd") else "ntt_inv"
-        limbs_per_launch = limbs_per_step[key] / max(launches_per_step, 1)
-        flops = limbs_per_launch * (N // 2) * stages * FLOPS_PER_BUTTERFLY
-        achieved = flops / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None}
+    per_launch_b = bytes_step / max(launches_per_step, 1)
+    per_launch_f = flops_step / max(launches_per_step, 1)
+    gbs = per_launch_b / (avg_ms * 1e-3) / 1e9
+    tfl = per_launch_f / (avg_ms * 1e-3) / 1e12
+    if gbs / HBM_PEAK_GBS >= tfl / FP64_PEAK_TFLOPS:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
     else:
-        per_launch = amount / max(launches_per_step, 1)
-        achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+        roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tfl / FP64_PEAK_TFLOPS, 4), "traffic": None}
+    roof["algorithmic_bytes_per_launch"] = int(per_launch_b)
+    roof["algorithmic_flops_per_launch"] = int(per_launch_f)
     roof["kernel"] = dominant
     roof["avg_launch_ms"] = round(avg_ms, 5)
 

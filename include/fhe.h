@@ -158,7 +158,8 @@ fhe_status fhe_drop_level(fhe_ctx *ctx, const fhe_ct *in, uint32_t limbs, fhe_ct
 /* Left rotation by step slots with the Galois key of that step. */
 fhe_status fhe_rotate(fhe_ctx *ctx, const fhe_evk *gk, const fhe_ct *in, int32_t step, fhe_ct *out);
 /* n independent rotations in one launch sequence: out[t] = rotate(in[t], steps[t])
- * with Galois key gk[t]; gk, in, steps, out are host arrays of n entries. */
+ * with Galois key gk[t]; gk, in, steps, out are host arrays of n entries.
+ * Outputs must not overlap any input (FHE_EINVAL). */
 fhe_status fhe_rotate_batch(fhe_ctx *ctx, const fhe_evk *gk, const fhe_ct *in, const int32_t *steps, uint32_t n,
                             fhe_ct *out);
 /* Hybrid key switch of d (limbs x N, evaluation form): out = (ks0, ks1), polys 2. */

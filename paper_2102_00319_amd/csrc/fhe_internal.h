@@ -183,8 +183,12 @@ struct ProfScope {
 
 // shared drivers (ops.hip)
 size_t ks_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t n);
-fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, const uint64_t *const *evk,
-                  uint64_t *const *out, const uint64_t *const *add, uint8_t *scr);
+// n key switches: inputs d[b] read through the Galois permutation gal[b] (gal null or
+// 0: none), keys evk[b], outputs out[b] (2 polys), addends add[2b + t] (null or a
+// polynomial read through gal[b]) added to output polynomial t.  scr: scratch of
+// ks_scratch_bytes(l, n) bytes, or null to take the context's.
+fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, const uint32_t *gal,
+                  const uint64_t *const *evk, uint64_t *const *out, const uint64_t *const *add, uint8_t *scr);
 size_t rescale_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n);
 fhe_status rescale_run(fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n, const uint64_t *const *in,
                        uint64_t *const *out, uint8_t *scr);

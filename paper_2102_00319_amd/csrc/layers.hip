@@ -181,7 +181,7 @@ static fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, 
             ri[t] = ko[t];
             ro[t] = Y[o0 + t];
         }
-        if ((s = ks_run(c, l, cn, kd.data(), ke.data(), ko.data(), ka.data(), ks_scr))) return s;
+        if ((s = ks_run(c, l, cn, kd.data(), nullptr, ke.data(), ko.data(), ka.data(), ks_scr))) return s;
         if ((s = rescale_run(c, l, 2, cn, ri.data(), ro.data(), rs_scr))) return s;
     }
     c->ops[OP_CT_MULT] += P;
@@ -233,7 +233,8 @@ fhe_status fhe_relin_batch(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *in3, ui
     if ((s = ctx_scratch(c, ks_scratch_bytes(c, l, C), &scr))) return s;
     for (uint32_t t0 = 0; t0 < n; t0 += C) {
         const uint32_t cn = std::min(C, n - t0);
-        if ((s = ks_run(c, l, cn, d.data() + t0, e.data() + t0, o.data() + t0, a.data() + 2 * t0, scr))) return s;
+        if ((s = ks_run(c, l, cn, d.data() + t0, nullptr, e.data() + t0, o.data() + t0, a.data() + 2 * t0, scr)))
+            return s;
     }
     for (uint32_t t = 0; t < n; ++t) out2[t].scale = in3[t].scale;
     c->ops[OP_RELIN] += n;

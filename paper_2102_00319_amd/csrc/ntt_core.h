@@ -1,0 +1,194 @@
+// ntt_core.h -- register/LDS round structure of the negacyclic NTT, shared by
+// the plain transforms (ntt.hip) and the fused key-switching kernels.
+//
+// A group of G = 2^LOGG elements, independent for LOGG consecutive stages, is
+// held by T = G/16 lanes, 16 elements each.  A round runs up to 4 stages in
+// registers (radix 16); rounds exchange through padded LDS.  COL groups are
+// strided columns (element g of group gi at gi + g*N/G, lanes of a wavefront
+// spread over consecutive columns); ROW groups are contiguous blocks.
+#pragma once
+#include "fhe_internal.h"
+
+namespace nttc {
+
+constexpr int LOGR = 4;
+constexpr int R = 1 << LOGR;
+
+// Local index of register k of lane tau in a round covering bits [blo, blo+rho).
+template <int LOGT>
+__device__ __forceinline__ int elem_local(int tau, int k, int blo, int rho)
+{
+    int fr = ((k >> rho) << LOGT) | tau;
+    return ((fr >> blo) << (blo + rho)) | ((k & ((1 << rho) - 1)) << blo) | (fr & ((1 << blo) - 1));
+}
+__device__ __forceinline__ int lds_pad(int g) { return g + (g >> LOGR); }
+
+template <int LOGG, int WG, bool COL>
+struct Geom {
+    static constexpr int G = 1 << LOGG, LOGT = LOGG - LOGR, T = 1 << LOGT, GPW = WG / T;
+    static constexpr int GS = G + G / R + 1;                  // padded group stride in LDS
+    static constexpr int NR = (LOGG + LOGR - 1) / LOGR;
+    static constexpr int RL = LOGG - (NR - 1) * LOGR;         // bits of the last round
+    static constexpr int LDS = GPW * GS;
+    int grp, tau;
+    uint32_t gi, N2;
+    __device__ __forceinline__ Geom(uint32_t logN, uint32_t block)
+    {
+        const int tid = threadIdx.x;
+        grp = COL ? (tid % GPW) : (tid / T);
+        tau = COL ? (tid / GPW) : (tid % T);
+        gi = block * GPW + grp;
+        N2 = (1u << logN) >> LOGG;
+    }
+    __device__ __forceinline__ uint32_t gidx(int g) const
+    {
+        return COL ? gi + (uint32_t)g * N2 : (gi << LOGG) + (uint32_t)g;
+    }
+    // forward: registers hold round-0 elements on entry, last-round elements on exit
+    __device__ __forceinline__ uint32_t fwd_in(int k) const { return gidx(elem_local<LOGT>(tau, k, LOGG - LOGR, LOGR)); }
+    __device__ __forceinline__ uint32_t fwd_out(int k) const { return gidx(elem_local<LOGT>(tau, k, 0, RL)); }
+    // inverse: the opposite round order
+    __device__ __forceinline__ uint32_t inv_in(int k) const
+    {
+        return gidx(elem_local<LOGT>(tau, k, 0, LOGG < LOGR ? LOGG : LOGR));
+    }
+    __device__ __forceinline__ uint32_t inv_out(int k) const
+    {
+        return gidx(elem_local<LOGT>(tau, k, (NR - 1) * LOGR, RL));
+    }
+
+    // Coalesced order: register k of lane tau holds local element k*T + tau, so that
+    // for a fixed k consecutive lanes touch consecutive addresses (ROW groups).
+    __device__ __forceinline__ uint32_t coal(int k) const { return gidx((k << LOGT) | tau); }
+    // Redistribute through LDS: from the forward output order to the coalesced order.
+    __device__ __forceinline__ void fwd_out_to_coal(double (&x)[R], double *lds) const
+    {
+#pragma unroll
+        for (int k = 0; k < R; k++) lds[grp * GS + lds_pad(elem_local<LOGT>(tau, k, 0, RL))] = x[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < R; k++) x[k] = lds[grp * GS + lds_pad((k << LOGT) | tau)];
+        __syncthreads();
+    }
+    // From the coalesced order to the inverse input order.
+    __device__ __forceinline__ void coal_to_inv_in(double (&x)[R], double *lds) const
+    {
+#pragma unroll
+        for (int k = 0; k < R; k++) lds[grp * GS + lds_pad((k << LOGT) | tau)] = x[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < R; k++) x[k] = lds[grp * GS + lds_pad(elem_local<LOGT>(tau, k, 0, LOGG < LOGR ? LOGG : LOGR))];
+        __syncthreads();
+    }
+
+    // Cooley-Tukey stages sigma0 .. sigma0 + LOGG - 1 (table psi^brv), lazy |x| < 2q.
+    __device__ __forceinline__ void fwd(double (&x)[R], double *lds, const double *__restrict__ tw, double q,
+                                        double qinv, uint32_t logN, uint32_t sigma0) const
+    {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const int bhi = LOGG - r * LOGR;
+            const int rho = bhi < LOGR ? bhi : LOGR;
+            const int blo = bhi - rho;
+            if (r > 0) {
+#pragma unroll
+                for (int k = 0; k < R; k++) lds[grp * GS + lds_pad(elem_local<LOGT>(tau, k, bhi, LOGR))] = x[k];
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < R; k++) x[k] = lds[grp * GS + lds_pad(elem_local<LOGT>(tau, k, blo, rho))];
+                __syncthreads();
+            }
+#pragma unroll
+            for (int s = 0; s < rho; s++) {
+                const int bit = rho - 1 - s;
+                const int lb = blo + bit;
+                const uint32_t sigma = sigma0 + (uint32_t)(LOGG - 1 - lb);
+#pragma unroll
+                for (int k = 0; k < R; k++) {
+                    if (k & (1 << bit)) continue;
+                    const int kt = k & ~((2 << bit) - 1);
+                    const uint32_t j = gidx(elem_local<LOGT>(tau, kt, blo, rho));
+                    const double W = tw[(1u << sigma) + (j >> (logN - sigma))];
+                    const double X = redc(x[k], q, qinv);
+                    const double V = mulmod(x[k | (1 << bit)], W, q, qinv);
+                    x[k] = X + V;
+                    x[k | (1 << bit)] = X - V;
+                }
+            }
+        }
+    }
+
+    // Gentleman-Sande stages (table psi^-brv); LASTSTAGE folds N^-1 into global stage 0.
+    template <bool LASTSTAGE>
+    __device__ __forceinline__ void inv(double (&x)[R], double *lds, const double *__restrict__ tw, double q,
+                                        double qinv, double ninv, uint32_t logN, uint32_t sigma0) const
+    {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const int blo = r * LOGR;
+            const int rho = (LOGG - blo) < LOGR ? (LOGG - blo) : LOGR;
+            if (r > 0) {
+#pragma unroll
+                for (int k = 0; k < R; k++) lds[grp * GS + lds_pad(elem_local<LOGT>(tau, k, blo - LOGR, LOGR))] = x[k];
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < R; k++) x[k] = lds[grp * GS + lds_pad(elem_local<LOGT>(tau, k, blo, rho))];
+                __syncthreads();
+            }
+#pragma unroll
+            for (int s = 0; s < rho; s++) {
+                const int bit = s;
+                const int lb = blo + bit;
+                const uint32_t sigma = sigma0 + (uint32_t)(LOGG - 1 - lb);
+                const bool fold_ninv = LASTSTAGE && (lb == LOGG - 1);
+#pragma unroll
+                for (int k = 0; k < R; k++) {
+                    if (k & (1 << bit)) continue;
+                    const int kt = k & ~((2 << bit) - 1);
+                    const uint32_t j = gidx(elem_local<LOGT>(tau, kt, blo, rho));
+                    double W = tw[(1u << sigma) + (j >> (logN - sigma))];
+                    const double U = x[k], V = x[k | (1 << bit)];
+                    if (fold_ninv) {
+                        W = canon(mulmod(W, ninv, q, qinv), q, qinv);
+                        x[k] = mulmod(U + V, ninv, q, qinv);
+                    } else {
+                        x[k] = redc(U + V, q, qinv);
+                    }
+                    x[k | (1 << bit)] = mulmod(U - V, W, q, qinv);
+                }
+            }
+        }
+    }
+};
+
+// NTT-domain Galois permutation: the element that lands at x under X -> X^g
+// (out[x] = in[perm(x)], 2 brv(perm(x)) + 1 = (2 brv(x) + 1) g mod 2N).  g = 0: identity.
+__device__ __forceinline__ uint32_t galois_src(uint32_t x, uint32_t g, uint32_t logN)
+{
+    if (!g) return x;
+    const uint32_t N = 1u << logN;
+    const uint32_t ex = 2u * (__brev(x) >> (32 - logN)) + 1u;
+    const uint32_t ey = (uint32_t)(((uint64_t)ex * g) & (2u * N - 1));
+    return __brev((ey - 1u) >> 1) >> (32 - logN);
+}
+
+// Split of a transform into passes: N <= 2^14 one ROW pass of G = N; 2^15 and
+// 2^16 a COL pass over the first LOGA stages and a ROW pass over the rest.
+struct Split {
+    uint32_t logA, logB;   // logA = 0: single pass of LOGG = logB
+};
+inline Split split_of(uint32_t logN)
+{
+    if (logN <= 14) return {0, logN};
+    if (logN == 15) return {7, 8};
+    return {8, 8};
+}
+// The key-switching path always uses two passes with a row pass of at most 2^8
+// elements, so that its fused row kernels run in 256-thread workgroups.
+inline Split split_ks(uint32_t logN)
+{
+    const uint32_t b = logN - 4 < 8 ? logN - 4 : 8;
+    return {logN - b, b};
+}
+
+}  // namespace nttc

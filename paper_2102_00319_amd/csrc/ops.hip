@@ -140,135 +140,6 @@ __global__ void k_rescale_fin(uint64_t *const *__restrict__ inp, const uint64_t 
     outp[b][((size_t)p * lo + limb) * N + k] = f64_to_u64(fold(r, q));
 }
 
-// ------------------------------------------------------------ key switching
-struct BcJob {
-    uint32_t off, nsrc, ndst;
-    uint32_t src0;       // first source limb (within one batch item of src)
-    uint32_t dst0;       // first destination limb (within one batch item of dst)
-};
-struct BcArgs {
-    uint32_t njobs;
-    uint32_t src_bstride, dst_bstride;   // limbs per batch item
-    BcJob job[16];
-};
-// Fast basis conversion, one thread per coefficient, blockIdx.y = job, blockIdx.z = batch item.
-// y_t = sum_a [x_a (B/b_a)^-1]_{b_a} (B/b_a mod c_t)  mod c_t.
-// ADD_HALF: the sources are first offset by hsrc (per source limb) and the results
-// are offset by -hdst (per destination limb): the rounding shift of ModDown.
-template <bool ADD_HALF>
-__global__ __launch_bounds__(TPB) void k_bconv(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
-                                               const double *__restrict__ tab, BcArgs args, uint32_t logN,
-                                               const double *__restrict__ hsrc, const double *__restrict__ hdst)
-{
-    const uint32_t N = 1u << logN;
-    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
-    if (k >= N) return;
-    const BcJob jb = args.job[blockIdx.y];
-    const uint64_t b = blockIdx.z;
-    const double *T = tab + jb.off;
-    const double *qhinv = T, *sq = T + jb.nsrc, *sqi = T + 2 * jb.nsrc, *dq = T + 3 * jb.nsrc,
-                 *dqi = T + 3 * jb.nsrc + jb.ndst, *qh = T + 3 * jb.nsrc + 2 * jb.ndst;
-    const uint64_t *S = src + (b * args.src_bstride + jb.src0) * N + k;
-    uint64_t *D = dst + (b * args.dst_bstride + jb.dst0) * N + k;
-    double v[16];
-#pragma unroll
-    for (int a = 0; a < 16; ++a) {
-        if (a < (int)jb.nsrc) {
-            double x = u64_to_f64(S[(size_t)a * N]);
-            if (ADD_HALF) x += hsrc[a];
-            v[a] = canon(mulmod(x, qhinv[a], sq[a], sqi[a]), sq[a], sqi[a]);
-        }
-    }
-    for (uint32_t t = 0; t < jb.ndst; ++t) {
-        const double q = dq[t], qi = dqi[t];
-        double acc = 0.0;
-#pragma unroll
-        for (int a = 0; a < 16; ++a) {
-            if (a < (int)jb.nsrc) {
-                acc += mulmod(v[a], qh[(size_t)a * jb.ndst + t], q, qi);
-                if ((a & 3) == 3) acc = redc(acc, q, qi);
-            }
-        }
-        if (ADD_HALF) acc -= hdst[t];
-        D[(size_t)t * N] = f64_to_u64(canon(acc, q, qi));
-    }
-}
-
-struct KsDims {
-    uint32_t l, K, L, alpha, nd, ups;
-    uint32_t upoff[16];   // first limb of digit j's converted limbs within one batch item of `up`
-};
-// u_t[x] = sum_j D_j[x] * evk_j,t[x] over the extended basis Q_l u P (x < l: Q, else P).
-// D_j[x] is the input limb itself inside digit j, else the converted limb.
-__global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ dptr,
-                                                  uint64_t *const *__restrict__ evkptr,
-                                                  const uint64_t *__restrict__ up, uint64_t *__restrict__ uQ,
-                                                  uint64_t *__restrict__ uP, const ModQ *__restrict__ mods,
-                                                  KsDims dm, uint32_t logN)
-{
-    const uint32_t N = 1u << logN;
-    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
-    if (k >= N) return;
-    const uint32_t x = blockIdx.y, b = blockIdx.z;
-    const uint32_t mx = x < dm.l ? x : dm.L + (x - dm.l);
-    const double q = mods[mx].q, qi = mods[mx].qinv;
-    const uint64_t *d = dptr[b];
-    const uint64_t *ev = evkptr[b];
-    const uint64_t *upb = up + (size_t)b * dm.ups * N;
-    const size_t ML = dm.L + dm.K;
-    double a0 = 0.0, a1 = 0.0;
-    for (uint32_t j = 0; j < dm.nd; ++j) {
-        const uint32_t lo = j * dm.alpha, hi = min(lo + dm.alpha, dm.l);
-        double D;
-        if (x >= lo && x < hi) D = u64_to_f64(d[(size_t)x * N + k]);
-        else {
-            const uint32_t pos = x < lo ? x : x - (hi - lo);
-            D = u64_to_f64(upb[(size_t)(dm.upoff[j] + pos) * N + k]);
-        }
-        const double e0 = u64_to_f64(ev[(((size_t)j * 2 + 0) * ML + mx) * N + k]);
-        const double e1 = u64_to_f64(ev[(((size_t)j * 2 + 1) * ML + mx) * N + k]);
-        a0 += mulmod(D, e0, q, qi);
-        a1 += mulmod(D, e1, q, qi);
-        if ((j & 3) == 3) { a0 = redc(a0, q, qi); a1 = redc(a1, q, qi); }
-    }
-    uint64_t *o0, *o1;
-    if (x < dm.l) {
-        o0 = uQ + ((size_t)b * 2 * dm.l + x) * N;
-        o1 = uQ + ((size_t)b * 2 * dm.l + dm.l + x) * N;
-    } else {
-        o0 = uP + ((size_t)b * 2 * dm.K + (x - dm.l)) * N;
-        o1 = uP + ((size_t)b * 2 * dm.K + dm.K + (x - dm.l)) * N;
-    }
-    o0[k] = f64_to_u64(canon(a0, q, qi));
-    o1[k] = f64_to_u64(canon(a1, q, qi));
-}
-// out_t[i] = (u_t[i] - z_t[i]) * P^-1 (+ add_t[i]) mod q_i.  blockIdx.y = limb i, blockIdx.z = 2*b + t.
-// addptr (optional) holds 2 pointers per item: the addend polynomials for t = 0, 1 (each may be null).
-__global__ __launch_bounds__(TPB) void k_ks_final(const uint64_t *__restrict__ uQ, const uint64_t *__restrict__ z,
-                                                  uint64_t *const *__restrict__ outptr,
-                                                  uint64_t *const *__restrict__ addptr, const double *__restrict__ pinv,
-                                                  const ModQ *__restrict__ mods, uint32_t l, uint32_t logN)
-{
-    const uint32_t N = 1u << logN;
-    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
-    if (k >= N) return;
-    const uint32_t i = blockIdx.y, t = blockIdx.z & 1, b = blockIdx.z >> 1;
-    const double q = mods[i].q, qi = mods[i].qinv;
-    const size_t e = ((size_t)b * 2 * l + (size_t)t * l + i) * N + k;
-    double r = mulmod(u64_to_f64(uQ[e]) - u64_to_f64(z[e]), pinv[i], q, qi);
-    r = fold(r, q);
-    const size_t oe = ((size_t)t * l + i) * N + k;
-    const uint64_t *ad = addptr ? addptr[2 * b + t] : nullptr;   // addend polynomial t of item b, or none
-    if (ad) r = fold(r + u64_to_f64(ad[(size_t)i * N + k]), q);
-    outptr[b][oe] = f64_to_u64(r);
-}
-__global__ void k_copy_limbs(uint64_t *const *__restrict__ srcptr, uint64_t *__restrict__ dst, uint64_t per_item)
-{
-    const uint64_t i = (uint64_t)blockIdx.x * TPB + threadIdx.x;
-    if (i >= per_item) return;
-    dst[(uint64_t)blockIdx.y * per_item + i] = srcptr[blockIdx.y][i];
-}
-
 }  // namespace
 
 // ============================================================ host helpers
@@ -280,124 +151,6 @@ static fhe_status chk_ct(const fhe_ctx *c, const fhe_ct *a, const char *what)
     return FHE_OK;
 }
 static bool scales_match(double a, double b) { return std::fabs(a / b - 1.0) <= 9.5367431640625e-07; }   // 2^-20
-
-// Host-side key switch driver: n inputs (each l limbs, NTT domain), keys, outputs
-// (2 polys, l limbs) and optional addends folded into the result: add[2b + t] is
-// the polynomial (l limbs) added to output polynomial t of item b, or null.
-size_t ks_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t n)
-{
-    const uint32_t nd = (l + c->alpha - 1) / c->alpha;
-    size_t ups = 0;
-    for (uint32_t j = 0; j < nd; ++j) ups += c->modup[(size_t)l * c->dnum + j].ndst;
-    return (size_t)n * (5 * (size_t)l + ups + 2 * (size_t)c->K) * c->N * sizeof(uint64_t);
-}
-
-fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, const uint64_t *const *evk,
-                  uint64_t *const *out, const uint64_t *const *add, uint8_t *scr_in)
-{
-    if (!c->K) return fhe_fail(FHE_EPARAM, "key switching needs special primes");
-    const uint32_t N = c->N, K = c->K, L = c->L, alpha = c->alpha;
-    const uint32_t nd = (l + alpha - 1) / alpha;
-    if (nd > 16 || alpha > 16 || K > 16)
-        return fhe_fail(FHE_EPARAM, "key switching supports at most 16 digits, 16 limbs per digit, 16 special primes");
-    KsDims dm;
-    std::memset(&dm, 0, sizeof(dm));
-    dm.l = l; dm.K = K; dm.L = L; dm.alpha = alpha; dm.nd = nd;
-    BcArgs up_args;
-    std::memset(&up_args, 0, sizeof(up_args));
-    uint32_t upmods[FHE_LIMBTAB], ups = 0;
-    for (uint32_t j = 0; j < nd; ++j) {
-        const BconvTab &t = c->modup[(size_t)l * c->dnum + j];
-        dm.upoff[j] = ups;
-        up_args.job[j] = BcJob{t.off, t.nsrc, t.ndst, j * alpha, ups};
-        for (uint32_t a = 0; a < t.ndst; ++a) {
-            if (ups >= FHE_LIMBTAB) return fhe_fail(FHE_EPARAM, "extended basis too large for one launch");
-            upmods[ups++] = t.dst[a];
-        }
-    }
-    dm.ups = ups;
-    up_args.njobs = nd;
-    up_args.src_bstride = l;
-    up_args.dst_bstride = ups;
-    const BconvTab &mdt = c->moddown[l];
-    BcArgs dn_args;
-    std::memset(&dn_args, 0, sizeof(dn_args));
-    dn_args.njobs = 1;
-    dn_args.src_bstride = K;   // batch item = one polynomial (2 per key switch)
-    dn_args.dst_bstride = l;
-    dn_args.job[0] = BcJob{mdt.off, mdt.nsrc, mdt.ndst, 0, 0};
-
-    // scratch: dc [n][l], up [n][ups], uQ [n][2][l], uP [n][2][K], z [n][2][l]
-    const size_t LB = (size_t)N * sizeof(uint64_t);
-    const size_t n_dc = (size_t)n * l, n_up = (size_t)n * ups, n_uq = (size_t)n * 2 * l, n_up2 = (size_t)n * 2 * K;
-    uint8_t *scr = scr_in;
-    fhe_status s = FHE_OK;
-    if (!scr && (s = ctx_scratch(c, (n_dc + n_up + n_uq + n_up2 + n_uq) * LB, &scr))) return s;
-    uint64_t *dc = (uint64_t *)scr, *up = dc + n_dc * N, *uQ = up + n_up * N, *uP = uQ + n_uq * N, *z = uP + n_up2 * N;
-
-    std::vector<uint64_t *> tab;
-    for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)d[b]);
-    for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)evk[b]);
-    for (uint32_t b = 0; b < n; ++b) tab.push_back(out[b]);
-    for (uint32_t b = 0; b < 2 * n; ++b) tab.push_back(add ? (uint64_t *)add[b] : nullptr);
-    uint64_t **dt;
-    if ((s = ctx_ptr_table(c, tab, &dt))) return s;
-    hipStream_t st = c->stream;
-    const uint32_t gx = blocks_for(N, TPB);
-
-    // 1. coefficient-domain copy of the inputs
-    {
-        ProfScope ps(c, "ks_copy");
-        hipLaunchKernelGGL(k_copy_limbs, dim3(blocks_for((uint64_t)l * N, TPB), n), dim3(TPB), 0, st, dt, dc,
-                           (uint64_t)l * N);
-    }
-    {
-        uint32_t m[FHE_LIMBTAB];
-        for (uint32_t i = 0; i < l; ++i) m[i] = i;
-        launch_ntt_inv(c, limbset_list(dc, m, l), n * l);
-    }
-    // 2. ModUp basis conversion, 3. NTT of the converted limbs
-    {
-        ProfScope ps(c, "bconv_up");
-        hipLaunchKernelGGL(k_bconv<false>, dim3(gx, nd, n), dim3(TPB), 0, st, (const uint64_t *)dc, up,
-                           (const double *)c->d_bconv, up_args, c->logN, (const double *)nullptr,
-                           (const double *)nullptr);
-    }
-    launch_ntt_fwd(c, limbset_list(up, upmods, ups), n * ups);
-    // 4. inner product with the key over Q_l u P
-    {
-        ProfScope ps(c, "ks_inner");
-        hipLaunchKernelGGL(k_ks_inner, dim3(gx, l + K, n), dim3(TPB), 0, st, (uint64_t *const *)dt,
-                           (uint64_t *const *)(dt + n), (const uint64_t *)up, uQ, uP, (const ModQ *)c->d_mod, dm,
-                           c->logN);
-    }
-    // 5. ModDown: P limbs to coefficients, rounded conversion to Q_l, NTT, finish
-    {
-        uint32_t m[FHE_LIMBTAB];
-        for (uint32_t k = 0; k < K; ++k) m[k] = L + k;
-        launch_ntt_inv(c, limbset_list(uP, m, K), n * 2 * K);
-    }
-    {
-        ProfScope ps(c, "bconv_down");
-        hipLaunchKernelGGL(k_bconv<true>, dim3(gx, 1, n * 2), dim3(TPB), 0, st, (const uint64_t *)uP, z,
-                           (const double *)c->d_bconv, dn_args, c->logN, (const double *)(c->d_phalf + L),
-                           (const double *)c->d_phalf);
-    }
-    {
-        uint32_t m[FHE_LIMBTAB];
-        for (uint32_t i = 0; i < l; ++i) m[i] = i;
-        launch_ntt_fwd(c, limbset_list(z, m, l), n * 2 * l);
-    }
-    {
-        ProfScope ps(c, "ks_final");
-        hipLaunchKernelGGL(k_ks_final, dim3(gx, l, 2 * n), dim3(TPB), 0, st, (const uint64_t *)uQ,
-                           (const uint64_t *)z, (uint64_t *const *)(dt + 2 * n),
-                           add ? (uint64_t *const *)(dt + 3 * n) : nullptr, (const double *)c->d_pinv,
-                           (const ModQ *)c->d_mod, l, c->logN);
-    }
-    HIPCHK(hipGetLastError());
-    return FHE_OK;
-}
 
 size_t rescale_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n)
 {
@@ -609,7 +362,7 @@ fhe_status fhe_keyswitch(fhe_ctx *c, const fhe_evk *evk, const uint64_t *d, uint
     const uint64_t *dd[1] = {d};
     const uint64_t *ek[1] = {evk->d};
     uint64_t *oo[1] = {out->d};
-    return ks_run(c, limbs, 1, dd, ek, oo, nullptr, nullptr);
+    return ks_run(c, limbs, 1, dd, nullptr, ek, oo, nullptr, nullptr);
 }
 fhe_status fhe_keyswitch_batch(fhe_ctx *c, const fhe_evk *evk, const uint64_t *const *d, uint32_t limbs, uint32_t n,
                                fhe_ct *out)
@@ -624,7 +377,7 @@ fhe_status fhe_keyswitch_batch(fhe_ctx *c, const fhe_evk *evk, const uint64_t *c
         if (out[b].limbs != limbs || out[b].polys != 2) return fhe_fail(FHE_EINVAL, "fhe_keyswitch_batch: bad output");
         dd[b] = d[b]; ek[b] = evk[b].d; oo[b] = out[b].d;
     }
-    return ks_run(c, limbs, n, dd.data(), ek.data(), oo.data(), nullptr, nullptr);
+    return ks_run(c, limbs, n, dd.data(), nullptr, ek.data(), oo.data(), nullptr, nullptr);
 }
 fhe_status fhe_relin(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *in3, fhe_ct *out2)
 {
@@ -639,7 +392,7 @@ fhe_status fhe_relin(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *in3, fhe_ct *
     const uint64_t *ek[1] = {rlk->d};
     uint64_t *oo[1] = {out2->d};
     const uint64_t *ad[2] = {in3->d, in3->d + per};   // (d0, d1) + (ks0, ks1)
-    fhe_status r = ks_run(c, in3->limbs, 1, dd, ek, oo, ad, nullptr);
+    fhe_status r = ks_run(c, in3->limbs, 1, dd, nullptr, ek, oo, ad, nullptr);
     out2->scale = in3->scale;
     c->ops[OP_RELIN] += 1;
     return r;
@@ -654,22 +407,22 @@ fhe_status fhe_rotate(fhe_ctx *c, const fhe_evk *gk, const fhe_ct *in, int32_t s
     if (gk->galois != g) return fhe_fail(FHE_ENOKEY, "fhe_rotate: Galois key is for another step");
     const uint32_t l = in->limbs;
     const size_t per = (size_t)l * c->N;
-    // sigma_g of both polys into scratch tail; key switch of sigma_g(c1), add sigma_g(c0)
+    // sigma_g of both polynomials into scratch (one pass; the permutation gathers,
+    // the writes are coalesced), then the key switch of sigma_g(c1) adds sigma_g(c0).
+    const size_t ksb = ks_scratch_bytes(c, l, 1);
     uint8_t *scr;
-    // the key-switch scratch is taken first; the permuted input lives past it
-    const uint32_t nd = (l + c->alpha - 1) / c->alpha;
-    size_t ups = 0;
-    for (uint32_t j = 0; j < nd; ++j) ups += c->modup[(size_t)l * c->dnum + j].ndst;
-    const size_t ks_limbs = l + ups + 4 * (size_t)l + 2 * c->K;
-    if ((s = ctx_scratch(c, (ks_limbs + 2 * (size_t)l) * c->N * sizeof(uint64_t), &scr))) return s;
-    uint64_t *perm = (uint64_t *)scr + ks_limbs * c->N;
-    hipLaunchKernelGGL(k_automorph, dim3(blocks_for(2 * per, TPB)), dim3(TPB), 0, c->stream, (const uint64_t *)in->d,
-                       perm, c->logN, (uint64_t)2 * l, (uint32_t)g);
+    if ((s = ctx_scratch(c, ksb + 2 * per * sizeof(uint64_t), &scr))) return s;
+    uint64_t *perm = (uint64_t *)(scr + ksb);
+    {
+        ProfScope ps(c, "automorph");
+        hipLaunchKernelGGL(k_automorph, dim3(blocks_for(2 * per, TPB)), dim3(TPB), 0, c->stream,
+                           (const uint64_t *)in->d, perm, c->logN, (uint64_t)2 * l, (uint32_t)g);
+    }
     const uint64_t *dd[1] = {perm + per};
     const uint64_t *ek[1] = {gk->d};
     uint64_t *oo[1] = {out->d};
     const uint64_t *ad[2] = {perm, nullptr};   // (sigma_g(c0) + ks0, ks1)
-    fhe_status r = ks_run(c, l, 1, dd, ek, oo, ad, scr);
+    fhe_status r = ks_run(c, l, 1, dd, nullptr, ek, oo, ad, scr);
     out->scale = in->scale;
     c->ops[OP_ROTATE] += 1;
     return r;
@@ -690,13 +443,14 @@ fhe_status fhe_rotate_batch(fhe_ctx *c, const fhe_evk *gk, const fhe_ct *in, con
             return fhe_fail(FHE_ENOKEY, "fhe_rotate_batch: Galois key is for another step");
     }
     const size_t per = (size_t)l * c->N;
-    const uint32_t nd = (l + c->alpha - 1) / c->alpha;
-    size_t ups = 0;
-    for (uint32_t j = 0; j < nd; ++j) ups += c->modup[(size_t)l * c->dnum + j].ndst;
-    const size_t ks_limbs = (size_t)n * (l + ups + 4 * (size_t)l + 2 * c->K);
+    for (uint32_t b = 0; b < n; ++b)
+        for (uint32_t b2 = 0; b2 < n; ++b2)
+            if (out[b].d < in[b2].d + 2 * per && in[b2].d < out[b].d + 2 * per)
+                return fhe_fail(FHE_EINVAL, "fhe_rotate_batch: outputs must not overlap inputs");
+    const size_t ksb = ks_scratch_bytes(c, l, n);
     uint8_t *scr;
-    if ((s = ctx_scratch(c, (ks_limbs + 2 * (size_t)n * l) * c->N * sizeof(uint64_t), &scr))) return s;
-    uint64_t *perm = (uint64_t *)scr + ks_limbs * c->N;
+    if ((s = ctx_scratch(c, ksb + 2 * per * n * sizeof(uint64_t), &scr))) return s;
+    uint64_t *perm = (uint64_t *)(scr + ksb);
     std::vector<const uint64_t *> dd(n), ek(n), ad(2 * (size_t)n, nullptr);
     std::vector<uint64_t *> oo(n);
     {
@@ -711,7 +465,7 @@ fhe_status fhe_rotate_batch(fhe_ctx *c, const fhe_evk *gk, const fhe_ct *in, con
             oo[b] = out[b].d;
         }
     }
-    fhe_status r = ks_run(c, l, n, dd.data(), ek.data(), oo.data(), ad.data(), scr);
+    fhe_status r = ks_run(c, l, n, dd.data(), nullptr, ek.data(), oo.data(), ad.data(), scr);
     for (uint32_t b = 0; b < n; ++b) out[b].scale = in[b].scale;
     c->ops[OP_ROTATE] += n;
     return r;
