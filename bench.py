@@ -28,6 +28,12 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector, TFLOP/s (FMA = 2 flops)
 FLOPS_PER_BUTTERFLY = 14
 
 
+# kernel categories of the library's event timing
+PROFILE_CATEGORIES = ["ntt_fwd", "ntt_fwd_col", "ntt_fwd_row", "ntt_inv", "ntt_inv_col", "ntt_inv_row", "bconv_up",
+                      "bconv_down", "ks_intt_first", "ks_inner", "ks_moddown_final", "automorph", "tensor",
+                      "elementwise", "rescale"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -36,8 +42,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=8, help="rotations (distinct keys) per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--param-set", default="c4_n16")
-    ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "cnn2"],
-                    help="keyswitch: the headline metric; cnn2: slot-packed encrypted CNN images/s")
+    ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "cnn2", "cnn4"],
+                    help="keyswitch: the headline metric; cnn2: slot-packed encrypted CNN images/s; "
+                         "cnn4: within-image packed deep CNN images/s")
     ap.add_argument("--fc1", type=int, default=100, help="cnn2: FC1 width (100 = the full network)")
     ap.add_argument("--unbatched", action="store_true", help="cnn2: also time the one-ciphertext-per-call form")
     return ap.parse_args()
@@ -90,6 +97,101 @@ def kernel_model(cat, N, l, K, alpha, B, dnum, L):
     return 0, 0
 
 
+# ---------------------------------------------------------------- FP64 checks
+# Plain forward passes used only to check the decrypted scores of a run.
+def _conv_fp64(x, w, stride, pad):
+    """x [B][Cin][H][W], w [Cout][Cin][k][k], zero padding pad on top/left (and enough
+    on the other sides), output size from the input (floor)."""
+    import numpy as np
+    B, Cin, H, W = x.shape
+    Cout, _, k, _ = w.shape
+    xp = np.zeros((B, Cin, H + 2 * pad + k, W + 2 * pad + k))
+    xp[:, :, pad:pad + H, pad:pad + W] = x
+    Ho = (H + 2 * pad - k) // stride + 1 if stride > 1 else H
+    Wo = (W + 2 * pad - k) // stride + 1 if stride > 1 else W
+    out = np.zeros((B, Cout, Ho, Wo))
+    for p in range(k):
+        for q in range(k):
+            patch = xp[:, :, p:p + stride * Ho:stride, q:q + stride * Wo:stride]
+            out += np.einsum("bchw,oc->bohw", patch, w[:, :, p, q])
+    return out
+
+
+def _slot_cnn_fp64(imgs, cw, f1, f2):
+    h = _conv_fp64(imgs[:, None], cw, 2, 1) ** 2
+    h = (h.reshape(h.shape[0], -1) @ f1.T) ** 2
+    return h @ f2.T
+
+
+def _packed_cnn_fp64(imgs, w1, w2, wfc, coef):
+    def act(x):
+        return coef[0] + coef[1] * x + coef[2] * x * x + coef[3] * x * x * x
+
+    def pool(x):
+        B, C, H, W = x.shape
+        return x.reshape(B, C, H // 2, 2, W // 2, 2).mean(axis=(3, 5))
+    h = pool(act(_conv_fp64(imgs[:, None], w1, 1, 1)))
+    h = pool(act(_conv_fp64(h, w2, 1, 1)))
+    return h.reshape(h.shape[0], -1) @ wfc.T
+
+
+def cnn4(args):
+    """Within-image packed deep CNN (32 images of 28 x 28 per ciphertext, N = 2^16,
+    24 limbs): conv 3x3 x 8 -> cubic -> pool -> conv 3x3 x 16 -> cubic -> pool -> FC 784->10,
+    images and weights encrypted; one step = one forward pass over one ciphertext batch."""
+    import numpy as np
+    import torch
+
+    import workloads
+    import paper_2102_00319_amd as P
+    from paper_2102_00319_amd import networks
+
+    torch.cuda.set_device(0)
+    g = P.Context.from_set("c4_n16")
+    net = networks.PackedCNN()
+    B = net.images_per_ct(g)
+    imgs = workloads.images(workloads.SEED_DATA, B, 28, 28)
+    w1 = workloads.weights(workloads.SEED_DATA + 1, (8, 1, 3, 3))
+    w2 = workloads.weights(workloads.SEED_DATA + 2, (16, 8, 3, 3))
+    wfc = workloads.weights(workloads.SEED_DATA + 3, (10, 784))
+    t_setup = time.perf_counter()
+    s = g.keygen_secret(workloads.SEED_SECRET)
+    pk = g.keygen_pk(s, workloads.SEED_PK)
+    rlk, gks = net.keygen(g, s, workloads.SEED_EVK)
+    X = net.encrypt_images(g, pk, imgs, workloads.SEED_ENC)
+    Wt = net.encrypt_weights(g, pk, w1, w2, wfc, (workloads.SEED_ENC + 100000, workloads.SEED_ENC + 200000,
+                                                  workloads.SEED_ENC + 300000))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    g.op_counts()
+    out = net.forward(g, rlk, gks, X, Wt)
+    ops = g.op_counts()
+    err = float(np.abs(net.decrypt_scores(g, s, out, B) - _packed_cnn_fp64(imgs, w1, w2, wfc, net.coef)).max())
+    for _ in range(args.warmup):
+        net.forward(g, rlk, gks, X, Wt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = net.forward(g, rlk, gks, X, Wt)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    # per-category kernel time of one forward pass
+    g.profile_enable("*")
+    net.forward(g, rlk, gks, X, Wt)
+    torch.cuda.synchronize()
+    prof = {c: g.profile_read(c)[0] for c in PROFILE_CATEGORIES}
+    g.profile_enable(None)
+    breakdown = {k: round(v, 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1]) if v > 0}
+    rec = {"metric": "encrypted-CNN images/s (within-image packing, N=2^16)", "value": round(B / dt, 1),
+           "unit": "images/s", "ms_per_batch": round(dt * 1e3, 3), "images_per_batch": B, "steps": args.steps,
+           "max_abs_logit_error_vs_fp64": err, "setup_s": round(t_setup, 1),
+           "ops_per_batch": {k: ops[k] for k in ("ct_mult", "relin", "rotate", "rescale")},
+           "kernel_ms_per_batch": breakdown,
+           "config": {"workload": "conv3x3x8 -> cubic -> avgpool -> conv3x3x16 -> cubic -> avgpool -> FC784x10, "
+                                  "32 images of 28x28 per ciphertext, N=2^16, 24 limbs, dnum 3"}}
+    print(json.dumps(rec))
+
+
 def cnn2(args):
     """Slot-packed encrypted CNN (8192 images per ciphertext): conv 5x5 stride 2 x 5
     channels -> x^2 -> FC 845->fc1 -> x^2 -> FC fc1->10; images and weights encrypted."""
@@ -97,7 +199,6 @@ def cnn2(args):
     import torch
 
     import workloads
-    from oracle import cnn
     import paper_2102_00319_amd as P
 
     torch.cuda.set_device(0)
@@ -126,7 +227,7 @@ def cnn2(args):
         return g.fc_slot(rlk, g.square_act(rlk, g.fc_slot(rlk, g.square_act(rlk, Y), W1, n1)), W2, n2)
 
     out = forward()
-    ref = cnn.slot_cnn_fp64(imgs, cw, f1, f2, 2, 1, 1, Ho, Wo)
+    ref = _slot_cnn_fp64(imgs, cw, f1, f2)
     err = max(float(np.abs(g.decode(g.decrypt(s, out[r]), n=B)[0] - ref[:, r]).max()) for r in range(n2))
     for _ in range(args.warmup):
         forward()
@@ -178,6 +279,8 @@ def main():
         sys.exit(2)
     if args.workload == "cnn2":
         return cnn2(args)
+    if args.workload == "cnn4":
+        return cnn4(args)
     import numpy as np
     import torch
 

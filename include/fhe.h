@@ -148,6 +148,9 @@ fhe_status fhe_add_pt(fhe_ctx *ctx, const fhe_ct *a, const fhe_pt *p, fhe_ct *ou
 fhe_status fhe_mul_pt(fhe_ctx *ctx, const fhe_ct *a, const fhe_pt *p, fhe_ct *out);
 /* Multiply by the integer round(value * const_scale); out->scale = a->scale * const_scale. */
 fhe_status fhe_mul_const(fhe_ctx *ctx, const fhe_ct *a, double value, double const_scale, fhe_ct *out);
+/* Add the constant polynomial round(value * a->scale) (every slot + value);
+ * out->scale = a->scale.  |round(value * scale)| must stay below 2^62. */
+fhe_status fhe_add_const(fhe_ctx *ctx, const fhe_ct *a, double value, fhe_ct *out);
 /* Tensor product (a0 b0, a0 b1 + a1 b0, a1 b1); out has 3 polys. */
 fhe_status fhe_mul(fhe_ctx *ctx, const fhe_ct *a, const fhe_ct *b, fhe_ct *out3);
 /* acc3 = sum_t a[t] (x) b[t]; a, b: host arrays of n descriptors. */
@@ -193,6 +196,43 @@ fhe_status fhe_conv2d_slot(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *X, ui
 fhe_status fhe_fc_slot(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *x, uint32_t n_in, const fhe_ct *Wt,
                        uint32_t n_out, fhe_ct *y);
 fhe_status fhe_square_act(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *x, uint32_t n, fhe_ct *y);
+/* --------------------------------------------- within-image packed CNN layers
+ * One ciphertext per channel; each image of the batch sits in its own frame of
+ * frame_w-wide rows of slots, zero beyond the image (pixel (y, x) of image b at
+ * slot b*frame_slots + y*frame_w + x).  Rotations (Sec. 3, Fig. 2) move
+ * neighbouring pixels into place in every frame at once; keys is a host array of
+ * Galois keys searched by Galois element (FHE_ENOKEY if a needed one is absent).
+ * The caller keeps the layout valid: the zero guard must cover dilation * (k/2)
+ * rows and columns, and positions outside the valid grid hold values that later
+ * masks clear.
+ *
+ * fhe_conv2d_packed: Y[co] = Rescale(Relin( sum_ci sum_(p,q) rot(X[ci], s_pq) (x) W[co][ci][p][q] )),
+ *   s_pq = dilation * ((p - k/2) * frame_w + (q - k/2)), taps row-major, k odd;
+ *   W[(co*Cin + ci)*k*k + p*k + q] are slot-replicated weights (Eq. (enc_conv)
+ *   with the window sum done by rotations); X, W at level l, Y at l - 1.
+ * fhe_poly_act: polynomial activation at depth 2 (Sec. 3 "Activation"):
+ *   deg 3: y = (c3 u + c2) u^2 + (c1 u + c0); deg 2: y = (c2 u + c1) u + c0,
+ *   coef = {c0, c1, c2, c3}; constants c multiply as the integer round(c * s):
+ *   c3 (deg 3) or c2 (deg 2) at s = q_(l-1), the linear term at the scale that
+ *   lands on the product's scale.  Inputs at l >= 3, one scale; outputs at l - 2.
+ * fhe_avgpool2x2 (Sec. 3 "Pooling", mean of a 2x2 window): t = x + rot(x, d);
+ *   t = t + rot(t, frame_w d); y = Rescale(t * mask).  mask is a plaintext at
+ *   level l (0.25 on the positions that survive, zero elsewhere; its scale sets
+ *   the output scale); outputs at l - 1, valid positions now at dilation 2d.
+ * fhe_fc_packed (Sec. 2.3, Z = WX without bias): z[o] = Rescale(Relin(sum_i x[i] (x) W[o*n_in + i]))
+ *   then z += rot(z, j) for j = 1, 2, 4, ..., frame_slots/2, so that slot 0 of
+ *   every frame holds the class score; W[o*n_in + i] holds the weights of input
+ *   channel i at its valid positions, zero elsewhere.  Outputs at l - 1. */
+fhe_status fhe_conv2d_packed(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *X,
+                             uint32_t Cin, const fhe_ct *Wt, uint32_t Cout, uint32_t k, uint32_t dilation,
+                             uint32_t frame_w, fhe_ct *Y);
+fhe_status fhe_poly_act(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *x, uint32_t n, const double *coef,
+                        uint32_t deg, fhe_ct *y);
+fhe_status fhe_avgpool2x2(fhe_ctx *ctx, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *x, uint32_t n,
+                          uint32_t dilation, uint32_t frame_w, const fhe_pt *mask, fhe_ct *y);
+fhe_status fhe_fc_packed(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *x,
+                         uint32_t n_in, const fhe_ct *Wt, uint32_t n_out, uint32_t frame_slots, fhe_ct *y);
+
 /* Model owner: encrypt n weights, each replicated in every slot (a constant
  * polynomial round(value * scale)), under the user's public key; per-weight
  * seeds (host array); outputs at out[0].limbs limbs. */

@@ -47,6 +47,7 @@ def slot_cnn_fp64(images, conv_w, fc1_w, fc2_w, stride, pad_t, pad_l, Ho, Wo):
 class Counter:
     def __init__(self):
         self.ct_mult = self.ct_add = self.relin = self.rescale = 0
+        self.rotate = self.pt_mult = self.pt_add = 0
 
 
 def _mac_relin_rescale(o, rlk, pairs, cnt):
@@ -102,3 +103,183 @@ def conv_op_count(H, W, kh, kw, stride, pad_t, pad_l, Ho, Wo, Cin, Cout):
                     y, x = i * stride + p - pad_t, j * stride + q - pad_l
                     n += 0 <= y < H and 0 <= x < W
     return n * Cin * Cout
+
+
+# ------------------------------------------- within-image packing (deep CNN)
+# A ciphertext holds one channel of a batch of images, each image in its own
+# frame of frame_h x frame_w slots (row-major, zero guard to the right and
+# below); image b, pixel (y, x) sits in slot b*frame_h*frame_w + y*frame_w + x.
+# The slot rotation of Sec. 3 (Fig. 2 "rotation") then moves whole neighbour
+# pixels: a left rotation by dy*frame_w + dx brings pixel (y+dy, x+dx) to (y, x).
+def frame_pack(img, frame_h, frame_w):
+    """img [B][H][W] -> slot vector of B * frame_h * frame_w values."""
+    B, H, W = img.shape
+    v = np.zeros((B, frame_h, frame_w))
+    v[:, :H, :W] = img
+    return v.ravel()
+
+
+def frame_positions(H, W, frame_h, frame_w, n_frames, dil):
+    """Slot indices of the valid positions (y, x) = (dil*i, dil*j), y < H, x < W, of every frame."""
+    ys, xs = np.arange(0, H, dil), np.arange(0, W, dil)
+    one = (ys[:, None] * frame_w + xs[None, :]).ravel()
+    return (np.arange(n_frames)[:, None] * (frame_h * frame_w) + one[None, :]).ravel()
+
+
+def conv2d_same_fp64(x, w):
+    """Stride 1, zero padding k // 2 on every side."""
+    k = w.shape[2]
+    return conv2d_fp64(x, w, 1, k // 2, k // 2, x.shape[2], x.shape[3])
+
+
+def poly_fp64(x, coef):
+    c = list(coef) + [0.0] * (4 - len(coef))
+    return c[0] + c[1] * x + c[2] * x * x + c[3] * x * x * x
+
+
+def avgpool2_fp64(x):
+    B, C, H, W = x.shape
+    return x.reshape(B, C, H // 2, 2, W // 2, 2).mean(axis=(3, 5))
+
+
+def packed_cnn_fp64(images, w1, w2, wfc, coef):
+    """conv 3x3 same -> poly -> avg pool 2x2 -> conv 3x3 same -> poly -> avg pool
+    -> flatten (c, y, x) -> fc, in FP64."""
+    x = images[:, None] if images.ndim == 3 else images
+    h = avgpool2_fp64(poly_fp64(conv2d_same_fp64(x, w1), coef))
+    h = avgpool2_fp64(poly_fp64(conv2d_same_fp64(h, w2), coef))
+    return h.reshape(h.shape[0], -1) @ wfc.T
+
+
+def conv_steps(k, dil, frame_w):
+    """Rotation step of each tap (p, q) of a k x k 'same' kernel, row-major."""
+    return [dil * ((p - k // 2) * frame_w + (q - k // 2)) for p in range(k) for q in range(k)]
+
+
+def add_const(o, ct, value):
+    """ct + value: the constant polynomial round(value * ct.scale) added to c0."""
+    m = np.zeros(o.N, dtype=np.int64)
+    m[0] = int(np.rint(value * ct.scale))
+    return o.add_pt(ct, o.small_to_rns(m, ct.level))
+
+
+def enc_conv2d_packed(o, rlk, gks, X, Cin, Wt, Cout, k, dil, frame_w, cnt):
+    """Y[co] = Rescale(Relin( sum_ci sum_(p,q) rot(X[ci], step(p,q)) (x) W[co][ci][p][q] )),
+    the weights replicated scalars; gks maps a step to its Galois key."""
+    steps = conv_steps(k, dil, frame_w)
+    R = []
+    for ci in range(Cin):
+        row = []
+        for r in steps:
+            if r == 0:
+                row.append(X[ci])
+            else:
+                row.append(o.rotate(X[ci], r, gks[r]))
+                cnt.rotate += 1
+        R.append(row)
+    Y = []
+    for co in range(Cout):
+        pairs = [(R[ci][t], Wt[(co * Cin + ci) * k * k + t]) for ci in range(Cin) for t in range(k * k)]
+        Y.append(_mac_relin_rescale(o, rlk, pairs, cnt))
+    return Y
+
+
+def enc_poly_act(o, rlk, xs, coef, deg, cnt):
+    """Polynomial activation at depth 2.
+    deg 3: (c3 u + c2) u^2 + (c1 u + c0); deg 2: (c2 u + c1) u + c0.
+    A constant multiplier c at plaintext scale s is the integer round(c s); the
+    branch c3 u (c2 u) uses s = q_(l-1) so that its rescale keeps u's scale, and
+    the linear branch's scale is chosen so that it lands on the product's scale."""
+    out = []
+    for x in xs:
+        l = x.level
+        ql, ql2 = o.q[l - 1], o.q[l - 2]
+        if deg == 3:
+            u2 = _mac_relin_rescale(o, rlk, [(x, x)], cnt)
+            a = o.rescale(o.mul_const(x, int(np.rint(coef[3] * float(ql))), float(ql)))
+            a = add_const(o, a, coef[2])
+            p = _mac_relin_rescale(o, rlk, [(a, u2)], cnt)
+            s1 = p.scale * float(ql2) / x.scale
+            b = o.rescale(o.mul_const(o.drop_level(x, l - 1), int(np.rint(coef[1] * s1)), s1))
+            b = add_const(o, b, coef[0])
+            cnt.pt_mult += 2
+            cnt.pt_add += 2
+            cnt.rescale += 2
+            cnt.ct_add += 1
+            out.append(o.add(p, b))
+        elif deg == 2:
+            a = o.rescale(o.mul_const(x, int(np.rint(coef[2] * float(ql))), float(ql)))
+            a = add_const(o, a, coef[1])
+            p = _mac_relin_rescale(o, rlk, [(a, o.drop_level(x, l - 1))], cnt)
+            cnt.pt_mult += 1
+            cnt.pt_add += 2
+            cnt.rescale += 1
+            out.append(add_const(o, p, coef[0]))
+        else:
+            raise ValueError("deg must be 2 or 3")
+    return out
+
+
+def pool_mask(o, H, W, frame_h, frame_w, dil, scale, limbs):
+    """Plaintext 0.25 at the positions that survive a 2x2 pool of inputs at
+    dilation dil (y, x multiples of 2 dil inside the image), 0 elsewhere."""
+    n = o.N // 2
+    v = np.zeros(n)
+    v[frame_positions(H, W, frame_h, frame_w, n // (frame_h * frame_w), 2 * dil)] = 0.25
+    return o.encode_rns(v, scale, limbs)
+
+
+def enc_avgpool2x2(o, gks, xs, dil, frame_w, mask, mask_scale, cnt):
+    """s = x + rot(x, dil); s = s + rot(s, frame_w dil); y = Rescale(s * mask)
+    (the 2x2 mean lands on the window's top-left position; the mask keeps those)."""
+    out = []
+    for x in xs:
+        t = o.add(x, o.rotate(x, dil, gks[dil]))
+        t = o.add(t, o.rotate(t, frame_w * dil, gks[frame_w * dil]))
+        out.append(o.rescale(o.mul_pt(t, mask, mask_scale)))
+        cnt.rotate += 2
+        cnt.ct_add += 2
+        cnt.pt_mult += 1
+        cnt.rescale += 1
+    return out
+
+
+def enc_fc_packed(o, rlk, gks, xs, Wt, n_out, frame_slots, cnt):
+    """z[r] = Rescale(Relin(sum_c x[c] (x) W[r][c])), then z += rot(z, i) for
+    i = 1, 2, 4, ..., frame_slots/2: slot 0 of every frame holds the class score."""
+    n_in = len(xs)
+    out = []
+    for r in range(n_out):
+        z = _mac_relin_rescale(o, rlk, [(xs[c], Wt[r * n_in + c]) for c in range(n_in)], cnt)
+        i = 1
+        while i < frame_slots:
+            z = o.add(z, o.rotate(z, i, gks[i]))
+            cnt.rotate += 1
+            cnt.ct_add += 1
+            i *= 2
+        out.append(z)
+    return out
+
+
+def fc_weight_slots(wrow, Hp, Wp, frame_h, frame_w, n_frames, dil):
+    """Slot vector of one FC weight ciphertext: weight (i, j) of a channel at
+    frame position (dil i, dil j) of every frame, zero elsewhere."""
+    v = np.zeros(n_frames * frame_h * frame_w)
+    pos = frame_positions(Hp * dil, Wp * dil, frame_h, frame_w, n_frames, dil)
+    v[pos] = np.tile(np.asarray(wrow, dtype=np.float64).ravel(), n_frames)
+    return v
+
+
+def packed_rotation_steps(k, frame_w, frame_slots, n_pools=2):
+    """Every rotation step the packed network uses (conv taps at dilation 1, 2, pools, fc sums)."""
+    st = set()
+    dil = 1
+    for _ in range(n_pools):
+        st.update(r for r in conv_steps(k, dil, frame_w) if r)
+        st.update([dil, frame_w * dil])
+        dil *= 2
+    i = 1
+    while i < frame_slots:
+        st.add(i)
+        i *= 2
+    return sorted(st)

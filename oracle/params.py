@@ -105,6 +105,9 @@ def build_all():
                  "key switch / deep CNN: q0 ~2^50, 23 primes nearest 2^49, 8 special, dnum 3"),
         make_set("t_n12", 12, 40, 5, 30, 2, 41, 30, 3,
                  "small CNN tests: q0 ~2^40, 5 primes nearest 2^30, 2 special ~2^41, dnum 3"),
+        make_set("t4_n12", 12, 50, 10, 49, 4, 50, 49, 3,
+                 "small within-image CNN tests: q0 ~2^50, 10 primes nearest 2^49, 4 special, dnum 3, "
+                 "scale 2^49 (the deep-CNN chain shortened to 11 limbs)"),
         make_set("p_n15", 15, 50, 15, 40, 4, 50, 40, 4,
                  "the paper's ring (m = 2^16): q0 ~2^50, 15 primes nearest 2^40, 4 special"),
     ]

@@ -175,7 +175,7 @@ static void ctx_free_all(fhe_ctx *c)
 {
     if (c->prof) (void)fhe_profile_enable(c, nullptr);
     void *ptrs[] = {c->d_mod, c->d_tw, c->d_itw, c->d_ninv, c->d_cdt, c->d_cos, c->d_sin, c->d_g5,
-                    c->d_bconv, c->d_pinv, c->d_phalf, c->d_pmod, c->d_qlinv, c->scratch, c->d_ptrs, c->d_big};
+                    c->d_bconv, c->d_pinv, c->d_phalf, c->d_pmod, c->d_qlinv, c->scratch, c->wksp, c->d_ptrs, c->d_big};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_ptrs) {
@@ -374,6 +374,27 @@ fhe_status ctx_scratch(fhe_ctx *c, size_t bytes, uint8_t **out)
         c->used += bytes;
     }
     *out = c->scratch;
+    return FHE_OK;
+}
+
+// Same growth rule for the layer workspace (a separate buffer, so that a layer's
+// intermediates survive the scratch use of the operations it calls).
+fhe_status ctx_workspace(fhe_ctx *c, size_t bytes, uint8_t **out)
+{
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes > c->wksp_bytes) {
+        size_t grow = bytes - c->wksp_bytes;
+        if (c->used + grow > c->budget) return fhe_fail(FHE_ENOMEM, "layer workspace exceeds the HBM budget");
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->wksp) HIPCHK(hipFree(c->wksp));
+        c->wksp = nullptr;
+        c->used -= c->wksp_bytes;
+        c->wksp_bytes = 0;
+        HIPCHK(hipMalloc((void **)&c->wksp, bytes));
+        c->wksp_bytes = bytes;
+        c->used += bytes;
+    }
+    *out = c->wksp;
     return FHE_OK;
 }
 

@@ -142,6 +142,10 @@ struct fhe_ctx {
     // scratch (device), grown on demand within the budget
     uint8_t *scratch;
     size_t scratch_bytes;
+    // layer workspace (device): intermediates a layer keeps across the batched
+    // operations it calls, which themselves use the scratch above
+    uint8_t *wksp;
+    size_t wksp_bytes;
     // pointer tables for batched launches: a ring of slots, each a pinned host
     // staging area and a device copy, reused once the slot's copy has completed
     uint64_t **d_ptrs;       // [PTR_SLOTS][PTR_SLOT_CAP]
@@ -165,6 +169,18 @@ fhe_status fhe_hip_check(hipError_t e, const char *what);
 
 // scratch / pointer tables
 fhe_status ctx_scratch(fhe_ctx *c, size_t bytes, uint8_t **out);
+fhe_status ctx_workspace(fhe_ctx *c, size_t bytes, uint8_t **out);
+
+// batched building blocks shared by the layer entry points
+enum { EW_ADD = 0, EW_MULC, EW_ADDC, EW_MULPT, EW_COPY };
+fhe_status ew_batch(fhe_ctx *c, int op, uint32_t l, uint32_t la, uint32_t polys, uint32_t n,
+                    const uint64_t *const *a, const uint64_t *const *b, uint64_t *const *out, const Consts64 &cst);
+fhe_status const_residues(const fhe_ctx *c, double v, uint32_t limbs, Consts64 *out);
+fhe_status rotate_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *in, const fhe_evk *const *keys,
+                      uint64_t *const *out);
+fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const std::vector<uint64_t *> &A,
+                             const std::vector<uint64_t *> &B, const std::vector<uint32_t> &off,
+                             const std::vector<uint64_t *> &Y);
 fhe_status ctx_ptr_table(fhe_ctx *c, const std::vector<uint64_t *> &ptrs, uint64_t ***dev);
 
 // Kernel timing: when enabled for a category (or "*"), launches of that

@@ -132,7 +132,7 @@ __global__ void k_encrypt_const(const uint64_t *__restrict__ pk, uint32_t L, con
 }  // namespace
 
 // Y[o] = Rescale(Relin(sum over CSR pairs)) for every output; all inputs at l limbs, 2 polys.
-static fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const std::vector<uint64_t *> &A,
+fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const std::vector<uint64_t *> &A,
                                     const std::vector<uint64_t *> &B, const std::vector<uint32_t> &off,
                                     const std::vector<uint64_t *> &Y)
 {
@@ -380,8 +380,10 @@ fhe_status fhe_encrypt_const_batch(fhe_ctx *c, const fhe_ct *pk, const double *v
     for (uint32_t t = 0; t < n; ++t)
         if (!out[t].d || out[t].polys != 2 || out[t].limbs != l)
             return fhe_fail(FHE_EINVAL, "fhe_encrypt_const_batch: outputs must be 2 x limbs, all at one level");
-    const uint32_t C = std::min<uint32_t>(n, 1024);
     const size_t LB = (size_t)N * 8;
+    // chunks of at most 1024 weights and about 2 GiB of scratch
+    const uint32_t C = (uint32_t)std::max<size_t>(
+        1, std::min<size_t>({(size_t)n, 1024, ((size_t)2 << 30) / (3 * LB * ((size_t)l + 1))}));
     // scratch: seeds [C], values [C], small [C][3][N] int64, residues [C][3][l][N]
     uint8_t *scr;
     fhe_status s;

@@ -447,28 +447,35 @@ fhe_status fhe_rotate_batch(fhe_ctx *c, const fhe_evk *gk, const fhe_ct *in, con
         for (uint32_t b2 = 0; b2 < n; ++b2)
             if (out[b].d < in[b2].d + 2 * per && in[b2].d < out[b].d + 2 * per)
                 return fhe_fail(FHE_EINVAL, "fhe_rotate_batch: outputs must not overlap inputs");
-    const size_t ksb = ks_scratch_bytes(c, l, n);
-    uint8_t *scr;
-    if ((s = ctx_scratch(c, ksb + 2 * per * n * sizeof(uint64_t), &scr))) return s;
-    uint64_t *perm = (uint64_t *)(scr + ksb);
-    std::vector<const uint64_t *> dd(n), ek(n), ad(2 * (size_t)n, nullptr);
-    std::vector<uint64_t *> oo(n);
-    {
-        ProfScope ps(c, "automorph");
-        for (uint32_t b = 0; b < n; ++b) {
-            uint64_t *pb = perm + (size_t)b * 2 * per;
-            hipLaunchKernelGGL(k_automorph, dim3(blocks_for(2 * per, TPB)), dim3(TPB), 0, c->stream,
-                               (const uint64_t *)in[b].d, pb, c->logN, (uint64_t)2 * l, (uint32_t)gk[b].galois);
-            dd[b] = pb + per;
-            ad[2 * b] = pb;
-            ek[b] = gk[b].d;
-            oo[b] = out[b].d;
-        }
+    std::vector<const uint64_t *> ip(n);
+    std::vector<const fhe_evk *> kp(n);
+    std::vector<uint64_t *> op(n);
+    for (uint32_t b = 0; b < n; ++b) {
+        ip[b] = in[b].d;
+        kp[b] = &gk[b];
+        op[b] = out[b].d;
     }
-    fhe_status r = ks_run(c, l, n, dd.data(), nullptr, ek.data(), oo.data(), ad.data(), scr);
+    if ((s = rotate_run(c, l, n, ip.data(), kp.data(), op.data()))) return s;
     for (uint32_t b = 0; b < n; ++b) out[b].scale = in[b].scale;
-    c->ops[OP_ROTATE] += n;
-    return r;
+    return FHE_OK;
+}
+
+// ct + value: the constant polynomial round(value * scale) (the same value at
+// every evaluation point) added to c0.
+fhe_status fhe_add_const(fhe_ctx *c, const fhe_ct *a, double value, fhe_ct *out)
+{
+    fhe_status s;
+    if (!c) return fhe_fail(FHE_EINVAL, "null context");
+    if ((s = chk_ct(c, a, "fhe_add_const")) || (s = chk_ct(c, out, "fhe_add_const"))) return s;
+    if (out->limbs != a->limbs || out->polys != a->polys) return fhe_fail(FHE_EINVAL, "fhe_add_const: shapes differ");
+    Consts64 cres;
+    if ((s = const_residues(c, value * a->scale, a->limbs, &cres))) return s;
+    const uint64_t *ap = a->d;
+    uint64_t *optr = out->d;
+    if ((s = ew_batch(c, EW_ADDC, a->limbs, a->limbs, a->polys, 1, &ap, nullptr, &optr, cres))) return s;
+    out->scale = a->scale;
+    c->ops[OP_PT_ADD] += 1;
+    return FHE_OK;
 }
 
 }  // extern "C"
@@ -478,4 +485,141 @@ void launch_automorph(fhe_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nl
 {
     hipLaunchKernelGGL(k_automorph, dim3(blocks_for((uint64_t)nlimbs * c->N, TPB)), dim3(TPB), 0, c->stream, in, out,
                        c->logN, (uint64_t)nlimbs, (uint32_t)g);
+}
+
+// n rotations (NTT-domain automorphism of the whole ciphertext, then a key
+// switch of the permuted c1 with the permuted c0 as addend), in chunks whose
+// scratch stays near 4 GiB.  Outputs must not overlap inputs.
+fhe_status rotate_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *in, const fhe_evk *const *keys,
+                      uint64_t *const *out)
+{
+    if (!n) return FHE_OK;
+    const size_t per = (size_t)l * c->N;
+    const size_t item = ks_scratch_bytes(c, l, 1) + 2 * per * sizeof(uint64_t);
+    const uint32_t C = (uint32_t)std::max<size_t>(1, std::min<size_t>(n, ((size_t)4 << 30) / item));
+    const size_t ksb = ks_scratch_bytes(c, l, C);
+    uint8_t *scr;
+    fhe_status s;
+    if ((s = ctx_scratch(c, ksb + 2 * per * C * sizeof(uint64_t), &scr))) return s;
+    uint64_t *perm = (uint64_t *)(scr + ksb);
+    std::vector<const uint64_t *> dd(C), ek(C), ad(2 * (size_t)C, nullptr);
+    std::vector<uint64_t *> oo(C);
+    for (uint32_t b0 = 0; b0 < n; b0 += C) {
+        const uint32_t cn = std::min(C, n - b0);
+        {
+            ProfScope ps(c, "automorph");
+            for (uint32_t b = 0; b < cn; ++b) {
+                uint64_t *pb = perm + (size_t)b * 2 * per;
+                hipLaunchKernelGGL(k_automorph, dim3(blocks_for(2 * per, TPB)), dim3(TPB), 0, c->stream,
+                                   in[b0 + b], pb, c->logN, (uint64_t)2 * l, (uint32_t)keys[b0 + b]->galois);
+                dd[b] = pb + per;
+                ad[2 * b] = pb;
+                ek[b] = keys[b0 + b]->d;
+                oo[b] = out[b0 + b];
+            }
+        }
+        if ((s = ks_run(c, l, cn, dd.data(), nullptr, ek.data(), oo.data(), ad.data(), scr))) return s;
+    }
+    c->ops[OP_ROTATE] += n;
+    return FHE_OK;
+}
+
+// Residues of the integer round(v) (|round(v)| < 2^62) on limbs 0..limbs-1.
+fhe_status const_residues(const fhe_ctx *c, double v, uint32_t limbs, Consts64 *out)
+{
+    const double r = std::nearbyint(v);
+    if (!(std::fabs(r) < 4611686018427387904.0)) return fhe_fail(FHE_EINVAL, "constant out of range");
+    std::memset(out, 0, sizeof(*out));
+    const int64_t iv = (int64_t)r;
+    for (uint32_t i = 0; i < limbs; ++i) {
+        int64_t m = iv % (int64_t)c->mod[i];
+        out->v[i] = (double)(m < 0 ? m + (int64_t)c->mod[i] : m);
+    }
+    return FHE_OK;
+}
+
+namespace {
+// Batched elementwise operations.  Item t (blockIdx.y) reads a[t] (layout
+// [polys][la][N], of which limbs 0..l-1 are used: la > l drops levels) and, for
+// EW_ADD, b[t] ([polys][l][N]); for EW_MULPT, b[t] is a plaintext [l][N].
+// Writes out[t] ([polys][l][N]).  EW_MULC multiplies by the per-limb constant,
+// EW_ADDC adds it to poly 0, EW_COPY copies.  Pointer table: [a: n][b: n][out: n].
+template <int OP>
+__global__ __launch_bounds__(TPB) void k_ew_batch(uint64_t *const *__restrict__ tab, uint32_t n, uint32_t logN,
+                                                  uint32_t l, uint32_t la, uint32_t polys, Consts64 cst,
+                                                  const ModQ *__restrict__ mods)
+{
+    const uint64_t per = (uint64_t)l << logN;
+    const uint64_t e = (uint64_t)blockIdx.x * TPB + threadIdx.x;
+    if (e >= per * polys) return;
+    const uint32_t t = blockIdx.y;
+    const uint32_t p = (uint32_t)(e / per);
+    const uint64_t r = e - (uint64_t)p * per;
+    const uint32_t limb = (uint32_t)(r >> logN);
+    const uint64_t a = tab[t][(uint64_t)p * ((uint64_t)la << logN) + r];
+    const uint64_t qq = (uint64_t)mods[limb].q;
+    uint64_t o;
+    if (OP == EW_ADD) {
+        o = a + tab[n + t][e];
+        o = o >= qq ? o - qq : o;
+    } else if (OP == EW_COPY) {
+        o = a;
+    } else if (OP == EW_ADDC) {
+        o = a;
+        if (p == 0) {
+            o = a + (uint64_t)cst.v[limb];
+            o = o >= qq ? o - qq : o;
+        }
+    } else {
+        const double q = mods[limb].q, qi = mods[limb].qinv;
+        const double m = OP == EW_MULC ? cst.v[limb] : u64_to_f64(tab[n + t][r]);
+        o = f64_to_u64(canon(mulmod(u64_to_f64(a), m, q, qi), q, qi));
+    }
+    tab[2 * n + t][e] = o;
+}
+}  // namespace
+
+fhe_status ew_batch(fhe_ctx *c, int op, uint32_t l, uint32_t la, uint32_t polys, uint32_t n,
+                    const uint64_t *const *a, const uint64_t *const *b, uint64_t *const *out, const Consts64 &cst)
+{
+    if (!n) return FHE_OK;
+    for (uint32_t t0 = 0; t0 < n; t0 += 65535) {
+        const uint32_t cn = std::min<uint32_t>(65535, n - t0);
+        std::vector<uint64_t *> tab(3 * (size_t)cn);
+        for (uint32_t t = 0; t < cn; ++t) {
+            tab[t] = (uint64_t *)a[t0 + t];
+            tab[cn + t] = b ? (uint64_t *)b[t0 + t] : nullptr;
+            tab[2 * cn + t] = out[t0 + t];
+        }
+        uint64_t **dt;
+        fhe_status s;
+        if ((s = ctx_ptr_table(c, tab, &dt))) return s;
+        const dim3 grid(blocks_for((uint64_t)polys * l * c->N, TPB), cn);
+        ProfScope ps(c, "elementwise");
+        switch (op) {
+        case EW_ADD:
+            hipLaunchKernelGGL(k_ew_batch<EW_ADD>, grid, dim3(TPB), 0, c->stream, (uint64_t *const *)dt, cn, c->logN,
+                               l, la, polys, cst, (const ModQ *)c->d_mod);
+            break;
+        case EW_MULC:
+            hipLaunchKernelGGL(k_ew_batch<EW_MULC>, grid, dim3(TPB), 0, c->stream, (uint64_t *const *)dt, cn,
+                               c->logN, l, la, polys, cst, (const ModQ *)c->d_mod);
+            break;
+        case EW_ADDC:
+            hipLaunchKernelGGL(k_ew_batch<EW_ADDC>, grid, dim3(TPB), 0, c->stream, (uint64_t *const *)dt, cn,
+                               c->logN, l, la, polys, cst, (const ModQ *)c->d_mod);
+            break;
+        case EW_MULPT:
+            hipLaunchKernelGGL(k_ew_batch<EW_MULPT>, grid, dim3(TPB), 0, c->stream, (uint64_t *const *)dt, cn,
+                               c->logN, l, la, polys, cst, (const ModQ *)c->d_mod);
+            break;
+        case EW_COPY:
+            hipLaunchKernelGGL(k_ew_batch<EW_COPY>, grid, dim3(TPB), 0, c->stream, (uint64_t *const *)dt, cn,
+                               c->logN, l, la, polys, cst, (const ModQ *)c->d_mod);
+            break;
+        default: return fhe_fail(FHE_EINVAL, "ew_batch: unknown operation");
+        }
+        HIPCHK(hipGetLastError());
+    }
+    return FHE_OK;
 }

@@ -1,0 +1,337 @@
+// packed.hip -- encrypted CNN layers with images packed inside the slots.
+//
+// Within-image packing: a ciphertext holds one channel of a batch of images,
+// each image in a frame of frame_h x frame_w slots (row-major, zero guard on the
+// right and below); pixel (y, x) of image b is slot b*frame_h*frame_w +
+// y*frame_w + x.  A left slot rotation (Sec. 3, Fig. 2 "rotation") by
+// dy*frame_w + dx then brings pixel (y+dy, x+dx) to (y, x) in every frame at
+// once, so that
+//   * a k x k "same" convolution is a sum of rotated inputs times replicated
+//     scalar weights, followed by one relinearisation and one rescale per output;
+//   * a 2x2 average pool is two rotations and adds, then one plaintext product
+//     with 0.25 on the surviving positions (it also clears everything else), and
+//     the dilation of the valid positions doubles;
+//   * a fully connected layer is a slot-wise product with weight ciphertexts that
+//     hold the weights at the valid positions, then a rotate-and-sum over the frame.
+// Every stage runs batched over all channels: one rotation batch, one tensor
+// multiply-accumulate launch, one batched key switch, one batched rescale.
+// Intermediates live in the context's layer workspace; the operations called
+// use the scratch buffer.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "fhe_internal.h"
+
+namespace {
+
+const fhe_evk *find_key(const fhe_evk *keys, uint32_t nkeys, uint64_t galois)
+{
+    for (uint32_t i = 0; i < nkeys; ++i)
+        if (keys[i].d && keys[i].galois == galois) return &keys[i];
+    return nullptr;
+}
+
+fhe_status chk2(const fhe_ct *x, uint32_t l, const char *what)
+{
+    if (!x->d || x->polys != 2 || x->limbs != l)
+        return fhe_fail(FHE_EINVAL, std::string(what) + ": ciphertexts must be 2 x limbs at the expected level");
+    return FHE_OK;
+}
+bool same_scale(double a, double b) { return std::fabs(a / b - 1.0) <= 9.5367431640625e-07; }
+
+fhe_status rescale_many(fhe_ctx *c, uint32_t l, uint32_t n, const std::vector<const uint64_t *> &in,
+                        const std::vector<uint64_t *> &out)
+{
+    const uint32_t C = std::min<uint32_t>(65535 / 2, (uint32_t)std::max<size_t>(
+                                                         1, ((size_t)2 << 30) / rescale_scratch_bytes(c, l, 2, 1)));
+    uint8_t *scr;
+    fhe_status s;
+    if ((s = ctx_scratch(c, rescale_scratch_bytes(c, l, 2, std::min(C, n)), &scr))) return s;
+    for (uint32_t t0 = 0; t0 < n; t0 += C) {
+        const uint32_t cn = std::min(C, n - t0);
+        if ((s = rescale_run(c, l, 2, cn, in.data() + t0, out.data() + t0, scr))) return s;
+    }
+    c->ops[OP_RESCALE] += n;
+    return FHE_OK;
+}
+
+Consts64 zero_consts()
+{
+    Consts64 z;
+    std::memset(&z, 0, sizeof(z));
+    return z;
+}
+
+}  // namespace
+
+extern "C" {
+
+fhe_status fhe_conv2d_packed(fhe_ctx *c, const fhe_evk *rlk, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *X,
+                             uint32_t Cin, const fhe_ct *Wt, uint32_t Cout, uint32_t k, uint32_t dil,
+                             uint32_t frame_w, fhe_ct *Y)
+{
+    fhe_status s;
+    if (!c || !rlk || !rlk->d || !X || !Wt || !Y || (nkeys && !keys))
+        return fhe_fail(FHE_EINVAL, "fhe_conv2d_packed: null argument");
+    if (!Cin || !Cout || !k || !(k & 1) || !dil || !frame_w)
+        return fhe_fail(FHE_EINVAL, "fhe_conv2d_packed: zero dimension or even kernel size");
+    if (rlk->galois != 0) return fhe_fail(FHE_ENOKEY, "fhe_conv2d_packed: needs the relinearisation key");
+    const uint32_t l = X[0].limbs, kk = k * k;
+    if (l < 2) return fhe_fail(FHE_ELEVEL, "fhe_conv2d_packed: inputs need two limbs");
+    for (uint32_t i = 0; i < Cin; ++i) {
+        if ((s = chk2(&X[i], l, "fhe_conv2d_packed"))) return s;
+        if (!same_scale(X[i].scale, X[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_packed: input scales differ");
+    }
+    for (uint32_t i = 0; i < Cout * Cin * kk; ++i) {
+        if ((s = chk2(&Wt[i], l, "fhe_conv2d_packed"))) return s;
+        if (!same_scale(Wt[i].scale, Wt[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_packed: weight scales differ");
+    }
+    for (uint32_t o = 0; o < Cout; ++o)
+        if ((s = chk2(&Y[o], l - 1, "fhe_conv2d_packed"))) return s;
+    // rotation step of tap t = (p, q), row-major
+    const int64_t half = k / 2;
+    std::vector<int64_t> step(kk);
+    std::vector<const fhe_evk *> tapkey(kk, nullptr);
+    uint32_t nz = 0;
+    for (uint32_t t = 0; t < kk; ++t) {
+        step[t] = (int64_t)dil * (((int64_t)(t / k) - half) * (int64_t)frame_w + ((int64_t)(t % k) - half));
+        if (!step[t]) continue;
+        ++nz;
+        if (!(tapkey[t] = find_key(keys, nkeys, fhe_galois_elt(c, (int32_t)step[t]))))
+            return fhe_fail(FHE_ENOKEY, "fhe_conv2d_packed: no Galois key for step " + std::to_string(step[t]));
+    }
+    const size_t ct_words = 2 * (size_t)l * c->N;
+    uint8_t *ws;
+    if ((s = ctx_workspace(c, (size_t)Cin * nz * ct_words * sizeof(uint64_t), &ws))) return s;
+    uint64_t *rot = (uint64_t *)ws;
+    // R[ci][t]: the input itself for the centre tap, else its rotation
+    std::vector<uint64_t *> R((size_t)Cin * kk);
+    std::vector<const uint64_t *> ri;
+    std::vector<const fhe_evk *> rk;
+    std::vector<uint64_t *> ro;
+    for (uint32_t ci = 0; ci < Cin; ++ci)
+        for (uint32_t t = 0; t < kk; ++t) {
+            if (!step[t]) {
+                R[(size_t)ci * kk + t] = X[ci].d;
+                continue;
+            }
+            uint64_t *dst = rot + ro.size() * ct_words;
+            R[(size_t)ci * kk + t] = dst;
+            ri.push_back(X[ci].d);
+            rk.push_back(tapkey[t]);
+            ro.push_back(dst);
+        }
+    if ((s = rotate_run(c, l, (uint32_t)ro.size(), ri.data(), rk.data(), ro.data()))) return s;
+    std::vector<uint64_t *> A, B, Yp;
+    std::vector<uint32_t> off{0};
+    for (uint32_t co = 0; co < Cout; ++co) {
+        for (uint32_t ci = 0; ci < Cin; ++ci)
+            for (uint32_t t = 0; t < kk; ++t) {
+                A.push_back(R[(size_t)ci * kk + t]);
+                B.push_back(Wt[((size_t)co * Cin + ci) * kk + t].d);
+            }
+        off.push_back((uint32_t)A.size());
+        Yp.push_back(Y[co].d);
+    }
+    if ((s = mac_relin_rescale(c, rlk, l, A, B, off, Yp))) return s;
+    const double so = X[0].scale * Wt[0].scale / (double)c->mod[l - 1];
+    for (uint32_t o = 0; o < Cout; ++o) Y[o].scale = so;
+    return FHE_OK;
+}
+
+fhe_status fhe_poly_act(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_t n, const double *coef, uint32_t deg,
+                        fhe_ct *y)
+{
+    fhe_status s;
+    if (!c || !rlk || !rlk->d || !x || !y || !coef || !n) return fhe_fail(FHE_EINVAL, "fhe_poly_act: null or empty");
+    if (rlk->galois != 0) return fhe_fail(FHE_ENOKEY, "fhe_poly_act: needs the relinearisation key");
+    if (deg != 2 && deg != 3) return fhe_fail(FHE_EINVAL, "fhe_poly_act: degree must be 2 or 3");
+    const uint32_t l = x[0].limbs;
+    if (l < 3) return fhe_fail(FHE_ELEVEL, "fhe_poly_act: inputs need three limbs (depth 2)");
+    const double S = x[0].scale;
+    for (uint32_t i = 0; i < n; ++i) {
+        if ((s = chk2(&x[i], l, "fhe_poly_act")) || (s = chk2(&y[i], l - 2, "fhe_poly_act"))) return s;
+        if (x[i].scale != S) return fhe_fail(FHE_ESCALE, "fhe_poly_act: input scales differ");
+    }
+    const size_t N = c->N, w1 = 2 * (size_t)(l - 1) * N, w2 = 2 * (size_t)(l - 2) * N;
+    // workspace: T [n][2][l], U [n][2][l-1], A [n][2][l-1], Bq [n][2][l-2]
+    uint8_t *ws;
+    if ((s = ctx_workspace(c, (size_t)n * (2 * (size_t)l * N + 2 * w1 + w2) * sizeof(uint64_t), &ws))) return s;
+    uint64_t *T = (uint64_t *)ws, *U = T + (size_t)n * 2 * l * N, *Aw = U + n * w1, *Bq = Aw + n * w1;
+    std::vector<const uint64_t *> xin(n), Tc(n), Ac(n), Bc(n);
+    std::vector<uint64_t *> Tp(n), Up(n), Ap(n), Bp(n), Yp(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        xin[i] = x[i].d;
+        Tp[i] = T + (size_t)i * 2 * l * N;
+        Up[i] = U + i * w1;
+        Ap[i] = Aw + i * w1;
+        Bp[i] = Bq + i * w2;
+        Yp[i] = y[i].d;
+        Tc[i] = Tp[i];
+        Ac[i] = Ap[i];
+        Bc[i] = Bp[i];
+    }
+    const double ql = (double)c->mod[l - 1], ql2 = (double)c->mod[l - 2];
+    const uint32_t cl = deg == 3 ? 3 : 2;   // coefficient of the branch that is multiplied by u (or u^2)
+    // a = Rescale(round(coef[cl] * q_(l-1)) * x) + coef[cl-1]
+    Consts64 k1, k2;
+    if ((s = const_residues(c, coef[cl] * ql, l, &k1))) return s;
+    if ((s = ew_batch(c, EW_MULC, l, l, 2, n, xin.data(), nullptr, Tp.data(), k1))) return s;
+    if ((s = rescale_many(c, l, n, Tc, Ap))) return s;
+    const double sA = S * ql / ql;
+    if ((s = const_residues(c, coef[cl - 1] * sA, l - 1, &k2))) return s;
+    if ((s = ew_batch(c, EW_ADDC, l - 1, l - 1, 2, n, Ac.data(), nullptr, Ap.data(), k2))) return s;
+    c->ops[OP_PT_MULT] += n;
+    c->ops[OP_PT_ADD] += n;
+    std::vector<uint64_t *> A1(Ap.begin(), Ap.end()), B1;
+    std::vector<uint32_t> off(n + 1);
+    for (uint32_t i = 0; i <= n; ++i) off[i] = i;
+    if (deg == 3) {
+        // u^2, then p = Rescale(Relin(a (x) u^2))
+        std::vector<uint64_t *> X2(n);
+        for (uint32_t i = 0; i < n; ++i) X2[i] = x[i].d;
+        if ((s = mac_relin_rescale(c, rlk, l, X2, X2, off, Up))) return s;
+        const double sU = S * S / ql;
+        if ((s = mac_relin_rescale(c, rlk, l - 1, A1, Up, off, Yp))) return s;
+        const double sp = sA * sU / ql2;
+        // b = Rescale(round(c1 * s1) * x at l-1 limbs) + c0, s1 chosen so that b lands on sp
+        const double s1 = sp * ql2 / S;
+        Consts64 k3, k4;
+        if ((s = const_residues(c, coef[1] * s1, l - 1, &k3))) return s;
+        if ((s = ew_batch(c, EW_MULC, l - 1, l, 2, n, xin.data(), nullptr, Tp.data(), k3))) return s;
+        if ((s = rescale_many(c, l - 1, n, Tc, Bp))) return s;
+        const double sB = S * s1 / ql2;
+        if ((s = const_residues(c, coef[0] * sB, l - 2, &k4))) return s;
+        if ((s = ew_batch(c, EW_ADDC, l - 2, l - 2, 2, n, Bc.data(), nullptr, Bp.data(), k4))) return s;
+        std::vector<const uint64_t *> Yc(Yp.begin(), Yp.end());
+        if ((s = ew_batch(c, EW_ADD, l - 2, l - 2, 2, n, Yc.data(), Bc.data(), Yp.data(), zero_consts()))) return s;
+        c->ops[OP_PT_MULT] += n;
+        c->ops[OP_PT_ADD] += n;
+        c->ops[OP_CT_ADD] += n;
+        for (uint32_t i = 0; i < n; ++i) y[i].scale = sp;
+    } else {
+        // p = Rescale(Relin(a (x) x at l-1 limbs)) + c0
+        if ((s = ew_batch(c, EW_COPY, l - 1, l, 2, n, xin.data(), nullptr, Up.data(), zero_consts()))) return s;
+        if ((s = mac_relin_rescale(c, rlk, l - 1, A1, Up, off, Yp))) return s;
+        const double sp = sA * S / ql2;
+        Consts64 k4;
+        if ((s = const_residues(c, coef[0] * sp, l - 2, &k4))) return s;
+        std::vector<const uint64_t *> Yc(Yp.begin(), Yp.end());
+        if ((s = ew_batch(c, EW_ADDC, l - 2, l - 2, 2, n, Yc.data(), nullptr, Yp.data(), k4))) return s;
+        c->ops[OP_PT_ADD] += n;
+        for (uint32_t i = 0; i < n; ++i) y[i].scale = sp;
+    }
+    return FHE_OK;
+}
+
+fhe_status fhe_avgpool2x2(fhe_ctx *c, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *x, uint32_t n,
+                          uint32_t dil, uint32_t frame_w, const fhe_pt *mask, fhe_ct *y)
+{
+    fhe_status s;
+    if (!c || !keys || !x || !y || !mask || !mask->d || !n || !dil || !frame_w)
+        return fhe_fail(FHE_EINVAL, "fhe_avgpool2x2: null or empty");
+    const uint32_t l = x[0].limbs;
+    if (l < 2) return fhe_fail(FHE_ELEVEL, "fhe_avgpool2x2: inputs need two limbs");
+    if (mask->limbs != l) return fhe_fail(FHE_ELEVEL, "fhe_avgpool2x2: mask must have the inputs' limbs");
+    for (uint32_t i = 0; i < n; ++i)
+        if ((s = chk2(&x[i], l, "fhe_avgpool2x2")) || (s = chk2(&y[i], l - 1, "fhe_avgpool2x2"))) return s;
+    const int32_t st1 = (int32_t)dil, st2 = (int32_t)(frame_w * dil);
+    const fhe_evk *k1 = find_key(keys, nkeys, fhe_galois_elt(c, st1));
+    const fhe_evk *k2 = find_key(keys, nkeys, fhe_galois_elt(c, st2));
+    if (!k1 || !k2) return fhe_fail(FHE_ENOKEY, "fhe_avgpool2x2: missing Galois key");
+    const size_t cw = 2 * (size_t)l * c->N;
+    uint8_t *ws;
+    if ((s = ctx_workspace(c, 2 * (size_t)n * cw * sizeof(uint64_t), &ws))) return s;
+    uint64_t *R1 = (uint64_t *)ws, *R2 = R1 + n * cw;
+    std::vector<const uint64_t *> xin(n), r1c(n), r2c(n);
+    std::vector<uint64_t *> r1(n), r2(n), yo(n);
+    std::vector<const fhe_evk *> kv1(n, k1), kv2(n, k2);
+    std::vector<const uint64_t *> mk(n, mask->d);
+    for (uint32_t i = 0; i < n; ++i) {
+        xin[i] = x[i].d;
+        r1[i] = R1 + i * cw;
+        r2[i] = R2 + i * cw;
+        r1c[i] = r1[i];
+        r2c[i] = r2[i];
+        yo[i] = y[i].d;
+    }
+    const Consts64 z = zero_consts();
+    // s = x + rot(x, dil); s = s + rot(s, frame_w dil); y = Rescale(s * mask)
+    if ((s = rotate_run(c, l, n, xin.data(), kv1.data(), r1.data()))) return s;
+    if ((s = ew_batch(c, EW_ADD, l, l, 2, n, xin.data(), r1c.data(), r1.data(), z))) return s;
+    if ((s = rotate_run(c, l, n, r1c.data(), kv2.data(), r2.data()))) return s;
+    if ((s = ew_batch(c, EW_ADD, l, l, 2, n, r1c.data(), r2c.data(), r2.data(), z))) return s;
+    if ((s = ew_batch(c, EW_MULPT, l, l, 2, n, r2c.data(), mk.data(), r1.data(), z))) return s;
+    if ((s = rescale_many(c, l, n, r1c, yo))) return s;
+    c->ops[OP_CT_ADD] += 2 * (uint64_t)n;
+    c->ops[OP_PT_MULT] += n;
+    for (uint32_t i = 0; i < n; ++i) y[i].scale = x[i].scale * mask->scale / (double)c->mod[l - 1];
+    return FHE_OK;
+}
+
+fhe_status fhe_fc_packed(fhe_ctx *c, const fhe_evk *rlk, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *x,
+                         uint32_t n_in, const fhe_ct *Wt, uint32_t n_out, uint32_t frame_slots, fhe_ct *y)
+{
+    fhe_status s;
+    if (!c || !rlk || !rlk->d || !x || !Wt || !y || !n_in || !n_out || (nkeys && !keys))
+        return fhe_fail(FHE_EINVAL, "fhe_fc_packed: null or empty");
+    if (rlk->galois != 0) return fhe_fail(FHE_ENOKEY, "fhe_fc_packed: needs the relinearisation key");
+    if (!frame_slots || (frame_slots & (frame_slots - 1)) || frame_slots > c->N / 2)
+        return fhe_fail(FHE_EINVAL, "fhe_fc_packed: frame size must be a power of two up to N/2");
+    const uint32_t l = x[0].limbs;
+    if (l < 2) return fhe_fail(FHE_ELEVEL, "fhe_fc_packed: inputs need two limbs");
+    for (uint32_t i = 0; i < n_in; ++i) {
+        if ((s = chk2(&x[i], l, "fhe_fc_packed"))) return s;
+        if (!same_scale(x[i].scale, x[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_packed: input scales differ");
+    }
+    for (uint32_t i = 0; i < n_in * n_out; ++i) {
+        if ((s = chk2(&Wt[i], l, "fhe_fc_packed"))) return s;
+        if (!same_scale(Wt[i].scale, Wt[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_packed: weight scales differ");
+    }
+    for (uint32_t o = 0; o < n_out; ++o)
+        if ((s = chk2(&y[o], l - 1, "fhe_fc_packed"))) return s;
+    std::vector<const fhe_evk *> sumkey;
+    for (uint32_t i = 1; i < frame_slots; i *= 2) {
+        const fhe_evk *kk = find_key(keys, nkeys, fhe_galois_elt(c, (int32_t)i));
+        if (!kk) return fhe_fail(FHE_ENOKEY, "fhe_fc_packed: no Galois key for step " + std::to_string(i));
+        sumkey.push_back(kk);
+    }
+    const size_t cw = 2 * (size_t)(l - 1) * c->N;
+    uint8_t *ws;
+    if ((s = ctx_workspace(c, 2 * (size_t)n_out * cw * sizeof(uint64_t), &ws))) return s;
+    uint64_t *Z = (uint64_t *)ws, *R = Z + n_out * cw;
+    std::vector<uint64_t *> A, B, zp(n_out), rp(n_out), yp(n_out);
+    std::vector<const uint64_t *> zc(n_out), rc(n_out);
+    std::vector<uint32_t> off{0};
+    for (uint32_t o = 0; o < n_out; ++o) {
+        for (uint32_t i = 0; i < n_in; ++i) {
+            A.push_back(x[i].d);
+            B.push_back(Wt[(size_t)o * n_in + i].d);
+        }
+        off.push_back((uint32_t)A.size());
+        zp[o] = Z + o * cw;
+        rp[o] = R + o * cw;
+        zc[o] = zp[o];
+        rc[o] = rp[o];
+        yp[o] = y[o].d;
+    }
+    if ((s = mac_relin_rescale(c, rlk, l, A, B, off, zp))) return s;
+    const Consts64 zk = zero_consts();
+    // z += rot(z, i) for i = 1, 2, ..., frame_slots / 2; the last sum goes to y
+    for (size_t j = 0; j < sumkey.size(); ++j) {
+        std::vector<const fhe_evk *> kv(n_out, sumkey[j]);
+        if ((s = rotate_run(c, l - 1, n_out, zc.data(), kv.data(), rp.data()))) return s;
+        const bool last = j + 1 == sumkey.size();
+        if ((s = ew_batch(c, EW_ADD, l - 1, l - 1, 2, n_out, zc.data(), rc.data(), last ? yp.data() : zp.data(), zk)))
+            return s;
+        c->ops[OP_CT_ADD] += n_out;
+    }
+    if (sumkey.empty())
+        if ((s = ew_batch(c, EW_COPY, l - 1, l - 1, 2, n_out, zc.data(), nullptr, yp.data(), zk))) return s;
+    const double so = x[0].scale * Wt[0].scale / (double)c->mod[l - 1];
+    for (uint32_t o = 0; o < n_out; ++o) y[o].scale = so;
+    return FHE_OK;
+}
+
+}  // extern "C"

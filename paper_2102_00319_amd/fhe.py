@@ -87,6 +87,15 @@ _sig = {
     "fhe_square_act": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_encrypt_const_batch": [_P, C.POINTER(fhe_ct), _P, C.c_uint32, C.c_double, _P, C.POINTER(fhe_ct)],
     "fhe_profile_read": [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)],
+    "fhe_add_const": [_P, C.POINTER(fhe_ct), C.c_double, C.POINTER(fhe_ct)],
+    "fhe_conv2d_packed": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_evk), C.c_uint32, C.POINTER(fhe_ct), C.c_uint32,
+                          C.POINTER(fhe_ct), C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
+    "fhe_poly_act": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), C.c_uint32, C.POINTER(C.c_double), C.c_uint32,
+                     C.POINTER(fhe_ct)],
+    "fhe_avgpool2x2": [_P, C.POINTER(fhe_evk), C.c_uint32, C.POINTER(fhe_ct), C.c_uint32, C.c_uint32, C.c_uint32,
+                       C.POINTER(fhe_pt), C.POINTER(fhe_ct)],
+    "fhe_fc_packed": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_evk), C.c_uint32, C.POINTER(fhe_ct), C.c_uint32,
+                      C.POINTER(fhe_ct), C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
 }
 for _n, _a in _sig.items():
     getattr(_lib, _n).argtypes = _a
@@ -514,6 +523,54 @@ class Context:
         _check(_lib.fhe_square_act(self._h, C.byref(rlk.s()), XA, len(x), YA))
         self._back(YA, y)
         return y
+
+    # -------------------------------------------- within-image packed layers
+    def _keys(self, gks):
+        keys = list(gks.values()) if isinstance(gks, dict) else list(gks)
+        return (fhe_evk * max(1, len(keys)))(*[k.s() for k in keys]), len(keys)
+
+    def conv2d_packed(self, rlk, gks, X, Wt, Cout, k, dilation, frame_w):
+        l = X[0].limbs
+        Y = [self.new_ct(l - 1, 2) for _ in range(Cout)]
+        K, nk = self._keys(gks)
+        XA, WA, YA = self._arr(X), self._arr(Wt), self._arr(Y)
+        _check(_lib.fhe_conv2d_packed(self._h, C.byref(rlk.s()), K, nk, XA, len(X), WA, Cout, k, dilation, frame_w,
+                                      YA))
+        self._back(YA, Y)
+        return Y
+
+    def poly_act(self, rlk, xs, coef, deg):
+        y = [self.new_ct(v.limbs - 2, 2) for v in xs]
+        cf = (C.c_double * 4)(*[float(v) for v in (list(coef) + [0.0] * 4)[:4]])
+        XA, YA = self._arr(xs), self._arr(y)
+        _check(_lib.fhe_poly_act(self._h, C.byref(rlk.s()), XA, len(xs), cf, deg, YA))
+        self._back(YA, y)
+        return y
+
+    def avgpool2x2(self, gks, xs, dilation, frame_w, mask):
+        y = [self.new_ct(v.limbs - 1, 2) for v in xs]
+        K, nk = self._keys(gks)
+        XA, YA = self._arr(xs), self._arr(y)
+        m = mask.s()
+        _check(_lib.fhe_avgpool2x2(self._h, K, nk, XA, len(xs), dilation, frame_w, C.byref(m), YA))
+        self._back(YA, y)
+        return y
+
+    def fc_packed(self, rlk, gks, xs, Wt, n_out, frame_slots):
+        l = xs[0].limbs
+        y = [self.new_ct(l - 1, 2) for _ in range(n_out)]
+        K, nk = self._keys(gks)
+        XA, WA, YA = self._arr(xs), self._arr(Wt), self._arr(y)
+        _check(_lib.fhe_fc_packed(self._h, C.byref(rlk.s()), K, nk, XA, len(xs), WA, n_out, frame_slots, YA))
+        self._back(YA, y)
+        return y
+
+    def add_const(self, a, value, out=None):
+        out = out or self.new_ct(a.limbs, a.polys)
+        x, o = a.s(), out.s()
+        _check(_lib.fhe_add_const(self._h, C.byref(x), float(value), C.byref(o)))
+        out.scale = o.scale
+        return out
 
     def mul_relin_rescale(self, rlk, a, b):
         return self.rescale(self.relin(rlk, self.mul(a, b)))

@@ -1,0 +1,155 @@
+"""Encrypted CNNs composed from the layer entry points of libfhe.
+
+Roles follow the paper's setting (Sec. 2.1): the user holds the secret key,
+encrypts images and decrypts scores; the model owner encrypts the weights under
+the user's public key (Sec. 3, "both image and model encrypted"); the cloud runs
+`forward` on ciphertexts only.
+
+PackedCNN -- within-image packing: one ciphertext per channel, a batch of images
+each in a frame_h x frame_w frame of slots (zero guard right and below):
+    conv k x k same (c1 channels) -> poly act -> 2x2 avg pool
+    -> conv k x k same (c2 channels, dilation 2) -> poly act -> 2x2 avg pool
+    -> fully connected (flatten order (c, y, x)) -> score in slot 0 of each frame.
+Every CT x CT product is followed by relinearisation and one rescale, so a
+forward pass takes 9 levels: conv 1, act 2, pool 1, conv 1, act 2, pool 1, fc 1.
+"""
+import numpy as np
+
+# ------------------------------------------------------------ slot layouts
+
+
+def frame_pack(images, frame_h, frame_w):
+    """images [B][H][W] -> slot vector, image b pixel (y, x) at b*frame_h*frame_w + y*frame_w + x."""
+    B, H, W = images.shape
+    if H > frame_h or W > frame_w:
+        raise ValueError("image larger than its frame")
+    out = np.zeros(B * frame_h * frame_w)
+    for b in range(B):
+        base = b * frame_h * frame_w
+        for y in range(H):
+            out[base + y * frame_w: base + y * frame_w + W] = images[b, y]
+    return out
+
+
+def grid_slots(H, W, frame_h, frame_w, n_frames, step):
+    """Slots of the grid positions (step*i, step*j) inside an H x W image, every frame, row-major per frame."""
+    rows = range(0, H, step)
+    cols = range(0, W, step)
+    return np.array([f * frame_h * frame_w + y * frame_w + x
+                     for f in range(n_frames) for y in rows for x in cols], dtype=np.int64)
+
+
+class PackedCNN:
+    def __init__(self, H=28, W=28, frame_h=32, frame_w=32, k=3, c1=8, c2=16, n_classes=10,
+                 coef=(0.47, 0.5, 0.09, -0.005), deg=3):
+        if H % 4 or W % 4:
+            raise ValueError("image sides must be multiples of 4 (two 2x2 pools)")
+        if frame_h - H < 2 * (k // 2) or frame_w - W < 2 * (k // 2):
+            raise ValueError("zero guard too small for the second convolution's dilation")
+        self.H, self.W, self.fh, self.fw, self.k = H, W, frame_h, frame_w, k
+        self.c1, self.c2, self.n_classes, self.coef, self.deg = c1, c2, n_classes, tuple(coef), deg
+        self.frame = frame_h * frame_w
+        if self.frame & (self.frame - 1):
+            raise ValueError("frame size must be a power of two")
+        self._masks = {}
+
+    # -------------------------------------------------------------- plan
+    def conv_steps(self, dil):
+        h = self.k // 2
+        return [dil * ((p - h) * self.fw + (q - h)) for p in range(self.k) for q in range(self.k)]
+
+    def rotation_steps(self):
+        st = set()
+        for dil in (1, 2):
+            st.update(r for r in self.conv_steps(dil) if r)
+            st.update([dil, self.fw * dil])
+        i = 1
+        while i < self.frame:
+            st.add(i)
+            i *= 2
+        return sorted(st)
+
+    def images_per_ct(self, ctx):
+        return (ctx.N // 2) // self.frame
+
+    @property
+    def depth(self):
+        return 9
+
+    # -------------------------------------------------------------- user
+    def keygen(self, ctx, s, seed):
+        """Relinearisation key (seed) and one Galois key per rotation step (seed + 1 + i)."""
+        rlk = ctx.keygen_relin(s, seed)
+        gks = {r: ctx.keygen_rot(s, r, seed + 1 + i) for i, r in enumerate(self.rotation_steps())}
+        return rlk, gks
+
+    def encrypt_images(self, ctx, pk, images, seed, scale=None):
+        B = images.shape[0]
+        if B > self.images_per_ct(ctx):
+            raise ValueError("more images than frames in one ciphertext")
+        v = frame_pack(images, self.fh, self.fw)
+        return [ctx.encrypt(pk, ctx.encode(v, scale=scale or ctx.scale), seed)]
+
+    def decrypt_scores(self, ctx, s, Z, B):
+        out = np.empty((B, len(Z)))
+        for r, z in enumerate(Z):
+            v, _ = ctx.decode(ctx.decrypt(s, z), n=B * self.frame)
+            out[:, r] = v[np.arange(B) * self.frame]
+        return out
+
+    # ------------------------------------------------------- model owner
+    def weight_levels(self, top):
+        return top, top - 4, top - 8
+
+    def fc_slots(self, ctx, wrow):
+        """One FC weight ciphertext's slots: weight (y, x) of a channel at frame position (4y, 4x)."""
+        nf = self.images_per_ct(ctx)
+        v = np.zeros(ctx.N // 2)
+        v[grid_slots(self.H, self.W, self.fh, self.fw, nf, 4)] = np.tile(np.asarray(wrow, np.float64).ravel(), nf)
+        return v
+
+    def encrypt_weights(self, ctx, pk, w1, w2, wfc, seeds, top=None, scale=None):
+        """w1 [c1][1][k][k], w2 [c2][c1][k][k] as slot-replicated constants, wfc [classes][c2*(H/4)*(W/4)]
+        as masked slot vectors; seeds = (conv1, conv2, fc) base seeds, one per ciphertext from there."""
+        top = ctx.L if top is None else top
+        D = scale or ctx.scale
+        l1, l2, l3 = self.weight_levels(top)
+        W1 = ctx.encrypt_const_batch(pk, w1.ravel(), D, [seeds[0] + t for t in range(w1.size)], l1)
+        W2 = ctx.encrypt_const_batch(pk, w2.ravel(), D, [seeds[1] + t for t in range(w2.size)], l2)
+        hp, wp = self.H // 4, self.W // 4
+        Wf = []
+        for r in range(self.n_classes):
+            rows = np.asarray(wfc[r]).reshape(self.c2, hp * wp)
+            for c in range(self.c2):
+                pt = ctx.encode(self.fc_slots(ctx, rows[c]), scale=D, limbs=l3)
+                Wf.append(ctx.encrypt(pk, pt, seeds[2] + r * self.c2 + c))
+        return W1, W2, Wf
+
+    # -------------------------------------------------------------- cloud
+    def pool_mask(self, ctx, dil, limbs):
+        """0.25 at the grid of step 2*dil, at scale q_(limbs-1) so that the rescale keeps the scale."""
+        key = (dil, limbs)
+        if key not in self._masks:
+            v = np.zeros(ctx.N // 2)
+            v[grid_slots(self.H, self.W, self.fh, self.fw, self.images_per_ct(ctx), 2 * dil)] = 0.25
+            self._masks[key] = ctx.encode(v, scale=float(ctx.q[limbs - 1]), limbs=limbs)
+        return self._masks[key]
+
+    def forward(self, ctx, rlk, gks, X, weights):
+        W1, W2, Wf = weights
+        Y = ctx.conv2d_packed(rlk, gks, X, W1, self.c1, self.k, 1, self.fw)
+        A = ctx.poly_act(rlk, Y, self.coef, self.deg)
+        P = ctx.avgpool2x2(gks, A, 1, self.fw, self.pool_mask(ctx, 1, A[0].limbs))
+        Y = ctx.conv2d_packed(rlk, gks, P, W2, self.c2, self.k, 2, self.fw)
+        A = ctx.poly_act(rlk, Y, self.coef, self.deg)
+        P = ctx.avgpool2x2(gks, A, 2, self.fw, self.pool_mask(ctx, 2, A[0].limbs))
+        return ctx.fc_packed(rlk, gks, P, Wf, self.n_classes, self.frame)
+
+    def op_counts(self):
+        """Expected (ct_mult, relin, rotate) of one forward pass."""
+        kk, nz = self.k * self.k, self.k * self.k - 1
+        act = 2 if self.deg == 3 else 1
+        ct_mult = self.c1 * kk + self.c2 * self.c1 * kk + act * (self.c1 + self.c2) + self.n_classes * self.c2
+        relin = self.c1 + self.c2 + act * (self.c1 + self.c2) + self.n_classes
+        rot = nz * (1 + self.c1) + 2 * (self.c1 + self.c2) + self.n_classes * int(np.log2(self.frame))
+        return ct_mult, relin, rot
