@@ -172,6 +172,26 @@ fhe_status fhe_keyswitch(fhe_ctx *ctx, const fhe_evk *evk, const uint64_t *d, ui
 fhe_status fhe_keyswitch_batch(fhe_ctx *ctx, const fhe_evk *evk, const uint64_t *const *d, uint32_t limbs,
                                uint32_t n, fhe_ct *out);
 
+/* Work list of independent or chained operations at mixed levels (one ring).
+ * Operations run as if in list order; those whose inputs are ready are grouped
+ * by kind and run as one ragged launch sequence (the GPU analogue of the paper's
+ * split of independent work over threads, Sec. 4.2).  An input may be the
+ * output of an earlier operation in the list; outputs must not overlap each
+ * other, nor any input of their own or an earlier operation (FHE_EINVAL).
+ *   FHE_OP_MUL_RELIN_RESCALE: out = Rescale(Relin(a (x) b)) with key (relin),
+ *     a and b at one level l >= 2, out at l - 1;
+ *   FHE_OP_ROTATE: out = rotate(a, step) with key (Galois key of step), out at l.
+ * Output scales are set on the out descriptors. */
+enum { FHE_OP_MUL_RELIN_RESCALE = 1, FHE_OP_ROTATE = 2 };
+typedef struct {
+    uint32_t kind;
+    int32_t step;
+    const fhe_ct *a, *b;
+    const fhe_evk *key;
+    fhe_ct *out;
+} fhe_op;
+fhe_status fhe_batch_run(fhe_ctx *ctx, const fhe_op *ops, uint32_t n_ops);
+
 /* Batched relinearisation and rescale of n ciphertexts (host descriptor arrays;
  * one key; rescale outputs must not overlap their inputs). */
 fhe_status fhe_relin_batch(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *in3, uint32_t n, fhe_ct *out2);

@@ -43,6 +43,7 @@ struct LimbSet {
     uint32_t period;
     uint32_t b0;                  // limb number of blockIdx.y == 0 (large batches are split)
     uint8_t mod[FHE_LIMBTAB];
+    const uint64_t *modlist;      // if set (device): limb b is reduced modulo mods[modlist[b] & 0xFFFF]
 };
 
 // ------------------------------------------------------------------ device
@@ -89,7 +90,10 @@ __device__ __forceinline__ uint64_t *limb_ptr(const LimbSet &ls, uint32_t b, uin
 {
     return ls.units ? ls.units[b / ls.lpu] + (size_t)(b % ls.lpu) * N : ls.base + (size_t)b * N;
 }
-__device__ __forceinline__ uint32_t limb_mod(const LimbSet &ls, uint32_t b) { return ls.mod[b % ls.period]; }
+__device__ __forceinline__ uint32_t limb_mod(const LimbSet &ls, uint32_t b)
+{
+    return ls.modlist ? (uint32_t)(ls.modlist[b] & 0xFFFF) : ls.mod[b % ls.period];
+}
 
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).
 __device__ __forceinline__ void philox4x64_10(uint64_t k0, uint64_t k1, uint64_t c0, uint64_t c1, uint64_t c2,
@@ -178,6 +182,8 @@ fhe_status ew_batch(fhe_ctx *c, int op, uint32_t l, uint32_t la, uint32_t polys,
 fhe_status const_residues(const fhe_ctx *c, double v, uint32_t limbs, Consts64 *out);
 fhe_status rotate_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *in, const fhe_evk *const *keys,
                       uint64_t *const *out);
+fhe_status rotate_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *in,
+                             const fhe_evk *const *keys, uint64_t *const *out);
 fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const std::vector<uint64_t *> &A,
                              const std::vector<uint64_t *> &B, const std::vector<uint32_t> &off,
                              const std::vector<uint64_t *> &Y);
@@ -205,10 +211,21 @@ size_t ks_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t n);
 // ks_scratch_bytes(l, n) bytes, or null to take the context's.
 fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, const uint32_t *gal,
                   const uint64_t *const *evk, uint64_t *const *out, const uint64_t *const *add, uint8_t *scr);
+// The same for items at different levels: item b has ls[b] limbs (input, output,
+// addends); scratch of ks_scratch_bytes_ragged(n, ls) bytes.
+size_t ks_scratch_bytes_ragged(const fhe_ctx *c, uint32_t n, const uint32_t *ls);
+fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *d, const uint32_t *gal,
+                         const uint64_t *const *evk, uint64_t *const *out, const uint64_t *const *add, uint8_t *scr);
 size_t rescale_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n);
 fhe_status rescale_run(fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n, const uint64_t *const *in,
                        uint64_t *const *out, uint8_t *scr);
+// Rescale of items at different levels (item b: ls[b] limbs in, ls[b] - 1 out).
+size_t rescale_scratch_bytes_ragged(const fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls);
+fhe_status rescale_run_ragged(fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls, const uint64_t *const *in,
+                              uint64_t *const *out, uint8_t *scr);
 void launch_automorph(fhe_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nlimbs, uint64_t g);
+fhe_status automorph_run(fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls, const uint32_t *gal,
+                         const uint64_t *const *in, uint64_t *const *out);
 
 // launchers (ntt.hip)
 void launch_ntt_fwd(fhe_ctx *c, const LimbSet &ls, uint32_t nlimbs);

@@ -2,10 +2,12 @@
 // a batch of inputs, the operation under relinearisation and slot rotation
 // (the CT-CT multiplications of Sec. 3 and the rotations of its packing).
 //
-// For each item b: input d_b (l limbs, NTT domain) read through a Galois
-// permutation gal_b (0 = none: relinearisation; 5^r: rotation, so that the
-// automorphism is never materialised), key evk_b [dnum][2][L+K][N], output
-// out_b (2 polys), optional addends add[2b], add[2b+1] (read through gal_b).
+// For each item b: input d_b (l_b limbs, NTT domain) read through a Galois
+// permutation gal_b (0 = none), key evk_b [dnum][2][L+K][N], output out_b
+// (2 polys of l_b limbs), optional addends add[2b], add[2b+1] (read through
+// gal_b).  Items may sit at different levels l_b: every launch walks flat lists
+// of (item, limb) or (item, digit) entries built on the host, so that one launch
+// sequence serves a whole ragged batch.
 //   ModUp:   digits D_j = limbs [j alpha, min((j+1) alpha, l)); each converted to
 //            Q_l u P by fast basis conversion (canonical representatives);
 //   inner:   u_t = sum_j D_j * evk_{j,t} over Q_l u P;
@@ -36,42 +38,62 @@ namespace {
 
 constexpr int TPB = 256;
 inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
+constexpr uint32_t GRID_Y = 65535;
 
-// pointer table of one ks_run: [d: n][evk: n][out: n][add: 2n][gal: n (integers)]
-__device__ __forceinline__ uint32_t tab_gal(uint64_t *const *tab, uint32_t n, uint32_t b)
+// Per-item layout of one batch (device copy in the pointer table, 7 words).
+struct KsItem {
+    uint32_t l, nd;
+    uint32_t dc_off;    // first limb of the item in dc
+    uint32_t up_off;    // first limb of the item in up
+    uint32_t uq_off;    // first limb of the item in uQ and z ([2][l] each)
+    uint32_t pad;
+    uint16_t upoff[16]; // first converted limb of digit j, relative to up_off
+};
+static_assert(sizeof(KsItem) == 56, "KsItem is 7 table words");
+struct BcJob {          // one basis conversion: nsrc source limbs -> ndst destination limbs
+    uint32_t off;       // constants in the conversion table
+    uint32_t nsrc, ndst;
+    uint32_t src0, dst0;   // absolute first limbs in the source and destination buffers
+    uint32_t pad;
+};
+static_assert(sizeof(BcJob) == 24, "BcJob is 3 table words");
+// Word offsets of the sections of one batch's table:
+//   [d: n][evk: n][out: n][add: 2n][gal: n][items: 7n][la: sum l][upjobs: 3 sum nd]
+//   [upmods: sum ups][inner: sum (l + K)][dnjobs: 3 * 2n][fl: sum 2l]
+// la entries: item << 16 | limb (dc order); inner: item << 16 | x (x < l: Q limb,
+// else special prime x - l); fl: item << 17 | poly << 16 | limb (z and uQ order).
+struct KsTab {
+    uint32_t n, K, L;
+    uint32_t it, la, uj, um, il, dj, fl;
+};
+__device__ __forceinline__ const KsItem &tab_item(uint64_t *const *tab, const KsTab &t, uint32_t b)
 {
-    return (uint32_t)(uintptr_t)tab[5 * n + b];
+    return reinterpret_cast<const KsItem *>(tab + t.it)[b];
+}
+__device__ __forceinline__ uint64_t tab_word(uint64_t *const *tab, uint32_t off, uint32_t y)
+{
+    return (uint64_t)(uintptr_t)tab[off + y];
 }
 
-struct BcJob {
-    uint32_t off, nsrc, ndst;
-    uint32_t src0;       // first source limb within one batch item of src
-    uint32_t dst0;       // first destination limb within one batch item of dst
-};
-struct BcArgs {
-    uint32_t njobs;
-    uint32_t src_bstride, dst_bstride;   // limbs per batch item
-    BcJob job[16];
-};
-// Fast basis conversion, one thread per coefficient, blockIdx.y = job, blockIdx.z = batch item:
+// Fast basis conversion, one thread per coefficient, blockIdx.y + y0 = job:
 //   y_t = sum_a [x_a (B/b_a)^-1]_{b_a} (B/b_a mod c_t)  mod c_t.
 // ADD_HALF: sources offset by hsrc (per source limb) and results by -hdst (per
 // destination limb): the rounding shift of ModDown.
 template <bool ADD_HALF>
 __global__ __launch_bounds__(TPB) void k_bconv(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
-                                               const double *__restrict__ tab, BcArgs args, uint32_t logN,
-                                               const double *__restrict__ hsrc, const double *__restrict__ hdst)
+                                               const double *__restrict__ ctab, const BcJob *__restrict__ jobs,
+                                               uint32_t y0, uint32_t logN, const double *__restrict__ hsrc,
+                                               const double *__restrict__ hdst)
 {
     const uint32_t N = 1u << logN;
     const uint32_t k = blockIdx.x * TPB + threadIdx.x;
     if (k >= N) return;
-    const BcJob jb = args.job[blockIdx.y];
-    const uint64_t b = blockIdx.z;
-    const double *T = tab + jb.off;
+    const BcJob jb = jobs[blockIdx.y + y0];
+    const double *T = ctab + jb.off;
     const double *qhinv = T, *sq = T + jb.nsrc, *sqi = T + 2 * jb.nsrc, *dq = T + 3 * jb.nsrc,
                  *dqi = T + 3 * jb.nsrc + jb.ndst, *qh = T + 3 * jb.nsrc + 2 * jb.ndst;
-    const uint64_t *S = src + (b * args.src_bstride + jb.src0) * N + k;
-    uint64_t *D = dst + (b * args.dst_bstride + jb.dst0) * N + k;
+    const uint64_t *S = src + (size_t)jb.src0 * N + k;
+    uint64_t *D = dst + (size_t)jb.dst0 * N + k;
     double v[16];
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
@@ -96,109 +118,109 @@ __global__ __launch_bounds__(TPB) void k_bconv(const uint64_t *__restrict__ src,
     }
 }
 
-struct KsDims {
-    uint32_t l, K, L, alpha, nd, ups;
-    uint32_t upoff[16];   // first converted limb of digit j within one batch item of `up`
-};
-
 // 1. First (row) pass of the inverse transform of d_b, gathered through gal_b,
-//    into dc as lazy FP64 bits (SINGLE: the whole inverse, canonical out).
-template <int LOGG, int WG, bool SINGLE>
-__global__ __launch_bounds__(WG) void k_ks_intt_first(uint64_t *const *__restrict__ tab, uint32_t n,
+//    into dc as lazy FP64 bits.  blockIdx.y + y0 = entry of the la list.
+template <int LOGG, int WG>
+__global__ __launch_bounds__(WG) void k_ks_intt_first(uint64_t *const *__restrict__ tab, KsTab t, uint32_t y0,
                                                       uint64_t *__restrict__ dc, const ModQ *__restrict__ mods,
-                                                      const double *__restrict__ itwt,
-                                                      const double *__restrict__ ninvt, uint32_t l, uint32_t logN,
+                                                      const double *__restrict__ itwt, uint32_t logN,
                                                       uint32_t sigma0)
 {
     using Gm = Geom<LOGG, WG, false>;
     __shared__ double lds[Gm::LDS];
     const uint32_t N = 1u << logN;
-    const uint32_t y = blockIdx.y, b = y / l, i = y % l;
+    const uint32_t y = blockIdx.y + y0;
+    const uint64_t e = tab_word(tab, t.la, y);
+    const uint32_t b = (uint32_t)(e >> 16), i = (uint32_t)(e & 0xFFFF);
     const uint64_t *src = tab[b] + (size_t)i * N;
-    const uint32_t gal = tab_gal(tab, n, b);
+    const uint32_t gal = (uint32_t)tab_word(tab, 5 * t.n, b);
     const double q = mods[i].q, qinv = mods[i].qinv;
     const Gm gm(logN, blockIdx.x);
     double x[R];
 #pragma unroll
     for (int k = 0; k < R; k++) x[k] = u64_to_f64(src[galois_src(gm.coal(k), gal, logN)]);
     gm.coal_to_inv_in(x, lds);
-    gm.template inv<SINGLE>(x, lds, itwt + (size_t)i * N, q, qinv, ninvt[i], logN, sigma0);
+    gm.template inv<false>(x, lds, itwt + (size_t)i * N, q, qinv, 0.0, logN, sigma0);
     uint64_t *dst = dc + (size_t)y * N;
 #pragma unroll
-    for (int k = 0; k < R; k++) dst[gm.inv_out(k)] = SINGLE ? f64_to_u64(canon(x[k], q, qinv)) : f64_to_bits(x[k]);
+    for (int k = 0; k < R; k++) dst[gm.inv_out(k)] = f64_to_bits(x[k]);
 }
 
-// 4b. Key inner product, one thread per coefficient of one limb x of Q_l u P:
+// 4b. Key inner product, one thread per coefficient of one limb x of Q_l u P
+//     (blockIdx.y + y0 = entry of the inner list):
 //     u_t[x] = sum_j D_j[x] * evk_{j,t}[x]; D_j[x] is the input limb itself
 //     inside digit j, else the converted limb.
-__global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ tab, uint32_t n,
+__global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ tab, KsTab t, uint32_t y0,
                                                   const uint64_t *__restrict__ up, uint64_t *__restrict__ uQ,
                                                   uint64_t *__restrict__ uP, const ModQ *__restrict__ mods,
-                                                  KsDims dm, uint32_t logN)
+                                                  uint32_t alpha, uint32_t logN)
 {
     const uint32_t N = 1u << logN;
     const uint32_t k = blockIdx.x * TPB + threadIdx.x;
     if (k >= N) return;
-    const uint32_t x = blockIdx.y, b = blockIdx.z;
-    const uint32_t mx = x < dm.l ? x : dm.L + (x - dm.l);
+    const uint64_t e = tab_word(tab, t.il, blockIdx.y + y0);
+    const uint32_t b = (uint32_t)(e >> 16), x = (uint32_t)(e & 0xFFFF);
+    const KsItem &it = tab_item(tab, t, b);
+    const uint32_t l = it.l;
+    const uint32_t mx = x < l ? x : t.L + (x - l);
     const double q = mods[mx].q, qi = mods[mx].qinv;
-    const uint64_t *d = tab[b], *ev = tab[n + b];
-    const uint64_t *upb = up + (size_t)b * dm.ups * N;
-    const size_t ML = dm.L + dm.K;
+    const uint64_t *d = tab[b], *ev = tab[t.n + b];
+    const uint64_t *upb = up + (size_t)it.up_off * N;
+    const size_t ML = t.L + t.K;
     double a0 = 0.0, a1 = 0.0;
-    for (uint32_t j = 0; j < dm.nd; ++j) {
-        const uint32_t lo = j * dm.alpha, hi = min(lo + dm.alpha, dm.l);
+    for (uint32_t j = 0; j < it.nd; ++j) {
+        const uint32_t lo = j * alpha, hi = min(lo + alpha, l);
         double D;
         if (x >= lo && x < hi) D = u64_to_f64(d[(size_t)x * N + k]);
         else {
             const uint32_t pos = x < lo ? x : x - (hi - lo);
-            D = u64_to_f64(upb[(size_t)(dm.upoff[j] + pos) * N + k]);
+            D = u64_to_f64(upb[(size_t)(it.upoff[j] + pos) * N + k]);
         }
         a0 += mulmod(D, u64_to_f64(ev[(((size_t)j * 2 + 0) * ML + mx) * N + k]), q, qi);
         a1 += mulmod(D, u64_to_f64(ev[(((size_t)j * 2 + 1) * ML + mx) * N + k]), q, qi);
         if ((j & 3) == 3) { a0 = redc(a0, q, qi); a1 = redc(a1, q, qi); }
     }
     uint64_t *o0, *o1;
-    if (x < dm.l) {
-        o0 = uQ + ((size_t)b * 2 * dm.l + x) * N;
-        o1 = uQ + ((size_t)b * 2 * dm.l + dm.l + x) * N;
+    if (x < l) {
+        o0 = uQ + ((size_t)it.uq_off + x) * N;
+        o1 = uQ + ((size_t)it.uq_off + l + x) * N;
     } else {
-        o0 = uP + ((size_t)b * 2 * dm.K + (x - dm.l)) * N;
-        o1 = uP + ((size_t)b * 2 * dm.K + dm.K + (x - dm.l)) * N;
+        o0 = uP + ((size_t)b * 2 * t.K + (x - l)) * N;
+        o1 = uP + ((size_t)b * 2 * t.K + t.K + (x - l)) * N;
     }
     o0[k] = f64_to_u64(canon(a0, q, qi));
     o1[k] = f64_to_u64(canon(a1, q, qi));
 }
 
 // 8. Forward row pass of z fused with the ModDown finish:
-//    out_t[i] = (u_t[i] - z_t[i]) * P^-1 + add_t[i].  blockIdx.y = limb i, blockIdx.z = 2b + t.
-template <int LOGG, int WG, bool IN_U64>
-__global__ __launch_bounds__(WG, 3) void k_ks_moddown_final(uint64_t *const *__restrict__ tab, uint32_t n,
+//    out_t[i] = (u_t[i] - z_t[i]) * P^-1 + add_t[i].  blockIdx.y + y0 = entry of fl.
+template <int LOGG, int WG>
+__global__ __launch_bounds__(WG, 3) void k_ks_moddown_final(uint64_t *const *__restrict__ tab, KsTab t, uint32_t y0,
                                                          const uint64_t *__restrict__ z,
                                                          const uint64_t *__restrict__ uQ,
                                                          const ModQ *__restrict__ mods, const double *__restrict__ twt,
-                                                         const double *__restrict__ pinv, uint32_t l, uint32_t logN,
+                                                         const double *__restrict__ pinv, uint32_t logN,
                                                          uint32_t sigma0)
 {
     using Gm = Geom<LOGG, WG, false>;
     __shared__ double lds[Gm::LDS];
     const uint32_t N = 1u << logN;
-    const uint32_t i = blockIdx.y, item = blockIdx.z, b = item >> 1, t = item & 1;
+    const uint32_t y = blockIdx.y + y0;
+    const uint64_t e = tab_word(tab, t.fl, y);
+    const uint32_t b = (uint32_t)(e >> 17), tt = (uint32_t)((e >> 16) & 1), i = (uint32_t)(e & 0xFFFF);
+    const uint32_t l = tab_item(tab, t, b).l;
     const double q = mods[i].q, qinv = mods[i].qinv;
     const Gm gm(logN, blockIdx.x);
-    const uint64_t *zs = z + ((size_t)item * l + i) * N;
+    const uint64_t *zs = z + (size_t)y * N;
     double v[R];
 #pragma unroll
-    for (int k = 0; k < R; k++) {
-        const uint64_t w = zs[gm.fwd_in(k)];
-        v[k] = IN_U64 ? u64_to_f64(w) : bits_to_f64(w);
-    }
+    for (int k = 0; k < R; k++) v[k] = bits_to_f64(zs[gm.fwd_in(k)]);
     gm.fwd(v, lds, twt + (size_t)i * N, q, qinv, logN, sigma0);
     gm.fwd_out_to_coal(v, lds);
-    const uint64_t *uq = uQ + ((size_t)item * l + i) * N;
-    const uint64_t *ad = tab[3 * n + 2 * b + t];
-    const uint32_t gal = tab_gal(tab, n, b);
-    uint64_t *out = tab[2 * n + b] + ((size_t)t * l + i) * N;
+    const uint64_t *uq = uQ + (size_t)y * N;
+    const uint64_t *ad = tab[3 * t.n + 2 * b + tt];
+    const uint32_t gal = (uint32_t)tab_word(tab, 5 * t.n, b);
+    uint64_t *out = tab[2 * t.n + b] + ((size_t)tt * l + i) * N;
     const double pi = pinv[i];
 #pragma unroll
     for (int k = 0; k < R; k++) {
@@ -209,21 +231,20 @@ __global__ __launch_bounds__(WG, 3) void k_ks_moddown_final(uint64_t *const *__r
     }
 }
 
-// Column passes of the key-switching path (split_ks): forward (canonical in,
-// lazy bits out) and inverse (bits in, canonical out, N^-1 folded).
-struct ModPat {
-    uint32_t period, b0;
-    uint8_t m[FHE_LIMBTAB];
-};
+// Column and row passes of the key-switching path (split_ks) over a flat limb
+// buffer whose limb y is reduced modulo mods[lst[y] & 0xFFFF]: forward (canonical
+// in, lazy bits out; row: bits in, canonical out, coalesced stores) and inverse
+// column (bits in, canonical out, N^-1 folded).
 template <int LOGG, int WG>
-__global__ __launch_bounds__(WG) void k_col_fwd(uint64_t *__restrict__ base, ModPat pat, const ModQ *__restrict__ mods,
+__global__ __launch_bounds__(WG) void k_col_fwd(uint64_t *__restrict__ base, const uint64_t *__restrict__ lst,
+                                                uint32_t y0, const ModQ *__restrict__ mods,
                                                 const double *__restrict__ twt, uint32_t logN)
 {
     using Gm = Geom<LOGG, WG, true>;
     __shared__ double lds[Gm::LDS];
     const uint32_t N = 1u << logN;
-    const uint32_t b = blockIdx.y + pat.b0;
-    const uint32_t m = pat.m[b % pat.period];
+    const uint32_t b = blockIdx.y + y0;
+    const uint32_t m = (uint32_t)(lst[b] & 0xFFFF);
     const double q = mods[m].q, qinv = mods[m].qinv;
     uint64_t *p = base + (size_t)b * N;
     const Gm gm(logN, blockIdx.x);
@@ -234,17 +255,16 @@ __global__ __launch_bounds__(WG) void k_col_fwd(uint64_t *__restrict__ base, Mod
 #pragma unroll
     for (int k = 0; k < R; k++) p[gm.fwd_out(k)] = f64_to_bits(x[k]);
 }
-// 4a. Forward row pass of the converted limbs: lazy bits in, canonical out,
-//     stores coalesced through an LDS transpose.
 template <int LOGG, int WG>
-__global__ __launch_bounds__(WG) void k_row_fwd(uint64_t *__restrict__ base, ModPat pat, const ModQ *__restrict__ mods,
+__global__ __launch_bounds__(WG) void k_row_fwd(uint64_t *__restrict__ base, const uint64_t *__restrict__ lst,
+                                                uint32_t y0, const ModQ *__restrict__ mods,
                                                 const double *__restrict__ twt, uint32_t logN, uint32_t sigma0)
 {
     using Gm = Geom<LOGG, WG, false>;
     __shared__ double lds[Gm::LDS];
     const uint32_t N = 1u << logN;
-    const uint32_t b = blockIdx.y + pat.b0;
-    const uint32_t m = pat.m[b % pat.period];
+    const uint32_t b = blockIdx.y + y0;
+    const uint32_t m = (uint32_t)(lst[b] & 0xFFFF);
     const double q = mods[m].q, qinv = mods[m].qinv;
     uint64_t *p = base + (size_t)b * N;
     const Gm gm(logN, blockIdx.x);
@@ -257,15 +277,16 @@ __global__ __launch_bounds__(WG) void k_row_fwd(uint64_t *__restrict__ base, Mod
     for (int k = 0; k < R; k++) p[gm.coal(k)] = f64_to_u64(canon(x[k], q, qinv));
 }
 template <int LOGG, int WG>
-__global__ __launch_bounds__(WG) void k_col_inv(uint64_t *__restrict__ base, uint32_t period, uint32_t b0,
-                                                const ModQ *__restrict__ mods, const double *__restrict__ itwt,
-                                                const double *__restrict__ ninvt, uint32_t logN)
+__global__ __launch_bounds__(WG) void k_col_inv(uint64_t *__restrict__ base, const uint64_t *__restrict__ lst,
+                                                uint32_t y0, const ModQ *__restrict__ mods,
+                                                const double *__restrict__ itwt, const double *__restrict__ ninvt,
+                                                uint32_t logN)
 {
     using Gm = Geom<LOGG, WG, true>;
     __shared__ double lds[Gm::LDS];
     const uint32_t N = 1u << logN;
-    const uint32_t b = blockIdx.y + b0;
-    const uint32_t m = b % period;          // limbs 0..period-1 of Q, repeated
+    const uint32_t b = blockIdx.y + y0;
+    const uint32_t m = (uint32_t)(lst[b] & 0xFFFF);
     const double q = mods[m].q, qinv = mods[m].qinv;
     uint64_t *p = base + (size_t)b * N;
     const Gm gm(logN, blockIdx.x);
@@ -307,158 +328,206 @@ void dispatch_logn(uint32_t logN, F f)
     default: break;
     }
 }
+// run f(y0, count) over [0, total) in grid-sized pieces
+template <typename F>
+void in_pieces(uint32_t total, F f)
+{
+    for (uint32_t y0 = 0; y0 < total; y0 += GRID_Y) f(y0, std::min(GRID_Y, total - y0));
+}
+
+// Host plan of one ragged batch.
+struct KsPlan {
+    uint32_t n, sum_l, sum_nd, sum_ups, sum_inner;
+    std::vector<KsItem> items;
+    std::vector<BcJob> upjobs, dnjobs;
+    std::vector<uint64_t> la, upmods, inner, fl;
+};
+
+fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, KsPlan &pl)
+{
+    const uint32_t K = c->K, alpha = c->alpha;
+    pl.n = n;
+    pl.items.assign(n, KsItem{});
+    uint32_t dc = 0, up = 0, uq = 0;
+    for (uint32_t b = 0; b < n; ++b) {
+        const uint32_t l = ls[b];
+        if (l < 1 || l > c->L) return fhe_fail(FHE_ELEVEL, "key switch: limb count out of range");
+        const uint32_t nd = (l + alpha - 1) / alpha;
+        if (nd > 16) return fhe_fail(FHE_EPARAM, "key switching supports at most 16 digits");
+        if (b >= 32768) return fhe_fail(FHE_EINVAL, "key-switch batch too large");
+        KsItem &it = pl.items[b];
+        it.l = l;
+        it.nd = nd;
+        it.dc_off = dc;
+        it.up_off = up;
+        it.uq_off = uq;
+        uint32_t u = 0;
+        for (uint32_t j = 0; j < nd; ++j) {
+            const BconvTab &t = c->modup[(size_t)l * c->dnum + j];
+            it.upoff[j] = (uint16_t)u;
+            pl.upjobs.push_back(BcJob{t.off, t.nsrc, t.ndst, dc + j * alpha, up + u, 0});
+            for (uint32_t a = 0; a < t.ndst; ++a) pl.upmods.push_back(t.dst[a]);
+            u += t.ndst;
+        }
+        for (uint32_t i = 0; i < l; ++i) pl.la.push_back(((uint64_t)b << 16) | i);
+        for (uint32_t x = 0; x < l + K; ++x) pl.inner.push_back(((uint64_t)b << 16) | x);
+        for (uint32_t tt = 0; tt < 2; ++tt) {
+            const BconvTab &md = c->moddown[l];
+            pl.dnjobs.push_back(BcJob{md.off, md.nsrc, md.ndst, (2 * b + tt) * K, uq + tt * l, 0});
+            for (uint32_t i = 0; i < l; ++i) pl.fl.push_back(((uint64_t)b << 17) | ((uint64_t)tt << 16) | i);
+        }
+        dc += l;
+        up += u;
+        uq += 2 * l;
+    }
+    pl.sum_l = dc;
+    pl.sum_ups = up;
+    pl.sum_nd = (uint32_t)pl.upjobs.size();
+    pl.sum_inner = (uint32_t)pl.inner.size();
+    return FHE_OK;
+}
 
 }  // namespace
 
 // ---- launchers of the key-switching path
-static void ks_col_fwd(fhe_ctx *c, uint64_t *base, const uint32_t *mods, uint32_t period, uint32_t nlimbs)
+static void ks_col_fwd(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs)
 {
     ProfScope ps(c, "ntt_fwd_col");
-    ModPat pat;
-    std::memset(&pat, 0, sizeof(pat));
-    pat.period = period;
-    for (uint32_t i = 0; i < period; ++i) pat.m[i] = (uint8_t)mods[i];
     dispatch_logn(c->logN, [&](auto sh) {
         using S = decltype(sh);
-        for (uint32_t done = 0; done < nlimbs; done += 65535u) {
-            pat.b0 = done;
-            hipLaunchKernelGGL((k_col_fwd<S::LOGA, S::WA>), dim3(S::GA, std::min(65535u, nlimbs - done)), dim3(S::WA),
-                               0, c->stream, base, pat, (const ModQ *)c->d_mod, (const double *)c->d_tw, c->logN);
-        }
+        in_pieces(nlimbs, [&](uint32_t y0, uint32_t cnt) {
+            hipLaunchKernelGGL((k_col_fwd<S::LOGA, S::WA>), dim3(S::GA, cnt), dim3(S::WA), 0, c->stream, base, lst, y0,
+                               (const ModQ *)c->d_mod, (const double *)c->d_tw, c->logN);
+        });
     });
 }
-static void ks_col_inv(fhe_ctx *c, uint64_t *base, uint32_t period, uint32_t nlimbs)
+static void ks_col_inv(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs)
 {
     ProfScope ps(c, "ntt_inv_col");
     dispatch_logn(c->logN, [&](auto sh) {
         using S = decltype(sh);
-        for (uint32_t done = 0; done < nlimbs; done += 65535u)
-            hipLaunchKernelGGL((k_col_inv<S::LOGA, S::WA>), dim3(S::GA, std::min(65535u, nlimbs - done)),
-                               dim3(S::WA), 0, c->stream, base, period, done, (const ModQ *)c->d_mod,
-                               (const double *)c->d_itw, (const double *)c->d_ninv, c->logN);
+        in_pieces(nlimbs, [&](uint32_t y0, uint32_t cnt) {
+            hipLaunchKernelGGL((k_col_inv<S::LOGA, S::WA>), dim3(S::GA, cnt), dim3(S::WA), 0, c->stream, base, lst, y0,
+                               (const ModQ *)c->d_mod, (const double *)c->d_itw, (const double *)c->d_ninv, c->logN);
+        });
     });
 }
-static void run_intt_first(fhe_ctx *c, uint64_t **dt, uint32_t n, uint64_t *dc, uint32_t l)
-{
-    ProfScope ps(c, "ks_intt_first");
-    dispatch_logn(c->logN, [&](auto sh) {
-        using S = decltype(sh);
-        hipLaunchKernelGGL((k_ks_intt_first<S::LOGB, S::WB, false>), dim3(S::GB, n * l), dim3(S::WB), 0, c->stream,
-                           (uint64_t *const *)dt, n, dc, (const ModQ *)c->d_mod, (const double *)c->d_itw,
-                           (const double *)c->d_ninv, l, c->logN, (uint32_t)S::LOGA);
-    });
-}
-static void ks_row_fwd(fhe_ctx *c, uint64_t *base, const uint32_t *mods, uint32_t period, uint32_t nlimbs)
+static void ks_row_fwd(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs)
 {
     ProfScope ps(c, "ntt_fwd_row");
-    ModPat pat;
-    std::memset(&pat, 0, sizeof(pat));
-    pat.period = period;
-    for (uint32_t i = 0; i < period; ++i) pat.m[i] = (uint8_t)mods[i];
     dispatch_logn(c->logN, [&](auto sh) {
         using S = decltype(sh);
-        for (uint32_t done = 0; done < nlimbs; done += 65535u) {
-            pat.b0 = done;
-            hipLaunchKernelGGL((k_row_fwd<S::LOGB, S::WB>), dim3(S::GB, std::min(65535u, nlimbs - done)), dim3(S::WB),
-                               0, c->stream, base, pat, (const ModQ *)c->d_mod, (const double *)c->d_tw, c->logN,
-                               (uint32_t)S::LOGA);
-        }
-    });
-}
-static void run_moddown_final(fhe_ctx *c, uint64_t **dt, uint32_t n, const uint64_t *z, const uint64_t *uQ,
-                              uint32_t l)
-{
-    ProfScope ps(c, "ks_moddown_final");
-    dispatch_logn(c->logN, [&](auto sh) {
-        using S = decltype(sh);
-        hipLaunchKernelGGL((k_ks_moddown_final<S::LOGB, S::WB, false>), dim3(S::GB, l, 2 * n), dim3(S::WB), 0,
-                           c->stream, (uint64_t *const *)dt, n, z, uQ, (const ModQ *)c->d_mod,
-                           (const double *)c->d_tw, (const double *)c->d_pinv, l, c->logN, (uint32_t)S::LOGA);
+        in_pieces(nlimbs, [&](uint32_t y0, uint32_t cnt) {
+            hipLaunchKernelGGL((k_row_fwd<S::LOGB, S::WB>), dim3(S::GB, cnt), dim3(S::WB), 0, c->stream, base, lst, y0,
+                               (const ModQ *)c->d_mod, (const double *)c->d_tw, c->logN, (uint32_t)S::LOGA);
+        });
     });
 }
 
+size_t ks_scratch_bytes_ragged(const fhe_ctx *c, uint32_t n, const uint32_t *ls)
+{
+    size_t limbs = 2 * (size_t)c->K * n;
+    for (uint32_t b = 0; b < n; ++b) {
+        const uint32_t l = ls[b], nd = (l + c->alpha - 1) / c->alpha;
+        size_t ups = 0;
+        for (uint32_t j = 0; j < nd; ++j) ups += c->modup[(size_t)l * c->dnum + j].ndst;
+        limbs += 5 * (size_t)l + ups;
+    }
+    return limbs * c->N * sizeof(uint64_t);
+}
 size_t ks_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t n)
 {
-    const uint32_t nd = (l + c->alpha - 1) / c->alpha;
-    size_t ups = 0;
-    for (uint32_t j = 0; j < nd; ++j) ups += c->modup[(size_t)l * c->dnum + j].ndst;
-    return (size_t)n * (5 * (size_t)l + ups + 2 * (size_t)c->K) * c->N * sizeof(uint64_t);
+    if (!n) return 0;
+    std::vector<uint32_t> ls(n, l);
+    return ks_scratch_bytes_ragged(c, n, ls.data());
 }
 
-fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, const uint32_t *gal,
-                  const uint64_t *const *evk, uint64_t *const *out, const uint64_t *const *add, uint8_t *scr_in)
+fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *d, const uint32_t *gal,
+                         const uint64_t *const *evk, uint64_t *const *out, const uint64_t *const *add, uint8_t *scr_in)
 {
+    if (!n) return FHE_OK;
     if (!c->K) return fhe_fail(FHE_EPARAM, "key switching needs special primes");
-    const uint32_t N = c->N, K = c->K, L = c->L, alpha = c->alpha;
-    const uint32_t nd = (l + alpha - 1) / alpha;
-    if (nd > 16 || alpha > 16 || K > 16)
-        return fhe_fail(FHE_EPARAM, "key switching supports at most 16 digits, 16 limbs per digit, 16 special primes");
-    if ((uint64_t)n * l > 65535u || 2ull * n > 65535u) return fhe_fail(FHE_EINVAL, "key-switch batch too large");
-    KsDims dm;
-    std::memset(&dm, 0, sizeof(dm));
-    dm.l = l; dm.K = K; dm.L = L; dm.alpha = alpha; dm.nd = nd;
-    BcArgs up_args;
-    std::memset(&up_args, 0, sizeof(up_args));
-    uint32_t upmods[FHE_LIMBTAB], ups = 0;
-    for (uint32_t j = 0; j < nd; ++j) {
-        const BconvTab &t = c->modup[(size_t)l * c->dnum + j];
-        dm.upoff[j] = ups;
-        up_args.job[j] = BcJob{t.off, t.nsrc, t.ndst, j * alpha, ups};
-        for (uint32_t a = 0; a < t.ndst; ++a) {
-            if (ups >= FHE_LIMBTAB) return fhe_fail(FHE_EPARAM, "extended basis too large for one launch");
-            upmods[ups++] = t.dst[a];
-        }
-    }
-    dm.ups = ups;
-    up_args.njobs = nd;
-    up_args.src_bstride = l;
-    up_args.dst_bstride = ups;
-    const BconvTab &mdt = c->moddown[l];
-    BcArgs dn_args;
-    std::memset(&dn_args, 0, sizeof(dn_args));
-    dn_args.njobs = 1;
-    dn_args.src_bstride = K;   // batch item = one polynomial (2 per key switch)
-    dn_args.dst_bstride = l;
-    dn_args.job[0] = BcJob{mdt.off, mdt.nsrc, mdt.ndst, 0, 0};
+    const uint32_t N = c->N, K = c->K, L = c->L;
+    if (c->alpha > 16 || K > 16)
+        return fhe_fail(FHE_EPARAM, "key switching supports at most 16 limbs per digit and 16 special primes");
+    if (2ull * n > GRID_Y) return fhe_fail(FHE_EINVAL, "key-switch batch too large");
+    KsPlan pl;
+    fhe_status s;
+    if ((s = ks_plan(c, n, ls, pl))) return s;
 
-    // scratch: dc [n][l], up [n][ups], uQ [n][2][l], uP [n][2][K], z [n][2][l]
-    const size_t n_dc = (size_t)n * l, n_up = (size_t)n * ups, n_uq = (size_t)n * 2 * l, n_up2 = (size_t)n * 2 * K;
+    // scratch: dc [sum l], up [sum ups], uQ [sum 2l], uP [n][2][K], z [sum 2l]
     uint8_t *scr = scr_in;
-    fhe_status s = FHE_OK;
-    if (!scr && (s = ctx_scratch(c, ks_scratch_bytes(c, l, n), &scr))) return s;
-    uint64_t *dc = (uint64_t *)scr, *up = dc + n_dc * N, *uQ = up + n_up * N, *uP = uQ + n_uq * N, *z = uP + n_up2 * N;
+    if (!scr && (s = ctx_scratch(c, ks_scratch_bytes_ragged(c, n, ls), &scr))) return s;
+    uint64_t *dc = (uint64_t *)scr, *up = dc + (size_t)pl.sum_l * N, *uQ = up + (size_t)pl.sum_ups * N,
+             *uP = uQ + 2 * (size_t)pl.sum_l * N, *z = uP + 2 * (size_t)n * K * N;
 
+    // one table: pointers, then the plan's lists
     std::vector<uint64_t *> tab;
-    tab.reserve(6 * (size_t)n);
+    auto push_words = [&](const void *src, size_t bytes) {
+        const uint64_t *w = (const uint64_t *)src;
+        for (size_t i = 0; i < bytes / 8; ++i) tab.push_back((uint64_t *)(uintptr_t)w[i]);
+    };
+    KsTab kt;
+    kt.n = n;
+    kt.K = K;
+    kt.L = L;
     for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)d[b]);
     for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)evk[b]);
     for (uint32_t b = 0; b < n; ++b) tab.push_back(out[b]);
     for (uint32_t b = 0; b < 2 * n; ++b) tab.push_back(add ? (uint64_t *)add[b] : nullptr);
     for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)(uintptr_t)(gal ? gal[b] : 0u));
+    kt.it = (uint32_t)tab.size();
+    push_words(pl.items.data(), pl.items.size() * sizeof(KsItem));
+    kt.la = (uint32_t)tab.size();
+    push_words(pl.la.data(), pl.la.size() * 8);
+    kt.uj = (uint32_t)tab.size();
+    push_words(pl.upjobs.data(), pl.upjobs.size() * sizeof(BcJob));
+    kt.um = (uint32_t)tab.size();
+    push_words(pl.upmods.data(), pl.upmods.size() * 8);
+    kt.il = (uint32_t)tab.size();
+    push_words(pl.inner.data(), pl.inner.size() * 8);
+    kt.dj = (uint32_t)tab.size();
+    push_words(pl.dnjobs.data(), pl.dnjobs.size() * sizeof(BcJob));
+    kt.fl = (uint32_t)tab.size();
+    push_words(pl.fl.data(), pl.fl.size() * 8);
     uint64_t **dt;
     if ((s = ctx_ptr_table(c, tab, &dt))) return s;
+    const uint64_t *dwords = (const uint64_t *)dt;
     hipStream_t st = c->stream;
     const uint32_t gx = blocks_for(N, TPB);
-    uint32_t qm[FHE_LIMBTAB];
-    for (uint32_t i = 0; i < l; ++i) qm[i] = i;
+    const uint32_t sum2l = 2 * pl.sum_l;
 
     // 1. coefficients of the (permuted) inputs
-    run_intt_first(c, dt, n, dc, l);
-    ks_col_inv(c, dc, l, n * l);
-    // 2-3. ModUp conversion and the column pass of the converted limbs
+    {
+        ProfScope ps(c, "ks_intt_first");
+        dispatch_logn(c->logN, [&](auto sh) {
+            using S = decltype(sh);
+            in_pieces(pl.sum_l, [&](uint32_t y0, uint32_t cnt) {
+                hipLaunchKernelGGL((k_ks_intt_first<S::LOGB, S::WB>), dim3(S::GB, cnt), dim3(S::WB), 0, st,
+                                   (uint64_t *const *)dt, kt, y0, dc, (const ModQ *)c->d_mod, (const double *)c->d_itw,
+                                   c->logN, (uint32_t)S::LOGA);
+            });
+        });
+    }
+    ks_col_inv(c, dc, dwords + kt.la, pl.sum_l);
+    // 2-3. ModUp conversion and the forward transform of the converted limbs
     {
         ProfScope ps(c, "bconv_up");
-        hipLaunchKernelGGL(k_bconv<false>, dim3(gx, nd, n), dim3(TPB), 0, st, (const uint64_t *)dc, up,
-                           (const double *)c->d_bconv, up_args, c->logN, (const double *)nullptr,
-                           (const double *)nullptr);
+        in_pieces(pl.sum_nd, [&](uint32_t y0, uint32_t cnt) {
+            hipLaunchKernelGGL(k_bconv<false>, dim3(gx, cnt), dim3(TPB), 0, st, (const uint64_t *)dc, up,
+                               (const double *)c->d_bconv, (const BcJob *)(dwords + kt.uj), y0, c->logN,
+                               (const double *)nullptr, (const double *)nullptr);
+        });
     }
-    ks_col_fwd(c, up, upmods, ups, n * ups);
-    ks_row_fwd(c, up, upmods, ups, n * ups);
+    ks_col_fwd(c, up, dwords + kt.um, pl.sum_ups);
+    ks_row_fwd(c, up, dwords + kt.um, pl.sum_ups);
     // 4. key inner product over the digits
     {
         ProfScope ps(c, "ks_inner");
-        hipLaunchKernelGGL(k_ks_inner, dim3(gx, l + K, n), dim3(TPB), 0, st, (uint64_t *const *)dt, n,
-                           (const uint64_t *)up, uQ, uP, (const ModQ *)c->d_mod, dm, c->logN);
+        in_pieces(pl.sum_inner, [&](uint32_t y0, uint32_t cnt) {
+            hipLaunchKernelGGL(k_ks_inner, dim3(gx, cnt), dim3(TPB), 0, st, (uint64_t *const *)dt, kt, y0,
+                               (const uint64_t *)up, uQ, uP, (const ModQ *)c->d_mod, c->alpha, c->logN);
+        });
     }
     // 5-6. ModDown: P limbs to coefficients, rounded conversion to Q_l
     {
@@ -468,13 +537,31 @@ fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, 
     }
     {
         ProfScope ps(c, "bconv_down");
-        hipLaunchKernelGGL(k_bconv<true>, dim3(gx, 1, n * 2), dim3(TPB), 0, st, (const uint64_t *)uP, z,
-                           (const double *)c->d_bconv, dn_args, c->logN, (const double *)(c->d_phalf + L),
-                           (const double *)c->d_phalf);
+        hipLaunchKernelGGL(k_bconv<true>, dim3(gx, 2 * n), dim3(TPB), 0, st, (const uint64_t *)uP, z,
+                           (const double *)c->d_bconv, (const BcJob *)(dwords + kt.dj), 0u, c->logN,
+                           (const double *)(c->d_phalf + L), (const double *)c->d_phalf);
     }
     // 7-8. column pass of z, row pass fused with the finish
-    ks_col_fwd(c, z, qm, l, n * 2 * l);
-    run_moddown_final(c, dt, n, z, uQ, l);
+    ks_col_fwd(c, z, dwords + kt.fl, sum2l);
+    {
+        ProfScope ps(c, "ks_moddown_final");
+        dispatch_logn(c->logN, [&](auto sh) {
+            using S = decltype(sh);
+            in_pieces(sum2l, [&](uint32_t y0, uint32_t cnt) {
+                hipLaunchKernelGGL((k_ks_moddown_final<S::LOGB, S::WB>), dim3(S::GB, cnt), dim3(S::WB), 0, st,
+                                   (uint64_t *const *)dt, kt, y0, (const uint64_t *)z, (const uint64_t *)uQ,
+                                   (const ModQ *)c->d_mod, (const double *)c->d_tw, (const double *)c->d_pinv,
+                                   c->logN, (uint32_t)S::LOGA);
+            });
+        });
+    }
     HIPCHK(hipGetLastError());
     return FHE_OK;
+}
+
+fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, const uint32_t *gal,
+                  const uint64_t *const *evk, uint64_t *const *out, const uint64_t *const *add, uint8_t *scr_in)
+{
+    std::vector<uint32_t> ls(n, l);
+    return ks_run_ragged(c, n, ls.data(), d, gal, evk, out, add, scr_in);
 }

@@ -99,45 +99,73 @@ __global__ void k_automorph(const uint64_t *__restrict__ in, uint64_t *__restric
     const uint32_t y = __brev((ey - 1u) >> 1) >> (32 - logN);
     out[i] = in[base + y];
 }
-// Rescale over a batch of ciphertexts given by pointer tables (item b = ciphertext).
+// Rescale over a ragged batch of ciphertexts (item b: l_b limbs, P polys).
+// Table: [in: n][out: n][lvl: n][last: n*P][spread: sum P (l_b - 1)]; a last
+// entry j = b*P + p holds j << 16 | (l_b - 1), a spread entry j << 16 | i.
 // Step 1: copy the last limb of every polynomial to tmp [n*P][N].
-__global__ void k_gather_last(uint64_t *const *__restrict__ inp, uint64_t *__restrict__ tmp, uint32_t logN, uint32_t l,
-                              uint32_t polys)
+__global__ void k_gather_last(uint64_t *const *__restrict__ tab, uint32_t n, uint32_t polys,
+                              uint64_t *__restrict__ tmp, uint32_t logN, uint32_t y0)
 {
     const uint32_t N = 1u << logN;
     const uint32_t k = blockIdx.x * TPB + threadIdx.x;
     if (k >= N) return;
-    const uint32_t item = blockIdx.y, b = item / polys, p = item % polys;
-    tmp[(size_t)item * N + k] = inp[b][((size_t)p * l + (l - 1)) * N + k];
+    const uint32_t j = blockIdx.y + y0, b = j / polys, p = j % polys;
+    const uint32_t l = (uint32_t)(uintptr_t)tab[2 * n + b];
+    tmp[(size_t)j * N + k] = tab[b][((size_t)p * l + (l - 1)) * N + k];
 }
 // Step 2: the last limb r (coefficient domain, mod q_last) lifted to (-q_last/2, q_last/2]
-// and reduced mod q_i for i < l-1: dst [n*P][l-1][N].
-__global__ void k_spread_centered(const uint64_t *__restrict__ r, uint64_t *__restrict__ dst,
-                                  const ModQ *__restrict__ mods, uint32_t logN, uint32_t l)
+// and reduced mod q_i for i < l-1, into the spread limb of the entry.
+__global__ void k_spread_centered(uint64_t *const *__restrict__ tab, uint32_t n, uint32_t polys, uint32_t sp,
+                                  const uint64_t *__restrict__ r, uint64_t *__restrict__ dst,
+                                  const ModQ *__restrict__ mods, uint32_t logN, uint32_t y0)
 {
     const uint32_t N = 1u << logN;
     const uint32_t k = blockIdx.x * TPB + threadIdx.x;
     if (k >= N) return;
-    const uint32_t limb = blockIdx.y, item = blockIdx.z, lo = l - 1;
+    const uint32_t y = blockIdx.y + y0;
+    const uint64_t e = (uint64_t)(uintptr_t)tab[sp + y];
+    const uint32_t j = (uint32_t)(e >> 16), limb = (uint32_t)(e & 0xFFFF);
+    const uint32_t l = (uint32_t)(uintptr_t)tab[2 * n + j / polys];
     const double ql = mods[l - 1].q;
-    double v = u64_to_f64(r[(size_t)item * N + k]);
+    double v = u64_to_f64(r[(size_t)j * N + k]);
     v = v > 0.5 * ql ? v - ql : v;   // centered lift (q_last odd: no ties)
     const double q = mods[limb].q, qi = mods[limb].qinv;
-    dst[((size_t)item * lo + limb) * N + k] = f64_to_u64(canon(v, q, qi));
+    dst[(size_t)y * N + k] = f64_to_u64(canon(v, q, qi));
 }
 // Step 3: out = (c - s) * q_last^-1 mod q_i.
-__global__ void k_rescale_fin(uint64_t *const *__restrict__ inp, const uint64_t *__restrict__ s,
-                              uint64_t *const *__restrict__ outp, const ModQ *__restrict__ mods,
-                              const double *__restrict__ qlinv_row, uint32_t logN, uint32_t l, uint32_t polys)
+__global__ void k_rescale_fin(uint64_t *const *__restrict__ tab, uint32_t n, uint32_t polys, uint32_t sp,
+                              const uint64_t *__restrict__ s, const ModQ *__restrict__ mods,
+                              const double *__restrict__ qlinv, uint32_t L, uint32_t logN, uint32_t y0)
 {
     const uint32_t N = 1u << logN;
     const uint32_t k = blockIdx.x * TPB + threadIdx.x;
     if (k >= N) return;
-    const uint32_t limb = blockIdx.y, item = blockIdx.z, b = item / polys, p = item % polys, lo = l - 1;
+    const uint32_t y = blockIdx.y + y0;
+    const uint64_t e = (uint64_t)(uintptr_t)tab[sp + y];
+    const uint32_t j = (uint32_t)(e >> 16), limb = (uint32_t)(e & 0xFFFF), b = j / polys, p = j % polys;
+    const uint32_t l = (uint32_t)(uintptr_t)tab[2 * n + b], lo = l - 1;
     const double q = mods[limb].q, qi = mods[limb].qinv;
-    const double c = u64_to_f64(inp[b][((size_t)p * l + limb) * N + k]);
-    const double r = mulmod(c - u64_to_f64(s[((size_t)item * lo + limb) * N + k]), qlinv_row[limb], q, qi);
-    outp[b][((size_t)p * lo + limb) * N + k] = f64_to_u64(fold(r, q));
+    const double c = u64_to_f64(tab[b][((size_t)p * l + limb) * N + k]);
+    const double r = mulmod(c - u64_to_f64(s[(size_t)y * N + k]), qlinv[(size_t)(l - 1) * L + limb], q, qi);
+    tab[n + b][((size_t)p * lo + limb) * N + k] = f64_to_u64(fold(r, q));
+}
+// NTT-domain automorphism over a batch: table [in: n][out: n][lvl: n][gal: n][list]
+// with list entries (b*P + p) << 16 | limb; out[x] = in[galois_src(x)].
+__global__ void k_automorph_batch(uint64_t *const *__restrict__ tab, uint32_t n, uint32_t polys, uint32_t lst,
+                                  uint32_t logN, uint32_t y0)
+{
+    const uint32_t N = 1u << logN;
+    const uint32_t x = blockIdx.x * TPB + threadIdx.x;
+    if (x >= N) return;
+    const uint64_t e = (uint64_t)(uintptr_t)tab[lst + blockIdx.y + y0];
+    const uint32_t j = (uint32_t)(e >> 16), limb = (uint32_t)(e & 0xFFFF), b = j / polys, p = j % polys;
+    const uint32_t l = (uint32_t)(uintptr_t)tab[2 * n + b];
+    const uint32_t g = (uint32_t)(uintptr_t)tab[3 * n + b];
+    const size_t off = ((size_t)p * l + limb) * N;
+    const uint32_t ex = 2u * (__brev(x) >> (32 - logN)) + 1u;
+    const uint32_t ey = (uint32_t)(((uint64_t)ex * g) & (2u * N - 1));
+    const uint32_t y = __brev((ey - 1u) >> 1) >> (32 - logN);
+    tab[n + b][off + x] = tab[b][off + y];
 }
 
 }  // namespace
@@ -156,35 +184,111 @@ size_t rescale_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t polys, uint3
 {
     return (size_t)n * polys * ((size_t)l) * c->N * sizeof(uint64_t);   // last limbs + spread limbs
 }
-// Rescale n ciphertexts (polys each, l limbs) into outputs (l-1 limbs); outputs must not overlap inputs.
-fhe_status rescale_run(fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n, const uint64_t *const *in,
-                       uint64_t *const *out, uint8_t *scr)
+size_t rescale_scratch_bytes_ragged(const fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls)
 {
+    size_t limbs = 0;
+    for (uint32_t b = 0; b < n; ++b) limbs += (size_t)polys * ls[b];
+    return limbs * c->N * sizeof(uint64_t);
+}
+template <typename F>
+static void in_pieces(uint32_t total, F f)
+{
+    for (uint32_t y0 = 0; y0 < total; y0 += 65535u) f(y0, std::min(65535u, total - y0));
+}
+// Rescale a ragged batch into outputs (l_b - 1 limbs); outputs must not overlap inputs.
+fhe_status rescale_run_ragged(fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls, const uint64_t *const *in,
+                              uint64_t *const *out, uint8_t *scr)
+{
+    if (!n) return FHE_OK;
     const size_t N = c->N;
     fhe_status s;
     std::vector<uint64_t *> tab;
     for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)in[b]);
     for (uint32_t b = 0; b < n; ++b) tab.push_back(out[b]);
+    for (uint32_t b = 0; b < n; ++b) {
+        if (ls[b] < 2 || ls[b] > c->L) return fhe_fail(FHE_ELEVEL, "rescale: limb count out of range");
+        tab.push_back((uint64_t *)(uintptr_t)ls[b]);
+    }
+    const uint32_t lastoff = (uint32_t)tab.size();
+    for (uint32_t b = 0; b < n; ++b)
+        for (uint32_t p = 0; p < polys; ++p)
+            tab.push_back((uint64_t *)(uintptr_t)((((uint64_t)(b * polys + p)) << 16) | (ls[b] - 1)));
+    const uint32_t sp = (uint32_t)tab.size();
+    for (uint32_t b = 0; b < n; ++b)
+        for (uint32_t p = 0; p < polys; ++p)
+            for (uint32_t i = 0; i + 1 < ls[b]; ++i)
+                tab.push_back((uint64_t *)(uintptr_t)((((uint64_t)(b * polys + p)) << 16) | i));
+    const uint32_t nsp = (uint32_t)tab.size() - sp, items = n * polys;
+    if ((uint64_t)items >= (1u << 16) * 1024ull) return fhe_fail(FHE_EINVAL, "rescale batch too large");
     uint64_t **dt;
     if ((s = ctx_ptr_table(c, tab, &dt))) return s;
-    uint64_t *last = (uint64_t *)scr, *spread = last + (size_t)n * polys * N;
-    const uint32_t gx = blocks_for(N, TPB), items = n * polys;
-    if (items > 65535u) return fhe_fail(FHE_EINVAL, "rescale batch too large for one launch");
+    const uint64_t *dw = (const uint64_t *)dt;
+    uint64_t *last = (uint64_t *)scr, *spread = last + (size_t)items * N;
+    const uint32_t gx = blocks_for(N, TPB);
     ProfScope ps(c, "rescale");
-    hipLaunchKernelGGL(k_gather_last, dim3(gx, items), dim3(TPB), 0, c->stream, (uint64_t *const *)dt, last, c->logN,
-                       l, polys);
-    uint32_t m1 = l - 1;
-    launch_ntt_inv(c, limbset_list(last, &m1, 1), items);
-    hipLaunchKernelGGL(k_spread_centered, dim3(gx, l - 1, items), dim3(TPB), 0, c->stream, (const uint64_t *)last,
-                       spread, (const ModQ *)c->d_mod, c->logN, l);
+    in_pieces(items, [&](uint32_t y0, uint32_t cnt) {
+        hipLaunchKernelGGL(k_gather_last, dim3(gx, cnt), dim3(TPB), 0, c->stream, (uint64_t *const *)dt, n, polys,
+                           last, c->logN, y0);
+    });
     {
-        uint32_t m[FHE_LIMBTAB];
-        for (uint32_t i = 0; i < l - 1; ++i) m[i] = i;
-        launch_ntt_fwd(c, limbset_list(spread, m, l - 1), items * (l - 1));
+        LimbSet ls_last;
+        std::memset((void *)&ls_last, 0, sizeof(ls_last));
+        ls_last.base = last;
+        ls_last.period = 1;
+        ls_last.modlist = dw + lastoff;
+        launch_ntt_inv(c, ls_last, items);
     }
-    hipLaunchKernelGGL(k_rescale_fin, dim3(gx, l - 1, items), dim3(TPB), 0, c->stream, (uint64_t *const *)dt,
-                       (const uint64_t *)spread, (uint64_t *const *)(dt + n), (const ModQ *)c->d_mod,
-                       (const double *)(c->d_qlinv + (size_t)(l - 1) * c->L), c->logN, l, polys);
+    in_pieces(nsp, [&](uint32_t y0, uint32_t cnt) {
+        hipLaunchKernelGGL(k_spread_centered, dim3(gx, cnt), dim3(TPB), 0, c->stream, (uint64_t *const *)dt, n, polys,
+                           sp, (const uint64_t *)last, spread, (const ModQ *)c->d_mod, c->logN, y0);
+    });
+    {
+        LimbSet ls_sp;
+        std::memset((void *)&ls_sp, 0, sizeof(ls_sp));
+        ls_sp.base = spread;
+        ls_sp.period = 1;
+        ls_sp.modlist = dw + sp;
+        launch_ntt_fwd(c, ls_sp, nsp);
+    }
+    in_pieces(nsp, [&](uint32_t y0, uint32_t cnt) {
+        hipLaunchKernelGGL(k_rescale_fin, dim3(gx, cnt), dim3(TPB), 0, c->stream, (uint64_t *const *)dt, n, polys, sp,
+                           (const uint64_t *)spread, (const ModQ *)c->d_mod, (const double *)c->d_qlinv, c->L,
+                           c->logN, y0);
+    });
+    HIPCHK(hipGetLastError());
+    return FHE_OK;
+}
+fhe_status rescale_run(fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n, const uint64_t *const *in,
+                       uint64_t *const *out, uint8_t *scr)
+{
+    std::vector<uint32_t> ls(n, l);
+    return rescale_run_ragged(c, polys, n, ls.data(), in, out, scr);
+}
+
+// Batched NTT-domain automorphisms: out[b] = sigma_g[b](in[b]) over polys x ls[b] limbs.
+fhe_status automorph_run(fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls, const uint32_t *gal,
+                         const uint64_t *const *in, uint64_t *const *out)
+{
+    if (!n) return FHE_OK;
+    std::vector<uint64_t *> tab;
+    for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)in[b]);
+    for (uint32_t b = 0; b < n; ++b) tab.push_back(out[b]);
+    for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)(uintptr_t)ls[b]);
+    for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)(uintptr_t)gal[b]);
+    const uint32_t lst = (uint32_t)tab.size();
+    for (uint32_t b = 0; b < n; ++b)
+        for (uint32_t p = 0; p < polys; ++p)
+            for (uint32_t i = 0; i < ls[b]; ++i)
+                tab.push_back((uint64_t *)(uintptr_t)((((uint64_t)(b * polys + p)) << 16) | i));
+    const uint32_t cnt = (uint32_t)tab.size() - lst;
+    uint64_t **dt;
+    fhe_status s;
+    if ((s = ctx_ptr_table(c, tab, &dt))) return s;
+    ProfScope ps(c, "automorph");
+    in_pieces(cnt, [&](uint32_t y0, uint32_t k) {
+        hipLaunchKernelGGL(k_automorph_batch, dim3(blocks_for(c->N, TPB), k), dim3(TPB), 0, c->stream,
+                           (uint64_t *const *)dt, n, polys, lst, c->logN, y0);
+    });
     HIPCHK(hipGetLastError());
     return FHE_OK;
 }
@@ -488,40 +592,55 @@ void launch_automorph(fhe_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nl
 }
 
 // n rotations (NTT-domain automorphism of the whole ciphertext, then a key
-// switch of the permuted c1 with the permuted c0 as addend), in chunks whose
-// scratch stays near 4 GiB.  Outputs must not overlap inputs.
-fhe_status rotate_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *in, const fhe_evk *const *keys,
-                      uint64_t *const *out)
+// switch of the permuted c1 with the permuted c0 as addend), items at levels
+// ls[b], in chunks whose scratch stays near 4 GiB.  Outputs must not overlap inputs.
+fhe_status rotate_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *in,
+                             const fhe_evk *const *keys, uint64_t *const *out)
 {
-    if (!n) return FHE_OK;
-    const size_t per = (size_t)l * c->N;
-    const size_t item = ks_scratch_bytes(c, l, 1) + 2 * per * sizeof(uint64_t);
-    const uint32_t C = (uint32_t)std::max<size_t>(1, std::min<size_t>(n, ((size_t)4 << 30) / item));
-    const size_t ksb = ks_scratch_bytes(c, l, C);
-    uint8_t *scr;
+    const size_t N = c->N, cap = (size_t)4 << 30;
     fhe_status s;
-    if ((s = ctx_scratch(c, ksb + 2 * per * C * sizeof(uint64_t), &scr))) return s;
-    uint64_t *perm = (uint64_t *)(scr + ksb);
-    std::vector<const uint64_t *> dd(C), ek(C), ad(2 * (size_t)C, nullptr);
-    std::vector<uint64_t *> oo(C);
-    for (uint32_t b0 = 0; b0 < n; b0 += C) {
-        const uint32_t cn = std::min(C, n - b0);
-        {
-            ProfScope ps(c, "automorph");
-            for (uint32_t b = 0; b < cn; ++b) {
-                uint64_t *pb = perm + (size_t)b * 2 * per;
-                hipLaunchKernelGGL(k_automorph, dim3(blocks_for(2 * per, TPB)), dim3(TPB), 0, c->stream,
-                                   in[b0 + b], pb, c->logN, (uint64_t)2 * l, (uint32_t)keys[b0 + b]->galois);
-                dd[b] = pb + per;
-                ad[2 * b] = pb;
-                ek[b] = keys[b0 + b]->d;
-                oo[b] = out[b0 + b];
-            }
+    for (uint32_t b0 = 0; b0 < n;) {
+        // grow the chunk while it fits
+        uint32_t cn = 0;
+        size_t bytes = 0;
+        while (b0 + cn < n && cn < 16384) {
+            const size_t item = ks_scratch_bytes(c, ls[b0 + cn], 1) + 2 * (size_t)ls[b0 + cn] * N * sizeof(uint64_t);
+            if (cn && bytes + item > cap) break;
+            bytes += item;
+            ++cn;
         }
-        if ((s = ks_run(c, l, cn, dd.data(), nullptr, ek.data(), oo.data(), ad.data(), scr))) return s;
+        const size_t ksb = ks_scratch_bytes_ragged(c, cn, ls + b0);
+        uint8_t *scr;
+        if ((s = ctx_scratch(c, bytes, &scr))) return s;
+        uint64_t *perm = (uint64_t *)(scr + ksb);
+        std::vector<const uint64_t *> dd(cn), ek(cn), ad(2 * (size_t)cn, nullptr), ip(cn);
+        std::vector<uint64_t *> oo(cn), pp(cn);
+        std::vector<uint32_t> gal(cn);
+        size_t off = 0;
+        for (uint32_t b = 0; b < cn; ++b) {
+            const size_t per = (size_t)ls[b0 + b] * N;
+            uint64_t *pb = perm + off;
+            off += 2 * per;
+            pp[b] = pb;
+            ip[b] = in[b0 + b];
+            gal[b] = (uint32_t)keys[b0 + b]->galois;
+            dd[b] = pb + per;
+            ad[2 * b] = pb;
+            ek[b] = keys[b0 + b]->d;
+            oo[b] = out[b0 + b];
+        }
+        if ((s = automorph_run(c, 2, cn, ls + b0, gal.data(), ip.data(), pp.data()))) return s;
+        if ((s = ks_run_ragged(c, cn, ls + b0, dd.data(), nullptr, ek.data(), oo.data(), ad.data(), scr))) return s;
+        b0 += cn;
     }
     c->ops[OP_ROTATE] += n;
     return FHE_OK;
+}
+fhe_status rotate_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *in, const fhe_evk *const *keys,
+                      uint64_t *const *out)
+{
+    std::vector<uint32_t> ls(n, l);
+    return rotate_run_ragged(c, n, ls.data(), in, keys, out);
 }
 
 // Residues of the integer round(v) (|round(v)| < 2^62) on limbs 0..limbs-1.

@@ -42,6 +42,23 @@ class fhe_evk(C.Structure):
     _fields_ = [("d", C.c_void_p), ("galois", C.c_uint64)]
 
 
+class fhe_op(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("step", C.c_int32), ("a", C.POINTER(fhe_ct)), ("b", C.POINTER(fhe_ct)),
+                ("key", C.POINTER(fhe_evk)), ("out", C.POINTER(fhe_ct))]
+
+
+OP_MUL_RELIN_RESCALE, OP_ROTATE = 1, 2
+
+
+class BatchOp:
+    """One entry of a work list for Context.batch_run: kind OP_MUL_RELIN_RESCALE
+    (a, b, key = relinearisation key) or OP_ROTATE (a, step, key = Galois key);
+    out is allocated when None.  a (and b) may be the out of an earlier entry."""
+
+    def __init__(self, kind, a, key, b=None, step=0, out=None):
+        self.kind, self.a, self.b, self.key, self.step, self.out = kind, a, b, key, int(step), out
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError("libfhe.so is not built (run paper_2102_00319_amd/build.py or __graft_entry__.build())")
 _lib = C.CDLL(LIB_PATH)
@@ -88,6 +105,7 @@ _sig = {
     "fhe_encrypt_const_batch": [_P, C.POINTER(fhe_ct), _P, C.c_uint32, C.c_double, _P, C.POINTER(fhe_ct)],
     "fhe_profile_read": [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)],
     "fhe_add_const": [_P, C.POINTER(fhe_ct), C.c_double, C.POINTER(fhe_ct)],
+    "fhe_batch_run": [_P, C.POINTER(fhe_op), C.c_uint32],
     "fhe_conv2d_packed": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_evk), C.c_uint32, C.POINTER(fhe_ct), C.c_uint32,
                           C.POINTER(fhe_ct), C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_poly_act": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), C.c_uint32, C.POINTER(C.c_double), C.c_uint32,
@@ -571,6 +589,36 @@ class Context:
         _check(_lib.fhe_add_const(self._h, C.byref(x), float(value), C.byref(o)))
         out.scale = o.scale
         return out
+
+    def batch_run(self, ops):
+        """Run a work list (BatchOp entries) through fhe_batch_run; returns the outputs."""
+        for op in ops:
+            if op.out is None:
+                lv = op.a.limbs - 1 if op.kind == OP_MUL_RELIN_RESCALE else op.a.limbs
+                op.out = self.new_ct(lv, 2)
+        descs, keys = {}, {}
+
+        def d(ct):
+            if id(ct) not in descs:
+                descs[id(ct)] = ct.s()
+            return C.pointer(descs[id(ct)])
+
+        def k(key):
+            if id(key) not in keys:
+                keys[id(key)] = key.s()
+            return C.pointer(keys[id(key)])
+        arr = (fhe_op * max(1, len(ops)))()
+        for i, op in enumerate(ops):
+            arr[i].kind = op.kind
+            arr[i].step = op.step
+            arr[i].a = d(op.a)
+            arr[i].b = d(op.b) if op.b is not None else C.POINTER(fhe_ct)()
+            arr[i].key = k(op.key)
+            arr[i].out = d(op.out)
+        _check(_lib.fhe_batch_run(self._h, arr, len(ops)))
+        for op in ops:
+            op.out.scale = descs[id(op.out)].scale
+        return [op.out for op in ops]
 
     def mul_relin_rescale(self, rlk, a, b):
         return self.rescale(self.relin(rlk, self.mul(a, b)))

@@ -74,3 +74,23 @@ def uniform_residues(seed, moduli, n):
 
 def small_ints(seed, n, bound):
     return rng(seed).integers(-bound, bound + 1, size=n, dtype=np.int64)
+
+
+# Batched uneven workload: independent jobs over three ring degrees, each job
+# multiplies two fresh ciphertexts at a random level, relinearises, rescales and
+# rotates the product by +1, -1, +ROW, -ROW (ROW = 28, one image row).
+UNEVEN_SETS = ("c3_n13", "c2_n14", "c3_n15")
+UNEVEN_ROW = 28
+UNEVEN_STEPS = (1, -1, UNEVEN_ROW, -UNEVEN_ROW)
+
+
+def uneven_jobs(seed=SEED_BATCH, n_jobs=256, sets=UNEVEN_SETS):
+    """List of (parameter set, level) per job: set uniform over `sets`, level
+    uniform in 2 .. L of that set."""
+    g = rng(seed)
+    Ls = [len(load_params(s)["q"]) for s in sets]
+    out = []
+    for _ in range(n_jobs):
+        i = int(g.integers(0, len(sets)))
+        out.append((sets[i], int(g.integers(2, Ls[i] + 1))))
+    return out
