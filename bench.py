@@ -42,9 +42,10 @@ def parse():
     ap.add_argument("--batch", type=int, default=8, help="rotations (distinct keys) per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--param-set", default="c4_n16")
-    ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "cnn2", "cnn4"],
+    ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "cnn2", "cnn4", "batch3"],
                     help="keyswitch: the headline metric; cnn2: slot-packed encrypted CNN images/s; "
-                         "cnn4: within-image packed deep CNN images/s")
+                         "cnn4: within-image packed deep CNN images/s; batch3: 256 uneven jobs (mixed N and "
+                         "level) per step")
     ap.add_argument("--fc1", type=int, default=100, help="cnn2: FC1 width (100 = the full network)")
     ap.add_argument("--unbatched", action="store_true", help="cnn2: also time the one-ciphertext-per-call form")
     return ap.parse_args()
@@ -192,6 +193,99 @@ def cnn4(args):
     print(json.dumps(rec))
 
 
+def batch3(args):
+    """Batched uneven workload: 256 independent jobs, ring degree uniform over
+    {2^13, 2^14, 2^15}, level uniform in 2..L; each job multiplies two fresh
+    ciphertexts, relinearises, rescales and rotates the product by +-1 and +-28.
+    One step = the whole batch (256 products + 1024 rotations = 1280 key switches),
+    scheduled by the autotuner; compared with the one-operation-per-call form."""
+    import torch
+
+    import workloads
+    import paper_2102_00319_amd as P
+    from paper_2102_00319_amd import runtime
+
+    torch.cuda.set_device(0)
+    spec = workloads.uneven_jobs(workloads.SEED_BATCH, 256)
+    steps = workloads.UNEVEN_STEPS
+    t_setup = time.perf_counter()
+    ctxs, keys = {}, {}
+    for name in workloads.UNEVEN_SETS:
+        g = P.Context.from_set(name, stream=torch.cuda.Stream())
+        s = g.keygen_secret(workloads.SEED_SECRET)
+        pk = g.keygen_pk(s, workloads.SEED_PK)
+        rlk = g.keygen_relin(s, workloads.SEED_EVK)
+        keys[name] = (rlk, {r: g.keygen_rot(s, r, workloads.SEED_EVK + 1 + i) for i, r in enumerate(steps)})
+        ctxs[name] = (g, pk)
+    jobs = []
+    for j, (name, l) in enumerate(spec):
+        g, pk = ctxs[name]
+        a = g.encrypt(pk, g.encode(workloads.slot_messages(workloads.SEED_DATA + 2 * j, 64), scale=g.scale, limbs=l),
+                      workloads.SEED_ENC + 2 * j)
+        b = g.encrypt(pk, g.encode(workloads.slot_messages(workloads.SEED_DATA + 2 * j + 1, 64), scale=g.scale,
+                                   limbs=l), workloads.SEED_ENC + 2 * j + 1)
+        jobs.append((name, a, b))
+    ctxs = {n: v[0] for n, v in ctxs.items()}
+    ub = runtime.UnevenBatch(ctxs, keys, jobs, steps)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+
+    # one operation per call (every context on its own stream, operations in job order)
+    def unbatched():
+        outs = []
+        for name, a, b in jobs:
+            g = ctxs[name]
+            rlk, gks = keys[name]
+            m = g.rescale(g.relin(rlk, g.mul(a, b)))
+            outs.append([m] + [g.rotate(gks[r], m, r) for r in steps])
+        return outs
+    ref = unbatched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    unbatched()
+    torch.cuda.synchronize()
+    t_unb = time.perf_counter() - t0
+
+    tuner = runtime.Autotuner()
+    best, times = tuner.tune(ub.signature(), ub.candidates(), lambda c: ub.time(c, reps=3))
+    for _ in range(args.warmup):
+        ub.run(best)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ub.run(best)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    same = all(torch.equal(ub.products[j].data, ref[j][0].data) and
+               all(torch.equal(ub.rotations[j][i].data, ref[j][1 + i].data) for i in range(len(steps)))
+               for j in range(len(jobs)))
+    # algorithmic bytes of one step: every operation reads its inputs and the key
+    # limbs it uses (Q_l and P of each digit) and writes its output
+    nbytes = 0
+    for name, a, b in jobs:
+        g = ctxs[name]
+        limb = g.N * 8
+        l = a.limbs
+
+        def key_limbs(lv):
+            return 2 * ((lv + g.alpha - 1) // g.alpha) * (lv + g.K)
+        nbytes += limb * (4 * l + key_limbs(l) + 2 * (l - 1))
+        nbytes += len(steps) * limb * (4 * (l - 1) + key_limbs(l - 1))
+    ub.close()
+    n_ks = len(jobs) * (1 + len(steps))
+    rec = {"metric": "uneven batch: jobs/s (HMult+relin+rescale+4 rotations per job)",
+           "value": round(len(jobs) / dt, 1), "unit": "jobs/s", "ms_per_step": round(dt * 1e3, 3),
+           "key_switches_per_s": round(n_ks / dt, 1), "steps": args.steps, "warmup": args.warmup,
+           "unbatched_jobs_per_s": round(len(jobs) / t_unb, 1), "unbatched_ms": round(t_unb * 1e3, 2),
+           "speedup_vs_unbatched": round(t_unb / dt, 2), "batched_equals_unbatched_bitwise": bool(same),
+           "hbm_frac_algorithmic": round(nbytes / dt / (HBM_PEAK_GBS * 1e9), 4),
+           "algorithmic_bytes_per_step": nbytes, "autotuned": best,
+           "autotune_ms": {k: round(v * 1e3, 3) for k, v in times.items()}, "setup_s": round(t_setup, 1),
+           "config": {"workload": "256 jobs, N in {2^13, 2^14, 2^15}, levels uniform 2..L, steps +-1, +-28",
+                      "jobs_per_ring": {n: sum(1 for s_, _ in spec if s_ == n) for n in ctxs}}}
+    print(json.dumps(rec))
+
+
 def cnn2(args):
     """Slot-packed encrypted CNN (8192 images per ciphertext): conv 5x5 stride 2 x 5
     channels -> x^2 -> FC 845->fc1 -> x^2 -> FC fc1->10; images and weights encrypted."""
@@ -281,6 +375,8 @@ def main():
         return cnn2(args)
     if args.workload == "cnn4":
         return cnn4(args)
+    if args.workload == "batch3":
+        return batch3(args)
     import numpy as np
     import torch
 

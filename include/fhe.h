@@ -192,6 +192,27 @@ typedef struct {
 } fhe_op;
 fhe_status fhe_batch_run(fhe_ctx *ctx, const fhe_op *ops, uint32_t n_ops);
 
+/* ------------------------------------------------------------ HIP graphs
+ * Capture the work that library calls enqueue on the streams of ctxs[0..n)
+ * (distinct contexts, e.g. one per ring degree, each on its own stream) into one
+ * graph, then replay it with fhe_graph_launch.  Between begin and end calls only
+ * enqueue work: the pointer tables they build go to an arena of table_bytes per
+ * context (0: 16 MiB) that the graph owns, and their scratch must already have
+ * been sized by the same calls run once eagerly (else FHE_ENOMEM and the capture
+ * fails at fhe_graph_end).  At fhe_graph_end the contexts' scratch buffers pass
+ * to the graph.  Replays read and write the device buffers of the captured
+ * calls; operation counters count the capture, not the replays.  Profiling must
+ * be off.  On any failure fhe_graph_end frees the graph and returns the error. */
+typedef struct fhe_graph fhe_graph;
+fhe_status fhe_graph_begin(fhe_ctx *const *ctxs, uint32_t n, uint64_t table_bytes, fhe_graph **out);
+fhe_status fhe_graph_end(fhe_ctx *const *ctxs, uint32_t n, fhe_graph *g);
+fhe_status fhe_graph_launch(fhe_graph *g, void *hip_stream);   /* null: the first context's stream */
+void fhe_graph_destroy(fhe_graph *g);                          /* waits for the device first */
+
+/* Tuning knobs read by the batched drivers (autotuned by the Python layer):
+ *   "chunk_items": most items per ragged launch sequence (0 = no limit). */
+fhe_status fhe_ctx_set_tuning(fhe_ctx *ctx, const char *key, uint64_t value);
+
 /* Batched relinearisation and rescale of n ciphertexts (host descriptor arrays;
  * one key; rescale outputs must not overlap their inputs). */
 fhe_status fhe_relin_batch(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *in3, uint32_t n, fhe_ct *out2);

@@ -80,7 +80,8 @@ fhe_status run_mrr(fhe_ctx *c, const std::vector<const fhe_op *> &g)
     fhe_status s;
     for (size_t t0 = 0; t0 < g.size();) {
         size_t cn = 0, bytes = 0;
-        while (t0 + cn < g.size() && cn < 16384) {
+        const size_t lim = c->tune_chunk ? c->tune_chunk : 16384;
+        while (t0 + cn < g.size() && cn < lim) {
             const uint32_t l = g[t0 + cn]->a->limbs;
             const size_t item = ks_scratch_bytes(c, l, 1) + 5 * (size_t)l * LB + rescale_scratch_bytes(c, l, 2, 1);
             if (cn && bytes + item > cap) break;

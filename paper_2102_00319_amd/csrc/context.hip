@@ -140,6 +140,7 @@ static void prof_collect(fhe_ctx *c)
 
 extern "C" fhe_status fhe_profile_enable(fhe_ctx *c, const char *category)
 {
+    if (c && c->capturing && category) return fhe_fail(FHE_EINVAL, "fhe_profile_enable: context is capturing");
     if (!c) return fhe_fail(FHE_EINVAL, "null context");
     if (!category) {
         if (c->prof) {
@@ -335,9 +336,19 @@ extern "C" void fhe_ctx_destroy(fhe_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     ctx_free_all(c);
 }
+extern "C" fhe_status fhe_ctx_set_tuning(fhe_ctx *c, const char *key, uint64_t value)
+{
+    if (!c || !key) return fhe_fail(FHE_EINVAL, "fhe_ctx_set_tuning: null argument");
+    if (!std::strcmp(key, "chunk_items")) {
+        c->tune_chunk = (uint32_t)std::min<uint64_t>(value, 1u << 30);
+        return FHE_OK;
+    }
+    return fhe_fail(FHE_EINVAL, std::string("fhe_ctx_set_tuning: unknown key ") + key);
+}
 extern "C" fhe_status fhe_set_stream(fhe_ctx *c, void *s)
 {
     if (!c) return fhe_fail(FHE_EINVAL, "null context");
+    if (c->capturing) return fhe_fail(FHE_EINVAL, "fhe_set_stream: context is capturing");
     c->stream = (hipStream_t)s;
     return FHE_OK;
 }
@@ -361,6 +372,10 @@ extern "C" uint64_t fhe_scratch_bytes(const fhe_ctx *c) { return c ? c->scratch_
 fhe_status ctx_scratch(fhe_ctx *c, size_t bytes, uint8_t **out)
 {
     bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes > c->scratch_bytes && c->capturing) {
+        c->cap_error = FHE_ENOMEM;
+        return fhe_fail(FHE_ENOMEM, "graph capture: device memory must be sized by an eager run first");
+    }
     if (bytes > c->scratch_bytes) {
         size_t grow = bytes - c->scratch_bytes;
         if (c->used + grow > c->budget) return fhe_fail(FHE_ENOMEM, "scratch exceeds the HBM budget");
@@ -382,6 +397,10 @@ fhe_status ctx_scratch(fhe_ctx *c, size_t bytes, uint8_t **out)
 fhe_status ctx_workspace(fhe_ctx *c, size_t bytes, uint8_t **out)
 {
     bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes > c->wksp_bytes && c->capturing) {
+        c->cap_error = FHE_ENOMEM;
+        return fhe_fail(FHE_ENOMEM, "graph capture: device memory must be sized by an eager run first");
+    }
     if (bytes > c->wksp_bytes) {
         size_t grow = bytes - c->wksp_bytes;
         if (c->used + grow > c->budget) return fhe_fail(FHE_ENOMEM, "layer workspace exceeds the HBM budget");
@@ -404,6 +423,18 @@ fhe_status ctx_workspace(fhe_ctx *c, size_t bytes, uint8_t **out)
 fhe_status ctx_ptr_table(fhe_ctx *c, const std::vector<uint64_t *> &ptrs, uint64_t ***dev)
 {
     const size_t n = ptrs.size() ? ptrs.size() : 1;
+    if (c->capturing) {
+        // the graph replays these launches later: keep the table in the capture arena
+        const size_t off = (c->cap_used + 255) & ~(size_t)255, bytes = n * sizeof(uint64_t *);
+        if (off + bytes > c->cap_bytes) {
+            c->cap_error = FHE_ENOMEM;
+            return fhe_fail(FHE_ENOMEM, "graph capture: pointer-table arena is full");
+        }
+        std::memcpy(c->cap_host + off, ptrs.data(), ptrs.size() * sizeof(uint64_t *));
+        c->cap_used = off + bytes;
+        *dev = (uint64_t **)(c->cap_dev + off);
+        return FHE_OK;
+    }
     if (!c->d_ptrs) {
         HIPCHK(hipMalloc((void **)&c->d_ptrs, sizeof(uint64_t *) * PTR_SLOTS * PTR_SLOT_CAP));
         HIPCHK(hipHostMalloc((void **)&c->h_ptrs, sizeof(uint64_t *) * PTR_SLOTS * PTR_SLOT_CAP));

@@ -158,6 +158,13 @@ struct fhe_ctx {
     uint32_t ptr_next;
     uint64_t **d_big;        // oversize table (synchronous path)
     size_t d_big_cap;
+    // HIP graph capture (fhe_graph_begin .. fhe_graph_end): pointer tables go to a
+    // pinned arena whose device copy the graph owns; scratch may not grow
+    bool capturing;
+    int cap_error;
+    uint8_t *cap_host, *cap_dev;
+    size_t cap_bytes, cap_used;
+    uint32_t tune_chunk;     // most items per ragged launch sequence (0: no limit)
     struct Prof *prof;       // kernel timing (HIP events), null until enabled
     uint64_t ops[8];         // operation counters, see OP_* (read and reset by fhe_op_counts)
 };

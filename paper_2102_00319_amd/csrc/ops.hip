@@ -603,7 +603,8 @@ fhe_status rotate_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const u
         // grow the chunk while it fits
         uint32_t cn = 0;
         size_t bytes = 0;
-        while (b0 + cn < n && cn < 16384) {
+        const uint32_t lim = c->tune_chunk ? c->tune_chunk : 16384;
+        while (b0 + cn < n && cn < lim) {
             const size_t item = ks_scratch_bytes(c, ls[b0 + cn], 1) + 2 * (size_t)ls[b0 + cn] * N * sizeof(uint64_t);
             if (cn && bytes + item > cap) break;
             bytes += item;

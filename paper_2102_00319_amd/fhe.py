@@ -106,6 +106,10 @@ _sig = {
     "fhe_profile_read": [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)],
     "fhe_add_const": [_P, C.POINTER(fhe_ct), C.c_double, C.POINTER(fhe_ct)],
     "fhe_batch_run": [_P, C.POINTER(fhe_op), C.c_uint32],
+    "fhe_graph_begin": [_P, C.c_uint32, C.c_uint64, C.POINTER(_P)],
+    "fhe_graph_end": [_P, C.c_uint32, _P],
+    "fhe_graph_launch": [_P, _P],
+    "fhe_ctx_set_tuning": [_P, C.c_char_p, C.c_uint64],
     "fhe_conv2d_packed": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_evk), C.c_uint32, C.POINTER(fhe_ct), C.c_uint32,
                           C.POINTER(fhe_ct), C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_poly_act": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), C.c_uint32, C.POINTER(C.c_double), C.c_uint32,
@@ -121,6 +125,8 @@ for _n, _a in _sig.items():
 _lib.fhe_ctx_destroy.argtypes = [_P]
 _lib.fhe_ctx_destroy.restype = None
 _lib.fhe_last_error.restype = C.c_char_p
+_lib.fhe_graph_destroy.argtypes = [_P]
+_lib.fhe_graph_destroy.restype = None
 for _n, _r in [("fhe_ring_degree", C.c_uint32), ("fhe_modulus", C.c_uint64), ("fhe_evk_bytes", C.c_size_t),
                ("fhe_galois_elt", C.c_uint64), ("fhe_scratch_bytes", C.c_uint64)]:
     getattr(_lib, _n).restype = _r
@@ -137,7 +143,7 @@ def lib():
 
 def exported_symbols():
     return sorted(_sig) + ["fhe_ctx_destroy", "fhe_last_error", "fhe_ring_degree", "fhe_modulus", "fhe_evk_bytes",
-                           "fhe_galois_elt", "fhe_scratch_bytes"]
+                           "fhe_galois_elt", "fhe_scratch_bytes", "fhe_graph_destroy"]
 
 
 def _check(rc):
@@ -232,7 +238,18 @@ class Context:
 
     # -------------------------------------------------------- allocation
     def empty(self, *shape):
-        return torch.empty(shape, dtype=torch.int64, device=self.device)
+        # allocate on the context's stream, so that the caching allocator orders
+        # the reuse of freed blocks after this stream's kernels
+        if self.stream == torch.cuda.current_stream(self.device):
+            return torch.empty(shape, dtype=torch.int64, device=self.device)
+        with torch.cuda.stream(self.stream):
+            return torch.empty(shape, dtype=torch.int64, device=self.device)
+
+    def use_stream(self, stream):
+        """Enqueue this context's work on another torch stream from now on."""
+        torch.cuda.synchronize(self.device)
+        _check(_lib.fhe_set_stream(self._h, C.c_void_p(stream.cuda_stream)))
+        self.stream = stream
 
     def new_ct(self, limbs, polys=2, scale=1.0):
         return Ciphertext(self.empty(polys, limbs, self.N), scale)
@@ -242,6 +259,9 @@ class Context:
 
     def new_evk(self):
         return EvalKey(self.empty(self.dnum, 2, self.L + self.K, self.N), 0)
+
+    def set_tuning(self, key, value):
+        _check(_lib.fhe_ctx_set_tuning(self._h, key.encode(), int(value)))
 
     def galois_elt(self, step):
         return int(_lib.fhe_galois_elt(self._h, int(step)))
@@ -622,3 +642,45 @@ class Context:
 
     def mul_relin_rescale(self, rlk, a, b):
         return self.rescale(self.relin(rlk, self.mul(a, b)))
+
+
+class Graph:
+    """A captured HIP graph over one or more contexts (fhe_graph_*)."""
+
+    def __init__(self, handle, ctxs):
+        self._h = handle
+        self._ctxs = ctxs   # keep the contexts (and their device tables) alive
+
+    def launch(self, stream=None):
+        _check(_lib.fhe_graph_launch(self._h, None if stream is None else C.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.fhe_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def capture_graph(ctxs, fn, table_bytes=0):
+    """Capture the work fn() enqueues on the contexts' streams into one graph.
+    fn must only enqueue work on those contexts: outputs preallocated, scratch
+    already sized by the same calls run once eagerly."""
+    ctxs = list(ctxs)
+    arr = (C.c_void_p * len(ctxs))(*[c._h.value for c in ctxs])
+    h = C.c_void_p()
+    _check(_lib.fhe_graph_begin(arr, len(ctxs), int(table_bytes), C.byref(h)))
+    err = None
+    try:
+        fn()
+    except Exception as e:   # still end the capture, then report
+        err = e
+    rc = _lib.fhe_graph_end(arr, len(ctxs), h)
+    if err is not None:
+        raise err
+    _check(rc)
+    return Graph(h, ctxs)

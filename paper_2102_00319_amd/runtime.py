@@ -1,0 +1,146 @@
+"""Batched execution of uneven work (mixed ring degrees and levels) and the
+autotuner that picks its schedule.
+
+A work list is split per parameter set (one context, and one HIP stream, per
+ring degree); fhe_batch_run turns each context's list into a few ragged launch
+sequences.  The schedule has four knobs, chosen by measurement:
+  * graph:      eager launches, or one HIP graph captured over all contexts and
+                replayed (no host launch cost on the critical path);
+  * concurrent: contexts on their own streams (their launch sequences overlap on
+                the GPU) or all on one stream;
+  * chunk:      most items per ragged launch sequence (0 = all of a stage);
+  * order:      the order in which the contexts' lists are issued.
+"""
+import json
+import os
+import time
+
+import torch
+
+from .fhe import OP_MUL_RELIN_RESCALE, OP_ROTATE, BatchOp, capture_graph
+
+
+class Autotuner:
+    """Measures candidate configurations and keeps the fastest per workload key
+    (a JSON cache, FHE_TUNE_CACHE or a file beside this module)."""
+
+    def __init__(self, path=None):
+        self.path = path or os.environ.get("FHE_TUNE_CACHE",
+                                           os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                        ".tune_cache.json"))
+        try:
+            with open(self.path) as f:
+                self.cache = json.load(f)
+        except (OSError, ValueError):
+            self.cache = {}
+
+    def lookup(self, key):
+        e = self.cache.get(key)
+        return None if e is None else e["best"]
+
+    def tune(self, key, candidates, measure):
+        """measure(candidate) -> seconds; returns (best candidate, {name: seconds})."""
+        times = {}
+        for cand in candidates:
+            times[json.dumps(cand, sort_keys=True)] = measure(cand)
+        best_name = min(times, key=times.get)
+        best = json.loads(best_name)
+        self.cache[key] = {"best": best, "seconds": times}
+        try:
+            with open(self.path, "w") as f:
+                json.dump(self.cache, f, indent=1)
+        except OSError:
+            pass
+        return best, times
+
+
+class UnevenBatch:
+    """Jobs over several contexts; job = (context name, a, b): Rescale(Relin(a (x) b))
+    then rotations of the product by each of `steps`.  Outputs are allocated once."""
+
+    def __init__(self, ctxs, keys, jobs, steps):
+        self.ctxs = ctxs              # name -> Context (each with its own stream)
+        self.names = list(ctxs)
+        self.ops = {n: [] for n in ctxs}
+        self.products, self.rotations = [], []
+        for name, a, b in jobs:
+            g = ctxs[name]
+            rlk, gks = keys[name]
+            m = BatchOp(OP_MUL_RELIN_RESCALE, a, rlk, b=b, out=g.new_ct(a.limbs - 1, 2))
+            self.ops[name].append(m)
+            rot = []
+            for r in steps:
+                op = BatchOp(OP_ROTATE, m.out, gks[r], step=r, out=g.new_ct(a.limbs - 1, 2))
+                self.ops[name].append(op)
+                rot.append(op.out)
+            self.products.append(m.out)
+            self.rotations.append(rot)
+        self.streams = {n: ctxs[n].stream for n in ctxs}
+        self._graph = None
+        self._graph_cfg = None
+
+    def _apply(self, cfg):
+        order = cfg.get("order", self.names)
+        first = self.streams[order[0]]
+        for n in self.names:
+            s = self.streams[n] if cfg.get("concurrent", True) else first
+            if self.ctxs[n].stream is not s:
+                self.ctxs[n].use_stream(s)
+            self.ctxs[n].set_tuning("chunk_items", cfg.get("chunk", 0))
+        return order
+
+    def run_eager(self, cfg):
+        for n in self._apply(cfg):
+            self.ctxs[n].batch_run(self.ops[n])
+
+    def _issue(self, order):
+        for n in order:
+            self.ctxs[n].batch_run(self.ops[n])
+
+    def run(self, cfg):
+        """One pass over the whole batch with configuration cfg (asynchronous)."""
+        if not cfg.get("graph"):
+            self._graph_cfg = None
+            return self.run_eager(cfg)
+        if self._graph is None or self._graph_cfg != cfg:
+            order = self._apply(cfg)
+            self._issue(order)                    # eager run: sizes every scratch buffer
+            torch.cuda.synchronize()
+            if self._graph is not None:
+                self._graph.close()
+            self._graph = capture_graph([self.ctxs[n] for n in order], lambda: self._issue(order))
+            self._graph_cfg = cfg
+        self._graph.launch()
+
+    def close(self):
+        if self._graph is not None:
+            self._graph.close()
+            self._graph = None
+
+    def time(self, cfg, reps=3):
+        self.run(cfg)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            self.run(cfg)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        return ts[len(ts) // 2]
+
+    def candidates(self):
+        out = []
+        for graph in (False, True):
+            for conc in (True, False):
+                for chunk in (0, 64, 16):
+                    out.append({"graph": graph, "concurrent": conc, "chunk": chunk,
+                                "order": sorted(self.names, key=lambda n: -self.ctxs[n].N)})
+        return out
+
+    def signature(self):
+        parts = []
+        for n in sorted(self.ops):
+            lv = sorted(op.a.limbs for op in self.ops[n] if op.kind == OP_MUL_RELIN_RESCALE)
+            parts.append("%s:%s" % (n, ",".join(map(str, lv))))
+        return "uneven|" + "|".join(parts) + "|" + torch.cuda.get_device_name(0)
