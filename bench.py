@@ -42,12 +42,17 @@ def parse():
     ap.add_argument("--batch", type=int, default=8, help="rotations (distinct keys) per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--param-set", default="c4_n16")
-    ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "cnn2", "cnn4", "batch3"],
+    ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "cnn2", "cnn4", "batch3", "serve"],
                     help="keyswitch: the headline metric; cnn2: slot-packed encrypted CNN images/s; "
                          "cnn4: within-image packed deep CNN images/s; batch3: 256 uneven jobs (mixed N and "
                          "level) per step")
     ap.add_argument("--fc1", type=int, default=100, help="cnn2: FC1 width (100 = the full network)")
     ap.add_argument("--unbatched", action="store_true", help="cnn2: also time the one-ciphertext-per-call form")
+    ap.add_argument("--rates", default="1,2,5,10,20,50,100,200", help="serve: Poisson arrival rates (req/s)")
+    ap.add_argument("--requests", type=int, default=40, help="serve: requests per rate")
+    ap.add_argument("--budget-gb", type=float, default=250.0, help="serve: HBM budget for admission (GB)")
+    ap.add_argument("--lanes", type=int, default=4, help="serve: concurrent execution lanes")
+    ap.add_argument("--packed-clients", type=int, default=4, help="serve: deep-CNN clients")
     return ap.parse_args()
 
 
@@ -286,6 +291,88 @@ def batch3(args):
     print(json.dumps(rec))
 
 
+def serve(args):
+    """Serving: Poisson arrivals of encrypted inference requests, half for the
+    slot-packed CNN (N=2^14, one client, FC1 width --fc1) and half for the deep
+    within-image CNN (N=2^16, --packed-clients clients), 1-64 images each;
+    admission by HBM budget for client state (evaluation keys + encrypted
+    weights) and working sets, continuous batching over --lanes lanes, slot
+    merging of same-client requests.  Reports p50/p99 latency (arrival to
+    decrypted scores) and images/s per rate."""
+    import numpy as np
+    import torch
+
+    import workloads
+    import paper_2102_00319_amd as P
+    from paper_2102_00319_amd import networks, serving
+
+    torch.cuda.set_device(0)
+    t_setup = time.perf_counter()
+    sets = {"slot": "c2_n14", "packed": "c4_n16"}
+    setup = {k: P.Context.from_set(v) for k, v in sets.items()}
+    clients = []
+    kinds = ["slot"] + ["packed"] * args.packed_clients
+    for cid, kind in enumerate(kinds):
+        g = setup[kind]
+        base = workloads.MASTER_SEED + 10000 * (cid + 1)
+        if kind == "slot":
+            net = networks.SlotCNN(fc1=args.fc1)
+            w = (workloads.weights(base + 1, (5, 1, 5, 5)), workloads.weights(base + 2, (args.fc1, 845)),
+                 workloads.weights(base + 3, (10, args.fc1)))
+        else:
+            net = networks.PackedCNN()
+            w = (workloads.weights(base + 1, (8, 1, 3, 3)), workloads.weights(base + 2, (16, 8, 3, 3)),
+                 workloads.weights(base + 3, (10, 784)))
+        seeds = {"secret": base + 4, "pk": base + 5, "evk": base + 6, "weights": (base + 100, base + 200, base + 300)}
+        clients.append(serving.Client(cid, net, g, sets[kind], w, seeds))
+        torch.cuda.synchronize()
+    srv = serving.Server(list(sets.values()), lanes=args.lanes, hbm_budget=args.budget_gb * 1e9)
+    for c in clients:
+        srv.add_client(c)
+    # payload pools (client-side encryption happens before a request arrives)
+    pools = []
+    for c in clients:
+        g = setup[c.kind]
+        pool = []
+        for t in range(4):
+            n = int(workloads.rng(workloads.MASTER_SEED + 70000 + 10 * c.cid + t).integers(1, 65))
+            seed = workloads.MASTER_SEED + 50000 + 100 * c.cid + 10 * t
+            imgs = workloads.images(seed, n, 28, 28)
+            if c.kind == "slot":
+                pool.append((c.net.encrypt_images(g, c.pk, imgs, seed, slot_offset=64 * t), n, 64 * t))
+            else:
+                pay = [c.net.encrypt_images(g, c.pk, imgs[i:i + 32], seed + i)[0] for i in range(0, n, 32)]
+                pool.append((pay, n, 0))
+        pools.append(pool)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    state_gb = {c.cid: round(c.nbytes / 1e9, 2) for c in clients}
+    per_rate = []
+    for rate in [float(x) for x in args.rates.split(",")]:
+        g_ = workloads.rng(workloads.SEED_BATCH + int(rate * 10))
+        t, reqs = 0.0, []
+        for i in range(args.requests):
+            t += float(g_.exponential(1.0 / rate))
+            cid = 0 if g_.uniform() < 0.5 else 1 + int(g_.integers(0, args.packed_clients))
+            tag = int(g_.integers(0, 4))
+            pay, n, off = pools[cid][tag]
+            reqs.append(serving.Request(i, clients[cid], pay, n, off, t, tag))
+        srv.stats.clear()
+        srv.run(reqs, time_limit=600)
+        s = serving.summarize(reqs)
+        s.update({"rate_req_s": rate, "evictions": srv.stats["evictions"], "cold_loads": srv.stats["cold_loads"],
+                  "cold_load_s": round(srv.stats["cold_load_s"], 2)})
+        print(json.dumps({"serve_rate": s}), flush=True)
+        per_rate.append(s)
+    rec = {"metric": "encrypted inference serving: p50/p99 latency and images/s per arrival rate",
+           "unit": "ms / images/s", "per_rate": per_rate, "lanes": args.lanes, "hbm_budget_gb": args.budget_gb,
+           "client_state_gb": state_gb, "setup_s": round(t_setup, 1),
+           "config": {"workload": "Poisson arrivals, 50/50 slot-packed CNN (N=2^14, FC1 %d) and deep within-image "
+                                  "CNN (N=2^16), 1-64 images per request" % args.fc1,
+                      "clients": {"slot": 1, "packed": args.packed_clients}}}
+    print(json.dumps(rec))
+
+
 def cnn2(args):
     """Slot-packed encrypted CNN (8192 images per ciphertext): conv 5x5 stride 2 x 5
     channels -> x^2 -> FC 845->fc1 -> x^2 -> FC fc1->10; images and weights encrypted."""
@@ -377,6 +464,8 @@ def main():
         return cnn4(args)
     if args.workload == "batch3":
         return batch3(args)
+    if args.workload == "serve":
+        return serve(args)
     import numpy as np
     import torch
 

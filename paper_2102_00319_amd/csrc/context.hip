@@ -176,13 +176,14 @@ static void ctx_free_all(fhe_ctx *c)
 {
     if (c->prof) (void)fhe_profile_enable(c, nullptr);
     void *ptrs[] = {c->d_mod, c->d_tw, c->d_itw, c->d_ninv, c->d_cdt, c->d_cos, c->d_sin, c->d_g5,
-                    c->d_bconv, c->d_pinv, c->d_phalf, c->d_pmod, c->d_qlinv, c->scratch, c->wksp, c->d_ptrs, c->d_big};
+                    c->d_bconv, c->d_pinv, c->d_phalf, c->d_pmod, c->d_qlinv, c->scratch, c->wksp, c->tbl_dev, c->d_big};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    if (c->h_ptrs) {
-        (void)hipHostFree(c->h_ptrs);
-        for (int i = 0; i < PTR_SLOTS; ++i) (void)hipEventDestroy(c->ptr_ev[i]);
-    }
+    if (c->tbl_host) (void)hipHostFree(c->tbl_host);
+    for (auto &a : c->tbl_live) (void)hipEventDestroy(a.ev);
+    for (hipEvent_t e : c->tbl_pool) (void)hipEventDestroy(e);
+    c->tbl_live.clear();
+    c->tbl_pool.clear();
     delete[] c->modup;
     delete[] c->moddown;
     delete c;
@@ -198,8 +199,7 @@ extern "C" fhe_status fhe_ctx_create(const fhe_params *pp, void *hip_stream, uin
     if (L < 1 || L + K > FHE_MAXMOD || pp->dnum < 1 || pp->dnum > L)
         return fhe_fail(FHE_EPARAM, "need 1 <= n_q, n_q + n_p <= 64, 1 <= dnum <= n_q");
     const uint32_t N = 1u << logN;
-    fhe_ctx *c = new fhe_ctx();
-    std::memset((void *)c, 0, sizeof(fhe_ctx));
+    fhe_ctx *c = new fhe_ctx();   // value-initialised: plain fields zero, containers constructed
     c->logN = logN; c->N = N; c->L = L; c->K = K; c->dnum = pp->dnum;
     c->alpha = (L + pp->dnum - 1) / pp->dnum;
     c->stream = (hipStream_t)hip_stream;
@@ -418,8 +418,10 @@ fhe_status ctx_workspace(fhe_ctx *c, size_t bytes, uint8_t **out)
 }
 
 // Upload a list of device pointers for the next launch(es) on the context's
-// stream.  Tables up to PTR_SLOT_CAP entries go through a ring of pinned
-// staging slots; a slot is refilled only after its previous copy completed.
+// stream.  Tables live in a ring over a device arena (copied from its pinned
+// twin on the stream); a table's region is reused only after the work enqueued
+// before the following table request has completed, so the host runs up to a
+// whole arena of tables ahead of the device.
 fhe_status ctx_ptr_table(fhe_ctx *c, const std::vector<uint64_t *> &ptrs, uint64_t ***dev)
 {
     const size_t n = ptrs.size() ? ptrs.size() : 1;
@@ -435,13 +437,8 @@ fhe_status ctx_ptr_table(fhe_ctx *c, const std::vector<uint64_t *> &ptrs, uint64
         *dev = (uint64_t **)(c->cap_dev + off);
         return FHE_OK;
     }
-    if (!c->d_ptrs) {
-        HIPCHK(hipMalloc((void **)&c->d_ptrs, sizeof(uint64_t *) * PTR_SLOTS * PTR_SLOT_CAP));
-        HIPCHK(hipHostMalloc((void **)&c->h_ptrs, sizeof(uint64_t *) * PTR_SLOTS * PTR_SLOT_CAP));
-        for (int i = 0; i < PTR_SLOTS; ++i) HIPCHK(hipEventCreateWithFlags(&c->ptr_ev[i], hipEventDisableTiming));
-        for (int i = 0; i < PTR_SLOTS; ++i) HIPCHK(hipEventRecord(c->ptr_ev[i], c->stream));
-    }
-    if (n > PTR_SLOT_CAP) {
+    const size_t bytes = (n * sizeof(uint64_t *) + 255) & ~(size_t)255;
+    if (bytes > TBL_ARENA_BYTES) {
         HIPCHK(hipStreamSynchronize(c->stream));
         if (n > c->d_big_cap) {
             if (c->d_big) HIPCHK(hipFree(c->d_big));
@@ -453,14 +450,54 @@ fhe_status ctx_ptr_table(fhe_ctx *c, const std::vector<uint64_t *> &ptrs, uint64
         *dev = c->d_big;
         return FHE_OK;
     }
-    const uint32_t slot = c->ptr_next;
-    c->ptr_next = (c->ptr_next + 1) % PTR_SLOTS;
-    HIPCHK(hipEventSynchronize(c->ptr_ev[slot]));
-    uint64_t **h = c->h_ptrs + (size_t)slot * PTR_SLOT_CAP, **d = c->d_ptrs + (size_t)slot * PTR_SLOT_CAP;
-    std::memcpy(h, ptrs.data(), ptrs.size() * sizeof(uint64_t *));
-    HIPCHK(hipMemcpyAsync(d, h, ptrs.size() * sizeof(uint64_t *), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipEventRecord(c->ptr_ev[slot], c->stream));
-    *dev = d;
+    if (!c->tbl_dev) {
+        HIPCHK(hipMalloc((void **)&c->tbl_dev, TBL_ARENA_BYTES));
+        HIPCHK(hipHostMalloc((void **)&c->tbl_host, TBL_ARENA_BYTES));
+    }
+    // every launch that reads the previous table has been enqueued: mark its release
+    if (!c->tbl_live.empty() && !c->tbl_live.back().recorded) {
+        HIPCHK(hipEventRecord(c->tbl_live.back().ev, c->stream));
+        c->tbl_live.back().recorded = true;
+    }
+    size_t off = 0;
+    for (;;) {
+        if (c->tbl_live.empty()) {
+            off = 0;
+            break;
+        }
+        const size_t tail = c->tbl_live.front().off;
+        const size_t head = c->tbl_live.back().off + c->tbl_live.back().len;
+        const bool wrapped = c->tbl_live.back().off < tail;
+        if (!wrapped && head + bytes <= TBL_ARENA_BYTES) {
+            off = head;
+            break;
+        }
+        if (!wrapped && bytes <= tail) {
+            off = 0;
+            break;
+        }
+        if (wrapped && head + bytes <= tail) {
+            off = head;
+            break;
+        }
+        // retire the oldest table (waits for the work enqueued up to its release point)
+        fhe_ctx::TblAlloc a = c->tbl_live.front();
+        HIPCHK(hipEventSynchronize(a.ev));
+        c->tbl_pool.push_back(a.ev);
+        c->tbl_live.pop_front();
+    }
+    hipEvent_t ev;
+    if (!c->tbl_pool.empty()) {
+        ev = c->tbl_pool.back();
+        c->tbl_pool.pop_back();
+    } else {
+        HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    std::memcpy(c->tbl_host + off, ptrs.data(), ptrs.size() * sizeof(uint64_t *));
+    HIPCHK(hipMemcpyAsync(c->tbl_dev + off, c->tbl_host + off, ptrs.size() * sizeof(uint64_t *),
+                          hipMemcpyHostToDevice, c->stream));
+    c->tbl_live.push_back(fhe_ctx::TblAlloc{off, bytes, ev, false});
+    *dev = (uint64_t **)(c->tbl_dev + off);
     return FHE_OK;
 }
 

@@ -13,14 +13,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
+#include <deque>
 #include <vector>
 
 #include "fhe.h"
 
 #define FHE_MAXMOD 64
 #define FHE_LIMBTAB 128
-#define PTR_SLOTS 16
-#define PTR_SLOT_CAP 131072
+#define TBL_ARENA_BYTES ((size_t)16 << 20)   // pointer-table ring per context
 
 enum { OP_CT_MULT = 0, OP_CT_ADD, OP_PT_MULT, OP_PT_ADD, OP_RELIN, OP_RESCALE, OP_ROTATE, OP_KEYSWITCH };
 
@@ -150,12 +150,17 @@ struct fhe_ctx {
     // operations it calls, which themselves use the scratch above
     uint8_t *wksp;
     size_t wksp_bytes;
-    // pointer tables for batched launches: a ring of slots, each a pinned host
-    // staging area and a device copy, reused once the slot's copy has completed
-    uint64_t **d_ptrs;       // [PTR_SLOTS][PTR_SLOT_CAP]
-    uint64_t **h_ptrs;       // pinned, same shape
-    hipEvent_t ptr_ev[16];
-    uint32_t ptr_next;
+    // pointer tables for batched launches: a ring over a device arena and its
+    // pinned staging; a table's region is reused once the work enqueued up to the
+    // next table request has completed (its release event)
+    uint8_t *tbl_dev, *tbl_host;
+    struct TblAlloc {
+        size_t off, len;
+        hipEvent_t ev;
+        bool recorded;
+    };
+    std::deque<TblAlloc> tbl_live;
+    std::vector<hipEvent_t> tbl_pool;
     uint64_t **d_big;        // oversize table (synchronous path)
     size_t d_big_cap;
     // HIP graph capture (fhe_graph_begin .. fhe_graph_end): pointer tables go to a

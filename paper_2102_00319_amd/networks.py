@@ -132,7 +132,9 @@ class PackedCNN:
         if key not in self._masks:
             v = np.zeros(ctx.N // 2)
             v[grid_slots(self.H, self.W, self.fh, self.fw, self.images_per_ct(ctx), 2 * dil)] = 0.25
-            self._masks[key] = ctx.encode(v, scale=float(ctx.q[limbs - 1]), limbs=limbs)
+            m = ctx.encode(v, scale=float(ctx.q[limbs - 1]), limbs=limbs)
+            ctx.stream.synchronize()   # other streams may read the cached mask next
+            self._masks.setdefault(key, m)
         return self._masks[key]
 
     def forward(self, ctx, rlk, gks, X, weights):
@@ -153,3 +155,62 @@ class PackedCNN:
         relin = self.c1 + self.c2 + act * (self.c1 + self.c2) + self.n_classes
         rot = nz * (1 + self.c1) + 2 * (self.c1 + self.c2) + self.n_classes * int(np.log2(self.frame))
         return ct_mult, relin, rot
+
+
+class SlotCNN:
+    """Slot packing (Sec. 3, Fig. 2): one ciphertext per pixel holding that pixel of
+    every image of the batch, one weight ciphertext per weight (replicated):
+        conv K x K stride s, zero padding pad on top and left (Cout channels) -> x^2
+        -> FC (Cout*Ho*Wo -> fc1) -> x^2 -> FC (fc1 -> n_classes).
+    Images of one client may occupy any slot range [off, off + B): ciphertexts of
+    requests with disjoint ranges add up to one batch (slot merging)."""
+
+    def __init__(self, H=28, W=28, K=5, Cout=5, stride=2, pad=1, fc1=100, n_classes=10):
+        self.H, self.W, self.K, self.Cout, self.stride, self.pad = H, W, K, Cout, stride, pad
+        self.Ho = (H + pad - K) // stride + 1
+        self.Wo = (W + pad - K) // stride + 1
+        self.fc1, self.n_classes = fc1, n_classes
+
+    @property
+    def depth(self):
+        return 4
+
+    def slots(self, ctx):
+        return ctx.N // 2
+
+    def keygen(self, ctx, s, seed):
+        return ctx.keygen_relin(s, seed), {}
+
+    def encrypt_images(self, ctx, pk, images, seed, slot_offset=0, scale=None):
+        B = images.shape[0]
+        if slot_offset + B > self.slots(ctx):
+            raise ValueError("images beyond the slot count")
+        out = []
+        for y in range(self.H):
+            for x in range(self.W):
+                v = np.zeros(slot_offset + B)
+                v[slot_offset:] = images[:, y, x]
+                out.append(ctx.encrypt(pk, ctx.encode(v, scale=scale or ctx.scale), seed + y * self.W + x))
+        return out
+
+    def encrypt_weights(self, ctx, pk, cw, f1, f2, seeds, top=None, scale=None):
+        top = ctx.L if top is None else top
+        D = scale or ctx.scale
+        Wc = ctx.encrypt_const_batch(pk, cw.ravel(), D, [seeds[0] + t for t in range(cw.size)], top)
+        W1 = ctx.encrypt_const_batch(pk, f1.ravel(), D, [seeds[1] + t for t in range(f1.size)], top - 2)
+        W2 = ctx.encrypt_const_batch(pk, f2.ravel(), D, [seeds[2] + t for t in range(f2.size)], top - 4)
+        return Wc, W1, W2
+
+    def forward(self, ctx, rlk, gks, X, weights):
+        Wc, W1, W2 = weights
+        Y = ctx.conv2d_slot(rlk, X, self.H, self.W, 1, Wc, self.Cout, self.K, self.K, self.stride, self.pad,
+                            self.pad, self.Ho, self.Wo)
+        Z = ctx.fc_slot(rlk, ctx.square_act(rlk, Y), W1, self.fc1)
+        return ctx.fc_slot(rlk, ctx.square_act(rlk, Z), W2, self.n_classes)
+
+    def decrypt_scores(self, ctx, s, Z, B, slot_offset=0):
+        out = np.empty((B, len(Z)))
+        for r, z in enumerate(Z):
+            v, _ = ctx.decode(ctx.decrypt(s, z), n=slot_offset + B)
+            out[:, r] = v[slot_offset:slot_offset + B]
+        return out

@@ -1,0 +1,240 @@
+"""Serving loop for encrypted inference requests (continuous batching on one GPU).
+
+The paper's setting (Sec. 2.1): a user sends encrypted images, the model is
+encrypted under the user's key by its owner, the cloud evaluates.  A serving
+process holds, per client, the evaluation keys and the encrypted weights
+("client state"), and per request the encrypted images.  This module:
+  * admits requests in arrival order as soon as a lane (an execution slot with
+    its own contexts and HIP stream) is free and the HBM budget covers the
+    client's state plus the request's working set; client state not resident is
+    loaded (cold start), evicting least-recently-used idle clients to host
+    memory when the budget requires;
+  * merges queued requests of one slot-packed client whose slot ranges are
+    disjoint into one batch (ciphertext addition: each request's images sit in
+    its own slots), up to max_merge requests;
+  * runs the forward passes of different lanes concurrently on the device
+    (requests that arrive while others run are admitted as lanes and memory free
+    up), and measures latency from arrival to the decrypted scores.
+"""
+import collections
+import threading
+import time
+
+import numpy as np
+import torch
+
+from .fhe import Context
+
+
+class Client:
+    """One user (secret key, public key, evaluation keys) with a model encrypted under
+    its key; kind 'slot' (SlotCNN) or 'packed' (PackedCNN)."""
+
+    def __init__(self, cid, net, ctx, set_name, weights_plain, seeds):
+        self.cid, self.net, self.set_name = cid, net, set_name
+        self.kind = "packed" if hasattr(net, "frame") else "slot"
+        self.sk = ctx.keygen_secret(seeds["secret"])
+        self.pk = ctx.keygen_pk(self.sk, seeds["pk"])
+        self.rlk, self.gks = net.keygen(ctx, self.sk, seeds["evk"])
+        self.weights = net.encrypt_weights(ctx, self.pk, *weights_plain, seeds["weights"])
+        self.objs = [self.rlk] + list(self.gks.values()) + [w for grp in self.weights for w in grp]
+        self.nbytes = sum(o.data.numel() * 8 for o in self.objs)
+        self.resident, self.inflight, self.last_used, self.loads = True, 0, 0.0, 0
+        self.device = ctx.device
+
+    def evict(self):
+        for o in self.objs:
+            o.data = o.data.to("cpu")
+        self.resident = False
+
+    def restore(self):
+        for o in self.objs:
+            o.data = o.data.to(self.device)
+        self.resident = True
+        self.loads += 1
+
+
+class Request:
+    def __init__(self, rid, client, payload, n_images, slot_offset, t_arrival, tag):
+        self.rid, self.client, self.payload = rid, client, payload
+        self.n, self.off, self.t_arrival, self.tag = n_images, slot_offset, t_arrival, tag
+        self.t_admit = self.t_done = None
+        self.scores = None
+        self.cold = False
+        self.merged = 1
+
+
+class Lane:
+    """An execution slot: its own contexts (one per parameter set) on its own HIP
+    stream, driven by its own host thread, so that a lane waiting for the device
+    never holds up the others."""
+
+    def __init__(self, set_names, device):
+        self.stream = torch.cuda.Stream(device=device)
+        self.ctx = {n: Context.from_set(n, stream=self.stream) for n in set_names}
+        self.group, self.thread, self.finished, self.error, self.ws = None, None, False, None, 0
+
+
+class Server:
+    def __init__(self, set_names, lanes=4, hbm_budget=250e9, merge=True, max_merge=64, scratch_bytes=4 << 30,
+                 device="cuda"):
+        self.device = torch.device(device)
+        self.scratch = int(scratch_bytes)   # device scratch a lane may hold while it runs
+        self.lanes = [Lane(set_names, self.device) for _ in range(lanes)]
+        self.budget, self.merge, self.max_merge = float(hbm_budget), merge, max_merge
+        self.clients = []
+        self.stats = collections.Counter()
+
+    # ------------------------------------------------------------ memory
+    def add_client(self, client):
+        self.clients.append(client)
+
+    def resident_bytes(self):
+        return sum(c.nbytes for c in self.clients if c.resident) + sum(l.ws for l in self.lanes)
+
+    def working_set(self, req, lane):
+        """Device bytes of one batch of `req`'s network beyond the client state:
+        inputs, layer outputs and the lane's scratch (an estimate)."""
+        ctx = lane.ctx[req.client.set_name]
+        ct = 2 * ctx.L * ctx.N * 8
+        if req.client.kind == "slot":
+            net = req.client.net
+            n_conv = net.Cout * net.Ho * net.Wo
+            return int(net.H * net.W * ct * 2 + 3 * n_conv * ct + self.scratch)
+        net = req.client.net
+        return int(len(req.payload) * ct * (4 + 2 * net.c2 + net.c1 * net.k * net.k) + self.scratch)
+
+    def _make_room(self, need, now):
+        """Evict least-recently-used idle clients until `need` more bytes fit."""
+        while self.resident_bytes() + need > self.budget:
+            idle = [c for c in self.clients if c.resident and c.inflight == 0]
+            if not idle:
+                return False
+            victim = min(idle, key=lambda c: c.last_used)
+            victim.evict()
+            self.stats["evictions"] += 1
+            torch.cuda.empty_cache()
+        return True
+
+    # -------------------------------------------------------- scheduling
+    def _admit(self, lane, queue, now):
+        for i, req in enumerate(queue):
+            c = req.client
+            ws = self.working_set(req, lane)
+            need = ws + (0 if c.resident else c.nbytes)
+            if self.resident_bytes() + need > self.budget and not self._make_room(need, now):
+                continue
+            cold = not c.resident
+            if cold:
+                t0 = time.perf_counter()
+                c.restore()
+                self.stats["cold_load_s"] += time.perf_counter() - t0
+                self.stats["cold_loads"] += 1
+            group = [req]
+            if self.merge and c.kind == "slot":
+                used = {req.tag}
+                for r2 in queue[i + 1:]:
+                    if len(group) >= self.max_merge:
+                        break
+                    if r2.client is c and r2.tag not in used:
+                        group.append(r2)
+                        used.add(r2.tag)
+            for r in group:
+                queue.remove(r)
+                r.t_admit = now
+                r.cold = cold
+                r.merged = len(group)
+            c.inflight += 1
+            c.last_used = now
+            self._launch(lane, group, ws, self._now)
+            return True
+        return False
+
+    def _launch(self, lane, group, ws, now_fn):
+        c = group[0].client
+        ctx = lane.ctx[c.set_name]
+
+        def work():
+            try:
+                with torch.cuda.stream(lane.stream):
+                    if len(group) == 1:
+                        xs = group[0].payload
+                    else:   # slot merging: the requests' images occupy disjoint slots
+                        xs = []
+                        for k in range(len(group[0].payload)):
+                            acc = ctx.add(group[0].payload[k], group[1].payload[k])
+                            for r in group[2:]:
+                                acc = ctx.add(acc, r.payload[k], out=acc)
+                            xs.append(acc)
+                    if c.kind == "packed":
+                        out = [c.net.forward(ctx, c.rlk, c.gks, [x], c.weights) for x in xs]
+                    else:
+                        out = c.net.forward(ctx, c.rlk, c.gks, xs, c.weights)
+                    for r in group:   # the user decrypts (decode waits for the stream)
+                        if c.kind == "packed":
+                            parts, left = [], r.n
+                            for z in out:
+                                m = min(left, c.net.images_per_ct(ctx))
+                                parts.append(c.net.decrypt_scores(ctx, c.sk, z, m))
+                                left -= m
+                            r.scores = np.concatenate(parts)
+                        else:
+                            r.scores = c.net.decrypt_scores(ctx, c.sk, out, r.n, r.off)
+                        r.t_done = now_fn()
+            except Exception as e:   # reported by the scheduler thread
+                lane.error = e
+            lane.finished = True
+
+        lane.group, lane.ws, lane.finished, lane.error = group, ws, False, None
+        lane.thread = threading.Thread(target=work, daemon=True)
+        lane.thread.start()
+
+    def _poll(self):
+        done = 0
+        for lane in self.lanes:
+            if lane.group is None or not lane.finished:
+                continue
+            lane.thread.join()
+            if lane.error is not None:
+                raise lane.error
+            lane.group[0].client.inflight -= 1
+            done += len(lane.group)
+            lane.group, lane.thread, lane.ws = None, None, 0
+        return done
+
+    def run(self, requests, time_limit=None):
+        """Serve `requests` (t_arrival in seconds from the start, sorted); returns them."""
+        t0 = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t0
+        self._now = now
+        pending = collections.deque(sorted(requests, key=lambda r: r.t_arrival))
+        queue, finished, total = [], 0, len(requests)
+        while finished < total:
+            t = now()
+            if time_limit is not None and t > time_limit:
+                raise TimeoutError("serving run exceeded its time limit")
+            while pending and pending[0].t_arrival <= t:
+                queue.append(pending.popleft())
+            finished += self._poll()
+            busy = False
+            for lane in self.lanes:
+                if lane.group is None and queue and self._admit(lane, queue, now()):
+                    busy = True
+            if not busy:
+                time.sleep(0.0002)
+        return requests
+
+
+def summarize(requests):
+    lat = np.array([r.t_done - r.t_arrival for r in requests])
+    wait = np.array([r.t_admit - r.t_arrival for r in requests])
+    imgs = sum(r.n for r in requests)
+    span = max(r.t_done for r in requests) - min(r.t_arrival for r in requests)
+    return {"requests": len(requests), "images": imgs, "images_per_s": round(imgs / span, 2),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+            "mean_admission_wait_ms": round(float(wait.mean()) * 1e3, 2),
+            "cold_requests": sum(1 for r in requests if r.cold),
+            "mean_merge": round(float(np.mean([r.merged for r in requests])), 2)}

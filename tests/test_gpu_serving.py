@@ -1,0 +1,103 @@
+"""Serving loop: continuous batching of encrypted inference requests from
+several clients under an HBM budget; every result equals the same request
+served alone (bitwise without slot merging; with it, to 1e-4: a merged batch
+also carries the other requests' fresh encryption noise, about 1e-6 here at
+scale 2^30) and the FP64 network to 1e-3."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+
+SLOT = dict(H=6, W=6, K=3, Cout=2, stride=2, pad=1, fc1=3, n_classes=2)
+PACKED = dict(H=12, W=12, frame_h=16, frame_w=16, c1=2, c2=3, n_classes=2)
+
+
+def _setup(merge, budget_frac):
+    import paper_2102_00319_amd as P
+    from paper_2102_00319_amd import networks, serving
+    sets = {"slot": "t_n12", "packed": "t4_n12"}
+    setup = {k: P.Context.from_set(v) for k, v in sets.items()}
+    clients, plain = [], []
+    for cid, kind in enumerate(["slot", "slot", "packed", "packed"]):
+        g = setup[kind]
+        base = workloads.MASTER_SEED + 10000 * (cid + 1)
+        if kind == "slot":
+            net = networks.SlotCNN(**SLOT)
+            w = (workloads.weights(base + 1, (2, 1, 3, 3)), workloads.weights(base + 2, (3, 2 * 3 * 3)),
+                 workloads.weights(base + 3, (2, 3)))
+        else:
+            net = networks.PackedCNN(**PACKED)
+            w = (workloads.weights(base + 1, (2, 1, 3, 3)), workloads.weights(base + 2, (3, 2, 3, 3)),
+                 workloads.weights(base + 3, (2, 3 * 3 * 3)))
+        seeds = {"secret": base + 4, "pk": base + 5, "evk": base + 6, "weights": (base + 100, base + 200, base + 300)}
+        clients.append(serving.Client(cid, net, g, sets[kind], w, seeds))
+        plain.append(w)
+    total = sum(c.nbytes for c in clients)
+    srv = serving.Server(list(sets.values()), lanes=2, hbm_budget=budget_frac * total + 2 * (64 << 20),
+                         merge=merge, scratch_bytes=32 << 20)
+    for c in clients:
+        srv.add_client(c)
+    # payload pool: 3 per client (tag t: slots / frames from t * 64 on for slot clients)
+    pools = []
+    for c in clients:
+        g = setup["slot" if c.kind == "slot" else "packed"]
+        pool = []
+        for t in range(3):
+            n = 2 + (c.cid + t) % 4
+            seed = workloads.MASTER_SEED + 50000 + 100 * c.cid + 10 * t
+            if c.kind == "slot":
+                imgs = workloads.images(seed, n, 6, 6)
+                pay = c.net.encrypt_images(g, c.pk, imgs, seed, slot_offset=64 * t)
+                pool.append((pay, imgs, 64 * t))
+            else:
+                imgs = workloads.images(seed, n, 12, 12)
+                pay = c.net.encrypt_images(g, c.pk, imgs, seed)
+                pool.append((pay, imgs, 0))
+        pools.append(pool)
+    torch.cuda.synchronize()
+    return srv, clients, plain, pools
+
+
+def _requests(serving, clients, pools, count=14):
+    rng = np.random.default_rng(7)
+    reqs = []
+    for i in range(count):
+        cid = int(rng.integers(0, len(clients)))
+        t = int(rng.integers(0, 3))
+        pay, imgs, off = pools[cid][t]
+        r = serving.Request(i, clients[cid], pay, imgs.shape[0], off, float(rng.uniform(0, 0.2)), t)
+        r.images = imgs
+        reqs.append(r)
+    return reqs
+
+
+def _fp64(c, w, imgs):
+    if c.kind == "slot":
+        return cnn.slot_cnn_fp64(imgs, w[0], w[1], w[2], 2, 1, 1, 3, 3)
+    return cnn.packed_cnn_fp64(imgs, w[0], w[1], w[2], c.net.coef)
+
+
+@pytest.mark.parametrize("merge", [False, True])
+def test_serving_mix_equals_alone(merge):
+    from paper_2102_00319_amd import serving
+    srv, clients, plain, pools = _setup(merge, 0.6)
+    reqs = _requests(serving, clients, pools)
+    srv.run(reqs, time_limit=120)
+    assert srv.stats["evictions"] > 0 and srv.stats["cold_loads"] > 0
+    if merge:
+        assert max(r.merged for r in reqs) > 1
+    for r in reqs:
+        ref = _fp64(r.client, plain[r.client.cid], r.images)
+        assert np.abs(r.scores - ref).max() < 1e-3, r.rid
+        alone = serving.Request(r.rid, r.client, r.payload, r.n, r.off, 0.0, r.tag)
+        srv.run([alone], time_limit=60)
+        if r.merged == 1:
+            assert np.array_equal(alone.scores, r.scores), r.rid
+        else:
+            assert np.abs(alone.scores - r.scores).max() < 1e-4, r.rid
+    s = serving.summarize(reqs)
+    assert s["requests"] == len(reqs) and s["p99_ms"] >= s["p50_ms"] > 0
