@@ -140,6 +140,10 @@ fhe_status fhe_encrypt(fhe_ctx *ctx, const fhe_ct *pk, const fhe_pt *m, uint64_t
 fhe_status fhe_decrypt(fhe_ctx *ctx, const int8_t *s_host, const fhe_ct *ct, fhe_pt *out);
 /* Plaintext -> n slots (host re/im, im may be NULL), dividing by pt->scale. */
 fhe_status fhe_decode(fhe_ctx *ctx, const fhe_pt *pt, double *re, double *im, uint32_t n);
+/* The same for the n slots listed in slots (host array, each < N/2): re[t], im[t]
+ * hold slot slots[t] (e.g. one score per image frame). */
+fhe_status fhe_decode_slots(fhe_ctx *ctx, const fhe_pt *pt, const uint32_t *slots, uint32_t n, double *re,
+                            double *im);
 
 /* --------------------------------------------------------- server side */
 fhe_status fhe_add(fhe_ctx *ctx, const fhe_ct *a, const fhe_ct *b, fhe_ct *out);

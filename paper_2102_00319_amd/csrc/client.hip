@@ -234,23 +234,43 @@ __global__ void k_lift(const uint64_t *__restrict__ m, uint32_t l, uint64_t q0, 
         }
     }
 }
-// decoding: one thread per slot j
-__global__ void k_decode(const double *__restrict__ mv, const double *__restrict__ cs, const double *__restrict__ sn,
-                         const uint32_t *__restrict__ g5, double scale, uint32_t logN, uint32_t n, double *re,
-                         double *im)
+__global__ void k_narrow_u32(const uint64_t *__restrict__ w, uint32_t n, uint32_t *out)
 {
+    const uint32_t t = blockIdx.x * TPB + threadIdx.x;
+    if (t < n) out[t] = (uint32_t)w[t];
+}
+// Decoding: slot j = sum_k m_k zeta^(k 5^j), one 256-thread block per slot
+// (blockIdx.x = output index, slot idx[blockIdx.x] or the index itself): thread t
+// sums the terms k = t mod 256, then a tree reduction in LDS.
+__global__ __launch_bounds__(TPB) void k_decode(const double *__restrict__ mv, const double *__restrict__ cs,
+                                               const double *__restrict__ sn, const uint32_t *__restrict__ g5,
+                                               const uint32_t *__restrict__ idx, double scale, uint32_t logN,
+                                               double *re, double *im)
+{
+    __shared__ double sr[TPB], si[TPB];
     const uint32_t N = 1u << logN;
-    const uint32_t j = blockIdx.x * TPB + threadIdx.x;
-    if (j >= n) return;
+    const uint32_t o = blockIdx.x, j = idx ? idx[o] : o;
     const uint32_t mask = 2u * N - 1u, g = g5[j];
     double ar = 0.0, ai = 0.0;
-    for (uint32_t k = 0; k < N; ++k) {
+    for (uint32_t k = threadIdx.x; k < N; k += TPB) {
         const uint32_t e = (k * g) & mask;
         ar += mv[k] * cs[e];
         ai += mv[k] * sn[e];
     }
-    re[j] = ar / scale;
-    im[j] = ai / scale;
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (uint32_t h = TPB / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sr[threadIdx.x] += sr[threadIdx.x + h];
+            si[threadIdx.x] += si[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        re[o] = sr[0] / scale;
+        im[o] = si[0] / scale;
+    }
 }
 
 ModList modlist_range(uint32_t first, uint32_t count)
@@ -528,19 +548,28 @@ fhe_status fhe_encode(fhe_ctx *c, const double *re, const double *im, uint32_t n
     return FHE_OK;
 }
 
-fhe_status fhe_decode(fhe_ctx *c, const fhe_pt *pt, double *re, double *im, uint32_t n)
+static fhe_status decode_common(fhe_ctx *c, const fhe_pt *pt, const uint32_t *slots, double *re, double *im,
+                                uint32_t n)
 {
-    if (!c || !pt || !pt->d || !re) return fhe_fail(FHE_EINVAL, "fhe_decode: null argument");
     const uint32_t N = c->N;
-    if (n > N / 2) return fhe_fail(FHE_EINVAL, "fhe_decode: more values than slots");
     if (pt->limbs < 1 || pt->limbs > c->L) return fhe_fail(FHE_ELEVEL, "fhe_decode: level out of range");
     const uint32_t lu = pt->limbs >= 2 ? 2 : 1;
     const size_t nn = n ? n : 1;
     uint8_t *scr;
-    fhe_status s = ctx_scratch(c, (size_t)lu * N * 8 + (size_t)N * 8 + 2 * nn * 8, &scr);
+    fhe_status s = ctx_scratch(c, (size_t)lu * N * 8 + (size_t)N * 8 + 2 * nn * 8 + nn * 4 + 256, &scr);
     if (s) return s;
     uint64_t *limbs = (uint64_t *)scr;
     double *mv = (double *)(limbs + (size_t)lu * N), *dre = mv + N, *dim = dre + nn;
+    uint32_t *didx = nullptr;
+    if (slots) {   // the slot list travels as a pointer table, narrowed to 32-bit words
+        std::vector<uint64_t *> tab(n);
+        for (uint32_t t = 0; t < n; ++t) tab[t] = (uint64_t *)(uintptr_t)slots[t];
+        uint64_t **dt;
+        if ((s = ctx_ptr_table(c, tab, &dt))) return s;
+        didx = (uint32_t *)(dim + nn);
+        hipLaunchKernelGGL(k_narrow_u32, dim3(blocks_for(n, TPB)), dim3(TPB), 0, c->stream, (const uint64_t *)dt, n,
+                           didx);
+    }
     HIPCHK(hipMemcpyAsync(limbs, pt->d, (size_t)lu * N * 8, hipMemcpyDeviceToDevice, c->stream));
     ModList ml = modlist_range(0, lu);
     ntt_list(c, limbs, ml, true);
@@ -555,15 +584,30 @@ fhe_status fhe_decode(fhe_ctx *c, const fhe_pt *pt, double *re, double *im, uint
     hipLaunchKernelGGL(k_lift, dim3(blocks_for(N, TPB)), dim3(TPB), 0, c->stream, (const uint64_t *)limbs, lu, q0, q1,
                        q0inv, mv, c->logN);
     if (n) {
-        hipLaunchKernelGGL(k_decode, dim3(blocks_for(n, TPB)), dim3(TPB), 0, c->stream, (const double *)mv,
-                           (const double *)c->d_cos, (const double *)c->d_sin, (const uint32_t *)c->d_g5, pt->scale,
-                           c->logN, n, dre, dim);
+        hipLaunchKernelGGL(k_decode, dim3(n), dim3(TPB), 0, c->stream, (const double *)mv, (const double *)c->d_cos,
+                           (const double *)c->d_sin, (const uint32_t *)c->d_g5, (const uint32_t *)didx, pt->scale,
+                           c->logN, dre, dim);
         HIPCHK(hipMemcpyAsync(re, dre, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
         if (im) HIPCHK(hipMemcpyAsync(im, dim, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());
     return FHE_OK;
+}
+
+fhe_status fhe_decode(fhe_ctx *c, const fhe_pt *pt, double *re, double *im, uint32_t n)
+{
+    if (!c || !pt || !pt->d || !re) return fhe_fail(FHE_EINVAL, "fhe_decode: null argument");
+    if (n > c->N / 2) return fhe_fail(FHE_EINVAL, "fhe_decode: more values than slots");
+    return decode_common(c, pt, nullptr, re, im, n);
+}
+
+fhe_status fhe_decode_slots(fhe_ctx *c, const fhe_pt *pt, const uint32_t *slots, uint32_t n, double *re, double *im)
+{
+    if (!c || !pt || !pt->d || !re || (n && !slots)) return fhe_fail(FHE_EINVAL, "fhe_decode_slots: null argument");
+    for (uint32_t t = 0; t < n; ++t)
+        if (slots[t] >= c->N / 2) return fhe_fail(FHE_EINVAL, "fhe_decode_slots: slot index out of range");
+    return decode_common(c, pt, slots, re, im, n);
 }
 
 }  // extern "C"

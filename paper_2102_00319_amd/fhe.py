@@ -105,6 +105,7 @@ _sig = {
     "fhe_encrypt_const_batch": [_P, C.POINTER(fhe_ct), _P, C.c_uint32, C.c_double, _P, C.POINTER(fhe_ct)],
     "fhe_profile_read": [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)],
     "fhe_add_const": [_P, C.POINTER(fhe_ct), C.c_double, C.POINTER(fhe_ct)],
+    "fhe_decode_slots": [_P, C.POINTER(fhe_pt), _P, C.c_uint32, _P, _P],
     "fhe_batch_run": [_P, C.POINTER(fhe_op), C.c_uint32],
     "fhe_graph_begin": [_P, C.c_uint32, C.c_uint64, C.POINTER(_P)],
     "fhe_graph_end": [_P, C.c_uint32, _P],
@@ -390,6 +391,17 @@ class Context:
         im = np.empty(n, dtype=np.float64)
         a = pt.s()
         _check(_lib.fhe_decode(self._h, C.byref(a), re.ctypes.data_as(C.c_void_p), im.ctypes.data_as(C.c_void_p), n))
+        return re, im
+
+    def decode_slots(self, pt, slots):
+        """Values of the listed slots (re, im)."""
+        idx = np.ascontiguousarray(slots, dtype=np.uint32)
+        n = len(idx)
+        re = np.empty(n, dtype=np.float64)
+        im = np.empty(n, dtype=np.float64)
+        a = pt.s()
+        _check(_lib.fhe_decode_slots(self._h, C.byref(a), idx.ctypes.data_as(C.c_void_p), n,
+                                     re.ctypes.data_as(C.c_void_p), im.ctypes.data_as(C.c_void_p)))
         return re, im
 
     # ---------------------------------------------------------- server

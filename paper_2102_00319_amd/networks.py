@@ -92,9 +92,9 @@ class PackedCNN:
 
     def decrypt_scores(self, ctx, s, Z, B):
         out = np.empty((B, len(Z)))
+        slots = np.arange(B) * self.frame   # the score of image b sits at its frame's first slot
         for r, z in enumerate(Z):
-            v, _ = ctx.decode(ctx.decrypt(s, z), n=B * self.frame)
-            out[:, r] = v[np.arange(B) * self.frame]
+            out[:, r], _ = ctx.decode_slots(ctx.decrypt(s, z), slots)
         return out
 
     # ------------------------------------------------------- model owner
@@ -210,7 +210,7 @@ class SlotCNN:
 
     def decrypt_scores(self, ctx, s, Z, B, slot_offset=0):
         out = np.empty((B, len(Z)))
+        slots = np.arange(slot_offset, slot_offset + B)
         for r, z in enumerate(Z):
-            v, _ = ctx.decode(ctx.decrypt(s, z), n=slot_offset + B)
-            out[:, r] = v[slot_offset:slot_offset + B]
+            out[:, r], _ = ctx.decode_slots(ctx.decrypt(s, z), slots)
         return out
