@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 
 #include "fhe_internal.h"
 
@@ -20,42 +21,66 @@ constexpr int TPB = 256;
 inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
 constexpr uint64_t TAG_UNIFORM = 2, TAG_ERROR = 3, TAG_EPHEMERAL = 4;
 
-// Pointer table layout: [a: P][b: P][out: n_out][offsets: n_out + 1 (as integers)].
-// Output o accumulates pairs off[o] .. off[o+1]-1 into a 3-poly ciphertext.
-__global__ __launch_bounds__(TPB) void k_tensor_acc_csr(uint64_t *const *__restrict__ tab, uint32_t P, uint32_t o0,
-                                                        uint32_t n_out, const ModQ *__restrict__ mods, uint32_t logN,
-                                                        uint32_t limbs)
+// Tensor multiply-accumulate over tiles of outputs that share their first
+// factors: tile t has P_t pairs and k_t <= TO outputs; output u of the tile
+// accumulates sum_p A[p] (x) B[u][p] into a 3-poly ciphertext.  Each thread
+// owns one (limb, coefficient) element and loads A[p] once for the whole tile.
+// Table: [a: sum P_t][b: sum k_t P_t][out: n_out][tiles: 2 words each]
+// tile words: a_off | P << 32, b_off | o0 << 32 (o0 = first output) ; k_t in the
+// top 8 bits of the second word's output field (o0 < 2^24).
+template <int TO>
+__global__ __launch_bounds__(TPB) void k_tensor_tile(uint64_t *const *__restrict__ tab, uint32_t nA, uint32_t nB,
+                                                     uint32_t n_out, const ModQ *__restrict__ mods, uint32_t logN,
+                                                     uint32_t limbs)
 {
     const uint32_t N = 1u << logN;
     const uint64_t e = (uint64_t)blockIdx.x * TPB + threadIdx.x;   // limb * N + k
     if (e >= ((uint64_t)limbs << logN)) return;
-    const uint32_t o = o0 + blockIdx.y;
-    uint64_t *const *ap = tab, *const *bp = tab + P;
-    uint64_t *out = tab[2 * P + o];
-    const uint64_t *off = (const uint64_t *)(tab + 2 * P + n_out);
+    const uint64_t w0 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * blockIdx.y];
+    const uint64_t w1 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * blockIdx.y + 1];
+    const uint32_t a_off = (uint32_t)w0, P = (uint32_t)(w0 >> 32), b_off = (uint32_t)w1;
+    const uint32_t o0 = (uint32_t)(w1 >> 32) & 0xFFFFFF, k = (uint32_t)(w1 >> 56);
+    uint64_t *const *ap = tab + a_off, *const *bp = tab + nA + b_off;
     const uint32_t limb = (uint32_t)(e >> logN);
     const uint64_t off1 = (uint64_t)limbs * N;
     const double q = mods[limb].q, qi = mods[limb].qinv;
-    double d0 = 0, d1 = 0, d2 = 0;
-    const uint32_t t0 = (uint32_t)off[o], t1 = (uint32_t)off[o + 1];
-    uint32_t cnt = 0;
-    for (uint32_t t = t0; t < t1; ++t, ++cnt) {
-        const uint64_t *A = ap[t], *B = bp[t];
+    double d0[TO], d1[TO], d2[TO];
+#pragma unroll
+    for (int u = 0; u < TO; ++u) d0[u] = d1[u] = d2[u] = 0.0;
+    for (uint32_t p = 0; p < P; ++p) {
+        const uint64_t *A = ap[p];
         const double a0 = u64_to_f64(A[e]), a1 = u64_to_f64(A[e + off1]);
-        const double b0 = u64_to_f64(B[e]), b1 = u64_to_f64(B[e + off1]);
-        d0 += mulmod(a0, b0, q, qi);
-        d1 += mulmod(a0, b1, q, qi) + mulmod(a1, b0, q, qi);
-        d2 += mulmod(a1, b1, q, qi);
-        if ((cnt & 3) == 3) {
-            d0 = redc(d0, q, qi);
-            d1 = redc(d1, q, qi);
-            d2 = redc(d2, q, qi);
+#pragma unroll
+        for (int u = 0; u < TO; ++u) {
+            if (u < (int)k) {
+                const uint64_t *Bp = bp[(size_t)u * P + p];
+                const double b0 = u64_to_f64(Bp[e]), b1 = u64_to_f64(Bp[e + off1]);
+                d0[u] += mulmod(a0, b0, q, qi);
+                d1[u] += mulmod(a0, b1, q, qi) + mulmod(a1, b0, q, qi);
+                d2[u] += mulmod(a1, b1, q, qi);
+            }
+        }
+        // |mulmod| <= 0.75 q + 2^46: four pairs keep every sum below 2^53 (q < 2^50)
+        if ((p & 3) == 3) {
+#pragma unroll
+            for (int u = 0; u < TO; ++u) {
+                d0[u] = redc(d0[u], q, qi);
+                d1[u] = redc(d1[u], q, qi);
+                d2[u] = redc(d2[u], q, qi);
+            }
         }
     }
-    out[e] = f64_to_u64(canon(d0, q, qi));
-    out[e + off1] = f64_to_u64(canon(d1, q, qi));
-    out[e + 2 * off1] = f64_to_u64(canon(d2, q, qi));
+#pragma unroll
+    for (int u = 0; u < TO; ++u) {
+        if (u < (int)k) {
+            uint64_t *out = tab[nA + nB + o0 + u];
+            out[e] = f64_to_u64(canon(d0[u], q, qi));
+            out[e + off1] = f64_to_u64(canon(d1[u], q, qi));
+            out[e + 2 * off1] = f64_to_u64(canon(d2[u], q, qi));
+        }
+    }
 }
+constexpr int MAC_TILE = 8;
 
 // ---- batched encryption of constant (slot-replicated) plaintexts
 __global__ void k_small_batch(int64_t *out, const uint64_t *__restrict__ seeds, const uint64_t *__restrict__ cdt,
@@ -132,13 +157,35 @@ __global__ void k_encrypt_const(const uint64_t *__restrict__ pk, uint32_t L, con
 }  // namespace
 
 // Y[o] = Rescale(Relin(sum over CSR pairs)) for every output; all inputs at l limbs, 2 polys.
+// Outputs whose first factors are the same list (conv channels over one window,
+// FC rows over one input vector) are grouped into tiles of up to MAC_TILE.
 fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const std::vector<uint64_t *> &A,
-                                    const std::vector<uint64_t *> &B, const std::vector<uint32_t> &off,
-                                    const std::vector<uint64_t *> &Y)
+                             const std::vector<uint64_t *> &B, const std::vector<uint32_t> &off,
+                             const std::vector<uint64_t *> &Y)
 {
     const uint32_t n_out = (uint32_t)Y.size();
     if (l < 2) return fhe_fail(FHE_ELEVEL, "layer: inputs need at least 2 limbs (one rescale)");
+    if (n_out >= (1u << 24)) return fhe_fail(FHE_EINVAL, "layer: too many outputs");
     const size_t N = c->N, LB = N * sizeof(uint64_t);
+    // order outputs so that those sharing their A list are adjacent
+    std::map<std::vector<uint64_t *>, std::vector<uint32_t>> groups;
+    std::vector<std::vector<uint64_t *>> keys;
+    for (uint32_t o = 0; o < n_out; ++o) {
+        std::vector<uint64_t *> key(A.begin() + off[o], A.begin() + off[o + 1]);
+        auto it = groups.find(key);
+        if (it == groups.end()) {
+            keys.push_back(key);
+            groups[key].push_back(o);
+        } else {
+            it->second.push_back(o);
+        }
+    }
+    std::vector<uint32_t> order, gid;
+    for (size_t g = 0; g < keys.size(); ++g)
+        for (uint32_t o : groups[keys[g]]) {
+            order.push_back(o);
+            gid.push_back((uint32_t)g);
+        }
     // chunk size: bound the scratch of one chunk to about 2 GiB
     const size_t per_out = ks_scratch_bytes(c, l, 1) + (3 * (size_t)l + 2 * (size_t)l) * LB +
                            rescale_scratch_bytes(c, l, 2, 1);
@@ -151,26 +198,46 @@ fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const s
     uint64_t *acc3 = (uint64_t *)(scr + ks_scratch_bytes(c, l, C));
     uint64_t *tmp2 = acc3 + (size_t)C * 3 * l * N;
     uint8_t *rs_scr = (uint8_t *)(tmp2 + (size_t)C * 2 * l * N);
-    // one pointer table for the whole layer
-    const uint32_t P = (uint32_t)A.size();
-    std::vector<uint64_t *> tab;
-    tab.reserve(2 * (size_t)P + 2 * (size_t)n_out + 1);
-    tab.insert(tab.end(), A.begin(), A.end());
-    tab.insert(tab.end(), B.begin(), B.end());
-    for (uint32_t o = 0; o < n_out; ++o) tab.push_back(nullptr);   // filled per chunk below
-    for (uint32_t o = 0; o <= n_out; ++o) tab.push_back((uint64_t *)(uintptr_t)off[o]);
     std::vector<const uint64_t *> kd(C), ke(C, rlk->d), ka(2 * (size_t)C);
     std::vector<uint64_t *> ko(C), ro(C);
     std::vector<const uint64_t *> ri(C);
+    uint64_t pairs = 0;
     for (uint32_t o0 = 0; o0 < n_out; o0 += C) {
         const uint32_t cn = std::min(C, n_out - o0);
-        for (uint32_t t = 0; t < cn; ++t) tab[2 * (size_t)P + o0 + t] = acc3 + (size_t)t * 3 * l * N;
+        // tiles inside this chunk: runs of one group, at most MAC_TILE outputs
+        std::vector<uint64_t *> ta, tb, tout, tt;
+        for (uint32_t t = 0; t < cn;) {
+            uint32_t k = 1;
+            while (t + k < cn && k < (uint32_t)MAC_TILE && gid[o0 + t + k] == gid[o0 + t]) ++k;
+            const uint32_t first = order[o0 + t];
+            const uint32_t P = off[first + 1] - off[first];
+            const uint64_t a_off = ta.size(), b_off = tb.size();
+            ta.insert(ta.end(), A.begin() + off[first], A.begin() + off[first + 1]);
+            for (uint32_t u = 0; u < k; ++u) {
+                const uint32_t o = order[o0 + t + u];
+                tb.insert(tb.end(), B.begin() + off[o], B.begin() + off[o + 1]);
+                pairs += P;
+            }
+            tt.push_back((uint64_t *)(uintptr_t)(a_off | ((uint64_t)P << 32)));
+            tt.push_back((uint64_t *)(uintptr_t)(b_off | ((uint64_t)t << 32) | ((uint64_t)k << 56)));
+            t += k;
+        }
+        for (uint32_t t = 0; t < cn; ++t) tout.push_back(acc3 + (size_t)t * 3 * l * N);
+        std::vector<uint64_t *> tab;
+        tab.reserve(ta.size() + tb.size() + tout.size() + tt.size());
+        tab.insert(tab.end(), ta.begin(), ta.end());
+        tab.insert(tab.end(), tb.begin(), tb.end());
+        tab.insert(tab.end(), tout.begin(), tout.end());
+        tab.insert(tab.end(), tt.begin(), tt.end());
         uint64_t **dt;
         if ((s = ctx_ptr_table(c, tab, &dt))) return s;
+        const uint32_t ntiles = (uint32_t)(tt.size() / 2);
         {
             ProfScope ps(c, "tensor");
-            hipLaunchKernelGGL(k_tensor_acc_csr, dim3(blocks_for((uint64_t)l * N, TPB), cn), dim3(TPB), 0, c->stream,
-                               (uint64_t *const *)dt, P, o0, n_out, (const ModQ *)c->d_mod, c->logN, l);
+            if (ntiles > 65535u) return fhe_fail(FHE_EINVAL, "layer: too many tiles in one chunk");
+            hipLaunchKernelGGL(k_tensor_tile<MAC_TILE>, dim3(blocks_for((uint64_t)l * N, TPB), ntiles), dim3(TPB), 0,
+                               c->stream, (uint64_t *const *)dt, (uint32_t)ta.size(), (uint32_t)tb.size(), cn,
+                               (const ModQ *)c->d_mod, c->logN, l);
         }
         for (uint32_t t = 0; t < cn; ++t) {
             uint64_t *a3 = acc3 + (size_t)t * 3 * l * N;
@@ -179,13 +246,13 @@ fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const s
             ka[2 * t + 1] = a3 + (size_t)l * N;
             ko[t] = tmp2 + (size_t)t * 2 * l * N;
             ri[t] = ko[t];
-            ro[t] = Y[o0 + t];
+            ro[t] = Y[order[o0 + t]];
         }
         if ((s = ks_run(c, l, cn, kd.data(), nullptr, ke.data(), ko.data(), ka.data(), ks_scr))) return s;
         if ((s = rescale_run(c, l, 2, cn, ri.data(), ro.data(), rs_scr))) return s;
     }
-    c->ops[OP_CT_MULT] += P;
-    c->ops[OP_CT_ADD] += P - n_out;
+    c->ops[OP_CT_MULT] += pairs;
+    c->ops[OP_CT_ADD] += pairs - n_out;
     c->ops[OP_RELIN] += n_out;
     c->ops[OP_RESCALE] += n_out;
     HIPCHK(hipGetLastError());
