@@ -278,6 +278,11 @@ fhe_status fhe_avgpool2x2(fhe_ctx *ctx, const fhe_evk *keys, uint32_t nkeys, con
 fhe_status fhe_fc_packed(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *x,
                          uint32_t n_in, const fhe_ct *Wt, uint32_t n_out, uint32_t frame_slots, fhe_ct *y);
 
+/* Sum pooling over 2x2 windows of slot-packed maps (Eq. (ActPool) without the 1/4,
+ * which a recipe folds into the activation's coefficients):
+ *   y[c][i][j] = x[c][2i][2j] + x[c][2i][2j+1] + x[c][2i+1][2j] + x[c][2i+1][2j+1],
+ * x[(c*H + yy)*W + xx], y[(c*(H/2) + i)*(W/2) + j], all at one level; no level used. */
+fhe_status fhe_pool2x2_sum_slot(fhe_ctx *ctx, const fhe_ct *x, uint32_t C, uint32_t H, uint32_t W, fhe_ct *y);
 /* Model owner: encrypt n weights, each replicated in every slot (a constant
  * polynomial round(value * scale)), under the user's public key; per-weight
  * seeds (host array); outputs at out[0].limbs limbs. */

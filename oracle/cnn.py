@@ -283,3 +283,45 @@ def packed_rotation_steps(k, frame_w, frame_slots, n_pools=2):
         st.add(i)
         i *= 2
     return sorted(st)
+
+
+# ------------------------------------------------------ the paper's network
+G_PAPER = (0.47, 0.50, 0.09)   # Eq. (approxReLU)
+
+
+def paper_cnn_fp64(images, wc, wfc, coef=G_PAPER):
+    """conv KxK stride 1 no padding -> g -> 2x2 mean (Eq. (ActPool)) -> flatten (c, y, x) -> FC."""
+    x = images[:, None] if images.ndim == 3 else images
+    K = wc.shape[2]
+    H, W = x.shape[2], x.shape[3]
+    y = conv2d_fp64(x, wc, 1, 0, 0, H - K + 1, W - K + 1)
+    a = poly_fp64(y, coef)
+    p = avgpool2_fp64(a)
+    return p.reshape(p.shape[0], -1) @ wfc.T
+
+
+def enc_sum_pool2x2_slot(o, xs, C, H, W, cnt):
+    """y[c][i][j] = x[c][2i][2j] + x[c][2i][2j+1] + x[c][2i+1][2j] + x[c][2i+1][2j+1]."""
+    out = []
+    for c in range(C):
+        for i in range(H // 2):
+            for j in range(W // 2):
+                def at(yy, xx):
+                    return xs[(c * H + yy) * W + xx]
+                t = o.add(at(2 * i, 2 * j), at(2 * i, 2 * j + 1))
+                t = o.add(t, at(2 * i + 1, 2 * j))
+                out.append(o.add(t, at(2 * i + 1, 2 * j + 1)))
+                cnt.ct_add += 3
+    return out
+
+
+def enc_paper_cnn(o, rlk, X, Wc, Wf, C, K, H, W, n_classes, cnt, coef=G_PAPER):
+    """The paper's network on the oracle: conv, g/4 on every output (depth 2), sum
+    pooling (= the mean of g), drop to two limbs, FC; returns (stages, scores)."""
+    Ho, Wo = H - K + 1, W - K + 1
+    Y = enc_conv2d_slot(o, rlk, X, H, W, 1, Wc, C, K, K, 1, 0, 0, Ho, Wo, cnt)
+    A = enc_poly_act(o, rlk, Y, tuple(c / 4.0 for c in coef), 2, cnt)
+    Pp = enc_sum_pool2x2_slot(o, A, C, Ho, Wo, cnt)
+    Pd = [o.drop_level(p, 2) for p in Pp]
+    Z = enc_fc_slot(o, rlk, Pd, Wf, n_classes, cnt)
+    return {"conv": Y, "act": A, "pool": Pp, "fc": Z}, Z

@@ -436,6 +436,44 @@ fhe_status fhe_square_act(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint3
     return FHE_OK;
 }
 
+fhe_status fhe_pool2x2_sum_slot(fhe_ctx *c, const fhe_ct *x, uint32_t C, uint32_t H, uint32_t W, fhe_ct *y)
+{
+    fhe_status s;
+    if (!c || !x || !y || !C || H < 2 || W < 2) return fhe_fail(FHE_EINVAL, "fhe_pool2x2_sum_slot: null or empty");
+    const uint32_t l = x[0].limbs, Hp = H / 2, Wp = W / 2, n = C * Hp * Wp;
+    for (uint32_t i = 0; i < C * H * W; ++i) {
+        if ((s = chk_in(&x[i], l, "fhe_pool2x2_sum_slot"))) return s;
+        if (!same_scale(x[i].scale, x[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_pool2x2_sum_slot: scales differ");
+    }
+    std::vector<const uint64_t *> a(n), b(n), cc(n), d(n), yc(n);
+    std::vector<uint64_t *> yo(n);
+    for (uint32_t ch = 0; ch < C; ++ch)
+        for (uint32_t i = 0; i < Hp; ++i)
+            for (uint32_t j = 0; j < Wp; ++j) {
+                const uint32_t o = (ch * Hp + i) * Wp + j;
+                auto at = [&](uint32_t yy, uint32_t xx) { return x[((size_t)ch * H + yy) * W + xx].d; };
+                if ((s = chk_in(&y[o], l, "fhe_pool2x2_sum_slot"))) return s;
+                a[o] = at(2 * i, 2 * j);
+                b[o] = at(2 * i, 2 * j + 1);
+                cc[o] = at(2 * i + 1, 2 * j);
+                d[o] = at(2 * i + 1, 2 * j + 1);
+                for (const uint64_t *q : {a[o], b[o], cc[o], d[o]}) {
+                    const uint64_t *ye = y[o].d + 2 * (size_t)l * c->N, *qe = q + 2 * (size_t)l * c->N;
+                    if (y[o].d < qe && q < ye) return fhe_fail(FHE_EINVAL, "fhe_pool2x2_sum_slot: output overlaps an input");
+                }
+                yo[o] = y[o].d;
+                yc[o] = y[o].d;
+            }
+    Consts64 z;
+    std::memset(&z, 0, sizeof(z));
+    if ((s = ew_batch(c, EW_ADD, l, l, 2, n, a.data(), b.data(), yo.data(), z))) return s;
+    if ((s = ew_batch(c, EW_ADD, l, l, 2, n, yc.data(), cc.data(), yo.data(), z))) return s;
+    if ((s = ew_batch(c, EW_ADD, l, l, 2, n, yc.data(), d.data(), yo.data(), z))) return s;
+    for (uint32_t o = 0; o < n; ++o) y[o].scale = x[0].scale;
+    c->ops[OP_CT_ADD] += 3 * (uint64_t)n;
+    return FHE_OK;
+}
+
 fhe_status fhe_encrypt_const_batch(fhe_ctx *c, const fhe_ct *pk, const double *values, uint32_t n, double scale,
                                    const uint64_t *seeds, fhe_ct *out)
 {

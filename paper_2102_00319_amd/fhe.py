@@ -106,6 +106,7 @@ _sig = {
     "fhe_profile_read": [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)],
     "fhe_add_const": [_P, C.POINTER(fhe_ct), C.c_double, C.POINTER(fhe_ct)],
     "fhe_decode_slots": [_P, C.POINTER(fhe_pt), _P, C.c_uint32, _P, _P],
+    "fhe_pool2x2_sum_slot": [_P, C.POINTER(fhe_ct), C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_batch_run": [_P, C.POINTER(fhe_op), C.c_uint32],
     "fhe_graph_begin": [_P, C.c_uint32, C.c_uint64, C.POINTER(_P)],
     "fhe_graph_end": [_P, C.c_uint32, _P],
@@ -564,6 +565,13 @@ class Context:
         y = [self.new_ct(l - 1, 2) for _ in range(n_out)]
         XA, WA, YA = self._arr(x), self._arr(Wt), self._arr(y)
         _check(_lib.fhe_fc_slot(self._h, C.byref(rlk.s()), XA, len(x), WA, n_out, YA))
+        self._back(YA, y)
+        return y
+
+    def pool2x2_sum_slot(self, x, C_, H, W):
+        y = [self.new_ct(x[0].limbs, 2) for _ in range(C_ * (H // 2) * (W // 2))]
+        XA, YA = self._arr(x), self._arr(y)
+        _check(_lib.fhe_pool2x2_sum_slot(self._h, XA, C_, H, W, YA))
         self._back(YA, y)
         return y
 

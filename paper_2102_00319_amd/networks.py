@@ -214,3 +214,81 @@ class SlotCNN:
         for r, z in enumerate(Z):
             out[:, r], _ = ctx.decode_slots(ctx.decrypt(s, z), slots)
         return out
+
+
+class PaperCNN:
+    """The paper's network (Sec. 4.3) with slot packing (one image per slot):
+        conv K x K, stride 1, no padding, C filters -> ActPool (g on every output,
+        then the mean of each 2x2 window, Eq. (ActPool)) -> FC (C*Hp*Wp -> classes).
+    g(u) = 0.47 + 0.50 u + 0.09 u^2 (Eq. (approxReLU)); the 1/4 of the mean is folded
+    into g's coefficients, so that pooling is three additions.  The conv and ActPool
+    run in bands of pooled rows (the conv outputs of one band are freed before the
+    next), and the pooled maps drop to two limbs before the FC, whose weights the
+    model owner encrypts at that level."""
+
+    def __init__(self, H=28, W=28, K=3, C=28, n_classes=10, coef=(0.47, 0.50, 0.09), band=1):
+        self.H, self.W, self.K, self.C, self.n_classes = H, W, K, C, n_classes
+        self.Ho, self.Wo = H - K + 1, W - K + 1
+        if self.Ho % 2 or self.Wo % 2:
+            raise ValueError("conv output sides must be even (2x2 pooling)")
+        self.Hp, self.Wp = self.Ho // 2, self.Wo // 2
+        self.coef = tuple(coef)
+        self.coef4 = tuple(c / 4.0 for c in coef)
+        self.band = band
+
+    @property
+    def n_in_fc(self):
+        return self.C * self.Hp * self.Wp
+
+    def keygen(self, ctx, s, seed):
+        return ctx.keygen_relin(s, seed), {}
+
+    def encrypt_images(self, ctx, pk, images, seed, slot_offset=0, scale=None):
+        B = images.shape[0]
+        out = []
+        for y in range(self.H):
+            for x in range(self.W):
+                v = np.zeros(slot_offset + B)
+                v[slot_offset:] = images[:, y, x]
+                out.append(ctx.encrypt(pk, ctx.encode(v, scale=scale or ctx.scale), seed + y * self.W + x))
+        return out
+
+    def encrypt_weights(self, ctx, pk, wc, wfc, seeds, top=None, scale=None):
+        """wc [C][1][K][K] at the top level, wfc [classes][C*Hp*Wp] at two limbs."""
+        top = ctx.L if top is None else top
+        D = scale or ctx.scale
+        Wc = ctx.encrypt_const_batch(pk, wc.ravel(), D, [seeds[0] + t for t in range(wc.size)], top)
+        Wf = ctx.encrypt_const_batch(pk, wfc.ravel(), D, [seeds[1] + t for t in range(wfc.size)], 2)
+        return Wc, Wf
+
+    def forward(self, ctx, rlk, gks, X, weights):
+        Wc, Wf = weights
+        pooled = [None] * self.n_in_fc
+        for i0 in range(0, self.Hp, self.band):
+            i1 = min(self.Hp, i0 + self.band)
+            rows = 2 * (i1 - i0)
+            Xs = X[2 * i0 * self.W:(2 * i1 + self.K - 1) * self.W]
+            Y = ctx.conv2d_slot(rlk, Xs, rows + self.K - 1, self.W, 1, Wc, self.C, self.K, self.K, 1, 0, 0,
+                                rows, self.Wo)
+            A = ctx.poly_act(rlk, Y, self.coef4, 2)
+            del Y
+            Pb = ctx.pool2x2_sum_slot(A, self.C, rows, self.Wo)
+            del A
+            for c in range(self.C):
+                for i in range(i1 - i0):
+                    for j in range(self.Wp):
+                        p = Pb[(c * (i1 - i0) + i) * self.Wp + j]
+                        pooled[(c * self.Hp + i0 + i) * self.Wp + j] = ctx.drop_level(p, 2)
+        return ctx.fc_slot(rlk, pooled, Wf, self.n_classes)
+
+    def decrypt_scores(self, ctx, s, Z, B, slot_offset=0):
+        out = np.empty((B, len(Z)))
+        slots = np.arange(slot_offset, slot_offset + B)
+        for r, z in enumerate(Z):
+            out[:, r], _ = ctx.decode_slots(ctx.decrypt(s, z), slots)
+        return out
+
+    def op_counts(self):
+        n_conv = self.C * self.Ho * self.Wo
+        return {"ct_mult": n_conv * self.K * self.K + n_conv + self.n_in_fc * self.n_classes,
+                "relin": n_conv * 2 + self.n_classes}

@@ -2,7 +2,8 @@
 the op-count formula of the paper and the FP64 network shape arithmetic."""
 import numpy as np
 
-from oracle import cnn
+import workloads
+from oracle import OracleCtx, cnn
 
 
 def test_conv_count_matches_paper_formula_without_padding():
@@ -45,3 +46,29 @@ def test_fp64_forward_matches_direct_sum():
     h = (conv ** 2).reshape(3, -1)
     ref = ((h @ f1.T) ** 2) @ f2.T
     assert np.allclose(out, ref, rtol=1e-12, atol=1e-14)
+
+
+def test_paper_network_on_oracle():
+    """The paper's network (Sec. 4.3) shrunk to N = 2^12: 6x6 images, conv 3x3 x 2
+    filters without padding, ActPool with g/4 folded, FC 8 -> 2; scores within 1e-3
+    of the FP64 network with the exact 2x2 mean of g."""
+    o = OracleCtx.from_set("t_n12")
+    D, B = o.scale, o.N // 2
+    imgs = workloads.images(workloads.SEED_DATA, B, 6, 6)
+    wc = workloads.weights(workloads.SEED_DATA + 1, (2, 1, 3, 3))
+    wfc = workloads.weights(workloads.SEED_DATA + 2, (2, 8))
+    s = o.keygen_secret(workloads.SEED_SECRET)
+    pk = o.keygen_pk(s, workloads.SEED_PK)
+    rlk = o.keygen_relin(s, workloads.SEED_EVK)
+    X = [o.encrypt(pk, o.encode_rns(imgs[:, y, x], D, o.L), workloads.SEED_ENC + y * 6 + x, D)
+         for y in range(6) for x in range(6)]
+    Wc = [cnn.encrypt_const(o, pk, v, D, o.L, workloads.SEED_ENC + 100000 + t) for t, v in enumerate(wc.ravel())]
+    Wf = [cnn.encrypt_const(o, pk, v, D, 2, workloads.SEED_ENC + 200000 + t) for t, v in enumerate(wfc.ravel())]
+    cnt = cnn.Counter()
+    _, Z = cnn.enc_paper_cnn(o, rlk, X, Wc, Wf, 2, 3, 6, 6, 2, cnt)
+    ref = cnn.paper_cnn_fp64(imgs, wc, wfc)
+    for r in range(2):
+        re, _ = o.decode(o.decrypt(Z[r], s), Z[r].scale, n=B)
+        assert np.abs(re - ref[:, r]).max() < 1e-3
+    assert cnt.ct_mult == 2 * 4 * 4 * 9 + 2 * 4 * 4 + 8 * 2
+    assert cnt.relin == 2 * 16 + 2 * 16 + 2   # conv outputs, one product each in g, FC outputs
