@@ -146,17 +146,23 @@ __global__ __launch_bounds__(WG) void k_ks_intt_first(uint64_t *const *__restric
     for (int k = 0; k < R; k++) dst[gm.inv_out(k)] = f64_to_bits(x[k]);
 }
 
-// 4b. Key inner product, one thread per coefficient of one limb x of Q_l u P
-//     (blockIdx.y + y0 = entry of the inner list):
+// 4b. Key inner product, one thread per pair of coefficients (16-byte loads) of
+//     one limb x of Q_l u P (blockIdx.y + y0 = entry of the inner list):
 //     u_t[x] = sum_j D_j[x] * evk_{j,t}[x]; D_j[x] is the input limb itself
 //     inside digit j, else the converted limb.
+__device__ __forceinline__ void ld2(const uint64_t *p, double &a, double &b)
+{
+    const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(p);
+    a = u64_to_f64(v.x);
+    b = u64_to_f64(v.y);
+}
 __global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ tab, KsTab t, uint32_t y0,
                                                   const uint64_t *__restrict__ up, uint64_t *__restrict__ uQ,
                                                   uint64_t *__restrict__ uP, const ModQ *__restrict__ mods,
                                                   uint32_t alpha, uint32_t logN)
 {
     const uint32_t N = 1u << logN;
-    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
+    const uint32_t k = 2 * (blockIdx.x * TPB + threadIdx.x);
     if (k >= N) return;
     const uint64_t e = tab_word(tab, t.il, blockIdx.y + y0);
     const uint32_t b = (uint32_t)(e >> 16), x = (uint32_t)(e & 0xFFFF);
@@ -167,18 +173,27 @@ __global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ 
     const uint64_t *d = tab[b], *ev = tab[t.n + b];
     const uint64_t *upb = up + (size_t)it.up_off * N;
     const size_t ML = t.L + t.K;
-    double a0 = 0.0, a1 = 0.0;
+    double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
     for (uint32_t j = 0; j < it.nd; ++j) {
         const uint32_t lo = j * alpha, hi = min(lo + alpha, l);
-        double D;
-        if (x >= lo && x < hi) D = u64_to_f64(d[(size_t)x * N + k]);
+        double D0, D1, e00, e01, e10, e11;
+        if (x >= lo && x < hi) ld2(d + (size_t)x * N + k, D0, D1);
         else {
             const uint32_t pos = x < lo ? x : x - (hi - lo);
-            D = u64_to_f64(upb[(size_t)(it.upoff[j] + pos) * N + k]);
+            ld2(upb + (size_t)(it.upoff[j] + pos) * N + k, D0, D1);
         }
-        a0 += mulmod(D, u64_to_f64(ev[(((size_t)j * 2 + 0) * ML + mx) * N + k]), q, qi);
-        a1 += mulmod(D, u64_to_f64(ev[(((size_t)j * 2 + 1) * ML + mx) * N + k]), q, qi);
-        if ((j & 3) == 3) { a0 = redc(a0, q, qi); a1 = redc(a1, q, qi); }
+        ld2(ev + (((size_t)j * 2 + 0) * ML + mx) * N + k, e00, e01);
+        ld2(ev + (((size_t)j * 2 + 1) * ML + mx) * N + k, e10, e11);
+        a0 += mulmod(D0, e00, q, qi);
+        c0 += mulmod(D1, e01, q, qi);
+        a1 += mulmod(D0, e10, q, qi);
+        c1 += mulmod(D1, e11, q, qi);
+        if ((j & 3) == 3) {
+            a0 = redc(a0, q, qi);
+            c0 = redc(c0, q, qi);
+            a1 = redc(a1, q, qi);
+            c1 = redc(c1, q, qi);
+        }
     }
     uint64_t *o0, *o1;
     if (x < l) {
@@ -188,8 +203,10 @@ __global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ 
         o0 = uP + ((size_t)b * 2 * t.K + (x - l)) * N;
         o1 = uP + ((size_t)b * 2 * t.K + t.K + (x - l)) * N;
     }
-    o0[k] = f64_to_u64(canon(a0, q, qi));
-    o1[k] = f64_to_u64(canon(a1, q, qi));
+    *reinterpret_cast<ulonglong2 *>(o0 + k) =
+        make_ulonglong2(f64_to_u64(canon(a0, q, qi)), f64_to_u64(canon(c0, q, qi)));
+    *reinterpret_cast<ulonglong2 *>(o1 + k) =
+        make_ulonglong2(f64_to_u64(canon(a1, q, qi)), f64_to_u64(canon(c1, q, qi)));
 }
 
 // 8. Forward row pass of z fused with the ModDown finish:
@@ -525,7 +542,8 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     {
         ProfScope ps(c, "ks_inner");
         in_pieces(pl.sum_inner, [&](uint32_t y0, uint32_t cnt) {
-            hipLaunchKernelGGL(k_ks_inner, dim3(gx, cnt), dim3(TPB), 0, st, (uint64_t *const *)dt, kt, y0,
+            hipLaunchKernelGGL(k_ks_inner, dim3(blocks_for(N / 2, TPB), cnt), dim3(TPB), 0, st, (uint64_t *const *)dt,
+                               kt, y0,
                                (const uint64_t *)up, uQ, uP, (const ModQ *)c->d_mod, c->alpha, c->logN);
         });
     }

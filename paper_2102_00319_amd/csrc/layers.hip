@@ -33,8 +33,9 @@ __global__ __launch_bounds__(TPB) void k_tensor_tile(uint64_t *const *__restrict
                                                      uint32_t n_out, const ModQ *__restrict__ mods, uint32_t logN,
                                                      uint32_t limbs)
 {
+    // two consecutive coefficients per thread (16-byte loads and stores)
     const uint32_t N = 1u << logN;
-    const uint64_t e = (uint64_t)blockIdx.x * TPB + threadIdx.x;   // limb * N + k
+    const uint64_t e = 2 * ((uint64_t)blockIdx.x * TPB + threadIdx.x);   // limb * N + k, k even
     if (e >= ((uint64_t)limbs << logN)) return;
     const uint64_t w0 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * blockIdx.y];
     const uint64_t w1 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * blockIdx.y + 1];
@@ -44,39 +45,55 @@ __global__ __launch_bounds__(TPB) void k_tensor_tile(uint64_t *const *__restrict
     const uint32_t limb = (uint32_t)(e >> logN);
     const uint64_t off1 = (uint64_t)limbs * N;
     const double q = mods[limb].q, qi = mods[limb].qinv;
-    double d0[TO], d1[TO], d2[TO];
+    double d0[TO][2], d1[TO][2], d2[TO][2];
 #pragma unroll
-    for (int u = 0; u < TO; ++u) d0[u] = d1[u] = d2[u] = 0.0;
+    for (int u = 0; u < TO; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) d0[u][h] = d1[u][h] = d2[u][h] = 0.0;
     for (uint32_t p = 0; p < P; ++p) {
         const uint64_t *A = ap[p];
-        const double a0 = u64_to_f64(A[e]), a1 = u64_to_f64(A[e + off1]);
+        const ulonglong2 av0 = *reinterpret_cast<const ulonglong2 *>(A + e);
+        const ulonglong2 av1 = *reinterpret_cast<const ulonglong2 *>(A + e + off1);
+        const double a0[2] = {u64_to_f64(av0.x), u64_to_f64(av0.y)};
+        const double a1[2] = {u64_to_f64(av1.x), u64_to_f64(av1.y)};
 #pragma unroll
         for (int u = 0; u < TO; ++u) {
             if (u < (int)k) {
                 const uint64_t *Bp = bp[(size_t)u * P + p];
-                const double b0 = u64_to_f64(Bp[e]), b1 = u64_to_f64(Bp[e + off1]);
-                d0[u] += mulmod(a0, b0, q, qi);
-                d1[u] += mulmod(a0, b1, q, qi) + mulmod(a1, b0, q, qi);
-                d2[u] += mulmod(a1, b1, q, qi);
+                const ulonglong2 bv0 = *reinterpret_cast<const ulonglong2 *>(Bp + e);
+                const ulonglong2 bv1 = *reinterpret_cast<const ulonglong2 *>(Bp + e + off1);
+                const double b0[2] = {u64_to_f64(bv0.x), u64_to_f64(bv0.y)};
+                const double b1[2] = {u64_to_f64(bv1.x), u64_to_f64(bv1.y)};
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    d0[u][h] += mulmod(a0[h], b0[h], q, qi);
+                    d1[u][h] += mulmod(a0[h], b1[h], q, qi) + mulmod(a1[h], b0[h], q, qi);
+                    d2[u][h] += mulmod(a1[h], b1[h], q, qi);
+                }
             }
         }
         // |mulmod| <= 0.75 q + 2^46: four pairs keep every sum below 2^53 (q < 2^50)
         if ((p & 3) == 3) {
 #pragma unroll
-            for (int u = 0; u < TO; ++u) {
-                d0[u] = redc(d0[u], q, qi);
-                d1[u] = redc(d1[u], q, qi);
-                d2[u] = redc(d2[u], q, qi);
-            }
+            for (int u = 0; u < TO; ++u)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    d0[u][h] = redc(d0[u][h], q, qi);
+                    d1[u][h] = redc(d1[u][h], q, qi);
+                    d2[u][h] = redc(d2[u][h], q, qi);
+                }
         }
     }
 #pragma unroll
     for (int u = 0; u < TO; ++u) {
         if (u < (int)k) {
             uint64_t *out = tab[nA + nB + o0 + u];
-            out[e] = f64_to_u64(canon(d0[u], q, qi));
-            out[e + off1] = f64_to_u64(canon(d1[u], q, qi));
-            out[e + 2 * off1] = f64_to_u64(canon(d2[u], q, qi));
+            *reinterpret_cast<ulonglong2 *>(out + e) =
+                make_ulonglong2(f64_to_u64(canon(d0[u][0], q, qi)), f64_to_u64(canon(d0[u][1], q, qi)));
+            *reinterpret_cast<ulonglong2 *>(out + e + off1) =
+                make_ulonglong2(f64_to_u64(canon(d1[u][0], q, qi)), f64_to_u64(canon(d1[u][1], q, qi)));
+            *reinterpret_cast<ulonglong2 *>(out + e + 2 * off1) =
+                make_ulonglong2(f64_to_u64(canon(d2[u][0], q, qi)), f64_to_u64(canon(d2[u][1], q, qi)));
         }
     }
 }
@@ -235,7 +252,7 @@ fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const s
         {
             ProfScope ps(c, "tensor");
             if (ntiles > 65535u) return fhe_fail(FHE_EINVAL, "layer: too many tiles in one chunk");
-            hipLaunchKernelGGL(k_tensor_tile<MAC_TILE>, dim3(blocks_for((uint64_t)l * N, TPB), ntiles), dim3(TPB), 0,
+            hipLaunchKernelGGL(k_tensor_tile<MAC_TILE>, dim3(blocks_for((uint64_t)l * N / 2, TPB), ntiles), dim3(TPB), 0,
                                c->stream, (uint64_t *const *)dt, (uint32_t)ta.size(), (uint32_t)tb.size(), cn,
                                (const ModQ *)c->d_mod, c->logN, l);
         }

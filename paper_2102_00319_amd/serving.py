@@ -77,10 +77,11 @@ class Lane:
 
 class Server:
     def __init__(self, set_names, lanes=4, hbm_budget=250e9, merge=True, max_merge=64, scratch_bytes=4 << 30,
-                 device="cuda"):
+                 device="cuda", lane_factory=None):
         self.device = torch.device(device)
         self.scratch = int(scratch_bytes)   # device scratch a lane may hold while it runs
-        self.lanes = [Lane(set_names, self.device) for _ in range(lanes)]
+        make = lane_factory or (lambda: Lane(set_names, self.device))
+        self.lanes = [make() for _ in range(lanes)]
         self.budget, self.merge, self.max_merge = float(hbm_budget), merge, max_merge
         self.clients = []
         self.stats = collections.Counter()
@@ -104,10 +105,10 @@ class Server:
         net = req.client.net
         return int(len(req.payload) * ct * (4 + 2 * net.c2 + net.c1 * net.k * net.k) + self.scratch)
 
-    def _make_room(self, need, now):
-        """Evict least-recently-used idle clients until `need` more bytes fit."""
+    def _make_room(self, need, keep):
+        """Evict least-recently-used idle clients other than `keep` until `need` more bytes fit."""
         while self.resident_bytes() + need > self.budget:
-            idle = [c for c in self.clients if c.resident and c.inflight == 0]
+            idle = [c for c in self.clients if c.resident and c.inflight == 0 and c is not keep]
             if not idle:
                 return False
             victim = min(idle, key=lambda c: c.last_used)
@@ -122,7 +123,7 @@ class Server:
             c = req.client
             ws = self.working_set(req, lane)
             need = ws + (0 if c.resident else c.nbytes)
-            if self.resident_bytes() + need > self.budget and not self._make_room(need, now):
+            if self.resident_bytes() + need > self.budget and not self._make_room(need, c):
                 continue
             cold = not c.resident
             if cold:

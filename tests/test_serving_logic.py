@@ -1,0 +1,100 @@
+"""Host logic of the serving loop on the CPU: admission in arrival order under an
+HBM budget, least-recently-used eviction of idle clients only, slot merging of
+one client's queued requests with distinct slot ranges, and completion
+bookkeeping.  Lanes and clients are stand-ins; no device work is done."""
+import types
+
+import numpy as np
+
+from paper_2102_00319_amd import serving
+
+
+class FakeClient:
+    def __init__(self, cid, kind, nbytes):
+        self.cid, self.kind, self.nbytes, self.set_name = cid, kind, nbytes, "s"
+        self.resident, self.inflight, self.last_used, self.loads = True, 0, 0.0, 0
+        self.net = types.SimpleNamespace(H=4, W=4, Cout=1, Ho=2, Wo=2, c1=1, c2=1, k=3)
+
+    def evict(self):
+        assert self.inflight == 0, "evicted a client with work in flight"
+        self.resident = False
+
+    def restore(self):
+        self.resident = True
+        self.loads += 1
+
+
+class FakeLane:
+    def __init__(self):
+        self.ctx = {"s": types.SimpleNamespace(L=2, N=4)}
+        self.group, self.thread, self.finished, self.error, self.ws = None, None, False, None, 0
+
+
+class FakeServer(serving.Server):
+    """Every batch finishes on the next poll; records what ran together."""
+
+    def __init__(self, **kw):
+        super().__init__(["s"], lane_factory=FakeLane, device="cpu", scratch_bytes=0, **kw)
+        self.batches = []
+
+    def _launch(self, lane, group, ws, now_fn):
+        # the admitted batch's client state and working set fit the budget
+        assert self.resident_bytes() + ws <= self.budget
+        assert group[0].client.resident
+        self.batches.append([r.rid for r in group])
+        for r in group:
+            r.scores = np.full((r.n, 1), float(r.rid))
+            r.t_done = now_fn()
+        lane.group, lane.ws, lane.finished, lane.error = group, ws, True, None
+        lane.thread = types.SimpleNamespace(join=lambda: None)
+
+
+def _ws(srv, req):
+    return srv.working_set(req, srv.lanes[0])
+
+
+def test_merging_takes_distinct_slot_ranges_of_one_client():
+    srv = FakeServer(lanes=1, hbm_budget=1e12, merge=True, max_merge=3)
+    a, b = FakeClient(0, "slot", 100), FakeClient(1, "slot", 100)
+    for c in (a, b):
+        srv.add_client(c)
+    reqs = [serving.Request(i, c, [None], 1, 64 * t, 0.0, t)
+            for i, (c, t) in enumerate([(a, 0), (a, 0), (a, 1), (b, 0), (a, 2), (a, 3)])]
+    srv.run(reqs, time_limit=10)
+    # first batch: request 0 plus the next requests of the same client with new tags (1 dup skipped), at most 3
+    assert srv.batches[0] == [0, 2, 4]
+    assert all(r.scores is not None for r in reqs)
+    assert {r.rid: r.merged for r in reqs}[0] == 3
+
+
+def test_budget_admission_and_lru_eviction():
+    srv = FakeServer(lanes=2, hbm_budget=0, merge=False)
+    cs = [FakeClient(i, "packed", 1000) for i in range(3)]
+    for c in cs:
+        srv.add_client(c)
+    probe = serving.Request(99, cs[0], [None], 1, 0, 0.0, 0)
+    ws = _ws(srv, probe)
+    # room for two client states and one working set
+    srv.budget = 2 * 1000 + ws
+    reqs = [serving.Request(i, cs[i % 3], [None], 1, 0, 0.001 * i, 0) for i in range(9)]
+    srv.run(reqs, time_limit=10)
+    assert all(r.t_done is not None for r in reqs)
+    # three clients over two resident slots: evictions and cold loads must have happened
+    assert srv.stats["evictions"] > 0 and srv.stats["cold_loads"] > 0
+    assert sum(c.resident for c in cs) <= 2
+    # admission is in arrival order: completion order follows request ids
+    order = [rid for b in srv.batches for rid in b]
+    assert order == sorted(order)
+
+
+def test_request_that_cannot_fit_waits_for_running_work():
+    srv = FakeServer(lanes=2, hbm_budget=0, merge=False)
+    c0, c1 = FakeClient(0, "packed", 1000), FakeClient(1, "packed", 1000)
+    srv.add_client(c0)
+    srv.add_client(c1)
+    ws = _ws(srv, serving.Request(0, c0, [None], 1, 0, 0.0, 0))
+    srv.budget = 1000 + ws          # only one client and one working set at a time
+    reqs = [serving.Request(0, c0, [None], 1, 0, 0.0, 0), serving.Request(1, c1, [None], 1, 0, 0.0, 0)]
+    srv.run(reqs, time_limit=10)
+    assert [b for b in srv.batches] == [[0], [1]]
+    assert c1.loads == 0 or c0.resident is False
