@@ -51,6 +51,21 @@ def measured_traffic(kernel):
         return None
 
 
+def _oracle_keyswitch_once(arg):
+    """One oracle key switch on random data (a separate process per host core)."""
+    name, seed = arg
+    sys.path.insert(0, ROOT)
+    import workloads
+    from oracle import OracleCtx
+    o = OracleCtx.from_set(name)
+    M = o.L + o.K
+    evk = workloads.uniform_residues(seed, o.moduli * (2 * o.dnum), o.N).reshape(o.dnum, 2, M, o.N)
+    d = workloads.uniform_residues(seed + 1, o.q, o.N)
+    t0 = time.perf_counter()
+    o.keyswitch(d, evk)
+    return time.perf_counter() - t0
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,7 +76,10 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB copy kernel (reference for HBM byte counters)")
     ap.add_argument("--param-set", default="c4_n16")
-    ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "cnn2", "cnn4", "batch3", "serve", "fig3", "paper"],
+    ap.add_argument("--ks-fuse", type=int, default=1, choices=[0, 1],
+                    help="keyswitch: fuse the digits' row pass into the key inner product (1) or not (0)")
+    ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "kssweep", "cnn2", "cnn4", "batch3", "serve", "fig3", "paper",
+                                                           "latency"],
                     help="keyswitch: the headline metric; cnn2: slot-packed encrypted CNN images/s; "
                          "cnn4: within-image packed deep CNN images/s; batch3: 256 uneven jobs (mixed N and "
                          "level) per step")
@@ -83,19 +101,21 @@ def ks_shape(logN):
     return logN - logB, logB
 
 
-def kernel_model(cat, N, l, K, alpha, B, dnum, L):
-    """Algorithmic work of one step (B key switches) per kernel category:
-    (bytes moved to and from HBM by the algorithm, FP64 flops)."""
+def kernel_model(cat, N, l, K, alpha, B, dnum, L, fused=True):
+    """Algorithmic work of one step (B key switches, each with its own key) per kernel
+    category: (bytes moved to and from HBM by the algorithm, FP64 flops).  fused: the
+    row pass of the converted digits runs inside the key inner product."""
     limb = N * 8
     logN = N.bit_length() - 1
     nd = (l + alpha - 1) // alpha
     ups = sum(l + K - min(alpha, l - j * alpha) for j in range(nd))
     logA, logB = ks_shape(logN)
     bfly = (N // 2) * FLOPS_PER_BUTTERFLY     # flops of one stage over one limb
-    if cat == "ntt_fwd_col":
-        n = B * (ups + 2 * l)
-        return 2 * n * limb, n * logA * bfly
+    if cat == "ntt_fwd_col":   # not launched by the key-switch path (fused into the conversions)
+        return 0, 0
     if cat == "ntt_fwd_row":
+        if fused:
+            return 0, 0
         n = B * ups
         return 2 * n * limb, n * logB * bfly
     if cat == "ntt_inv_col":
@@ -112,12 +132,16 @@ def kernel_model(cat, N, l, K, alpha, B, dnum, L):
         # z in, u in, out; the rotation addend sigma_g(c0); one exact product per element
         return (3 * n + B * l) * limb, n * logB * bfly + n * N * 8
     if cat == "ks_inner":
-        # D_j and both key polynomials per digit in, u out (2 products per element per digit)
-        return B * (3 * nd * (l + K) + 2 * (l + K)) * limb, B * 2 * nd * (l + K) * N * 9
+        # D_j and both key polynomials per digit in, u out (2 products per element per
+        # digit); fused: D_j of the converted limbs enters in column-pass form and gets
+        # its row pass here
+        return (B * (3 * nd * (l + K) + 2 * (l + K)) * limb,
+                B * 2 * nd * (l + K) * N * 9 + (B * ups * logB * bfly if fused else 0))
     if cat == "bconv_up":
-        return B * (l + ups) * limb, B * ups * alpha * N * 9
+        # conversion fused with the forward column pass: the digit sources in, the converted limbs out
+        return B * (l + ups) * limb, B * (ups * alpha * N * 9 + ups * logA * bfly)
     if cat == "bconv_down":
-        return B * (2 * K + 2 * l) * limb, B * 2 * l * K * N * 9
+        return B * (2 * K + 2 * l) * limb, B * (2 * l * K * N * 9 + 2 * l * logA * bfly)
     if cat == "automorph":
         return B * 4 * l * limb, 0
     return 0, 0
@@ -393,6 +417,9 @@ def serve(args):
     print(json.dumps(rec))
 
 
+FIG3_SET = "c3_n15"   # N = 2^15 (the paper's m = 2^16), 16 limbs
+
+
 def fig3(args):
     """Ciphertext operation cost against the modulus size at the paper's ring (m = 2^16,
     N = 2^15, 16384 slots; Sec. 4.2, Fig. 3): for each limb count l, the average time of
@@ -405,7 +432,7 @@ def fig3(args):
     import paper_2102_00319_amd as P
 
     torch.cuda.set_device(0)
-    g = P.Context.from_set("p_n15")
+    g = P.Context.from_set(FIG3_SET)
     s = g.keygen_secret(workloads.SEED_SECRET)
     pk = g.keygen_pk(s, workloads.SEED_PK)
     rlk = g.keygen_relin(s, workloads.SEED_EVK)
@@ -449,7 +476,8 @@ def fig3(args):
                      "batched_mults_per_s": round(64 / t_b, 1)})
         print(json.dumps({"fig3_row": rows[-1]}), flush=True)
     print(json.dumps({"metric": "CT-CT add / mult time against the modulus size, N=2^15 (Fig. 3 analogue)",
-                      "rows": rows, "config": {"workload": "p_n15: q0 ~2^50, 15 primes ~2^40, 4 special, dnum 4"}}))
+                      "rows": rows, "config": {"workload": "%s: N=2^15, q0 ~2^45, 15 primes ~2^40, 4 special primes "
+                                                           "~2^46, dnum 4" % FIG3_SET}}))
 
 
 def _paper_cnn_fp64(imgs, wc, wfc, coef):
@@ -513,6 +541,105 @@ def paper(args):
            "config": {"workload": "conv3x3x28 (no pad) -> ActPool(g, 2x2 mean) -> FC4732x10, N=2^15, 16 limbs "
                                   "(q0 ~2^50, 15 x ~2^40), scale 2^40, 16384 images, band %d" % args.band}}
     print(json.dumps(rec))
+
+
+def kssweep(args):
+    """Key switches per second against batch size B in {1, 8, 32, 64}, with B distinct
+    Galois keys and with B ciphertexts sharing one key (N = 2^16, l = 24, K = 8,
+    dnum = 3); the compulsory bytes per key switch are the input, the output and the
+    key's share: (3 l + 2 dnum (L + K) / k) limbs with k items per key."""
+    import numpy as np
+    import torch
+
+    import workloads
+    import paper_2102_00319_amd as P
+
+    torch.cuda.set_device(0)
+    g = P.Context.from_set(args.param_set)
+    N, l = g.N, g.L
+    s = g.keygen_secret(workloads.SEED_SECRET)
+    pk = g.keygen_pk(s, workloads.SEED_PK)
+    Bmax = 64
+    gks = [g.keygen_rot(s, r, workloads.SEED_EVK + r) for r in range(1, Bmax + 1)]
+    cts = [g.encrypt(pk, g.encode(workloads.slot_messages(workloads.SEED_DATA + b, 64), scale=g.scale, limbs=l),
+                     workloads.SEED_ENC + b) for b in range(Bmax)]
+    outs = [g.new_ct(l, 2) for _ in range(Bmax)]
+    z0 = workloads.slot_messages(workloads.SEED_DATA, 64)
+    rows = []
+    for B in (1, 8, 32, 64):
+        for mode in ("distinct", "shared"):
+            keys = gks[:B] if mode == "distinct" else [gks[0]] * B
+            steps = list(range(1, B + 1)) if mode == "distinct" else [1] * B
+            g.rotate_batch(keys, cts[:B], steps, outs[:B])
+            got, _ = g.decode(g.decrypt(s, outs[0]), n=63)
+            assert np.abs(got - z0[1:64]).max() < 1e-6, "rotation result is wrong"
+            reps = max(2, min(args.steps, 256 // B))
+            for _ in range(2):
+                g.rotate_batch(keys, cts[:B], steps, outs[:B])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                g.rotate_batch(keys, cts[:B], steps, outs[:B])
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            per_key = B if mode == "shared" else 1
+            ks_bytes = (3 * l + 2 * g.dnum * (g.L + g.K) / per_key) * N * 8
+            rate = B / dt
+            rows.append({"batch": B, "keys": mode, "key_switch_per_s": round(rate, 1), "ms_per_batch": round(dt * 1e3, 3),
+                         "compulsory_MiB_per_ks": round(ks_bytes / 2 ** 20, 1),
+                         "hbm_frac_compulsory": round(rate * ks_bytes / (HBM_PEAK_GBS * 1e9), 4)})
+            print(json.dumps({"kssweep_row": rows[-1]}), file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "key-switch ops/s at N=2^16,L=24 against batch size, distinct or shared keys",
+                      "unit": "key-switch/s", "rows": rows,
+                      "config": {"workload": "rotation key switch, N=2^16, l=24, K=8, dnum=3"}}))
+
+
+def latency(args):
+    """Single-image latency with the whole image in one ciphertext (the low-latency
+    packing of Sec. 4.4, last paragraph): the deep within-image CNN at N = 2^16 on one
+    28x28 image, with the model encrypted and with the model in the clear.  The paper
+    reports 8.8 s and 2.5 s for its own single-image runs on its CPU (context only)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    import paper_2102_00319_amd as P
+    from paper_2102_00319_amd import networks
+
+    torch.cuda.set_device(0)
+    g = P.Context.from_set("c4_n16")
+    net = networks.PackedCNN()
+    img = workloads.images(workloads.SEED_DATA, 1, 28, 28)
+    w1 = workloads.weights(workloads.SEED_DATA + 1, (8, 1, 3, 3))
+    w2 = workloads.weights(workloads.SEED_DATA + 2, (16, 8, 3, 3))
+    wfc = workloads.weights(workloads.SEED_DATA + 3, (10, 784))
+    s = g.keygen_secret(workloads.SEED_SECRET)
+    pk = g.keygen_pk(s, workloads.SEED_PK)
+    rlk, gks = net.keygen(g, s, workloads.SEED_EVK)
+    X = net.encrypt_images(g, pk, img, workloads.SEED_ENC)
+    Wenc = net.encrypt_weights(g, pk, w1, w2, wfc, (workloads.SEED_ENC + 100000, workloads.SEED_ENC + 200000,
+                                                    workloads.SEED_ENC + 300000))
+    Wpt = net.plain_fc_weights(g, wfc, g.L - 8)
+    ref = _packed_cnn_fp64(img, w1, w2, wfc, net.coef)
+    res = {}
+    for name, run in [("encrypted_model", lambda: net.forward(g, rlk, gks, X, Wenc)),
+                      ("plain_model", lambda: net.forward_plain(g, rlk, gks, X, w1, w2, Wpt))]:
+        out = run()
+        err = float(np.abs(net.decrypt_scores(g, s, out, 1) - ref).max())
+        times = []
+        for _ in range(max(3, args.steps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = run()
+            scores = net.decrypt_scores(g, s, out, 1)   # the user decrypts: included in the latency
+            times.append(time.perf_counter() - t0)
+        times.sort()
+        res[name] = {"median_ms": round(times[len(times) // 2] * 1e3, 2), "min_ms": round(times[0] * 1e3, 2),
+                     "max_abs_logit_error_vs_fp64": err}
+    print(json.dumps({"metric": "single-image encrypted inference latency (deep CNN, one 28x28 image per "
+                                "ciphertext, N=2^16)", "unit": "ms", "results": res,
+                      "paper_context": "8.8 s (encrypted model) and 2.5 s (plain model) on the paper's CPU, "
+                                       "another machine and network"}))
 
 
 def cnn2(args):
@@ -612,6 +739,24 @@ def main():
         return fig3(args)
     if args.workload == "paper":
         return paper(args)
+    if args.workload == "latency":
+        return latency(args)
+    if args.workload == "kssweep":
+        return kssweep(args)
+    # CPU baseline first, before anything touches the GPU: the single-threaded oracle,
+    # one independent key switch per host core (separate processes)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import multiprocessing as mp
+        cores = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+        c0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(cores) as pool:
+            per = pool.map(_oracle_keyswitch_once, [(args.param_set, 90 + 2 * i) for i in range(cores)])
+        c1 = time.perf_counter()
+        cpu = {"value": round(cores / (c1 - c0), 4), "unit": "key-switch/s", "cores": cores, "kind": "oracle",
+               "sample": "%d key switches at N=2^16, l=24, K=8, dnum=3 (random inputs and keys), one per process, "
+                         "%.1f s wall (%.1f s per key switch)" % (cores, c1 - c0, sum(per) / len(per))}
+        print("cpu baseline: %s" % cpu["sample"], file=sys.stderr, flush=True)
     import numpy as np
     import torch
 
@@ -620,6 +765,7 @@ def main():
 
     torch.cuda.set_device(0)
     g = P.Context.from_set(args.param_set)
+    g.set_tuning("ks_fuse_row_inner", args.ks_fuse)
     N, l, K, alpha = g.N, g.L, g.K, g.alpha
     B = args.batch
     s = g.keygen_secret(workloads.SEED_SECRET)
@@ -680,7 +826,7 @@ def main():
     ks_bytes = (l + g.dnum * 2 * (g.L + g.K) + 2 * l) * N * 8
     hbm_frac = ks_per_s * ks_bytes / (HBM_PEAK_GBS * 1e9)
 
-    bytes_step, flops_step = kernel_model(dominant, N, l, K, alpha, B, g.dnum, g.L)
+    bytes_step, flops_step = kernel_model(dominant, N, l, K, alpha, B, g.dnum, g.L, fused=bool(args.ks_fuse))
     avg_ms = dom_ms / max(dom_cnt, 1)
     launches_per_step = dom_cnt / args.steps
     per_launch_b = bytes_step / max(launches_per_step, 1)
@@ -699,21 +845,6 @@ def main():
     roof["kernel"] = dominant
     roof["avg_launch_ms"] = round(avg_ms, 5)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import OracleCtx
-        o = OracleCtx.from_set(args.param_set)
-        M = o.L + o.K
-        evk = workloads.uniform_residues(90, o.moduli * (2 * o.dnum), o.N).reshape(o.dnum, 2, M, o.N)
-        d = workloads.uniform_residues(91, o.q, o.N)
-        reps = 3
-        c0 = time.perf_counter()
-        for _ in range(reps):
-            o.keyswitch(d, evk)
-        c1 = time.perf_counter()
-        cpu = {"value": round(reps / (c1 - c0), 4), "unit": "key-switch/s", "cores": 1, "kind": "oracle",
-               "sample": "%d key switches at N=2^16, l=24, K=8, dnum=3 (random input and key), %.1f s"
-                         % (reps, c1 - c0)}
 
     rec = {
         "metric": "key-switch ops/s at N=2^16,L=24",
@@ -730,7 +861,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rotation key switch, N=2^16, l=24 limbs (~49-bit), K=8 special primes, dnum=3, "
                                "%d distinct Galois keys per step" % B,
-                   "batch": B, "ring_degree": N, "limbs": l, "special_primes": K, "dnum": g.dnum},
+                   "batch": B, "ring_degree": N, "limbs": l, "special_primes": K, "dnum": g.dnum,
+                   "ks_fuse_row_inner": args.ks_fuse},
         "hbm_frac_compulsory": round(hbm_frac, 4),
         "roofline": roof,
         "cpu_baseline": cpu,

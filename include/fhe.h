@@ -162,7 +162,8 @@ fhe_status fhe_mul_acc(fhe_ctx *ctx, const fhe_ct *a, const fhe_ct *b, uint32_t 
 fhe_status fhe_relin(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *in3, fhe_ct *out2);
 fhe_status fhe_rescale(fhe_ctx *ctx, const fhe_ct *in, fhe_ct *out);
 fhe_status fhe_drop_level(fhe_ctx *ctx, const fhe_ct *in, uint32_t limbs, fhe_ct *out);
-/* Left rotation by step slots with the Galois key of that step. */
+/* Left rotation by step slots with the Galois key of that step; out may equal in
+ * (the permuted input is staged in the context's scratch). */
 fhe_status fhe_rotate(fhe_ctx *ctx, const fhe_evk *gk, const fhe_ct *in, int32_t step, fhe_ct *out);
 /* n independent rotations in one launch sequence: out[t] = rotate(in[t], steps[t])
  * with Galois key gk[t]; gk, in, steps, out are host arrays of n entries.
@@ -214,7 +215,10 @@ fhe_status fhe_graph_launch(fhe_graph *g, void *hip_stream);   /* null: the firs
 void fhe_graph_destroy(fhe_graph *g);                          /* waits for the device first */
 
 /* Tuning knobs read by the batched drivers (autotuned by the Python layer):
- *   "chunk_items": most items per ragged launch sequence (0 = no limit). */
+ *   "chunk_items": most items per ragged launch sequence (0 = no limit);
+ *   "ks_fuse_row_inner": 1 (default) fuses the forward row pass of the converted
+ *     digits into the key inner product when every item has its own key, 0 runs
+ *     them as two kernels (same results). */
 fhe_status fhe_ctx_set_tuning(fhe_ctx *ctx, const char *key, uint64_t value);
 
 /* Batched relinearisation and rescale of n ciphertexts (host descriptor arrays;
@@ -278,6 +282,17 @@ fhe_status fhe_avgpool2x2(fhe_ctx *ctx, const fhe_evk *keys, uint32_t nkeys, con
 fhe_status fhe_fc_packed(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *x,
                          uint32_t n_in, const fhe_ct *Wt, uint32_t n_out, uint32_t frame_slots, fhe_ct *y);
 
+/* The same layers with a plain (unencrypted) model, for the low-latency setting of
+ * one image per ciphertext (Sec. 4.4, last paragraph: model parameters not encrypted):
+ * fhe_conv2d_packed_pw: Y[co] = Rescale( sum_ci sum_(p,q) rot(X[ci], s_pq) * round(w[co][ci][p][q] * wscale) ),
+ *   w a host array [Cout][Cin][k][k]; no relinearisation; Y scale = X scale * wscale / q_(l-1).
+ * fhe_fc_packed_pw: z[o] = Rescale( sum_i x[i] * W[o*n_in + i] ) with plaintext weights (slot
+ *   vectors at the valid positions, at the inputs' level), then the rotate-and-sum of fhe_fc_packed. */
+fhe_status fhe_conv2d_packed_pw(fhe_ctx *ctx, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *X, uint32_t Cin,
+                                const double *w, uint32_t Cout, uint32_t k, uint32_t dilation, uint32_t frame_w,
+                                double wscale, fhe_ct *Y);
+fhe_status fhe_fc_packed_pw(fhe_ctx *ctx, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *x, uint32_t n_in,
+                            const fhe_pt *Wt, uint32_t n_out, uint32_t frame_slots, fhe_ct *y);
 /* Sum pooling over 2x2 windows of slot-packed maps (Eq. (ActPool) without the 1/4,
  * which a recipe folds into the activation's coefficients):
  *   y[c][i][j] = x[c][2i][2j] + x[c][2i][2j+1] + x[c][2i+1][2j] + x[c][2i+1][2j+1],

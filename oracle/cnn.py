@@ -325,3 +325,55 @@ def enc_paper_cnn(o, rlk, X, Wc, Wf, C, K, H, W, n_classes, cnt, coef=G_PAPER):
     Pd = [o.drop_level(p, 2) for p in Pp]
     Z = enc_fc_slot(o, rlk, Pd, Wf, n_classes, cnt)
     return {"conv": Y, "act": A, "pool": Pp, "fc": Z}, Z
+
+
+# -------------------------------------- within-image packing, plain model
+def enc_conv2d_packed_pw(o, gks, X, Cin, w, Cout, k, dil, frame_w, wscale, cnt):
+    """Y[co] = Rescale( sum_ci sum_t rot(X[ci], s_t) * round(w[co][ci][t] * wscale) )."""
+    steps = conv_steps(k, dil, frame_w)
+    R = []
+    for ci in range(Cin):
+        row = []
+        for r in steps:
+            if r == 0:
+                row.append(X[ci])
+            else:
+                row.append(o.rotate(X[ci], r, gks[r]))
+                cnt.rotate += 1
+        R.append(row)
+    w = np.asarray(w, dtype=np.float64).reshape(Cout, Cin, k * k)
+    Y = []
+    for co in range(Cout):
+        acc = None
+        for ci in range(Cin):
+            for t in range(k * k):
+                term = o.mul_const(R[ci][t], int(np.rint(w[co, ci, t] * wscale)), wscale)
+                acc = term if acc is None else o.add(acc, term)
+                cnt.pt_mult += 1
+        cnt.ct_add += Cin * k * k - 1
+        cnt.rescale += 1
+        Y.append(o.rescale(acc))
+    return Y
+
+
+def enc_fc_packed_pw(o, gks, xs, Wpt, pt_scale, n_out, frame_slots, cnt):
+    """z[r] = Rescale( sum_c x[c] * W[r][c] ) with plaintext weights, then rotate-and-sum."""
+    n_in = len(xs)
+    out = []
+    for r in range(n_out):
+        acc = None
+        for c in range(n_in):
+            term = o.mul_pt(xs[c], Wpt[r * n_in + c], pt_scale)
+            acc = term if acc is None else o.add(acc, term)
+            cnt.pt_mult += 1
+        cnt.ct_add += n_in - 1
+        cnt.rescale += 1
+        z = o.rescale(acc)
+        i = 1
+        while i < frame_slots:
+            z = o.add(z, o.rotate(z, i, gks[i]))
+            cnt.rotate += 1
+            cnt.ct_add += 1
+            i *= 2
+        out.append(z)
+    return out

@@ -170,6 +170,7 @@ struct fhe_ctx {
     uint8_t *cap_host, *cap_dev;
     size_t cap_bytes, cap_used;
     uint32_t tune_chunk;     // most items per ragged launch sequence (0: no limit)
+    uint32_t tune_fuse_row_inner;   // key switch: fuse the digits' row pass into the inner product
     struct Prof *prof;       // kernel timing (HIP events), null until enabled
     uint64_t ops[8];         // operation counters, see OP_* (read and reset by fhe_op_counts)
 };

@@ -18,16 +18,22 @@
 // Kernel sequence (every transform split into a column pass and a row pass of at
 // most 2^8 elements, so that the fused row kernels run in 256-thread groups):
 //   1 k_ks_intt_first   inverse row pass of d_b, gathered through gal_b  -> dc
-//     inverse column pass                                               -> dc (coefficients)
-//   2 k_bconv           ModUp conversion of every digit                  -> up
-//   3 forward column and row passes of up
+//     k_col_inv         inverse column pass, times (Q_j/q_a)^-1 mod q_a   -> dc (conversion sources)
+//   2 k_col_fwd_bconv   per converted limb: the ModUp sum over its digit's sources,
+//                       then the forward column pass                     -> up
+//   3 k_row_fwd         forward row pass of up
 //   4 k_ks_inner        key inner product over the digits                -> uQ, uP
-//   5 inverse transform of uP (coefficients)
-//   6 k_bconv<true>     rounded conversion P -> Q_l                       -> z
-//   7 forward column pass of z
-//   8 k_ks_moddown_final forward row pass of z fused with (u - z) P^-1 + add -> out
+//   5 k_row_inv, k_col_inv  inverse transform of uP, plus (P-1)/2, times (P/p_a)^-1
+//   6 k_col_fwd_bconv   per limb of Q_l: the ModDown sum over P, minus (P-1)/2,
+//                       then the forward column pass                     -> z
+//   7 k_ks_moddown_final forward row pass of z fused with (u - z) P^-1 + add -> out
+// The conversions are recomputed per target limb from the sources, which the
+// column blocks of all the targets of one digit read while they are in cache,
+// so the converted limbs never make a round trip through HBM before their
+// first transform pass.
 #include <algorithm>
 #include <cstring>
+#include <map>
 
 #include "ntt_core.h"
 
@@ -57,14 +63,27 @@ struct BcJob {          // one basis conversion: nsrc source limbs -> ndst desti
     uint32_t pad;
 };
 static_assert(sizeof(BcJob) == 24, "BcJob is 3 table words");
+// Items of one batch that use the same key at the same level share the key reads
+// of the inner product: up to KS_GRP of them form a group.
+constexpr uint32_t KS_GRP = 8;
+struct KsGrp {
+    uint32_t m;              // members
+    uint16_t it[KS_GRP];     // item indices
+    uint32_t pad;
+};
+static_assert(sizeof(KsGrp) == 24, "KsGrp is 3 table words");
 // Word offsets of the sections of one batch's table:
 //   [d: n][evk: n][out: n][add: 2n][gal: n][items: 7n][la: sum l][upjobs: 3 sum nd]
-//   [upmods: sum ups][inner: sum (l + K)][dnjobs: 3 * 2n][fl: sum 2l]
-// la entries: item << 16 | limb (dc order); inner: item << 16 | x (x < l: Q limb,
-// else special prime x - l); fl: item << 17 | poly << 16 | limb (z and uQ order).
+//   [upmods: sum ups][inner: sum over groups (l + K)][dnjobs: 3 * 2n][fl: sum 2l]
+//   [ut: sum ups][zt: sum 2l][pl: 2nK][groups: 3 per group]
+// la entries: item << 16 | limb, plus the offset of the limb's (Q_j/q_a)^-1 in the
+// conversion constants << 32 (dc order); inner: group << 16 | x (x < l: Q limb,
+// else special prime x - l); fl: item << 17 | poly << 16 | limb (z and uQ order);
+// ut / zt (targets of the fused conversions): job | t << 20 | modulus << 40;
+// pl (uP limbs): modulus | offset of (P/p_a)^-1 << 32.
 struct KsTab {
     uint32_t n, K, L;
-    uint32_t it, la, uj, um, il, dj, fl;
+    uint32_t it, la, uj, um, il, dj, fl, ut, zt, pl, gr;
 };
 __device__ __forceinline__ const KsItem &tab_item(uint64_t *const *tab, const KsTab &t, uint32_t b)
 {
@@ -73,49 +92,6 @@ __device__ __forceinline__ const KsItem &tab_item(uint64_t *const *tab, const Ks
 __device__ __forceinline__ uint64_t tab_word(uint64_t *const *tab, uint32_t off, uint32_t y)
 {
     return (uint64_t)(uintptr_t)tab[off + y];
-}
-
-// Fast basis conversion, one thread per coefficient, blockIdx.y + y0 = job:
-//   y_t = sum_a [x_a (B/b_a)^-1]_{b_a} (B/b_a mod c_t)  mod c_t.
-// ADD_HALF: sources offset by hsrc (per source limb) and results by -hdst (per
-// destination limb): the rounding shift of ModDown.
-template <bool ADD_HALF>
-__global__ __launch_bounds__(TPB) void k_bconv(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
-                                               const double *__restrict__ ctab, const BcJob *__restrict__ jobs,
-                                               uint32_t y0, uint32_t logN, const double *__restrict__ hsrc,
-                                               const double *__restrict__ hdst)
-{
-    const uint32_t N = 1u << logN;
-    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
-    if (k >= N) return;
-    const BcJob jb = jobs[blockIdx.y + y0];
-    const double *T = ctab + jb.off;
-    const double *qhinv = T, *sq = T + jb.nsrc, *sqi = T + 2 * jb.nsrc, *dq = T + 3 * jb.nsrc,
-                 *dqi = T + 3 * jb.nsrc + jb.ndst, *qh = T + 3 * jb.nsrc + 2 * jb.ndst;
-    const uint64_t *S = src + (size_t)jb.src0 * N + k;
-    uint64_t *D = dst + (size_t)jb.dst0 * N + k;
-    double v[16];
-#pragma unroll
-    for (int a = 0; a < 16; ++a) {
-        if (a < (int)jb.nsrc) {
-            double x = u64_to_f64(S[(size_t)a * N]);
-            if (ADD_HALF) x += hsrc[a];
-            v[a] = canon(mulmod(x, qhinv[a], sq[a], sqi[a]), sq[a], sqi[a]);
-        }
-    }
-    for (uint32_t t = 0; t < jb.ndst; ++t) {
-        const double q = dq[t], qi = dqi[t];
-        double acc = 0.0;
-#pragma unroll
-        for (int a = 0; a < 16; ++a) {
-            if (a < (int)jb.nsrc) {
-                acc += mulmod(v[a], qh[(size_t)a * jb.ndst + t], q, qi);
-                if ((a & 3) == 3) acc = redc(acc, q, qi);
-            }
-        }
-        if (ADD_HALF) acc -= hdst[t];
-        D[(size_t)t * N] = f64_to_u64(canon(acc, q, qi));
-    }
 }
 
 // 1. First (row) pass of the inverse transform of d_b, gathered through gal_b,
@@ -131,7 +107,7 @@ __global__ __launch_bounds__(WG) void k_ks_intt_first(uint64_t *const *__restric
     const uint32_t N = 1u << logN;
     const uint32_t y = blockIdx.y + y0;
     const uint64_t e = tab_word(tab, t.la, y);
-    const uint32_t b = (uint32_t)(e >> 16), i = (uint32_t)(e & 0xFFFF);
+    const uint32_t b = (uint32_t)((e >> 16) & 0xFFFF), i = (uint32_t)(e & 0xFFFF);
     const uint64_t *src = tab[b] + (size_t)i * N;
     const uint32_t gal = (uint32_t)tab_word(tab, 5 * t.n, b);
     const double q = mods[i].q, qinv = mods[i].qinv;
@@ -147,15 +123,17 @@ __global__ __launch_bounds__(WG) void k_ks_intt_first(uint64_t *const *__restric
 }
 
 // 4b. Key inner product, one thread per pair of coefficients (16-byte loads) of
-//     one limb x of Q_l u P (blockIdx.y + y0 = entry of the inner list):
-//     u_t[x] = sum_j D_j[x] * evk_{j,t}[x]; D_j[x] is the input limb itself
-//     inside digit j, else the converted limb.
+//     one limb x of Q_l u P for the TI (or fewer) items of one group, which share
+//     the key: u_t[x] = sum_j D_j[x] * evk_{j,t}[x]; D_j[x] is the item's input limb
+//     itself (read through gal_b) inside digit j, else its converted limb.  blockIdx.y + y0 = entry of
+//     the inner list.
 __device__ __forceinline__ void ld2(const uint64_t *p, double &a, double &b)
 {
     const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(p);
     a = u64_to_f64(v.x);
     b = u64_to_f64(v.y);
 }
+template <int TI>
 __global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ tab, KsTab t, uint32_t y0,
                                                   const uint64_t *__restrict__ up, uint64_t *__restrict__ uQ,
                                                   uint64_t *__restrict__ uP, const ModQ *__restrict__ mods,
@@ -165,34 +143,143 @@ __global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ 
     const uint32_t k = 2 * (blockIdx.x * TPB + threadIdx.x);
     if (k >= N) return;
     const uint64_t e = tab_word(tab, t.il, blockIdx.y + y0);
-    const uint32_t b = (uint32_t)(e >> 16), x = (uint32_t)(e & 0xFFFF);
-    const KsItem &it = tab_item(tab, t, b);
-    const uint32_t l = it.l;
+    const uint32_t g = (uint32_t)(e >> 16), x = (uint32_t)(e & 0xFFFF);
+    const KsGrp &gr = reinterpret_cast<const KsGrp *>(tab + t.gr)[g];
+    const uint32_t m = TI == 1 ? 1u : gr.m;
+    const KsItem &i0 = tab_item(tab, t, gr.it[0]);
+    const uint32_t l = i0.l, nd = i0.nd;
     const uint32_t mx = x < l ? x : t.L + (x - l);
     const double q = mods[mx].q, qi = mods[mx].qinv;
-    const uint64_t *d = tab[b], *ev = tab[t.n + b];
-    const uint64_t *upb = up + (size_t)it.up_off * N;
+    const uint64_t *ev = tab[t.n + gr.it[0]];
     const size_t ML = t.L + t.K;
-    double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
-    for (uint32_t j = 0; j < it.nd; ++j) {
+    // the input limb is read through the Galois permutation of the group's key, which
+    // maps the pair (k, k+1) onto the pair (y, y^1): one 16-byte load, swapped when y is odd
+    const uint32_t gal = (uint32_t)tab_word(tab, 5 * t.n, gr.it[0]);
+    const uint32_t ys = galois_src(k, gal, logN), yk = ys & ~1u;
+    const bool swp = ys & 1u;
+    double a0[TI], a1[TI], c0[TI], c1[TI];
+#pragma unroll
+    for (int u = 0; u < TI; ++u) a0[u] = a1[u] = c0[u] = c1[u] = 0.0;
+    for (uint32_t j = 0; j < nd; ++j) {
         const uint32_t lo = j * alpha, hi = min(lo + alpha, l);
-        double D0, D1, e00, e01, e10, e11;
-        if (x >= lo && x < hi) ld2(d + (size_t)x * N + k, D0, D1);
-        else {
-            const uint32_t pos = x < lo ? x : x - (hi - lo);
-            ld2(upb + (size_t)(it.upoff[j] + pos) * N + k, D0, D1);
-        }
+        const bool inside = x >= lo && x < hi;
+        const uint32_t pos = x < lo ? x : x - (hi - lo);
+        double e00, e01, e10, e11;
         ld2(ev + (((size_t)j * 2 + 0) * ML + mx) * N + k, e00, e01);
         ld2(ev + (((size_t)j * 2 + 1) * ML + mx) * N + k, e10, e11);
-        a0 += mulmod(D0, e00, q, qi);
-        c0 += mulmod(D1, e01, q, qi);
-        a1 += mulmod(D0, e10, q, qi);
-        c1 += mulmod(D1, e11, q, qi);
+#pragma unroll
+        for (int u = 0; u < TI; ++u) {
+            if (u < (int)m) {
+                const uint32_t b = gr.it[u];
+                double D0, D1;
+                if (inside) {
+                    ld2(tab[b] + (size_t)x * N + yk, D0, D1);
+                    if (swp) {
+                        const double t0 = D0;
+                        D0 = D1;
+                        D1 = t0;
+                    }
+                } else {
+                    const KsItem &it = tab_item(tab, t, b);
+                    ld2(up + ((size_t)it.up_off + it.upoff[j] + pos) * N + k, D0, D1);
+                }
+                a0[u] += mulmod(D0, e00, q, qi);
+                c0[u] += mulmod(D1, e01, q, qi);
+                a1[u] += mulmod(D0, e10, q, qi);
+                c1[u] += mulmod(D1, e11, q, qi);
+            }
+        }
         if ((j & 3) == 3) {
-            a0 = redc(a0, q, qi);
-            c0 = redc(c0, q, qi);
-            a1 = redc(a1, q, qi);
-            c1 = redc(c1, q, qi);
+#pragma unroll
+            for (int u = 0; u < TI; ++u) {
+                a0[u] = redc(a0[u], q, qi);
+                c0[u] = redc(c0[u], q, qi);
+                a1[u] = redc(a1[u], q, qi);
+                c1[u] = redc(c1[u], q, qi);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < TI; ++u) {
+        if (u < (int)m) {
+            const uint32_t b = gr.it[u];
+            uint64_t *o0, *o1;
+            if (x < l) {
+                const uint32_t uq = tab_item(tab, t, b).uq_off;
+                o0 = uQ + ((size_t)uq + x) * N;
+                o1 = uQ + ((size_t)uq + l + x) * N;
+            } else {
+                o0 = uP + ((size_t)b * 2 * t.K + (x - l)) * N;
+                o1 = uP + ((size_t)b * 2 * t.K + t.K + (x - l)) * N;
+            }
+            *reinterpret_cast<ulonglong2 *>(o0 + k) =
+                make_ulonglong2(f64_to_u64(canon(a0[u], q, qi)), f64_to_u64(canon(c0[u], q, qi)));
+            *reinterpret_cast<ulonglong2 *>(o1 + k) =
+                make_ulonglong2(f64_to_u64(canon(a1[u], q, qi)), f64_to_u64(canon(c1[u], q, qi)));
+        }
+    }
+}
+
+// 3+4. The forward row pass of the converted digits fused with the key inner
+//     product, for items with their own key (groups of one): one block covers the
+//     rows of limb x of Q_l u P that the row pass gives it, in the row-pass geometry;
+//     per digit j, D_j[x] is the input limb (canonical) or the converted limb,
+//     transformed in registers and redistributed to the coalesced order, then
+//     multiplied by both key polynomials.  blockIdx.y + y0 = entry of the inner list.
+template <int LOGG, int WG>
+__global__ __launch_bounds__(WG) void k_ks_row_inner(uint64_t *const *__restrict__ tab, KsTab t, uint32_t y0,
+                                                     const uint64_t *__restrict__ up, uint64_t *__restrict__ uQ,
+                                                     uint64_t *__restrict__ uP, const ModQ *__restrict__ mods,
+                                                     const double *__restrict__ twt, uint32_t alpha, uint32_t logN,
+                                                     uint32_t sigma0)
+{
+    using Gm = Geom<LOGG, WG, false>;
+    __shared__ double lds[Gm::LDS];
+    const uint32_t N = 1u << logN;
+    const uint64_t e = tab_word(tab, t.il, blockIdx.y + y0);
+    const uint32_t g = (uint32_t)(e >> 16), x = (uint32_t)(e & 0xFFFF);
+    const uint32_t b = reinterpret_cast<const KsGrp *>(tab + t.gr)[g].it[0];
+    const KsItem &it = tab_item(tab, t, b);
+    const uint32_t l = it.l, nd = it.nd;
+    const uint32_t mx = x < l ? x : t.L + (x - l);
+    const double q = mods[mx].q, qi = mods[mx].qinv;
+    const uint64_t *ev = tab[t.n + b];
+    const uint32_t gal = (uint32_t)tab_word(tab, 5 * t.n, b);
+    const size_t ML = t.L + t.K;
+    const Gm gm(logN, blockIdx.x);
+    double a0[R], a1[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) a0[k] = a1[k] = 0.0;
+    for (uint32_t j = 0; j < nd; ++j) {
+        const uint32_t lo = j * alpha, hi = min(lo + alpha, l);
+        double v[R];
+        if (x >= lo && x < hi) {   // block-uniform branch; the input limb through the permutation
+            const uint64_t *src = tab[b] + (size_t)x * N;
+#pragma unroll
+            for (int k = 0; k < R; k++) v[k] = u64_to_f64(src[galois_src(gm.coal(k), gal, logN)]);
+        } else {
+            const uint32_t pos = x < lo ? x : x - (hi - lo);
+            const uint64_t *src = up + ((size_t)it.up_off + it.upoff[j] + pos) * N;
+#pragma unroll
+            for (int k = 0; k < R; k++) v[k] = bits_to_f64(src[gm.fwd_in(k)]);
+            gm.fwd(v, lds, twt + (size_t)mx * N, q, qi, logN, sigma0);
+            gm.fwd_out_to_coal(v, lds);
+#pragma unroll
+            for (int k = 0; k < R; k++) v[k] = canon(v[k], q, qi);
+        }
+        const uint64_t *e0 = ev + (((size_t)j * 2 + 0) * ML + mx) * N, *e1 = ev + (((size_t)j * 2 + 1) * ML + mx) * N;
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            const uint32_t idx = gm.coal(k);
+            a0[k] += mulmod(v[k], u64_to_f64(e0[idx]), q, qi);
+            a1[k] += mulmod(v[k], u64_to_f64(e1[idx]), q, qi);
+        }
+        if ((j & 3) == 3) {
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                a0[k] = redc(a0[k], q, qi);
+                a1[k] = redc(a1[k], q, qi);
+            }
         }
     }
     uint64_t *o0, *o1;
@@ -203,10 +290,12 @@ __global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ 
         o0 = uP + ((size_t)b * 2 * t.K + (x - l)) * N;
         o1 = uP + ((size_t)b * 2 * t.K + t.K + (x - l)) * N;
     }
-    *reinterpret_cast<ulonglong2 *>(o0 + k) =
-        make_ulonglong2(f64_to_u64(canon(a0, q, qi)), f64_to_u64(canon(c0, q, qi)));
-    *reinterpret_cast<ulonglong2 *>(o1 + k) =
-        make_ulonglong2(f64_to_u64(canon(a1, q, qi)), f64_to_u64(canon(c1, q, qi)));
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        const uint32_t idx = gm.coal(k);
+        o0[idx] = f64_to_u64(canon(a0[k], q, qi));
+        o1[idx] = f64_to_u64(canon(a1[k], q, qi));
+    }
 }
 
 // 8. Forward row pass of z fused with the ModDown finish:
@@ -248,30 +337,11 @@ __global__ __launch_bounds__(WG, 3) void k_ks_moddown_final(uint64_t *const *__r
     }
 }
 
-// Column and row passes of the key-switching path (split_ks) over a flat limb
-// buffer whose limb y is reduced modulo mods[lst[y] & 0xFFFF]: forward (canonical
-// in, lazy bits out; row: bits in, canonical out, coalesced stores) and inverse
-// column (bits in, canonical out, N^-1 folded).
-template <int LOGG, int WG>
-__global__ __launch_bounds__(WG) void k_col_fwd(uint64_t *__restrict__ base, const uint64_t *__restrict__ lst,
-                                                uint32_t y0, const ModQ *__restrict__ mods,
-                                                const double *__restrict__ twt, uint32_t logN)
-{
-    using Gm = Geom<LOGG, WG, true>;
-    __shared__ double lds[Gm::LDS];
-    const uint32_t N = 1u << logN;
-    const uint32_t b = blockIdx.y + y0;
-    const uint32_t m = (uint32_t)(lst[b] & 0xFFFF);
-    const double q = mods[m].q, qinv = mods[m].qinv;
-    uint64_t *p = base + (size_t)b * N;
-    const Gm gm(logN, blockIdx.x);
-    double x[R];
-#pragma unroll
-    for (int k = 0; k < R; k++) x[k] = u64_to_f64(p[gm.fwd_in(k)]);
-    gm.fwd(x, lds, twt + (size_t)m * N, q, qinv, logN, 0);
-#pragma unroll
-    for (int k = 0; k < R; k++) p[gm.fwd_out(k)] = f64_to_bits(x[k]);
-}
+// Passes of the key-switching path (split_ks) over a flat limb buffer whose limb y
+// is reduced modulo mods[lst[y] & 0xFFFF]: the forward row pass (lazy bits in,
+// canonical out, coalesced stores), the inverse column pass (bits in, N^-1
+// folded, canonical or prepared-source out), the inverse row pass, and the
+// forward column pass fused with a basis conversion.
 template <int LOGG, int WG>
 __global__ __launch_bounds__(WG) void k_row_fwd(uint64_t *__restrict__ base, const uint64_t *__restrict__ lst,
                                                 uint32_t y0, const ModQ *__restrict__ mods,
@@ -293,13 +363,47 @@ __global__ __launch_bounds__(WG) void k_row_fwd(uint64_t *__restrict__ base, con
 #pragma unroll
     for (int k = 0; k < R; k++) p[gm.coal(k)] = f64_to_u64(canon(x[k], q, qinv));
 }
-template <int LOGG, int WG>
+// EPI 0: canonical out; EPI 1: times ctab[lst[y] >> 32]; EPI 2: plus half[m], then
+// times ctab[lst[y] >> 32] (the conversion sources of ModUp and ModDown, stored as
+// FP64 bits of their canonical values: every target limb reads them again).
+template <int LOGG, int WG, int EPI>
 __global__ __launch_bounds__(WG) void k_col_inv(uint64_t *__restrict__ base, const uint64_t *__restrict__ lst,
                                                 uint32_t y0, const ModQ *__restrict__ mods,
                                                 const double *__restrict__ itwt, const double *__restrict__ ninvt,
-                                                uint32_t logN)
+                                                uint32_t logN, const double *__restrict__ ctab,
+                                                const double *__restrict__ half)
 {
     using Gm = Geom<LOGG, WG, true>;
+    __shared__ double lds[Gm::LDS];
+    const uint32_t N = 1u << logN;
+    const uint32_t b = blockIdx.y + y0;
+    const uint64_t e = lst[b];
+    const uint32_t m = (uint32_t)(e & 0xFFFF);
+    const double q = mods[m].q, qinv = mods[m].qinv;
+    uint64_t *p = base + (size_t)b * N;
+    const Gm gm(logN, blockIdx.x);
+    double x[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) x[k] = bits_to_f64(p[gm.inv_in(k)]);
+    gm.template inv<true>(x, lds, itwt + (size_t)m * N, q, qinv, ninvt[m], logN, 0);
+    double mul = 0.0, h = 0.0;
+    if (EPI) mul = ctab[e >> 32];
+    if (EPI == 2) h = half[m];
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        double v = canon(x[k], q, qinv);
+        if (EPI == 2) v += h;
+        if (EPI) v = canon(mulmod(v, mul, q, qinv), q, qinv);
+        p[gm.inv_out(k)] = EPI ? f64_to_bits(v) : f64_to_u64(v);
+    }
+}
+// Inverse row pass over a flat buffer (canonical in, coalesced loads; lazy bits out).
+template <int LOGG, int WG>
+__global__ __launch_bounds__(WG) void k_row_inv(uint64_t *__restrict__ base, const uint64_t *__restrict__ lst,
+                                                uint32_t y0, const ModQ *__restrict__ mods,
+                                                const double *__restrict__ itwt, uint32_t logN, uint32_t sigma0)
+{
+    using Gm = Geom<LOGG, WG, false>;
     __shared__ double lds[Gm::LDS];
     const uint32_t N = 1u << logN;
     const uint32_t b = blockIdx.y + y0;
@@ -309,10 +413,144 @@ __global__ __launch_bounds__(WG) void k_col_inv(uint64_t *__restrict__ base, con
     const Gm gm(logN, blockIdx.x);
     double x[R];
 #pragma unroll
-    for (int k = 0; k < R; k++) x[k] = bits_to_f64(p[gm.inv_in(k)]);
-    gm.template inv<true>(x, lds, itwt + (size_t)m * N, q, qinv, ninvt[m], logN, 0);
+    for (int k = 0; k < R; k++) x[k] = u64_to_f64(p[gm.coal(k)]);
+    gm.coal_to_inv_in(x, lds);
+    gm.template inv<false>(x, lds, itwt + (size_t)m * N, q, qinv, 0.0, logN, sigma0);
 #pragma unroll
-    for (int k = 0; k < R; k++) p[gm.inv_out(k)] = f64_to_u64(canon(x[k], q, qinv));
+    for (int k = 0; k < R; k++) p[gm.inv_out(k)] = f64_to_bits(x[k]);
+}
+// Fast basis conversion fused with the forward column pass of its result: target
+// entry y holds (job, t, modulus m); the target limb's elements of this block's
+// columns are  y_t = sum_a v_a (B/b_a mod c_t) mod c_t  (v_a the prepared sources as FP64 bits,
+// accumulated source by source, reduced every four terms), minus half[t] for
+// ModDown, then transformed by the forward column pass (lazy bits out).
+template <int LOGG, int WG, bool SUB_HALF>
+__global__ __launch_bounds__(WG) void k_col_fwd_bconv(uint64_t *__restrict__ dst, const uint64_t *__restrict__ src,
+                                                      const double *__restrict__ ctab, const BcJob *__restrict__ jobs,
+                                                      const uint64_t *__restrict__ tl, uint32_t y0,
+                                                      const ModQ *__restrict__ mods, const double *__restrict__ twt,
+                                                      uint32_t logN, const double *__restrict__ hdst)
+{
+    using Gm = Geom<LOGG, WG, true>;
+    __shared__ double lds[Gm::LDS];
+    const uint32_t N = 1u << logN;
+    const uint64_t e = tl[blockIdx.y + y0];
+    const BcJob jb = jobs[(uint32_t)(e & 0xFFFFF)];
+    const uint32_t tt = (uint32_t)((e >> 20) & 0xFFFFF), m = (uint32_t)(e >> 40);
+    const double *T = ctab + jb.off;
+    const double cq = T[3 * jb.nsrc + tt], cqi = T[3 * jb.nsrc + jb.ndst + tt];
+    const double *qh = T + 3 * jb.nsrc + 2 * jb.ndst;
+    const Gm gm(logN, blockIdx.x);
+    uint32_t pos[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) pos[k] = gm.fwd_in(k);
+    double x[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) x[k] = 0.0;
+    const uint64_t *S = src + (size_t)jb.src0 * N;
+    for (uint32_t a = 0; a < jb.nsrc; ++a) {
+        const double w = qh[(size_t)a * jb.ndst + tt];
+        const uint64_t *Sa = S + (size_t)a * N;
+#pragma unroll
+        for (int k = 0; k < R; k++) x[k] += mulmod(bits_to_f64(Sa[pos[k]]), w, cq, cqi);
+        if ((a & 3) == 3) {
+#pragma unroll
+            for (int k = 0; k < R; k++) x[k] = redc(x[k], cq, cqi);
+        }
+    }
+    const double q = mods[m].q, qinv = mods[m].qinv;
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        double v = x[k];
+        if (SUB_HALF) v -= hdst[tt];
+        x[k] = canon(v, cq, cqi);
+    }
+    gm.fwd(x, lds, twt + (size_t)m * N, q, qinv, logN, 0);
+    uint64_t *p = dst + ((size_t)jb.dst0 + tt) * N;
+#pragma unroll
+    for (int k = 0; k < R; k++) p[gm.fwd_out(k)] = f64_to_bits(x[k]);
+}
+
+// ---- rescale over a ragged batch (item b: l_b limbs, P polys).  Table:
+// [in: n][out: n][lvl: n][last: n*P][spread: sum P (l_b - 1)]; a last entry
+// j = b*P + p holds j << 16 | (l_b - 1), a spread entry j << 16 | i.
+// Step 1: copy the last limb of every polynomial to tmp [n*P][N].
+__global__ __launch_bounds__(TPB) void k_rs_gather_last(uint64_t *const *__restrict__ tab, uint32_t n,
+                                                        uint32_t polys, uint64_t *__restrict__ last, uint32_t logN,
+                                                        uint32_t y0)
+{
+    const uint32_t N = 1u << logN;
+    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
+    if (k >= N) return;
+    const uint32_t j = blockIdx.y + y0, b = j / polys, p = j % polys;
+    const uint32_t l = (uint32_t)(uintptr_t)tab[2 * n + b];
+    last[(size_t)j * N + k] = tab[b][((size_t)p * l + (l - 1)) * N + k];
+}
+// Step 2 (after the inverse transform of the last limbs): per spread entry y, the
+// last limb's coefficients r lifted to (-q_last/2, q_last/2] and reduced mod q_i,
+// then the forward column pass (lazy bits out into s[y]).
+template <int LOGG, int WG>
+__global__ __launch_bounds__(WG) void k_rs_spread_col(uint64_t *const *__restrict__ tab, uint32_t n, uint32_t polys,
+                                                      uint32_t sp, const uint64_t *__restrict__ last,
+                                                      uint64_t *__restrict__ sbuf, const ModQ *__restrict__ mods,
+                                                      const double *__restrict__ twt, uint32_t logN, uint32_t y0)
+{
+    using Gm = Geom<LOGG, WG, true>;
+    __shared__ double lds[Gm::LDS];
+    const uint32_t N = 1u << logN;
+    const uint32_t y = blockIdx.y + y0;
+    const uint64_t e = (uint64_t)(uintptr_t)tab[sp + y];
+    const uint32_t j = (uint32_t)(e >> 16), i = (uint32_t)(e & 0xFFFF);
+    const uint32_t l = (uint32_t)(uintptr_t)tab[2 * n + j / polys];
+    const double ql = mods[l - 1].q;
+    const double q = mods[i].q, qinv = mods[i].qinv;
+    const uint64_t *r = last + (size_t)j * N;
+    const Gm gm(logN, blockIdx.x);
+    double x[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        double v = u64_to_f64(r[gm.fwd_in(k)]);
+        v = v > 0.5 * ql ? v - ql : v;   // centered lift (q_last odd: no ties)
+        x[k] = canon(v, q, qinv);
+    }
+    gm.fwd(x, lds, twt + (size_t)i * N, q, qinv, logN, 0);
+    uint64_t *o = sbuf + (size_t)y * N;
+#pragma unroll
+    for (int k = 0; k < R; k++) o[gm.fwd_out(k)] = f64_to_bits(x[k]);
+}
+// Step 3: the forward row pass of s fused with out = (c - s) * q_last^-1 mod q_i.
+template <int LOGG, int WG>
+__global__ __launch_bounds__(WG) void k_rs_row_fin(uint64_t *const *__restrict__ tab, uint32_t n, uint32_t polys,
+                                                   uint32_t sp, const uint64_t *__restrict__ sbuf,
+                                                   const ModQ *__restrict__ mods, const double *__restrict__ twt,
+                                                   const double *__restrict__ qlinv, uint32_t L, uint32_t logN,
+                                                   uint32_t sigma0, uint32_t y0)
+{
+    using Gm = Geom<LOGG, WG, false>;
+    __shared__ double lds[Gm::LDS];
+    const uint32_t N = 1u << logN;
+    const uint32_t y = blockIdx.y + y0;
+    const uint64_t e = (uint64_t)(uintptr_t)tab[sp + y];
+    const uint32_t j = (uint32_t)(e >> 16), i = (uint32_t)(e & 0xFFFF), b = j / polys, p = j % polys;
+    const uint32_t l = (uint32_t)(uintptr_t)tab[2 * n + b];
+    const double q = mods[i].q, qinv = mods[i].qinv;
+    const Gm gm(logN, blockIdx.x);
+    const uint64_t *sv = sbuf + (size_t)y * N;
+    double x[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) x[k] = bits_to_f64(sv[gm.fwd_in(k)]);
+    gm.fwd(x, lds, twt + (size_t)i * N, q, qinv, logN, sigma0);
+    gm.fwd_out_to_coal(x, lds);
+    const uint64_t *cin = tab[b] + ((size_t)p * l + i) * N;
+    uint64_t *out = tab[n + b] + ((size_t)p * (l - 1) + i) * N;
+    const double w = qlinv[(size_t)(l - 1) * L + i];
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        const uint32_t idx = gm.coal(k);
+        const double sval = canon(x[k], q, qinv);
+        const double r = mulmod(u64_to_f64(cin[idx]) - sval, w, q, qinv);
+        out[idx] = f64_to_u64(fold(r, q));
+    }
 }
 
 // Per ring degree: column pass (LOGA stages, WA threads, GA blocks per limb) and
@@ -354,13 +592,14 @@ void in_pieces(uint32_t total, F f)
 
 // Host plan of one ragged batch.
 struct KsPlan {
-    uint32_t n, sum_l, sum_nd, sum_ups, sum_inner;
+    uint32_t n, sum_l, sum_nd, sum_ups, sum_inner, max_grp;
     std::vector<KsItem> items;
     std::vector<BcJob> upjobs, dnjobs;
-    std::vector<uint64_t> la, upmods, inner, fl;
+    std::vector<KsGrp> groups;
+    std::vector<uint64_t> la, upmods, inner, fl, ut, zt, pl;
 };
 
-fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, KsPlan &pl)
+fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *evk, KsPlan &pl)
 {
     const uint32_t K = c->K, alpha = c->alpha;
     pl.n = n;
@@ -382,21 +621,51 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, KsPlan &pl)
         for (uint32_t j = 0; j < nd; ++j) {
             const BconvTab &t = c->modup[(size_t)l * c->dnum + j];
             it.upoff[j] = (uint16_t)u;
+            const uint64_t job = pl.upjobs.size();
             pl.upjobs.push_back(BcJob{t.off, t.nsrc, t.ndst, dc + j * alpha, up + u, 0});
-            for (uint32_t a = 0; a < t.ndst; ++a) pl.upmods.push_back(t.dst[a]);
+            for (uint32_t a = 0; a < t.ndst; ++a) {
+                pl.upmods.push_back(t.dst[a]);
+                pl.ut.push_back(job | ((uint64_t)a << 20) | ((uint64_t)t.dst[a] << 40));
+            }
             u += t.ndst;
         }
-        for (uint32_t i = 0; i < l; ++i) pl.la.push_back(((uint64_t)b << 16) | i);
-        for (uint32_t x = 0; x < l + K; ++x) pl.inner.push_back(((uint64_t)b << 16) | x);
+        for (uint32_t i = 0; i < l; ++i) {
+            const BconvTab &t = c->modup[(size_t)l * c->dnum + i / alpha];
+            pl.la.push_back(((uint64_t)b << 16) | i | ((uint64_t)(t.off + i % alpha) << 32));
+        }
         for (uint32_t tt = 0; tt < 2; ++tt) {
             const BconvTab &md = c->moddown[l];
+            const uint64_t job = pl.dnjobs.size();
             pl.dnjobs.push_back(BcJob{md.off, md.nsrc, md.ndst, (2 * b + tt) * K, uq + tt * l, 0});
-            for (uint32_t i = 0; i < l; ++i) pl.fl.push_back(((uint64_t)b << 17) | ((uint64_t)tt << 16) | i);
+            for (uint32_t i = 0; i < l; ++i) {
+                pl.fl.push_back(((uint64_t)b << 17) | ((uint64_t)tt << 16) | i);
+                pl.zt.push_back(job | ((uint64_t)i << 20) | ((uint64_t)i << 40));
+            }
+            for (uint32_t k = 0; k < K; ++k)
+                pl.pl.push_back((uint64_t)(c->L + k) | ((uint64_t)(md.off + k) << 32));
         }
         dc += l;
         up += u;
         uq += 2 * l;
     }
+    // groups of items with the same key and level, in order of first appearance
+    std::map<std::pair<const uint64_t *, uint32_t>, uint32_t> open;
+    pl.max_grp = 0;
+    for (uint32_t b = 0; b < n; ++b) {
+        const auto key = std::make_pair(evk[b], ls[b]);
+        auto f = open.find(key);
+        if (f == open.end() || pl.groups[f->second].m == KS_GRP) {
+            open[key] = (uint32_t)pl.groups.size();
+            pl.groups.push_back(KsGrp{});
+            f = open.find(key);
+        }
+        KsGrp &g = pl.groups[f->second];
+        g.it[g.m++] = (uint16_t)b;
+        pl.max_grp = std::max(pl.max_grp, g.m);
+    }
+    if (pl.groups.size() >= 65536) return fhe_fail(FHE_EINVAL, "key-switch batch too large");
+    for (uint32_t g = 0; g < pl.groups.size(); ++g)
+        for (uint32_t x = 0; x < ls[pl.groups[g].it[0]] + K; ++x) pl.inner.push_back(((uint64_t)g << 16) | x);
     pl.sum_l = dc;
     pl.sum_ups = up;
     pl.sum_nd = (uint32_t)pl.upjobs.size();
@@ -407,25 +676,16 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, KsPlan &pl)
 }  // namespace
 
 // ---- launchers of the key-switching path
-static void ks_col_fwd(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs)
+template <int EPI>
+static void ks_col_inv(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs, const char *cat)
 {
-    ProfScope ps(c, "ntt_fwd_col");
+    ProfScope ps(c, cat);
     dispatch_logn(c->logN, [&](auto sh) {
         using S = decltype(sh);
         in_pieces(nlimbs, [&](uint32_t y0, uint32_t cnt) {
-            hipLaunchKernelGGL((k_col_fwd<S::LOGA, S::WA>), dim3(S::GA, cnt), dim3(S::WA), 0, c->stream, base, lst, y0,
-                               (const ModQ *)c->d_mod, (const double *)c->d_tw, c->logN);
-        });
-    });
-}
-static void ks_col_inv(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs)
-{
-    ProfScope ps(c, "ntt_inv_col");
-    dispatch_logn(c->logN, [&](auto sh) {
-        using S = decltype(sh);
-        in_pieces(nlimbs, [&](uint32_t y0, uint32_t cnt) {
-            hipLaunchKernelGGL((k_col_inv<S::LOGA, S::WA>), dim3(S::GA, cnt), dim3(S::WA), 0, c->stream, base, lst, y0,
-                               (const ModQ *)c->d_mod, (const double *)c->d_itw, (const double *)c->d_ninv, c->logN);
+            hipLaunchKernelGGL((k_col_inv<S::LOGA, S::WA, EPI>), dim3(S::GA, cnt), dim3(S::WA), 0, c->stream, base, lst,
+                               y0, (const ModQ *)c->d_mod, (const double *)c->d_itw, (const double *)c->d_ninv, c->logN,
+                               (const double *)c->d_bconv, (const double *)c->d_phalf);
         });
     });
 }
@@ -437,6 +697,31 @@ static void ks_row_fwd(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t
         in_pieces(nlimbs, [&](uint32_t y0, uint32_t cnt) {
             hipLaunchKernelGGL((k_row_fwd<S::LOGB, S::WB>), dim3(S::GB, cnt), dim3(S::WB), 0, c->stream, base, lst, y0,
                                (const ModQ *)c->d_mod, (const double *)c->d_tw, c->logN, (uint32_t)S::LOGA);
+        });
+    });
+}
+static void ks_row_inv(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs)
+{
+    ProfScope ps(c, "ntt_inv_row");
+    dispatch_logn(c->logN, [&](auto sh) {
+        using S = decltype(sh);
+        in_pieces(nlimbs, [&](uint32_t y0, uint32_t cnt) {
+            hipLaunchKernelGGL((k_row_inv<S::LOGB, S::WB>), dim3(S::GB, cnt), dim3(S::WB), 0, c->stream, base, lst, y0,
+                               (const ModQ *)c->d_mod, (const double *)c->d_itw, c->logN, (uint32_t)S::LOGA);
+        });
+    });
+}
+template <bool SUB_HALF>
+static void ks_col_fwd_bconv(fhe_ctx *c, uint64_t *dst, const uint64_t *src, const uint64_t *jobs, const uint64_t *tl,
+                             uint32_t ntargets, const char *cat)
+{
+    ProfScope ps(c, cat);
+    dispatch_logn(c->logN, [&](auto sh) {
+        using S = decltype(sh);
+        in_pieces(ntargets, [&](uint32_t y0, uint32_t cnt) {
+            hipLaunchKernelGGL((k_col_fwd_bconv<S::LOGA, S::WA, SUB_HALF>), dim3(S::GA, cnt), dim3(S::WA), 0, c->stream,
+                               dst, src, (const double *)c->d_bconv, (const BcJob *)jobs, tl, y0,
+                               (const ModQ *)c->d_mod, (const double *)c->d_tw, c->logN, (const double *)c->d_phalf);
         });
     });
 }
@@ -470,7 +755,7 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     if (2ull * n > GRID_Y) return fhe_fail(FHE_EINVAL, "key-switch batch too large");
     KsPlan pl;
     fhe_status s;
-    if ((s = ks_plan(c, n, ls, pl))) return s;
+    if ((s = ks_plan(c, n, ls, evk, pl))) return s;
 
     // scratch: dc [sum l], up [sum ups], uQ [sum 2l], uP [n][2][K], z [sum 2l]
     uint8_t *scr = scr_in;
@@ -507,11 +792,18 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     push_words(pl.dnjobs.data(), pl.dnjobs.size() * sizeof(BcJob));
     kt.fl = (uint32_t)tab.size();
     push_words(pl.fl.data(), pl.fl.size() * 8);
+    kt.ut = (uint32_t)tab.size();
+    push_words(pl.ut.data(), pl.ut.size() * 8);
+    kt.zt = (uint32_t)tab.size();
+    push_words(pl.zt.data(), pl.zt.size() * 8);
+    kt.pl = (uint32_t)tab.size();
+    push_words(pl.pl.data(), pl.pl.size() * 8);
+    kt.gr = (uint32_t)tab.size();
+    push_words(pl.groups.data(), pl.groups.size() * sizeof(KsGrp));
     uint64_t **dt;
     if ((s = ctx_ptr_table(c, tab, &dt))) return s;
     const uint64_t *dwords = (const uint64_t *)dt;
     hipStream_t st = c->stream;
-    const uint32_t gx = blocks_for(N, TPB);
     const uint32_t sum2l = 2 * pl.sum_l;
 
     // 1. coefficients of the (permuted) inputs
@@ -526,41 +818,43 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
             });
         });
     }
-    ks_col_inv(c, dc, dwords + kt.la, pl.sum_l);
-    // 2-3. ModUp conversion and the forward transform of the converted limbs
-    {
-        ProfScope ps(c, "bconv_up");
-        in_pieces(pl.sum_nd, [&](uint32_t y0, uint32_t cnt) {
-            hipLaunchKernelGGL(k_bconv<false>, dim3(gx, cnt), dim3(TPB), 0, st, (const uint64_t *)dc, up,
-                               (const double *)c->d_bconv, (const BcJob *)(dwords + kt.uj), y0, c->logN,
-                               (const double *)nullptr, (const double *)nullptr);
+    ks_col_inv<1>(c, dc, dwords + kt.la, pl.sum_l, "ntt_inv_col");
+    // 2-3. ModUp conversion fused with the forward column pass, then the row pass
+    ks_col_fwd_bconv<false>(c, up, dc, dwords + kt.uj, dwords + kt.ut, pl.sum_ups, "bconv_up");
+    if (pl.max_grp == 1 && c->tune_fuse_row_inner) {
+        // 3+4. row pass of the converted digits fused with the key inner product
+        ProfScope ps(c, "ks_inner");
+        dispatch_logn(c->logN, [&](auto sh) {
+            using S = decltype(sh);
+            in_pieces(pl.sum_inner, [&](uint32_t y0, uint32_t cnt) {
+                hipLaunchKernelGGL((k_ks_row_inner<S::LOGB, S::WB>), dim3(S::GB, cnt), dim3(S::WB), 0, st,
+                                   (uint64_t *const *)dt, kt, y0, (const uint64_t *)up, uQ, uP, (const ModQ *)c->d_mod,
+                                   (const double *)c->d_tw, c->alpha, c->logN, (uint32_t)S::LOGA);
+            });
         });
-    }
-    ks_col_fwd(c, up, dwords + kt.um, pl.sum_ups);
+    } else {
     ks_row_fwd(c, up, dwords + kt.um, pl.sum_ups);
     // 4. key inner product over the digits
     {
         ProfScope ps(c, "ks_inner");
         in_pieces(pl.sum_inner, [&](uint32_t y0, uint32_t cnt) {
-            hipLaunchKernelGGL(k_ks_inner, dim3(blocks_for(N / 2, TPB), cnt), dim3(TPB), 0, st, (uint64_t *const *)dt,
-                               kt, y0,
-                               (const uint64_t *)up, uQ, uP, (const ModQ *)c->d_mod, c->alpha, c->logN);
+            if (pl.max_grp > 1)
+                hipLaunchKernelGGL(k_ks_inner<KS_GRP>, dim3(blocks_for(N / 2, TPB), cnt), dim3(TPB), 0, st,
+                                   (uint64_t *const *)dt, kt, y0, (const uint64_t *)up, uQ, uP,
+                                   (const ModQ *)c->d_mod, c->alpha, c->logN);
+            else
+                hipLaunchKernelGGL(k_ks_inner<1>, dim3(blocks_for(N / 2, TPB), cnt), dim3(TPB), 0, st,
+                                   (uint64_t *const *)dt, kt, y0, (const uint64_t *)up, uQ, uP,
+                                   (const ModQ *)c->d_mod, c->alpha, c->logN);
         });
     }
-    // 5-6. ModDown: P limbs to coefficients, rounded conversion to Q_l
-    {
-        uint32_t m[FHE_LIMBTAB];
-        for (uint32_t k = 0; k < K; ++k) m[k] = L + k;
-        launch_ntt_inv(c, limbset_list(uP, m, K), n * 2 * K);
     }
-    {
-        ProfScope ps(c, "bconv_down");
-        hipLaunchKernelGGL(k_bconv<true>, dim3(gx, 2 * n), dim3(TPB), 0, st, (const uint64_t *)uP, z,
-                           (const double *)c->d_bconv, (const BcJob *)(dwords + kt.dj), 0u, c->logN,
-                           (const double *)(c->d_phalf + L), (const double *)c->d_phalf);
-    }
-    // 7-8. column pass of z, row pass fused with the finish
-    ks_col_fwd(c, z, dwords + kt.fl, sum2l);
+    // 5-6. ModDown: P limbs to coefficients (prepared as conversion sources), the
+    //      rounded conversion to Q_l fused with the forward column pass of z
+    ks_row_inv(c, uP, dwords + kt.pl, n * 2 * K);
+    ks_col_inv<2>(c, uP, dwords + kt.pl, n * 2 * K, "ntt_inv_col");
+    ks_col_fwd_bconv<true>(c, z, uP, dwords + kt.dj, dwords + kt.zt, sum2l, "bconv_down");
+    // 7. row pass of z fused with the finish
     {
         ProfScope ps(c, "ks_moddown_final");
         dispatch_logn(c->logN, [&](auto sh) {
@@ -582,4 +876,81 @@ fhe_status ks_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const *d, 
 {
     std::vector<uint32_t> ls(n, l);
     return ks_run_ragged(c, n, ls.data(), d, gal, evk, out, add, scr_in);
+}
+
+size_t rescale_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n)
+{
+    return (size_t)n * polys * ((size_t)l) * c->N * sizeof(uint64_t);   // last limbs + spread limbs
+}
+size_t rescale_scratch_bytes_ragged(const fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls)
+{
+    size_t limbs = 0;
+    for (uint32_t b = 0; b < n; ++b) limbs += (size_t)polys * ls[b];
+    return limbs * c->N * sizeof(uint64_t);
+}
+// Rescale a ragged batch into outputs (l_b - 1 limbs); outputs must not overlap inputs.
+fhe_status rescale_run_ragged(fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls, const uint64_t *const *in,
+                              uint64_t *const *out, uint8_t *scr)
+{
+    if (!n) return FHE_OK;
+    const size_t N = c->N;
+    fhe_status s;
+    std::vector<uint64_t *> tab;
+    for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)in[b]);
+    for (uint32_t b = 0; b < n; ++b) tab.push_back(out[b]);
+    for (uint32_t b = 0; b < n; ++b) {
+        if (ls[b] < 2 || ls[b] > c->L) return fhe_fail(FHE_ELEVEL, "rescale: limb count out of range");
+        tab.push_back((uint64_t *)(uintptr_t)ls[b]);
+    }
+    const uint32_t items = n * polys;
+    if (items >= (1u << 16) * 1024u) return fhe_fail(FHE_EINVAL, "rescale batch too large");
+    const uint32_t lastoff = (uint32_t)tab.size();
+    for (uint32_t b = 0; b < n; ++b)
+        for (uint32_t p = 0; p < polys; ++p)
+            tab.push_back((uint64_t *)(uintptr_t)((((uint64_t)(b * polys + p)) << 16) | (ls[b] - 1)));
+    const uint32_t sp = (uint32_t)tab.size();
+    for (uint32_t b = 0; b < n; ++b)
+        for (uint32_t p = 0; p < polys; ++p)
+            for (uint32_t i = 0; i + 1 < ls[b]; ++i)
+                tab.push_back((uint64_t *)(uintptr_t)((((uint64_t)(b * polys + p)) << 16) | i));
+    const uint32_t nsp = (uint32_t)tab.size() - sp;
+    uint64_t **dt;
+    if ((s = ctx_ptr_table(c, tab, &dt))) return s;
+    const uint64_t *dw = (const uint64_t *)dt;
+    uint64_t *last = (uint64_t *)scr, *sbuf = last + (size_t)items * N;
+    ProfScope ps(c, "rescale");
+    in_pieces(items, [&](uint32_t y0, uint32_t cnt) {
+        hipLaunchKernelGGL(k_rs_gather_last, dim3(blocks_for(N, TPB), cnt), dim3(TPB), 0, c->stream,
+                           (uint64_t *const *)dt, n, polys, last, c->logN, y0);
+    });
+    {
+        LimbSet ls_last;
+        std::memset((void *)&ls_last, 0, sizeof(ls_last));
+        ls_last.base = last;
+        ls_last.period = 1;
+        ls_last.modlist = dw + lastoff;
+        launch_ntt_inv(c, ls_last, items);
+    }
+    dispatch_logn(c->logN, [&](auto sh) {
+        using S = decltype(sh);
+        in_pieces(nsp, [&](uint32_t y0, uint32_t cnt) {
+            hipLaunchKernelGGL((k_rs_spread_col<S::LOGA, S::WA>), dim3(S::GA, cnt), dim3(S::WA), 0, c->stream,
+                               (uint64_t *const *)dt, n, polys, sp, (const uint64_t *)last, sbuf,
+                               (const ModQ *)c->d_mod, (const double *)c->d_tw, c->logN, y0);
+        });
+        in_pieces(nsp, [&](uint32_t y0, uint32_t cnt) {
+            hipLaunchKernelGGL((k_rs_row_fin<S::LOGB, S::WB>), dim3(S::GB, cnt), dim3(S::WB), 0, c->stream,
+                               (uint64_t *const *)dt, n, polys, sp, (const uint64_t *)sbuf, (const ModQ *)c->d_mod,
+                               (const double *)c->d_tw, (const double *)c->d_qlinv, c->L, c->logN, (uint32_t)S::LOGA,
+                               y0);
+        });
+    });
+    HIPCHK(hipGetLastError());
+    return FHE_OK;
+}
+fhe_status rescale_run(fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n, const uint64_t *const *in,
+                       uint64_t *const *out, uint8_t *scr)
+{
+    std::vector<uint32_t> ls(n, l);
+    return rescale_run_ragged(c, polys, n, ls.data(), in, out, scr);
 }

@@ -81,7 +81,10 @@ struct Geom {
         __syncthreads();
     }
 
-    // Cooley-Tukey stages sigma0 .. sigma0 + LOGG - 1 (table psi^brv), lazy |x| < 2q.
+    // Cooley-Tukey stages sigma0 .. sigma0 + LOGG - 1 (table psi^brv).  The upper input
+    // of a butterfly is reduced to [-q/2-1, q/2+1] on every other stage only (the first,
+    // third, ... of each round): with q < 2^50 and inputs |x| < 2.7q the values stay
+    // below 2.7q (< 2^51.5), where every operation is exact.  Out: |x| < 2.7q.
     __device__ __forceinline__ void fwd(double (&x)[R], double *lds, const double *__restrict__ tw, double q,
                                         double qinv, uint32_t logN, uint32_t sigma0) const
     {
@@ -109,7 +112,7 @@ struct Geom {
                     const int kt = k & ~((2 << bit) - 1);
                     const uint32_t j = gidx(elem_local<LOGT>(tau, kt, blo, rho));
                     const double W = tw[(1u << sigma) + (j >> (logN - sigma))];
-                    const double X = redc(x[k], q, qinv);
+                    const double X = (s & 1) ? x[k] : redc(x[k], q, qinv);
                     const double V = mulmod(x[k | (1 << bit)], W, q, qinv);
                     x[k] = X + V;
                     x[k | (1 << bit)] = X - V;

@@ -99,56 +99,6 @@ __global__ void k_automorph(const uint64_t *__restrict__ in, uint64_t *__restric
     const uint32_t y = __brev((ey - 1u) >> 1) >> (32 - logN);
     out[i] = in[base + y];
 }
-// Rescale over a ragged batch of ciphertexts (item b: l_b limbs, P polys).
-// Table: [in: n][out: n][lvl: n][last: n*P][spread: sum P (l_b - 1)]; a last
-// entry j = b*P + p holds j << 16 | (l_b - 1), a spread entry j << 16 | i.
-// Step 1: copy the last limb of every polynomial to tmp [n*P][N].
-__global__ void k_gather_last(uint64_t *const *__restrict__ tab, uint32_t n, uint32_t polys,
-                              uint64_t *__restrict__ tmp, uint32_t logN, uint32_t y0)
-{
-    const uint32_t N = 1u << logN;
-    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
-    if (k >= N) return;
-    const uint32_t j = blockIdx.y + y0, b = j / polys, p = j % polys;
-    const uint32_t l = (uint32_t)(uintptr_t)tab[2 * n + b];
-    tmp[(size_t)j * N + k] = tab[b][((size_t)p * l + (l - 1)) * N + k];
-}
-// Step 2: the last limb r (coefficient domain, mod q_last) lifted to (-q_last/2, q_last/2]
-// and reduced mod q_i for i < l-1, into the spread limb of the entry.
-__global__ void k_spread_centered(uint64_t *const *__restrict__ tab, uint32_t n, uint32_t polys, uint32_t sp,
-                                  const uint64_t *__restrict__ r, uint64_t *__restrict__ dst,
-                                  const ModQ *__restrict__ mods, uint32_t logN, uint32_t y0)
-{
-    const uint32_t N = 1u << logN;
-    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
-    if (k >= N) return;
-    const uint32_t y = blockIdx.y + y0;
-    const uint64_t e = (uint64_t)(uintptr_t)tab[sp + y];
-    const uint32_t j = (uint32_t)(e >> 16), limb = (uint32_t)(e & 0xFFFF);
-    const uint32_t l = (uint32_t)(uintptr_t)tab[2 * n + j / polys];
-    const double ql = mods[l - 1].q;
-    double v = u64_to_f64(r[(size_t)j * N + k]);
-    v = v > 0.5 * ql ? v - ql : v;   // centered lift (q_last odd: no ties)
-    const double q = mods[limb].q, qi = mods[limb].qinv;
-    dst[(size_t)y * N + k] = f64_to_u64(canon(v, q, qi));
-}
-// Step 3: out = (c - s) * q_last^-1 mod q_i.
-__global__ void k_rescale_fin(uint64_t *const *__restrict__ tab, uint32_t n, uint32_t polys, uint32_t sp,
-                              const uint64_t *__restrict__ s, const ModQ *__restrict__ mods,
-                              const double *__restrict__ qlinv, uint32_t L, uint32_t logN, uint32_t y0)
-{
-    const uint32_t N = 1u << logN;
-    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
-    if (k >= N) return;
-    const uint32_t y = blockIdx.y + y0;
-    const uint64_t e = (uint64_t)(uintptr_t)tab[sp + y];
-    const uint32_t j = (uint32_t)(e >> 16), limb = (uint32_t)(e & 0xFFFF), b = j / polys, p = j % polys;
-    const uint32_t l = (uint32_t)(uintptr_t)tab[2 * n + b], lo = l - 1;
-    const double q = mods[limb].q, qi = mods[limb].qinv;
-    const double c = u64_to_f64(tab[b][((size_t)p * l + limb) * N + k]);
-    const double r = mulmod(c - u64_to_f64(s[(size_t)y * N + k]), qlinv[(size_t)(l - 1) * L + limb], q, qi);
-    tab[n + b][((size_t)p * lo + limb) * N + k] = f64_to_u64(fold(r, q));
-}
 // NTT-domain automorphism over a batch: table [in: n][out: n][lvl: n][gal: n][list]
 // with list entries (b*P + p) << 16 | limb; out[x] = in[galois_src(x)].
 __global__ void k_automorph_batch(uint64_t *const *__restrict__ tab, uint32_t n, uint32_t polys, uint32_t lst,
@@ -180,91 +130,11 @@ static fhe_status chk_ct(const fhe_ctx *c, const fhe_ct *a, const char *what)
 }
 static bool scales_match(double a, double b) { return std::fabs(a / b - 1.0) <= 9.5367431640625e-07; }   // 2^-20
 
-size_t rescale_scratch_bytes(const fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n)
-{
-    return (size_t)n * polys * ((size_t)l) * c->N * sizeof(uint64_t);   // last limbs + spread limbs
-}
-size_t rescale_scratch_bytes_ragged(const fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls)
-{
-    size_t limbs = 0;
-    for (uint32_t b = 0; b < n; ++b) limbs += (size_t)polys * ls[b];
-    return limbs * c->N * sizeof(uint64_t);
-}
 template <typename F>
 static void in_pieces(uint32_t total, F f)
 {
     for (uint32_t y0 = 0; y0 < total; y0 += 65535u) f(y0, std::min(65535u, total - y0));
 }
-// Rescale a ragged batch into outputs (l_b - 1 limbs); outputs must not overlap inputs.
-fhe_status rescale_run_ragged(fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls, const uint64_t *const *in,
-                              uint64_t *const *out, uint8_t *scr)
-{
-    if (!n) return FHE_OK;
-    const size_t N = c->N;
-    fhe_status s;
-    std::vector<uint64_t *> tab;
-    for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)in[b]);
-    for (uint32_t b = 0; b < n; ++b) tab.push_back(out[b]);
-    for (uint32_t b = 0; b < n; ++b) {
-        if (ls[b] < 2 || ls[b] > c->L) return fhe_fail(FHE_ELEVEL, "rescale: limb count out of range");
-        tab.push_back((uint64_t *)(uintptr_t)ls[b]);
-    }
-    const uint32_t lastoff = (uint32_t)tab.size();
-    for (uint32_t b = 0; b < n; ++b)
-        for (uint32_t p = 0; p < polys; ++p)
-            tab.push_back((uint64_t *)(uintptr_t)((((uint64_t)(b * polys + p)) << 16) | (ls[b] - 1)));
-    const uint32_t sp = (uint32_t)tab.size();
-    for (uint32_t b = 0; b < n; ++b)
-        for (uint32_t p = 0; p < polys; ++p)
-            for (uint32_t i = 0; i + 1 < ls[b]; ++i)
-                tab.push_back((uint64_t *)(uintptr_t)((((uint64_t)(b * polys + p)) << 16) | i));
-    const uint32_t nsp = (uint32_t)tab.size() - sp, items = n * polys;
-    if ((uint64_t)items >= (1u << 16) * 1024ull) return fhe_fail(FHE_EINVAL, "rescale batch too large");
-    uint64_t **dt;
-    if ((s = ctx_ptr_table(c, tab, &dt))) return s;
-    const uint64_t *dw = (const uint64_t *)dt;
-    uint64_t *last = (uint64_t *)scr, *spread = last + (size_t)items * N;
-    const uint32_t gx = blocks_for(N, TPB);
-    ProfScope ps(c, "rescale");
-    in_pieces(items, [&](uint32_t y0, uint32_t cnt) {
-        hipLaunchKernelGGL(k_gather_last, dim3(gx, cnt), dim3(TPB), 0, c->stream, (uint64_t *const *)dt, n, polys,
-                           last, c->logN, y0);
-    });
-    {
-        LimbSet ls_last;
-        std::memset((void *)&ls_last, 0, sizeof(ls_last));
-        ls_last.base = last;
-        ls_last.period = 1;
-        ls_last.modlist = dw + lastoff;
-        launch_ntt_inv(c, ls_last, items);
-    }
-    in_pieces(nsp, [&](uint32_t y0, uint32_t cnt) {
-        hipLaunchKernelGGL(k_spread_centered, dim3(gx, cnt), dim3(TPB), 0, c->stream, (uint64_t *const *)dt, n, polys,
-                           sp, (const uint64_t *)last, spread, (const ModQ *)c->d_mod, c->logN, y0);
-    });
-    {
-        LimbSet ls_sp;
-        std::memset((void *)&ls_sp, 0, sizeof(ls_sp));
-        ls_sp.base = spread;
-        ls_sp.period = 1;
-        ls_sp.modlist = dw + sp;
-        launch_ntt_fwd(c, ls_sp, nsp);
-    }
-    in_pieces(nsp, [&](uint32_t y0, uint32_t cnt) {
-        hipLaunchKernelGGL(k_rescale_fin, dim3(gx, cnt), dim3(TPB), 0, c->stream, (uint64_t *const *)dt, n, polys, sp,
-                           (const uint64_t *)spread, (const ModQ *)c->d_mod, (const double *)c->d_qlinv, c->L,
-                           c->logN, y0);
-    });
-    HIPCHK(hipGetLastError());
-    return FHE_OK;
-}
-fhe_status rescale_run(fhe_ctx *c, uint32_t l, uint32_t polys, uint32_t n, const uint64_t *const *in,
-                       uint64_t *const *out, uint8_t *scr)
-{
-    std::vector<uint32_t> ls(n, l);
-    return rescale_run_ragged(c, polys, n, ls.data(), in, out, scr);
-}
-
 // Batched NTT-domain automorphisms: out[b] = sigma_g[b](in[b]) over polys x ls[b] limbs.
 fhe_status automorph_run(fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls, const uint32_t *gal,
                          const uint64_t *const *in, uint64_t *const *out)
@@ -597,6 +467,10 @@ void launch_automorph(fhe_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nl
 fhe_status rotate_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *in,
                              const fhe_evk *const *keys, uint64_t *const *out)
 {
+    // The key switch reads c1 through the Galois permutation in its first pass and
+    // adds sigma_g(c0) in its last one: a wavefront's 64 consecutive outputs gather
+    // from one aligned block of 64 inputs (the permutation is affine in bit-reversed
+    // index order), so the gathers stay coalesced and no permuted copy is made.
     const size_t N = c->N, cap = (size_t)4 << 30;
     fhe_status s;
     for (uint32_t b0 = 0; b0 < n;) {
@@ -605,33 +479,25 @@ fhe_status rotate_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const u
         size_t bytes = 0;
         const uint32_t lim = c->tune_chunk ? c->tune_chunk : 16384;
         while (b0 + cn < n && cn < lim) {
-            const size_t item = ks_scratch_bytes(c, ls[b0 + cn], 1) + 2 * (size_t)ls[b0 + cn] * N * sizeof(uint64_t);
+            const size_t item = ks_scratch_bytes(c, ls[b0 + cn], 1);
             if (cn && bytes + item > cap) break;
             bytes += item;
             ++cn;
         }
-        const size_t ksb = ks_scratch_bytes_ragged(c, cn, ls + b0);
         uint8_t *scr;
-        if ((s = ctx_scratch(c, bytes, &scr))) return s;
-        uint64_t *perm = (uint64_t *)(scr + ksb);
-        std::vector<const uint64_t *> dd(cn), ek(cn), ad(2 * (size_t)cn, nullptr), ip(cn);
-        std::vector<uint64_t *> oo(cn), pp(cn);
+        if ((s = ctx_scratch(c, ks_scratch_bytes_ragged(c, cn, ls + b0), &scr))) return s;
+        std::vector<const uint64_t *> dd(cn), ek(cn), ad(2 * (size_t)cn, nullptr);
+        std::vector<uint64_t *> oo(cn);
         std::vector<uint32_t> gal(cn);
-        size_t off = 0;
         for (uint32_t b = 0; b < cn; ++b) {
-            const size_t per = (size_t)ls[b0 + b] * N;
-            uint64_t *pb = perm + off;
-            off += 2 * per;
-            pp[b] = pb;
-            ip[b] = in[b0 + b];
+            const uint64_t *x = in[b0 + b];
             gal[b] = (uint32_t)keys[b0 + b]->galois;
-            dd[b] = pb + per;
-            ad[2 * b] = pb;
+            dd[b] = x + (size_t)ls[b0 + b] * N;   // c1
+            ad[2 * b] = x;                         // c0
             ek[b] = keys[b0 + b]->d;
             oo[b] = out[b0 + b];
         }
-        if ((s = automorph_run(c, 2, cn, ls + b0, gal.data(), ip.data(), pp.data()))) return s;
-        if ((s = ks_run_ragged(c, cn, ls + b0, dd.data(), nullptr, ek.data(), oo.data(), ad.data(), scr))) return s;
+        if ((s = ks_run_ragged(c, cn, ls + b0, dd.data(), gal.data(), ek.data(), oo.data(), ad.data(), scr))) return s;
         b0 += cn;
     }
     c->ops[OP_ROTATE] += n;

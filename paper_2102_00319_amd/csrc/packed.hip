@@ -63,6 +63,127 @@ Consts64 zero_consts()
     return z;
 }
 
+constexpr int TPB = 256;
+constexpr int PW_TILE = 8;
+inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
+
+// Multiply-accumulate with plain weights, for up to TO outputs sharing their
+// ciphertext list A: out_u = sum_p A[p] * W[u][p] (both polynomials), where W is
+// a per-limb integer constant (PT = false: words are the residues as doubles,
+// [u][p][limb]) or a plaintext [limbs][N] (PT = true: words are pointers, [u][p]).
+// Table: [a: P][w: ...][out: n_out][tiles: 2 words: o0 | k << 32, unused]; one
+// block row (blockIdx.y) per tile.
+template <int TO, bool PT>
+__global__ __launch_bounds__(TPB) void k_plain_mac(uint64_t *const *__restrict__ tab, uint32_t P, uint32_t nW,
+                                                   uint32_t n_out, const ModQ *__restrict__ mods, uint32_t logN,
+                                                   uint32_t limbs)
+{
+    const uint32_t N = 1u << logN;
+    const uint64_t e = (uint64_t)blockIdx.x * TPB + threadIdx.x;   // limb * N + k
+    if (e >= ((uint64_t)limbs << logN)) return;
+    const uint64_t w0 = (uint64_t)(uintptr_t)tab[P + nW + n_out + 2 * blockIdx.y];
+    const uint32_t o0 = (uint32_t)w0, k = (uint32_t)(w0 >> 32);
+    const uint32_t limb = (uint32_t)(e >> logN);
+    const uint64_t off1 = (uint64_t)limbs * N;
+    const double q = mods[limb].q, qi = mods[limb].qinv;
+    double d0[TO], d1[TO];
+#pragma unroll
+    for (int u = 0; u < TO; ++u) d0[u] = d1[u] = 0.0;
+    for (uint32_t p = 0; p < P; ++p) {
+        const uint64_t *A = tab[p];
+        const double a0 = u64_to_f64(A[e]), a1 = u64_to_f64(A[e + off1]);
+#pragma unroll
+        for (int u = 0; u < TO; ++u) {
+            if (u < (int)k) {
+                double w;
+                if (PT) w = u64_to_f64(tab[P + (size_t)(o0 + u) * P + p][e]);
+                else w = __longlong_as_double((long long)(uintptr_t)tab[P + ((size_t)(o0 + u) * P + p) * limbs + limb]);
+                d0[u] += mulmod(a0, w, q, qi);
+                d1[u] += mulmod(a1, w, q, qi);
+            }
+        }
+        if ((p & 7) == 7) {   // |mulmod| <= 0.75 q + 2^46: eight terms stay below 2^53
+#pragma unroll
+            for (int u = 0; u < TO; ++u) {
+                d0[u] = redc(d0[u], q, qi);
+                d1[u] = redc(d1[u], q, qi);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < TO; ++u) {
+        if (u < (int)k) {
+            uint64_t *out = tab[P + nW + o0 + u];
+            out[e] = f64_to_u64(canon(d0[u], q, qi));
+            out[e + off1] = f64_to_u64(canon(d1[u], q, qi));
+        }
+    }
+}
+
+// out[o] = Rescale(sum_p A[p] * W[o][p]) for all outputs (all outputs share A); W
+// as constants (cst: n_out x P values, multiplied as round(value * wscale)) or as
+// plaintexts (pts: n_out x P device pointers).  Writes 2 x (l-1) outputs.
+fhe_status plain_mac_rescale(fhe_ctx *c, uint32_t l, const std::vector<uint64_t *> &A, const double *cst,
+                             double wscale, const std::vector<const uint64_t *> &pts, uint32_t n_out,
+                             const std::vector<uint64_t *> &Y)
+{
+    const uint32_t P = (uint32_t)A.size();
+    const size_t N = c->N;
+    fhe_status s;
+    const bool pt = cst == nullptr;
+    // accumulators (2 polys at l limbs) per output and the rescale scratch
+    const size_t acc_bytes = (size_t)n_out * 2 * l * N * sizeof(uint64_t);
+    const size_t rs_bytes = rescale_scratch_bytes(c, l, 2, n_out);
+    uint8_t *scr;
+    if ((s = ctx_scratch(c, acc_bytes + rs_bytes, &scr))) return s;
+    uint64_t *acc = (uint64_t *)scr;
+    std::vector<uint64_t *> tab(A.begin(), A.end());
+    if (pt) {
+        for (uint32_t o = 0; o < n_out; ++o)
+            for (uint32_t p = 0; p < P; ++p) tab.push_back((uint64_t *)pts[(size_t)o * P + p]);
+    } else {
+        for (uint32_t o = 0; o < n_out; ++o)
+            for (uint32_t p = 0; p < P; ++p) {
+                Consts64 r;
+                if ((s = const_residues(c, cst[(size_t)o * P + p] * wscale, l, &r))) return s;
+                for (uint32_t i = 0; i < l; ++i) {
+                    uint64_t bits;
+                    std::memcpy(&bits, &r.v[i], 8);
+                    tab.push_back((uint64_t *)(uintptr_t)bits);
+                }
+            }
+    }
+    const uint32_t nW = (uint32_t)(tab.size() - P);
+    for (uint32_t o = 0; o < n_out; ++o) tab.push_back(acc + (size_t)o * 2 * l * N);
+    uint32_t ntiles = 0;
+    for (uint32_t o0 = 0; o0 < n_out; o0 += PW_TILE, ++ntiles) {
+        const uint32_t k = std::min<uint32_t>(PW_TILE, n_out - o0);
+        tab.push_back((uint64_t *)(uintptr_t)(o0 | ((uint64_t)k << 32)));
+        tab.push_back(nullptr);
+    }
+    uint64_t **dt;
+    if ((s = ctx_ptr_table(c, tab, &dt))) return s;
+    {
+        ProfScope ps(c, "tensor");
+        const dim3 grid(blocks_for((uint64_t)l * N, TPB), ntiles);
+        if (pt)
+            hipLaunchKernelGGL((k_plain_mac<PW_TILE, true>), grid, dim3(TPB), 0, c->stream, (uint64_t *const *)dt, P,
+                               nW, n_out, (const ModQ *)c->d_mod, c->logN, l);
+        else
+            hipLaunchKernelGGL((k_plain_mac<PW_TILE, false>), grid, dim3(TPB), 0, c->stream, (uint64_t *const *)dt, P,
+                               nW, n_out, (const ModQ *)c->d_mod, c->logN, l);
+    }
+    std::vector<const uint64_t *> ai(n_out);
+    for (uint32_t o = 0; o < n_out; ++o) ai[o] = acc + (size_t)o * 2 * l * N;
+    if ((s = rescale_run(c, l, 2, n_out, ai.data(), Y.data(), scr + acc_bytes))) return s;
+    c->ops[OP_PT_MULT] += (uint64_t)P * n_out;
+    c->ops[OP_PT_ADD] += 0;
+    c->ops[OP_CT_ADD] += (uint64_t)(P - 1) * n_out;
+    c->ops[OP_RESCALE] += n_out;
+    HIPCHK(hipGetLastError());
+    return FHE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -319,6 +440,123 @@ fhe_status fhe_fc_packed(fhe_ctx *c, const fhe_evk *rlk, const fhe_evk *keys, ui
     if ((s = mac_relin_rescale(c, rlk, l, A, B, off, zp))) return s;
     const Consts64 zk = zero_consts();
     // z += rot(z, i) for i = 1, 2, ..., frame_slots / 2; the last sum goes to y
+    for (size_t j = 0; j < sumkey.size(); ++j) {
+        std::vector<const fhe_evk *> kv(n_out, sumkey[j]);
+        if ((s = rotate_run(c, l - 1, n_out, zc.data(), kv.data(), rp.data()))) return s;
+        const bool last = j + 1 == sumkey.size();
+        if ((s = ew_batch(c, EW_ADD, l - 1, l - 1, 2, n_out, zc.data(), rc.data(), last ? yp.data() : zp.data(), zk)))
+            return s;
+        c->ops[OP_CT_ADD] += n_out;
+    }
+    if (sumkey.empty())
+        if ((s = ew_batch(c, EW_COPY, l - 1, l - 1, 2, n_out, zc.data(), nullptr, yp.data(), zk))) return s;
+    const double so = x[0].scale * Wt[0].scale / (double)c->mod[l - 1];
+    for (uint32_t o = 0; o < n_out; ++o) y[o].scale = so;
+    return FHE_OK;
+}
+
+
+fhe_status fhe_conv2d_packed_pw(fhe_ctx *c, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *X, uint32_t Cin,
+                                const double *w, uint32_t Cout, uint32_t k, uint32_t dil, uint32_t frame_w,
+                                double wscale, fhe_ct *Y)
+{
+    fhe_status s;
+    if (!c || !X || !w || !Y || (nkeys && !keys)) return fhe_fail(FHE_EINVAL, "fhe_conv2d_packed_pw: null argument");
+    if (!Cin || !Cout || !k || !(k & 1) || !dil || !frame_w || !(wscale > 0.0))
+        return fhe_fail(FHE_EINVAL, "fhe_conv2d_packed_pw: zero dimension, even kernel size or bad scale");
+    const uint32_t l = X[0].limbs, kk = k * k;
+    if (l < 2) return fhe_fail(FHE_ELEVEL, "fhe_conv2d_packed_pw: inputs need two limbs");
+    for (uint32_t i = 0; i < Cin; ++i) {
+        if ((s = chk2(&X[i], l, "fhe_conv2d_packed_pw"))) return s;
+        if (!same_scale(X[i].scale, X[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_packed_pw: input scales differ");
+    }
+    for (uint32_t o = 0; o < Cout; ++o)
+        if ((s = chk2(&Y[o], l - 1, "fhe_conv2d_packed_pw"))) return s;
+    const int64_t half = k / 2;
+    std::vector<int64_t> step(kk);
+    std::vector<const fhe_evk *> tapkey(kk, nullptr);
+    uint32_t nz = 0;
+    for (uint32_t t = 0; t < kk; ++t) {
+        step[t] = (int64_t)dil * (((int64_t)(t / k) - half) * (int64_t)frame_w + ((int64_t)(t % k) - half));
+        if (!step[t]) continue;
+        ++nz;
+        if (!(tapkey[t] = find_key(keys, nkeys, fhe_galois_elt(c, (int32_t)step[t]))))
+            return fhe_fail(FHE_ENOKEY, "fhe_conv2d_packed_pw: no Galois key for step " + std::to_string(step[t]));
+    }
+    const size_t ct_words = 2 * (size_t)l * c->N;
+    uint8_t *ws;
+    if ((s = ctx_workspace(c, (size_t)Cin * nz * ct_words * sizeof(uint64_t), &ws))) return s;
+    uint64_t *rot = (uint64_t *)ws;
+    std::vector<uint64_t *> R((size_t)Cin * kk);
+    std::vector<const uint64_t *> ri;
+    std::vector<const fhe_evk *> rk;
+    std::vector<uint64_t *> ro;
+    for (uint32_t ci = 0; ci < Cin; ++ci)
+        for (uint32_t t = 0; t < kk; ++t) {
+            if (!step[t]) {
+                R[(size_t)ci * kk + t] = X[ci].d;
+                continue;
+            }
+            uint64_t *dst = rot + ro.size() * ct_words;
+            R[(size_t)ci * kk + t] = dst;
+            ri.push_back(X[ci].d);
+            rk.push_back(tapkey[t]);
+            ro.push_back(dst);
+        }
+    if ((s = rotate_run(c, l, (uint32_t)ro.size(), ri.data(), rk.data(), ro.data()))) return s;
+    std::vector<uint64_t *> Yp(Cout);
+    for (uint32_t o = 0; o < Cout; ++o) Yp[o] = Y[o].d;
+    // weights w[(co*Cin + ci)*k*k + t] follow the A order (ci, t) per output
+    if ((s = plain_mac_rescale(c, l, R, w, wscale, {}, Cout, Yp))) return s;
+    const double so = X[0].scale * wscale / (double)c->mod[l - 1];
+    for (uint32_t o = 0; o < Cout; ++o) Y[o].scale = so;
+    return FHE_OK;
+}
+
+fhe_status fhe_fc_packed_pw(fhe_ctx *c, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *x, uint32_t n_in,
+                            const fhe_pt *Wt, uint32_t n_out, uint32_t frame_slots, fhe_ct *y)
+{
+    fhe_status s;
+    if (!c || !x || !Wt || !y || !n_in || !n_out || (nkeys && !keys))
+        return fhe_fail(FHE_EINVAL, "fhe_fc_packed_pw: null or empty");
+    if (!frame_slots || (frame_slots & (frame_slots - 1)) || frame_slots > c->N / 2)
+        return fhe_fail(FHE_EINVAL, "fhe_fc_packed_pw: frame size must be a power of two up to N/2");
+    const uint32_t l = x[0].limbs;
+    if (l < 2) return fhe_fail(FHE_ELEVEL, "fhe_fc_packed_pw: inputs need two limbs");
+    for (uint32_t i = 0; i < n_in; ++i) {
+        if ((s = chk2(&x[i], l, "fhe_fc_packed_pw"))) return s;
+        if (!same_scale(x[i].scale, x[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_packed_pw: input scales differ");
+    }
+    std::vector<const uint64_t *> pts((size_t)n_in * n_out);
+    for (uint32_t i = 0; i < n_in * n_out; ++i) {
+        if (!Wt[i].d || Wt[i].limbs != l) return fhe_fail(FHE_ELEVEL, "fhe_fc_packed_pw: weights must have l limbs");
+        if (!same_scale(Wt[i].scale, Wt[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_packed_pw: weight scales differ");
+        pts[i] = Wt[i].d;
+    }
+    for (uint32_t o = 0; o < n_out; ++o)
+        if ((s = chk2(&y[o], l - 1, "fhe_fc_packed_pw"))) return s;
+    std::vector<const fhe_evk *> sumkey;
+    for (uint32_t i = 1; i < frame_slots; i *= 2) {
+        const fhe_evk *kk = find_key(keys, nkeys, fhe_galois_elt(c, (int32_t)i));
+        if (!kk) return fhe_fail(FHE_ENOKEY, "fhe_fc_packed_pw: no Galois key for step " + std::to_string(i));
+        sumkey.push_back(kk);
+    }
+    const size_t cw = 2 * (size_t)(l - 1) * c->N;
+    uint8_t *ws;
+    if ((s = ctx_workspace(c, 2 * (size_t)n_out * cw * sizeof(uint64_t), &ws))) return s;
+    uint64_t *Z = (uint64_t *)ws, *R = Z + n_out * cw;
+    std::vector<uint64_t *> A(n_in), zp(n_out), rp(n_out), yp(n_out);
+    std::vector<const uint64_t *> zc(n_out), rc(n_out);
+    for (uint32_t i = 0; i < n_in; ++i) A[i] = x[i].d;
+    for (uint32_t o = 0; o < n_out; ++o) {
+        zp[o] = Z + o * cw;
+        rp[o] = R + o * cw;
+        zc[o] = zp[o];
+        rc[o] = rp[o];
+        yp[o] = y[o].d;
+    }
+    if ((s = plain_mac_rescale(c, l, A, nullptr, 0.0, pts, n_out, zp))) return s;
+    const Consts64 zk = zero_consts();
     for (size_t j = 0; j < sumkey.size(); ++j) {
         std::vector<const fhe_evk *> kv(n_out, sumkey[j]);
         if ((s = rotate_run(c, l - 1, n_out, zc.data(), kv.data(), rp.data()))) return s;

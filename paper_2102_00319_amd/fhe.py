@@ -107,6 +107,10 @@ _sig = {
     "fhe_add_const": [_P, C.POINTER(fhe_ct), C.c_double, C.POINTER(fhe_ct)],
     "fhe_decode_slots": [_P, C.POINTER(fhe_pt), _P, C.c_uint32, _P, _P],
     "fhe_pool2x2_sum_slot": [_P, C.POINTER(fhe_ct), C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
+    "fhe_conv2d_packed_pw": [_P, C.POINTER(fhe_evk), C.c_uint32, C.POINTER(fhe_ct), C.c_uint32, _P, C.c_uint32,
+                             C.c_uint32, C.c_uint32, C.c_uint32, C.c_double, C.POINTER(fhe_ct)],
+    "fhe_fc_packed_pw": [_P, C.POINTER(fhe_evk), C.c_uint32, C.POINTER(fhe_ct), C.c_uint32, C.POINTER(fhe_pt),
+                         C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_batch_run": [_P, C.POINTER(fhe_op), C.c_uint32],
     "fhe_graph_begin": [_P, C.c_uint32, C.c_uint64, C.POINTER(_P)],
     "fhe_graph_end": [_P, C.c_uint32, _P],
@@ -620,6 +624,27 @@ class Context:
         K, nk = self._keys(gks)
         XA, WA, YA = self._arr(xs), self._arr(Wt), self._arr(y)
         _check(_lib.fhe_fc_packed(self._h, C.byref(rlk.s()), K, nk, XA, len(xs), WA, n_out, frame_slots, YA))
+        self._back(YA, y)
+        return y
+
+    def conv2d_packed_pw(self, gks, X, w, Cout, k, dilation, frame_w, wscale):
+        l = X[0].limbs
+        Y = [self.new_ct(l - 1, 2) for _ in range(Cout)]
+        K, nk = self._keys(gks)
+        wv = np.ascontiguousarray(w, dtype=np.float64).ravel()
+        XA, YA = self._arr(X), self._arr(Y)
+        _check(_lib.fhe_conv2d_packed_pw(self._h, K, nk, XA, len(X), wv.ctypes.data_as(C.c_void_p), Cout, k, dilation,
+                                         frame_w, float(wscale), YA))
+        self._back(YA, Y)
+        return Y
+
+    def fc_packed_pw(self, gks, xs, Wpt, n_out, frame_slots):
+        l = xs[0].limbs
+        y = [self.new_ct(l - 1, 2) for _ in range(n_out)]
+        K, nk = self._keys(gks)
+        WA = (fhe_pt * len(Wpt))(*[w.s() for w in Wpt])
+        XA, YA = self._arr(xs), self._arr(y)
+        _check(_lib.fhe_fc_packed_pw(self._h, K, nk, XA, len(xs), WA, n_out, frame_slots, YA))
         self._back(YA, y)
         return y
 

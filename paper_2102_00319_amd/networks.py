@@ -147,6 +147,32 @@ class PackedCNN:
         P = ctx.avgpool2x2(gks, A, 2, self.fw, self.pool_mask(ctx, 2, A[0].limbs))
         return ctx.fc_packed(rlk, gks, P, Wf, self.n_classes, self.frame)
 
+    # ---------------------------------------------- plain (unencrypted) model
+    def plain_fc_weights(self, ctx, wfc, limbs):
+        """FC weights as plaintexts at `limbs` limbs, scale q_(limbs-1) (the rescale keeps the scale)."""
+        hp, wp = self.H // 4, self.W // 4
+        sc = float(ctx.q[limbs - 1])
+        out = []
+        for r in range(self.n_classes):
+            rows = np.asarray(wfc[r]).reshape(self.c2, hp * wp)
+            for c in range(self.c2):
+                out.append(ctx.encode(self.fc_slots(ctx, rows[c]), scale=sc, limbs=limbs))
+        return out
+
+    def forward_plain(self, ctx, rlk, gks, X, w1, w2, Wfc_pt):
+        """Forward pass with the model in the clear: conv taps multiply by integer
+        constants (scale q_(l-1)), FC weights are plaintexts; activations and pools as
+        in forward().  One relinearisation per activation product only."""
+        l = X[0].limbs
+        Y = ctx.conv2d_packed_pw(gks, X, w1, self.c1, self.k, 1, self.fw, float(ctx.q[l - 1]))
+        A = ctx.poly_act(rlk, Y, self.coef, self.deg)
+        P = ctx.avgpool2x2(gks, A, 1, self.fw, self.pool_mask(ctx, 1, A[0].limbs))
+        l = P[0].limbs
+        Y = ctx.conv2d_packed_pw(gks, P, w2, self.c2, self.k, 2, self.fw, float(ctx.q[l - 1]))
+        A = ctx.poly_act(rlk, Y, self.coef, self.deg)
+        P = ctx.avgpool2x2(gks, A, 2, self.fw, self.pool_mask(ctx, 2, A[0].limbs))
+        return ctx.fc_packed_pw(gks, P, Wfc_pt, self.n_classes, self.frame)
+
     def op_counts(self):
         """Expected (ct_mult, relin, rotate) of one forward pass."""
         kk, nz = self.k * self.k, self.k * self.k - 1

@@ -1,0 +1,44 @@
+"""Host logic of bench.py: the algorithmic byte model of the key-switch kernels, the
+one-GPU guard and the committed-counter lookup (no GPU needed)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_inner_product_bytes_per_key_switch():
+    # N = 2^16, l = 24, K = 8, dnum 3 (alpha 8): per key switch the three digits and
+    # both key polynomials over 32 limbs (3 * 3 * 32) plus u over 32 limbs (2 * 32)
+    limb = (1 << 16) * 8
+    b, _ = bench.kernel_model("ks_inner", 1 << 16, 24, 8, 8, 8, 3, 24)
+    assert b == 8 * (3 * 3 * 32 + 2 * 32) * limb == 1476395008
+
+
+def test_fused_row_pass_moves_no_bytes_of_its_own():
+    args = (1 << 16, 24, 8, 8, 8, 3, 24)
+    assert bench.kernel_model("ntt_fwd_row", *args, fused=True) == (0, 0)
+    b_split, f_split = bench.kernel_model("ntt_fwd_row", *args, fused=False)
+    b_in0, f_in0 = bench.kernel_model("ks_inner", *args, fused=False)
+    b_in1, f_in1 = bench.kernel_model("ks_inner", *args, fused=True)
+    assert b_in1 == b_in0 and f_in1 == f_in0 + f_split and b_split > 0
+
+
+def test_conversion_targets():
+    # ModUp: each of the 3 digits (8 limbs) converts to the other 16 + 8 limbs
+    limb = (1 << 16) * 8
+    b, _ = bench.kernel_model("bconv_up", 1 << 16, 24, 8, 8, 1, 3, 24)
+    assert b == (24 + 3 * 24) * limb
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_counter_lookup_needs_matching_source():
+    assert bench.measured_traffic("no_such_kernel") is None

@@ -163,3 +163,42 @@ def test_config4_network_full_size():
     assert np.array_equal(g.export_ct(Pl[0]), p0.data)
     assert Pl[0].scale == p0.scale
     _say("sampled pool stage bit-exact")
+
+
+def test_small_plain_model_bit_exact():
+    """The within-image network with the model in the clear: the scores ciphertexts
+    equal the oracle's and decrypt to the FP64 network within 1e-3."""
+    from test_packed_oracle import run_packed_oracle_plain
+    P, networks = _P()
+    g, o = P.Context.from_set("t4_n12"), OracleCtx.from_set("t4_n12")
+    c1, c2, ncls = 2, 3, 2
+    B, imgs, w1, w2, wfc, s, _ = _setup(o, c1, c2, ncls)
+    cnt = cnn.Counter()
+    Zo, st = run_packed_oracle_plain(o, imgs, w1, w2, wfc, s, COEF, cnt)
+    _say("oracle plain-model network done")
+    net = networks.PackedCNN(H=H, W=W, frame_h=FH, frame_w=FW, k=K, c1=c1, c2=c2, n_classes=ncls, coef=COEF)
+    sg = g.keygen_secret(workloads.SEED_SECRET)
+    pk = g.keygen_pk(sg, workloads.SEED_PK)
+    rlk, gks = net.keygen(g, sg, workloads.SEED_EVK)
+    X = net.encrypt_images(g, pk, imgs, workloads.SEED_ENC)
+    Wpt = net.plain_fc_weights(g, wfc, g.L - 8)
+    g.op_counts()
+    Y = g.conv2d_packed_pw(gks, X, w1, c1, K, 1, FW, float(g.q[g.L - 1]))
+    A = g.poly_act(rlk, Y, COEF, 3)
+    Pl = g.avgpool2x2(gks, A, 1, FW, net.pool_mask(g, 1, A[0].limbs))
+    Y2 = g.conv2d_packed_pw(gks, Pl, w2, c2, K, 2, FW, float(g.q[Pl[0].limbs - 1]))
+    A2 = g.poly_act(rlk, Y2, COEF, 3)
+    P2 = g.avgpool2x2(gks, A2, 2, FW, net.pool_mask(g, 2, A2[0].limbs))
+    Z = g.fc_packed_pw(gks, P2, Wpt, ncls, FH * FW)
+    ops = g.op_counts()
+    for name, got in [("conv1", Y), ("act1", A), ("pool1", Pl), ("conv2", Y2), ("act2", A2), ("pool2", P2),
+                      ("fc", Z)]:
+        for a, b in zip(got, st[name]):
+            assert np.array_equal(g.export_ct(a), b.data), "stage %s differs" % name
+            assert a.scale == b.scale, name
+    assert (ops["relin"], ops["rotate"]) == (cnt.relin, cnt.rotate)
+    # the composed forward pass gives the same ciphertexts
+    for a, b in zip(net.forward_plain(g, rlk, gks, X, w1, w2, Wpt), Z):
+        assert np.array_equal(g.export_ct(a), g.export_ct(b))
+    ref = cnn.packed_cnn_fp64(imgs, w1, w2, wfc, COEF)
+    assert np.abs(net.decrypt_scores(g, sg, Z, B) - ref).max() < 1e-3

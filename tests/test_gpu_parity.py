@@ -231,6 +231,66 @@ def test_keyswitch_batch_matches_single(sets):
         assert np.array_equal(g.export_ct(outs[b]), g.export_ct(single))
 
 
+@pytest.mark.parametrize("name,l", [("c1_n12", 3), ("c3_n15", 16), ("c4_n16", 24), ("c4_n16", 7)])
+def test_keyswitch_fused_row_inner_matches_split(sets, name, l):
+    """The row pass of the converted digits fused into the key inner product gives
+    the same key switch as the two separate kernels, and as the oracle."""
+    g, o = sets(name)
+    evk_np = workloads.uniform_residues(300 + l, o.moduli * (2 * o.dnum), o.N).reshape(o.dnum, 2, o.L + o.K, o.N)
+    d_np = [workloads.uniform_residues(310 + l + i, o.q[:l], o.N) for i in range(2)]
+    evk = g.import_evk(evk_np)
+    ds = [g.import_limbs(d, list(range(l))) for d in d_np]
+    evk2 = workloads.uniform_residues(320 + l, o.moduli * (2 * o.dnum), o.N).reshape(o.dnum, 2, o.L + o.K, o.N)
+    keys = [evk, g.import_evk(evk2)]
+    outs = {}
+    for fuse in (1, 0):
+        g.set_tuning("ks_fuse_row_inner", fuse)
+        outs[fuse] = [g.export_ct(x) for x in g.keyswitch_batch(keys, ds)]
+    g.set_tuning("ks_fuse_row_inner", 1)
+    for a, b in zip(outs[1], outs[0]):
+        assert np.array_equal(a, b)
+    if o.N <= 1 << 15 or l < 10:
+        eq(outs[1][0], o.keyswitch(d_np[0], evk_np))
+
+
+def test_keyswitch_batch_shared_keys(sets):
+    """Items that share a key at one level share the key reads of the inner
+    product (groups of at most 8): batches with interleaved keys and a group split
+    in two equal single calls and the oracle."""
+    g, o = sets("c3_n15")
+    keys_np = [workloads.uniform_residues(90 + b, o.moduli * (2 * o.dnum), o.N).reshape(o.dnum, 2, o.L + o.K, o.N)
+               for b in range(2)]
+    keys = [g.import_evk(k) for k in keys_np]
+    for l, plan in [(9, [0] * 6 + [1] * 2 + [0] * 5 + [1] * 3), (4, [1, 0, 1])]:
+        ds_np = [workloads.uniform_residues(100 + i, o.q[:l], o.N) for i in range(len(plan))]
+        ds = [g.import_limbs(d, list(range(l))) for d in ds_np]
+        outs = g.keyswitch_batch([keys[k] for k in plan], ds)
+        for i, k in enumerate(plan):
+            assert np.array_equal(g.export_ct(outs[i]), g.export_ct(g.keyswitch(keys[k], ds[i]))), (l, i)
+        # members of every group, both halves of the split one
+        for i in ((0, 6, 9, 12, 15) if l == 9 else (0, 1)):
+            eq(g.export_ct(outs[i]), o.keyswitch(ds_np[i], keys_np[plan[i]]))
+
+
+def test_rotate_batch_gathered(sets):
+    """Batched rotations read c1 and c0 through the Galois permutation inside the key
+    switch (no permuted copy): equal to single rotations (which stage a permuted
+    copy) and to the oracle, at N = 2^15 (two-pass transforms), shared and distinct
+    keys."""
+    g, o = sets("c3_n15")
+    s = g.keygen_secret(5)
+    steps = [1, -1, 28, 1, 5]
+    keys = {r: g.keygen_rot(s, r, 60 + r % 64) for r in set(steps)}
+    for l in (9, 2):
+        xs_np = [rand_ct(o, l, 2, 200 + 10 * l + i) for i in range(len(steps))]
+        xs = [g.import_ct(x, 1.0) for x in xs_np]
+        outs = g.rotate_batch([keys[r] for r in steps], xs, steps)
+        for i, r in enumerate(steps):
+            assert np.array_equal(g.export_ct(outs[i]), g.export_ct(g.rotate(keys[r], xs[i], r))), (l, i)
+    gko = o.keygen_rot(s.astype(np.int64), 28, 60 + 28)
+    eq(g.export_ct(outs[2]), o.rotate(ckks.Ct(xs_np[2], 1.0), 28, gko).data)
+
+
 def test_relin_rotate_parity(sets):
     g, o = sets("c1_n12")
     s = g.keygen_secret(3)

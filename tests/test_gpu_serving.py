@@ -62,14 +62,18 @@ def _setup(merge, budget_frac):
     return srv, clients, plain, pools
 
 
-def _requests(serving, clients, pools, count=14):
+def _requests(serving, clients, pools, count=14, burst=False):
+    """Requests drawn from the pools; arrivals spread over 0.2 s, or all at once (burst:
+    the queue then holds same-client requests whenever a lane frees up, whatever the
+    device's speed, so that slot merging is exercised deterministically)."""
     rng = np.random.default_rng(7)
     reqs = []
     for i in range(count):
         cid = int(rng.integers(0, len(clients)))
         t = int(rng.integers(0, 3))
         pay, imgs, off = pools[cid][t]
-        r = serving.Request(i, clients[cid], pay, imgs.shape[0], off, float(rng.uniform(0, 0.2)), t)
+        arrival = float(rng.uniform(0, 0.2))
+        r = serving.Request(i, clients[cid], pay, imgs.shape[0], off, 0.0 if burst else arrival, t)
         r.images = imgs
         reqs.append(r)
     return reqs
@@ -85,7 +89,7 @@ def _fp64(c, w, imgs):
 def test_serving_mix_equals_alone(merge):
     from paper_2102_00319_amd import serving
     srv, clients, plain, pools = _setup(merge, 0.6)
-    reqs = _requests(serving, clients, pools)
+    reqs = _requests(serving, clients, pools, burst=merge)
     srv.run(reqs, time_limit=120)
     assert srv.stats["evictions"] > 0 and srv.stats["cold_loads"] > 0
     if merge:

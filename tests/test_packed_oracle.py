@@ -149,3 +149,58 @@ def test_layouts_of_both_codebases_agree():
         b = np.sort(cnn.frame_positions(H, W, FH, FW, B, 2 * dil))
         assert np.array_equal(a, b)
     assert net.rotation_steps() == cnn.packed_rotation_steps(K, FW, FH * FW)
+
+
+def run_packed_oracle_plain(o, imgs, w1, w2, wfc, s, coef, cnt):
+    """The within-image network with the model in the clear (constants and
+    plaintext FC weights); returns the scores ciphertexts and every stage."""
+    D = o.scale
+    B = imgs.shape[0]
+    c1, c2, ncls = w1.shape[0], w2.shape[0], wfc.shape[0]
+    pk = o.keygen_pk(s, workloads.SEED_PK)
+    rlk = o.keygen_relin(s, workloads.SEED_EVK)
+    steps = cnn.packed_rotation_steps(K, FW, FH * FW)
+    gks = {r: o.keygen_rot(s, r, workloads.SEED_EVK + 1 + i) for i, r in enumerate(steps)}
+    L = o.L
+    X = [o.encrypt(pk, o.encode_rns(cnn.frame_pack(imgs, FH, FW), D, L), workloads.SEED_ENC, D)]
+    st = {}
+    Y = cnn.enc_conv2d_packed_pw(o, gks, X, 1, w1, c1, K, 1, FW, float(o.q[L - 1]), cnt)
+    A = cnn.enc_poly_act(o, rlk, Y, coef, 3, cnt)
+    l = A[0].level
+    P = cnn.enc_avgpool2x2(o, gks, A, 1, FW, cnn.pool_mask(o, H, W, FH, FW, 1, float(o.q[l - 1]), l),
+                           float(o.q[l - 1]), cnt)
+    st.update(conv1=Y, act1=A, pool1=P)
+    l = P[0].level
+    Y = cnn.enc_conv2d_packed_pw(o, gks, P, c1, w2, c2, K, 2, FW, float(o.q[l - 1]), cnt)
+    A = cnn.enc_poly_act(o, rlk, Y, coef, 3, cnt)
+    l = A[0].level
+    P = cnn.enc_avgpool2x2(o, gks, A, 2, FW, cnn.pool_mask(o, H, W, FH, FW, 2, float(o.q[l - 1]), l),
+                           float(o.q[l - 1]), cnt)
+    st.update(conv2=Y, act2=A, pool2=P)
+    l = P[0].level
+    hp = H // 4
+    sc = float(o.q[l - 1])
+    Wpt = []
+    for r in range(ncls):
+        rows = wfc[r].reshape(c2, hp * hp)
+        for c in range(c2):
+            Wpt.append(o.encode_rns(cnn.fc_weight_slots(rows[c], hp, hp, FH, FW, B, 4), sc, l))
+    Z = cnn.enc_fc_packed_pw(o, gks, P, Wpt, sc, ncls, FH * FW, cnt)
+    st["fc"] = Z
+    return Z, st
+
+
+def test_packed_network_plain_model():
+    """The same network with an unencrypted model (constant conv taps, plaintext
+    FC weights): scores within 1e-3 of FP64, relinearisations only in the activations."""
+    o = OracleCtx.from_set("t4_n12")
+    c1, c2, ncls = 2, 3, 2
+    B, imgs, w1, w2, wfc, s, _ = _setup(o, c1, c2, ncls)
+    cnt = cnn.Counter()
+    Z, _ = run_packed_oracle_plain(o, imgs, w1, w2, wfc, s, COEF, cnt)
+    ref = cnn.packed_cnn_fp64(imgs, w1, w2, wfc, COEF)
+    for r in range(ncls):
+        re, _ = o.decode(o.decrypt(Z[r], s), Z[r].scale)
+        assert np.abs(re[np.arange(B) * FH * FW] - ref[:, r]).max() < 1e-3
+    assert cnt.relin == 2 * (c1 + c2) and cnt.ct_mult == 2 * (c1 + c2)
+    assert cnt.rotate == (K * K - 1) * (1 + c1) + 2 * (c1 + c2) + ncls * 8
