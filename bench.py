@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB copy kernel (reference for HBM byte counters)")
     ap.add_argument("--param-set", default="c4_n16")
-    ap.add_argument("--ks-fuse", type=int, default=1, choices=[0, 1],
+    ap.add_argument("--ks-fuse", type=int, default=0, choices=[0, 1],
                     help="keyswitch: fuse the digits' row pass into the key inner product (1) or not (0)")
     ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "kssweep", "cnn2", "cnn4", "batch3", "serve", "fig3", "paper",
                                                            "latency"],
@@ -101,7 +101,7 @@ def ks_shape(logN):
     return logN - logB, logB
 
 
-def kernel_model(cat, N, l, K, alpha, B, dnum, L, fused=True):
+def kernel_model(cat, N, l, K, alpha, B, dnum, L, fused=False):
     """Algorithmic work of one step (B key switches, each with its own key) per kernel
     category: (bytes moved to and from HBM by the algorithm, FP64 flops).  fused: the
     row pass of the converted digits runs inside the key inner product."""
@@ -111,8 +111,9 @@ def kernel_model(cat, N, l, K, alpha, B, dnum, L, fused=True):
     ups = sum(l + K - min(alpha, l - j * alpha) for j in range(nd))
     logA, logB = ks_shape(logN)
     bfly = (N // 2) * FLOPS_PER_BUTTERFLY     # flops of one stage over one limb
-    if cat == "ntt_fwd_col":   # not launched by the key-switch path (fused into the conversions)
-        return 0, 0
+    if cat == "ntt_fwd_col":   # the converted ModUp digits and the ModDown conversions z
+        n = B * (ups + 2 * l)
+        return 2 * n * limb, n * logA * bfly
     if cat == "ntt_fwd_row":
         if fused:
             return 0, 0
@@ -138,10 +139,10 @@ def kernel_model(cat, N, l, K, alpha, B, dnum, L, fused=True):
         return (B * (3 * nd * (l + K) + 2 * (l + K)) * limb,
                 B * 2 * nd * (l + K) * N * 9 + (B * ups * logB * bfly if fused else 0))
     if cat == "bconv_up":
-        # conversion fused with the forward column pass: the digit sources in, the converted limbs out
-        return B * (l + ups) * limb, B * (ups * alpha * N * 9 + ups * logA * bfly)
+        # the digit sources in, the converted limbs out (alpha products per target element)
+        return B * (l + ups) * limb, B * ups * alpha * N * 9
     if cat == "bconv_down":
-        return B * (2 * K + 2 * l) * limb, B * (2 * l * K * N * 9 + 2 * l * logA * bfly)
+        return B * (2 * K + 2 * l) * limb, B * 2 * l * K * N * 9
     if cat == "automorph":
         return B * 4 * l * limb, 0
     return 0, 0

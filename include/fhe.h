@@ -216,9 +216,9 @@ void fhe_graph_destroy(fhe_graph *g);                          /* waits for the 
 
 /* Tuning knobs read by the batched drivers (autotuned by the Python layer):
  *   "chunk_items": most items per ragged launch sequence (0 = no limit);
- *   "ks_fuse_row_inner": 1 (default) fuses the forward row pass of the converted
- *     digits into the key inner product when every item has its own key, 0 runs
- *     them as two kernels (same results). */
+ *   "ks_fuse_row_inner": 1 fuses the forward row pass of the converted digits into
+ *     the key inner product when every item has its own key; 0 (default) runs them
+ *     as two kernels.  Results are the same. */
 fhe_status fhe_ctx_set_tuning(fhe_ctx *ctx, const char *key, uint64_t value);
 
 /* Batched relinearisation and rescale of n ciphertexts (host descriptor arrays;

@@ -200,7 +200,6 @@ extern "C" fhe_status fhe_ctx_create(const fhe_params *pp, void *hip_stream, uin
         return fhe_fail(FHE_EPARAM, "need 1 <= n_q, n_q + n_p <= 64, 1 <= dnum <= n_q");
     const uint32_t N = 1u << logN;
     fhe_ctx *c = new fhe_ctx();   // value-initialised: plain fields zero, containers constructed
-    c->tune_fuse_row_inner = 1;
     c->logN = logN; c->N = N; c->L = L; c->K = K; c->dnum = pp->dnum;
     c->alpha = (L + pp->dnum - 1) / pp->dnum;
     c->stream = (hipStream_t)hip_stream;

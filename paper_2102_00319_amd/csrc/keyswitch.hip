@@ -19,18 +19,18 @@
 // most 2^8 elements, so that the fused row kernels run in 256-thread groups):
 //   1 k_ks_intt_first   inverse row pass of d_b, gathered through gal_b  -> dc
 //     k_col_inv         inverse column pass, times (Q_j/q_a)^-1 mod q_a   -> dc (conversion sources)
-//   2 k_col_fwd_bconv   per converted limb: the ModUp sum over its digit's sources,
-//                       then the forward column pass                     -> up
+//   2 k_bconv           ModUp conversion of every digit, one thread per coefficient -> up
+//     k_col_fwd         forward column pass of up
 //   3 k_row_fwd         forward row pass of up
 //   4 k_ks_inner        key inner product over the digits                -> uQ, uP
+//     (3 and 4 as one kernel, k_ks_row_inner, when the fusion is switched on)
 //   5 k_row_inv, k_col_inv  inverse transform of uP, plus (P-1)/2, times (P/p_a)^-1
-//   6 k_col_fwd_bconv   per limb of Q_l: the ModDown sum over P, minus (P-1)/2,
-//                       then the forward column pass                     -> z
+//   6 k_bconv           rounded conversion P -> Q_l, minus (P-1)/2        -> z
+//     k_col_fwd         forward column pass of z
 //   7 k_ks_moddown_final forward row pass of z fused with (u - z) P^-1 + add -> out
-// The conversions are recomputed per target limb from the sources, which the
-// column blocks of all the targets of one digit read while they are in cache,
-// so the converted limbs never make a round trip through HBM before their
-// first transform pass.
+// A conversion thread loads all sources of its coefficient at once and writes every
+// target: fusing the conversion into the column pass of each target instead re-reads
+// the digit's sources once per target and measured 1.6x slower on MI355X.
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -75,15 +75,14 @@ static_assert(sizeof(KsGrp) == 24, "KsGrp is 3 table words");
 // Word offsets of the sections of one batch's table:
 //   [d: n][evk: n][out: n][add: 2n][gal: n][items: 7n][la: sum l][upjobs: 3 sum nd]
 //   [upmods: sum ups][inner: sum over groups (l + K)][dnjobs: 3 * 2n][fl: sum 2l]
-//   [ut: sum ups][zt: sum 2l][pl: 2nK][groups: 3 per group]
+//   [pl: 2nK][groups: 3 per group]
 // la entries: item << 16 | limb, plus the offset of the limb's (Q_j/q_a)^-1 in the
 // conversion constants << 32 (dc order); inner: group << 16 | x (x < l: Q limb,
 // else special prime x - l); fl: item << 17 | poly << 16 | limb (z and uQ order);
-// ut / zt (targets of the fused conversions): job | t << 20 | modulus << 40;
 // pl (uP limbs): modulus | offset of (P/p_a)^-1 << 32.
 struct KsTab {
     uint32_t n, K, L;
-    uint32_t it, la, uj, um, il, dj, fl, ut, zt, pl, gr;
+    uint32_t it, la, uj, um, il, dj, fl, pl, gr;
 };
 __device__ __forceinline__ const KsItem &tab_item(uint64_t *const *tab, const KsTab &t, uint32_t b)
 {
@@ -419,54 +418,60 @@ __global__ __launch_bounds__(WG) void k_row_inv(uint64_t *__restrict__ base, con
 #pragma unroll
     for (int k = 0; k < R; k++) p[gm.inv_out(k)] = f64_to_bits(x[k]);
 }
-// Fast basis conversion fused with the forward column pass of its result: target
-// entry y holds (job, t, modulus m); the target limb's elements of this block's
-// columns are  y_t = sum_a v_a (B/b_a mod c_t) mod c_t  (v_a the prepared sources as FP64 bits,
-// accumulated source by source, reduced every four terms), minus half[t] for
-// ModDown, then transformed by the forward column pass (lazy bits out).
-template <int LOGG, int WG, bool SUB_HALF>
-__global__ __launch_bounds__(WG) void k_col_fwd_bconv(uint64_t *__restrict__ dst, const uint64_t *__restrict__ src,
-                                                      const double *__restrict__ ctab, const BcJob *__restrict__ jobs,
-                                                      const uint64_t *__restrict__ tl, uint32_t y0,
-                                                      const ModQ *__restrict__ mods, const double *__restrict__ twt,
-                                                      uint32_t logN, const double *__restrict__ hdst)
+// Fast basis conversion, one thread per coefficient, blockIdx.y + y0 = job:
+//   y_t = sum_a v_a (B/b_a mod c_t) mod c_t,  v_a the prepared sources (FP64 bits of
+//   [x_a (B/b_a)^-1]_{b_a}, written by the inverse column pass), all nsrc of them
+//   loaded at once; SUB_HALF subtracts hdst[t] (the rounding shift of ModDown).
+//   Canonical targets out, for the forward column pass.
+template <bool SUB_HALF>
+__global__ __launch_bounds__(TPB) void k_bconv(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
+                                               const double *__restrict__ ctab, const BcJob *__restrict__ jobs,
+                                               uint32_t y0, uint32_t logN, const double *__restrict__ hdst)
+{
+    const uint32_t N = 1u << logN;
+    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
+    if (k >= N) return;
+    const BcJob jb = jobs[blockIdx.y + y0];
+    const double *T = ctab + jb.off;
+    const double *dq = T + 3 * jb.nsrc, *dqi = T + 3 * jb.nsrc + jb.ndst, *qh = T + 3 * jb.nsrc + 2 * jb.ndst;
+    const uint64_t *S = src + (size_t)jb.src0 * N + k;
+    uint64_t *D = dst + (size_t)jb.dst0 * N + k;
+    double v[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a)
+        if (a < (int)jb.nsrc) v[a] = bits_to_f64(S[(size_t)a * N]);
+    for (uint32_t t = 0; t < jb.ndst; ++t) {
+        const double q = dq[t], qi = dqi[t];
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < 16; ++a) {
+            if (a < (int)jb.nsrc) {
+                acc += mulmod(v[a], qh[(size_t)a * jb.ndst + t], q, qi);
+                if ((a & 3) == 3) acc = redc(acc, q, qi);
+            }
+        }
+        if (SUB_HALF) acc -= hdst[t];
+        D[(size_t)t * N] = f64_to_u64(canon(acc, q, qi));
+    }
+}
+// Forward column pass over a flat buffer (canonical in, lazy bits out).
+template <int LOGG, int WG>
+__global__ __launch_bounds__(WG) void k_col_fwd(uint64_t *__restrict__ base, const uint64_t *__restrict__ lst,
+                                                uint32_t y0, const ModQ *__restrict__ mods,
+                                                const double *__restrict__ twt, uint32_t logN)
 {
     using Gm = Geom<LOGG, WG, true>;
     __shared__ double lds[Gm::LDS];
     const uint32_t N = 1u << logN;
-    const uint64_t e = tl[blockIdx.y + y0];
-    const BcJob jb = jobs[(uint32_t)(e & 0xFFFFF)];
-    const uint32_t tt = (uint32_t)((e >> 20) & 0xFFFFF), m = (uint32_t)(e >> 40);
-    const double *T = ctab + jb.off;
-    const double cq = T[3 * jb.nsrc + tt], cqi = T[3 * jb.nsrc + jb.ndst + tt];
-    const double *qh = T + 3 * jb.nsrc + 2 * jb.ndst;
+    const uint32_t b = blockIdx.y + y0;
+    const uint32_t m = (uint32_t)(lst[b] & 0xFFFF);
+    const double q = mods[m].q, qinv = mods[m].qinv;
+    uint64_t *p = base + (size_t)b * N;
     const Gm gm(logN, blockIdx.x);
-    uint32_t pos[R];
-#pragma unroll
-    for (int k = 0; k < R; k++) pos[k] = gm.fwd_in(k);
     double x[R];
 #pragma unroll
-    for (int k = 0; k < R; k++) x[k] = 0.0;
-    const uint64_t *S = src + (size_t)jb.src0 * N;
-    for (uint32_t a = 0; a < jb.nsrc; ++a) {
-        const double w = qh[(size_t)a * jb.ndst + tt];
-        const uint64_t *Sa = S + (size_t)a * N;
-#pragma unroll
-        for (int k = 0; k < R; k++) x[k] += mulmod(bits_to_f64(Sa[pos[k]]), w, cq, cqi);
-        if ((a & 3) == 3) {
-#pragma unroll
-            for (int k = 0; k < R; k++) x[k] = redc(x[k], cq, cqi);
-        }
-    }
-    const double q = mods[m].q, qinv = mods[m].qinv;
-#pragma unroll
-    for (int k = 0; k < R; k++) {
-        double v = x[k];
-        if (SUB_HALF) v -= hdst[tt];
-        x[k] = canon(v, cq, cqi);
-    }
+    for (int k = 0; k < R; k++) x[k] = u64_to_f64(p[gm.fwd_in(k)]);
     gm.fwd(x, lds, twt + (size_t)m * N, q, qinv, logN, 0);
-    uint64_t *p = dst + ((size_t)jb.dst0 + tt) * N;
 #pragma unroll
     for (int k = 0; k < R; k++) p[gm.fwd_out(k)] = f64_to_bits(x[k]);
 }
@@ -596,7 +601,7 @@ struct KsPlan {
     std::vector<KsItem> items;
     std::vector<BcJob> upjobs, dnjobs;
     std::vector<KsGrp> groups;
-    std::vector<uint64_t> la, upmods, inner, fl, ut, zt, pl;
+    std::vector<uint64_t> la, upmods, inner, fl, pl;
 };
 
 fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *evk, KsPlan &pl)
@@ -621,12 +626,8 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
         for (uint32_t j = 0; j < nd; ++j) {
             const BconvTab &t = c->modup[(size_t)l * c->dnum + j];
             it.upoff[j] = (uint16_t)u;
-            const uint64_t job = pl.upjobs.size();
             pl.upjobs.push_back(BcJob{t.off, t.nsrc, t.ndst, dc + j * alpha, up + u, 0});
-            for (uint32_t a = 0; a < t.ndst; ++a) {
-                pl.upmods.push_back(t.dst[a]);
-                pl.ut.push_back(job | ((uint64_t)a << 20) | ((uint64_t)t.dst[a] << 40));
-            }
+            for (uint32_t a = 0; a < t.ndst; ++a) pl.upmods.push_back(t.dst[a]);
             u += t.ndst;
         }
         for (uint32_t i = 0; i < l; ++i) {
@@ -635,12 +636,8 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
         }
         for (uint32_t tt = 0; tt < 2; ++tt) {
             const BconvTab &md = c->moddown[l];
-            const uint64_t job = pl.dnjobs.size();
             pl.dnjobs.push_back(BcJob{md.off, md.nsrc, md.ndst, (2 * b + tt) * K, uq + tt * l, 0});
-            for (uint32_t i = 0; i < l; ++i) {
-                pl.fl.push_back(((uint64_t)b << 17) | ((uint64_t)tt << 16) | i);
-                pl.zt.push_back(job | ((uint64_t)i << 20) | ((uint64_t)i << 40));
-            }
+            for (uint32_t i = 0; i < l; ++i) pl.fl.push_back(((uint64_t)b << 17) | ((uint64_t)tt << 16) | i);
             for (uint32_t k = 0; k < K; ++k)
                 pl.pl.push_back((uint64_t)(c->L + k) | ((uint64_t)(md.off + k) << 32));
         }
@@ -712,16 +709,23 @@ static void ks_row_inv(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t
     });
 }
 template <bool SUB_HALF>
-static void ks_col_fwd_bconv(fhe_ctx *c, uint64_t *dst, const uint64_t *src, const uint64_t *jobs, const uint64_t *tl,
-                             uint32_t ntargets, const char *cat)
+static void ks_bconv(fhe_ctx *c, const uint64_t *src, uint64_t *dst, const uint64_t *jobs, uint32_t njobs,
+                     const char *cat)
 {
     ProfScope ps(c, cat);
+    in_pieces(njobs, [&](uint32_t y0, uint32_t cnt) {
+        hipLaunchKernelGGL(k_bconv<SUB_HALF>, dim3(blocks_for(c->N, TPB), cnt), dim3(TPB), 0, c->stream, src, dst,
+                           (const double *)c->d_bconv, (const BcJob *)jobs, y0, c->logN, (const double *)c->d_phalf);
+    });
+}
+static void ks_col_fwd(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs)
+{
+    ProfScope ps(c, "ntt_fwd_col");
     dispatch_logn(c->logN, [&](auto sh) {
         using S = decltype(sh);
-        in_pieces(ntargets, [&](uint32_t y0, uint32_t cnt) {
-            hipLaunchKernelGGL((k_col_fwd_bconv<S::LOGA, S::WA, SUB_HALF>), dim3(S::GA, cnt), dim3(S::WA), 0, c->stream,
-                               dst, src, (const double *)c->d_bconv, (const BcJob *)jobs, tl, y0,
-                               (const ModQ *)c->d_mod, (const double *)c->d_tw, c->logN, (const double *)c->d_phalf);
+        in_pieces(nlimbs, [&](uint32_t y0, uint32_t cnt) {
+            hipLaunchKernelGGL((k_col_fwd<S::LOGA, S::WA>), dim3(S::GA, cnt), dim3(S::WA), 0, c->stream, base, lst, y0,
+                               (const ModQ *)c->d_mod, (const double *)c->d_tw, c->logN);
         });
     });
 }
@@ -792,10 +796,6 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     push_words(pl.dnjobs.data(), pl.dnjobs.size() * sizeof(BcJob));
     kt.fl = (uint32_t)tab.size();
     push_words(pl.fl.data(), pl.fl.size() * 8);
-    kt.ut = (uint32_t)tab.size();
-    push_words(pl.ut.data(), pl.ut.size() * 8);
-    kt.zt = (uint32_t)tab.size();
-    push_words(pl.zt.data(), pl.zt.size() * 8);
     kt.pl = (uint32_t)tab.size();
     push_words(pl.pl.data(), pl.pl.size() * 8);
     kt.gr = (uint32_t)tab.size();
@@ -819,8 +819,10 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
         });
     }
     ks_col_inv<1>(c, dc, dwords + kt.la, pl.sum_l, "ntt_inv_col");
-    // 2-3. ModUp conversion fused with the forward column pass, then the row pass
-    ks_col_fwd_bconv<false>(c, up, dc, dwords + kt.uj, dwords + kt.ut, pl.sum_ups, "bconv_up");
+    // 2-3. ModUp conversion, the forward column pass of the converted limbs, then
+    //      their row pass (alone, or inside the inner product)
+    ks_bconv<false>(c, dc, up, dwords + kt.uj, pl.sum_nd, "bconv_up");
+    ks_col_fwd(c, up, dwords + kt.um, pl.sum_ups);
     if (pl.max_grp == 1 && c->tune_fuse_row_inner) {
         // 3+4. row pass of the converted digits fused with the key inner product
         ProfScope ps(c, "ks_inner");
@@ -850,10 +852,11 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     }
     }
     // 5-6. ModDown: P limbs to coefficients (prepared as conversion sources), the
-    //      rounded conversion to Q_l fused with the forward column pass of z
+    //      rounded conversion to Q_l, the forward column pass of z
     ks_row_inv(c, uP, dwords + kt.pl, n * 2 * K);
     ks_col_inv<2>(c, uP, dwords + kt.pl, n * 2 * K, "ntt_inv_col");
-    ks_col_fwd_bconv<true>(c, z, uP, dwords + kt.dj, dwords + kt.zt, sum2l, "bconv_down");
+    ks_bconv<true>(c, uP, z, dwords + kt.dj, 2 * n, "bconv_down");
+    ks_col_fwd(c, z, dwords + kt.fl, sum2l);
     // 7. row pass of z fused with the finish
     {
         ProfScope ps(c, "ks_moddown_final");
