@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB copy kernel (reference for HBM byte counters)")
     ap.add_argument("--param-set", default="c4_n16")
+    ap.add_argument("--row-wg", type=int, default=128, choices=[128, 256],
+                    help="keyswitch / cnn4: workgroup size of the row passes")
     ap.add_argument("--ks-fuse", type=int, default=0, choices=[0, 1],
                     help="keyswitch: fuse the digits' row pass into the key inner product (1) or not (0)")
     ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "kssweep", "cnn2", "cnn4", "batch3", "serve", "fig3", "paper",
@@ -199,6 +201,7 @@ def cnn4(args):
 
     torch.cuda.set_device(0)
     g = P.Context.from_set("c4_n16")
+    g.set_tuning("row_wg", args.row_wg)
     net = networks.PackedCNN()
     B = net.images_per_ct(g)
     imgs = workloads.images(workloads.SEED_DATA, B, 28, 28)
@@ -767,6 +770,7 @@ def main():
     torch.cuda.set_device(0)
     g = P.Context.from_set(args.param_set)
     g.set_tuning("ks_fuse_row_inner", args.ks_fuse)
+    g.set_tuning("row_wg", args.row_wg)
     N, l, K, alpha = g.N, g.L, g.K, g.alpha
     B = args.batch
     s = g.keygen_secret(workloads.SEED_SECRET)
@@ -863,7 +867,7 @@ def main():
         "config": {"workload": "rotation key switch, N=2^16, l=24 limbs (~49-bit), K=8 special primes, dnum=3, "
                                "%d distinct Galois keys per step" % B,
                    "batch": B, "ring_degree": N, "limbs": l, "special_primes": K, "dnum": g.dnum,
-                   "ks_fuse_row_inner": args.ks_fuse},
+                   "ks_fuse_row_inner": args.ks_fuse, "row_wg": args.row_wg},
         "hbm_frac_compulsory": round(hbm_frac, 4),
         "roofline": roof,
         "cpu_baseline": cpu,

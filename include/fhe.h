@@ -218,7 +218,9 @@ void fhe_graph_destroy(fhe_graph *g);                          /* waits for the 
  *   "chunk_items": most items per ragged launch sequence (0 = no limit);
  *   "ks_fuse_row_inner": 1 fuses the forward row pass of the converted digits into
  *     the key inner product when every item has its own key; 0 (default) runs them
- *     as two kernels.  Results are the same. */
+ *     as two kernels.  Results are the same;
+ *   "row_wg": 128 (default) or 256, the workgroup size of the row passes of the key
+ *     switch and the rescale (same results). */
 fhe_status fhe_ctx_set_tuning(fhe_ctx *ctx, const char *key, uint64_t value);
 
 /* Batched relinearisation and rescale of n ciphertexts (host descriptor arrays;

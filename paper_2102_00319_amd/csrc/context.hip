@@ -200,6 +200,7 @@ extern "C" fhe_status fhe_ctx_create(const fhe_params *pp, void *hip_stream, uin
         return fhe_fail(FHE_EPARAM, "need 1 <= n_q, n_q + n_p <= 64, 1 <= dnum <= n_q");
     const uint32_t N = 1u << logN;
     fhe_ctx *c = new fhe_ctx();   // value-initialised: plain fields zero, containers constructed
+    c->tune_row_wg = 128;
     c->logN = logN; c->N = N; c->L = L; c->K = K; c->dnum = pp->dnum;
     c->alpha = (L + pp->dnum - 1) / pp->dnum;
     c->stream = (hipStream_t)hip_stream;
@@ -345,6 +346,11 @@ extern "C" fhe_status fhe_ctx_set_tuning(fhe_ctx *c, const char *key, uint64_t v
     }
     if (!std::strcmp(key, "ks_fuse_row_inner")) {
         c->tune_fuse_row_inner = value ? 1u : 0u;
+        return FHE_OK;
+    }
+    if (!std::strcmp(key, "row_wg")) {
+        if (value != 128 && value != 256) return fhe_fail(FHE_EINVAL, "fhe_ctx_set_tuning: row_wg must be 128 or 256");
+        c->tune_row_wg = (uint32_t)value;
         return FHE_OK;
     }
     return fhe_fail(FHE_EINVAL, std::string("fhe_ctx_set_tuning: unknown key ") + key);

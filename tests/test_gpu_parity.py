@@ -253,6 +253,26 @@ def test_keyswitch_fused_row_inner_matches_split(sets, name, l):
         eq(outs[1][0], o.keyswitch(d_np[0], evk_np))
 
 
+@pytest.mark.parametrize("name,l", [("c3_n15", 16), ("c4_n16", 24)])
+def test_row_workgroup_128_matches_256(sets, name, l):
+    """The row passes of the key switch and the rescale in 128-thread workgroups give
+    the same results as in 256-thread ones."""
+    g, o = sets(name)
+    s = g.keygen_secret(9)
+    keys = [g.keygen_rot(s, r, 70 + r) for r in (1, 3)]
+    xs = [g.import_ct(rand_ct(o, l, 2, 400 + i), 1.0) for i in range(2)]
+    res = {}
+    for wg in (128, 256):
+        g.set_tuning("row_wg", wg)
+        rot = g.rotate_batch(keys, xs, [1, 3])
+        res[wg] = [g.export_ct(x) for x in rot] + [g.export_ct(x) for x in g.rescale_batch(rot)]
+    for a, b in zip(res[128], res[256]):
+        assert np.array_equal(a, b)
+    P = _fhe()
+    with pytest.raises(P.FheError):
+        g.set_tuning("row_wg", 64)
+
+
 def test_keyswitch_batch_shared_keys(sets):
     """Items that share a key at one level share the key reads of the inner
     product (groups of at most 8): batches with interleaved keys and a group split
