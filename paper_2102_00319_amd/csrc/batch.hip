@@ -32,8 +32,8 @@ __global__ __launch_bounds__(TPB) void k_tensor_batch(uint64_t *const *__restric
     const uint32_t b = (uint32_t)(e >> 16), limb = (uint32_t)(e & 0xFFFF);
     const uint32_t l = (uint32_t)(uintptr_t)tab[3 * n + b];
     const size_t off1 = (size_t)l * N, x = (size_t)limb * N + k;
-    const uint64_t *A = tab[b], *B = tab[n + b];
-    uint64_t *out = tab[2 * n + b];
+    const gu64 *A = gview(tab[b]), *B = gview(tab[n + b]);
+    gu64 *out = gview(tab[2 * n + b]);
     const double q = mods[limb].q, qi = mods[limb].qinv;
     const double a0 = u64_to_f64(A[x]), a1 = u64_to_f64(A[x + off1]);
     const double b0 = u64_to_f64(B[x]), b1 = u64_to_f64(B[x + off1]);

@@ -86,6 +86,14 @@ __device__ __forceinline__ double fold(double x, double q)
     return x >= q ? x - q : x;
 }
 
+// Device memory reached through a pointer table arrives as generic pointers, which the
+// compiler accesses with flat instructions (those also count against the scalar-load
+// counter, so every wait for a table word waits for them too): these views make the
+// accesses global.
+typedef __attribute__((address_space(1))) uint64_t gu64;
+__device__ __forceinline__ const gu64 *gview(const uint64_t *p) { return (const gu64 *)p; }
+__device__ __forceinline__ gu64 *gview(uint64_t *p) { return (gu64 *)p; }
+
 __device__ __forceinline__ uint64_t *limb_ptr(const LimbSet &ls, uint32_t b, uint32_t N)
 {
     return ls.units ? ls.units[b / ls.lpu] + (size_t)(b % ls.lpu) * N : ls.base + (size_t)b * N;

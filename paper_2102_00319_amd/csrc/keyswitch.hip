@@ -108,7 +108,7 @@ __global__ __launch_bounds__(WG) void k_ks_intt_first(uint64_t *const *__restric
     const uint32_t y = blockIdx.y + y0;
     const uint64_t e = tab_word(tab, t.la, y);
     const uint32_t b = (uint32_t)((e >> 16) & 0xFFFF), i = (uint32_t)(e & 0xFFFF);
-    const uint64_t *src = tab[b] + (size_t)i * N;
+    const gu64 *src = gview(tab[b] + (size_t)i * N);
     const uint32_t gal = (uint32_t)tab_word(tab, 5 * t.n, b);
     const double q = mods[i].q, qinv = mods[i].qinv;
     const Gm gm(logN, blockIdx.x);
@@ -129,9 +129,11 @@ __global__ __launch_bounds__(WG) void k_ks_intt_first(uint64_t *const *__restric
 //     the inner list.
 __device__ __forceinline__ void ld2(const uint64_t *p, double &a, double &b)
 {
-    const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(p);
-    a = u64_to_f64(v.x);
-    b = u64_to_f64(v.y);
+    // p comes from the pointer table: a generic pointer to device memory, loaded as
+    // global memory (a flat load would also wait on the scalar loads of the table)
+    const gu64 *g = gview(p);
+    a = u64_to_f64(g[0]);
+    b = u64_to_f64(g[1]);
 }
 template <int TI>
 __global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ tab, KsTab t, uint32_t y0,
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(WG) void k_ks_row_inner(uint64_t *const *__restrict
         const uint32_t lo = j * alpha, hi = min(lo + alpha, l);
         double v[R];
         if (x >= lo && x < hi) {   // block-uniform branch; the input limb through the permutation
-            const uint64_t *src = tab[b] + (size_t)x * N;
+            const gu64 *src = gview(tab[b] + (size_t)x * N);
 #pragma unroll
             for (int k = 0; k < R; k++) v[k] = u64_to_f64(src[galois_src(gm.coal(k), gal, logN)]);
         } else {
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(WG) void k_ks_row_inner(uint64_t *const *__restrict
 #pragma unroll
             for (int k = 0; k < R; k++) v[k] = canon(v[k], q, qi);
         }
-        const uint64_t *e0 = ev + (((size_t)j * 2 + 0) * ML + mx) * N, *e1 = ev + (((size_t)j * 2 + 1) * ML + mx) * N;
+        const gu64 *e0 = gview(ev + (((size_t)j * 2 + 0) * ML + mx) * N), *e1 = gview(ev + (((size_t)j * 2 + 1) * ML + mx) * N);
 #pragma unroll
         for (int k = 0; k < R; k++) {
             const uint32_t idx = gm.coal(k);
@@ -325,15 +327,16 @@ __global__ __launch_bounds__(WG, 3) void k_ks_moddown_final(uint64_t *const *__r
     gm.fwd(v, lds, twt + (size_t)i * N, q, qinv, logN, sigma0);
     gm.fwd_out_to_coal(v, lds);
     const uint64_t *uq = uQ + row * N;
-    const uint64_t *ad = tab[3 * t.n + 2 * b + tt];
+    const uint64_t *adp = tab[3 * t.n + 2 * b + tt];
+    const gu64 *ad = gview(adp);
     const uint32_t gal = (uint32_t)tab_word(tab, 5 * t.n, b);
-    uint64_t *out = tab[2 * t.n + b] + ((size_t)tt * l + i) * N;
+    gu64 *out = gview(tab[2 * t.n + b] + ((size_t)tt * l + i) * N);
     const double pi = pinv[i];
 #pragma unroll
     for (int k = 0; k < R; k++) {
         const uint32_t idx = gm.coal(k);
         double r = canon(mulmod(u64_to_f64(uq[idx]) - v[k], pi, q, qinv), q, qinv);
-        if (ad) r = fold(r + u64_to_f64(ad[(size_t)i * N + galois_src(idx, gal, logN)]), q);
+        if (adp) r = fold(r + u64_to_f64(ad[(size_t)i * N + galois_src(idx, gal, logN)]), q);
         out[idx] = f64_to_u64(r);
     }
 }
@@ -494,7 +497,7 @@ __global__ __launch_bounds__(TPB) void k_rs_gather_last(uint64_t *const *__restr
     if (k >= N) return;
     const uint32_t j = blockIdx.y + y0, b = j / polys, p = j % polys;
     const uint32_t l = (uint32_t)(uintptr_t)tab[2 * n + b];
-    last[(size_t)j * N + k] = tab[b][((size_t)p * l + (l - 1)) * N + k];
+    last[(size_t)j * N + k] = gview(tab[b])[((size_t)p * l + (l - 1)) * N + k];
 }
 // Step 2 (after the inverse transform of the last limbs): per spread entry y, the
 // last limb's coefficients r lifted to (-q_last/2, q_last/2] and reduced mod q_i,
@@ -551,8 +554,8 @@ __global__ __launch_bounds__(WG) void k_rs_row_fin(uint64_t *const *__restrict__
     for (int k = 0; k < R; k++) x[k] = bits_to_f64(sv[gm.fwd_in(k)]);
     gm.fwd(x, lds, twt + (size_t)i * N, q, qinv, logN, sigma0);
     gm.fwd_out_to_coal(x, lds);
-    const uint64_t *cin = tab[b] + ((size_t)p * l + i) * N;
-    uint64_t *out = tab[n + b] + ((size_t)p * (l - 1) + i) * N;
+    const gu64 *cin = gview(tab[b] + ((size_t)p * l + i) * N);
+    gu64 *out = gview(tab[n + b] + ((size_t)p * (l - 1) + i) * N);
     const double w = qlinv[(size_t)(l - 1) * L + i];
 #pragma unroll
     for (int k = 0; k < R; k++) {

@@ -51,19 +51,15 @@ __global__ __launch_bounds__(TPB) void k_tensor_tile(uint64_t *const *__restrict
 #pragma unroll
         for (int h = 0; h < 2; ++h) d0[u][h] = d1[u][h] = d2[u][h] = 0.0;
     for (uint32_t p = 0; p < P; ++p) {
-        const uint64_t *A = ap[p];
-        const ulonglong2 av0 = *reinterpret_cast<const ulonglong2 *>(A + e);
-        const ulonglong2 av1 = *reinterpret_cast<const ulonglong2 *>(A + e + off1);
-        const double a0[2] = {u64_to_f64(av0.x), u64_to_f64(av0.y)};
-        const double a1[2] = {u64_to_f64(av1.x), u64_to_f64(av1.y)};
+        const gu64 *A = gview(ap[p]);
+        const double a0[2] = {u64_to_f64(A[e]), u64_to_f64(A[e + 1])};
+        const double a1[2] = {u64_to_f64(A[e + off1]), u64_to_f64(A[e + off1 + 1])};
 #pragma unroll
         for (int u = 0; u < TO; ++u) {
             if (u < (int)k) {
-                const uint64_t *Bp = bp[(size_t)u * P + p];
-                const ulonglong2 bv0 = *reinterpret_cast<const ulonglong2 *>(Bp + e);
-                const ulonglong2 bv1 = *reinterpret_cast<const ulonglong2 *>(Bp + e + off1);
-                const double b0[2] = {u64_to_f64(bv0.x), u64_to_f64(bv0.y)};
-                const double b1[2] = {u64_to_f64(bv1.x), u64_to_f64(bv1.y)};
+                const gu64 *Bp = gview(bp[(size_t)u * P + p]);
+                const double b0[2] = {u64_to_f64(Bp[e]), u64_to_f64(Bp[e + 1])};
+                const double b1[2] = {u64_to_f64(Bp[e + off1]), u64_to_f64(Bp[e + off1 + 1])};
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     d0[u][h] += mulmod(a0[h], b0[h], q, qi);
@@ -87,13 +83,13 @@ __global__ __launch_bounds__(TPB) void k_tensor_tile(uint64_t *const *__restrict
 #pragma unroll
     for (int u = 0; u < TO; ++u) {
         if (u < (int)k) {
-            uint64_t *out = tab[nA + nB + o0 + u];
-            *reinterpret_cast<ulonglong2 *>(out + e) =
-                make_ulonglong2(f64_to_u64(canon(d0[u][0], q, qi)), f64_to_u64(canon(d0[u][1], q, qi)));
-            *reinterpret_cast<ulonglong2 *>(out + e + off1) =
-                make_ulonglong2(f64_to_u64(canon(d1[u][0], q, qi)), f64_to_u64(canon(d1[u][1], q, qi)));
-            *reinterpret_cast<ulonglong2 *>(out + e + 2 * off1) =
-                make_ulonglong2(f64_to_u64(canon(d2[u][0], q, qi)), f64_to_u64(canon(d2[u][1], q, qi)));
+            gu64 *out = gview(tab[nA + nB + o0 + u]);
+            out[e] = f64_to_u64(canon(d0[u][0], q, qi));
+            out[e + 1] = f64_to_u64(canon(d0[u][1], q, qi));
+            out[e + off1] = f64_to_u64(canon(d1[u][0], q, qi));
+            out[e + off1 + 1] = f64_to_u64(canon(d1[u][1], q, qi));
+            out[e + 2 * off1] = f64_to_u64(canon(d2[u][0], q, qi));
+            out[e + 2 * off1 + 1] = f64_to_u64(canon(d2[u][1], q, qi));
         }
     }
 }
@@ -166,7 +162,7 @@ __global__ void k_encrypt_const(const uint64_t *__restrict__ pk, uint32_t L, con
     const double b = u64_to_f64(pk[(size_t)i * N + k]), a = u64_to_f64(pk[((size_t)L + i) * N + k]);
     const double c0 = mulmod(v, b, q, qi) + e0 + (double)mv;
     const double c1 = mulmod(v, a, q, qi) + e1;
-    uint64_t *o = outp[item];
+    gu64 *o = gview(outp[item]);
     o[(size_t)i * N + k] = f64_to_u64(canon(c0, q, qi));
     o[((size_t)l + i) * N + k] = f64_to_u64(canon(c1, q, qi));
 }

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(WG) void k_ntt_fwd(LimbSet ls, const ModQ *__restri
     __shared__ double lds[Gm::LDS];
     const uint32_t N = 1u << logN;
     const uint32_t b = blockIdx.y + ls.b0;
-    uint64_t *p = limb_ptr(ls, b, N);
+    gu64 *p = gview(limb_ptr(ls, b, N));
     const uint32_t m = limb_mod(ls, b);
     const double q = mods[m].q, qinv = mods[m].qinv;
     const Gm gm(logN, blockIdx.x);
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(WG) void k_ntt_inv(LimbSet ls, const ModQ *__restri
     __shared__ double lds[Gm::LDS];
     const uint32_t N = 1u << logN;
     const uint32_t b = blockIdx.y + ls.b0;
-    uint64_t *p = limb_ptr(ls, b, N);
+    gu64 *p = gview(limb_ptr(ls, b, N));
     const uint32_t m = limb_mod(ls, b);
     const double q = mods[m].q, qinv = mods[m].qinv;
     const Gm gm(logN, blockIdx.x);

@@ -70,7 +70,7 @@ __global__ void k_tensor_acc(uint64_t *const *__restrict__ ap, uint64_t *const *
     const double q = mods[limb].q, qi = mods[limb].qinv;
     double d0 = 0, d1 = 0, d2 = 0;
     for (uint32_t t = 0; t < n; ++t) {
-        const uint64_t *A = ap[t], *B = bp[t];
+        const gu64 *A = gview(ap[t]), *B = gview(bp[t]);
         const double a0 = u64_to_f64(A[e]), a1 = u64_to_f64(A[e + off1]);
         const double b0 = u64_to_f64(B[e]), b1 = u64_to_f64(B[e + off1]);
         d0 += mulmod(a0, b0, q, qi);
@@ -115,7 +115,7 @@ __global__ void k_automorph_batch(uint64_t *const *__restrict__ tab, uint32_t n,
     const uint32_t ex = 2u * (__brev(x) >> (32 - logN)) + 1u;
     const uint32_t ey = (uint32_t)(((uint64_t)ex * g) & (2u * N - 1));
     const uint32_t y = __brev((ey - 1u) >> 1) >> (32 - logN);
-    tab[n + b][off + x] = tab[b][off + y];
+    gview(tab[n + b])[off + x] = gview(tab[b])[off + y];
 }
 
 }  // namespace
@@ -542,11 +542,11 @@ __global__ __launch_bounds__(TPB) void k_ew_batch(uint64_t *const *__restrict__ 
     const uint32_t p = (uint32_t)(e / per);
     const uint64_t r = e - (uint64_t)p * per;
     const uint32_t limb = (uint32_t)(r >> logN);
-    const uint64_t a = tab[t][(uint64_t)p * ((uint64_t)la << logN) + r];
+    const uint64_t a = gview(tab[t])[(uint64_t)p * ((uint64_t)la << logN) + r];
     const uint64_t qq = (uint64_t)mods[limb].q;
     uint64_t o;
     if (OP == EW_ADD) {
-        o = a + tab[n + t][e];
+        o = a + gview(tab[n + t])[e];
         o = o >= qq ? o - qq : o;
     } else if (OP == EW_COPY) {
         o = a;
@@ -558,10 +558,10 @@ __global__ __launch_bounds__(TPB) void k_ew_batch(uint64_t *const *__restrict__ 
         }
     } else {
         const double q = mods[limb].q, qi = mods[limb].qinv;
-        const double m = OP == EW_MULC ? cst.v[limb] : u64_to_f64(tab[n + t][r]);
+        const double m = OP == EW_MULC ? cst.v[limb] : u64_to_f64(gview(tab[n + t])[r]);
         o = f64_to_u64(canon(mulmod(u64_to_f64(a), m, q, qi), q, qi));
     }
-    tab[2 * n + t][e] = o;
+    gview(tab[2 * n + t])[e] = o;
 }
 }  // namespace
 

@@ -90,13 +90,13 @@ __global__ __launch_bounds__(TPB) void k_plain_mac(uint64_t *const *__restrict__
 #pragma unroll
     for (int u = 0; u < TO; ++u) d0[u] = d1[u] = 0.0;
     for (uint32_t p = 0; p < P; ++p) {
-        const uint64_t *A = tab[p];
+        const gu64 *A = gview(tab[p]);
         const double a0 = u64_to_f64(A[e]), a1 = u64_to_f64(A[e + off1]);
 #pragma unroll
         for (int u = 0; u < TO; ++u) {
             if (u < (int)k) {
                 double w;
-                if (PT) w = u64_to_f64(tab[P + (size_t)(o0 + u) * P + p][e]);
+                if (PT) w = u64_to_f64(gview(tab[P + (size_t)(o0 + u) * P + p])[e]);
                 else w = __longlong_as_double((long long)(uintptr_t)tab[P + ((size_t)(o0 + u) * P + p) * limbs + limb]);
                 d0[u] += mulmod(a0, w, q, qi);
                 d1[u] += mulmod(a1, w, q, qi);
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(TPB) void k_plain_mac(uint64_t *const *__restrict__
 #pragma unroll
     for (int u = 0; u < TO; ++u) {
         if (u < (int)k) {
-            uint64_t *out = tab[P + nW + o0 + u];
+            gu64 *out = gview(tab[P + nW + o0 + u]);
             out[e] = f64_to_u64(canon(d0[u], q, qi));
             out[e + off1] = f64_to_u64(canon(d1[u], q, qi));
         }

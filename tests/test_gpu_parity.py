@@ -253,10 +253,10 @@ def test_keyswitch_fused_row_inner_matches_split(sets, name, l):
         eq(outs[1][0], o.keyswitch(d_np[0], evk_np))
 
 
-@pytest.mark.parametrize("name,l", [("c3_n15", 16), ("c4_n16", 24)])
-def test_row_workgroup_128_matches_256(sets, name, l):
-    """The row passes of the key switch and the rescale in 128-thread workgroups give
-    the same results as in 256-thread ones."""
+@pytest.mark.parametrize("name,l", [("c3_n15", 16), ("c4_n16", 24), ("c4_n16", 9)])
+def test_tuning_knobs_same_results(sets, name, l):
+    """The row passes of the key switch and the rescale in 128- or 256-thread
+    workgroups give the same rotations and rescales."""
     g, o = sets(name)
     s = g.keygen_secret(9)
     keys = [g.keygen_rot(s, r, 70 + r) for r in (1, 3)]
@@ -266,6 +266,7 @@ def test_row_workgroup_128_matches_256(sets, name, l):
         g.set_tuning("row_wg", wg)
         rot = g.rotate_batch(keys, xs, [1, 3])
         res[wg] = [g.export_ct(x) for x in rot] + [g.export_ct(x) for x in g.rescale_batch(rot)]
+    g.set_tuning("row_wg", 128)
     for a, b in zip(res[128], res[256]):
         assert np.array_equal(a, b)
     P = _fhe()
