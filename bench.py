@@ -673,6 +673,8 @@ def cnn2(args):
     Wc = g.encrypt_const_batch(pk, cw.ravel(), D, [workloads.SEED_ENC + 100000 + t for t in range(cw.size)], L)
     W1 = g.encrypt_const_batch(pk, f1.ravel(), D, [workloads.SEED_ENC + 200000 + t for t in range(f1.size)], L - 2)
     W2 = g.encrypt_const_batch(pk, f2.ravel(), D, [workloads.SEED_ENC + 300000 + t for t in range(f2.size)], L - 4)
+    # descriptor arrays of the model and the batch's inputs, built once
+    X, Wc, W1, W2 = P.CtArray(X), P.CtArray(Wc), P.CtArray(W1), P.CtArray(W2)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
 
@@ -691,9 +693,22 @@ def cnn2(args):
         out = forward()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    # per-category kernel time of one forward pass
+    g.profile_enable("*")
+    forward()
+    torch.cuda.synchronize()
+    prof = {c: g.profile_read(c)[0] for c in PROFILE_CATEGORIES}
+    g.profile_enable(None)
+    breakdown = {k: round(v, 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1]) if v > 0}
+    # compulsory HBM bytes of one batch: every weight ciphertext and image ciphertext read once
+    limb = g.N * 8
+    wbytes = (cw.size * 2 * L + f1.size * 2 * (L - 2) + f2.size * 2 * (L - 4)) * limb
+    xbytes = H * W * 2 * L * limb
     rec = {"metric": "encrypted-CNN images/s (slot packing, batched layers)", "value": round(B / dt, 1),
            "unit": "images/s", "ms_per_batch": round(dt * 1e3, 3), "images_per_batch": B, "steps": args.steps,
-           "max_abs_logit_error_vs_fp64": err, "setup_s": round(t_setup, 1),
+           "max_abs_logit_error_vs_fp64": err, "setup_s": round(t_setup, 1), "kernel_ms_per_batch": breakdown,
+           "compulsory_GB_per_batch": round((wbytes + xbytes) / 1e9, 2),
+           "hbm_frac_compulsory": round((wbytes + xbytes) / dt / (HBM_PEAK_GBS * 1e9), 4),
            "config": {"workload": "conv5x5s2x5 -> x^2 -> FC845x%d -> x^2 -> FC%dx10, N=2^14, 8 x ~40-bit primes, "
                                   "scale 2^40" % (n1, n1), "weight_ciphertexts": int(cw.size + f1.size + f2.size)}}
     if args.unbatched:

@@ -15,6 +15,8 @@ forward pass takes 9 levels: conv 1, act 2, pool 1, conv 1, act 2, pool 1, fc 1.
 """
 import numpy as np
 
+from .fhe import CtArray
+
 # ------------------------------------------------------------ slot layouts
 
 
@@ -123,7 +125,7 @@ class PackedCNN:
             for c in range(self.c2):
                 pt = ctx.encode(self.fc_slots(ctx, rows[c]), scale=D, limbs=l3)
                 Wf.append(ctx.encrypt(pk, pt, seeds[2] + r * self.c2 + c))
-        return W1, W2, Wf
+        return CtArray(W1), CtArray(W2), CtArray(Wf)
 
     # -------------------------------------------------------------- cloud
     def pool_mask(self, ctx, dil, limbs):
@@ -225,7 +227,7 @@ class SlotCNN:
         Wc = ctx.encrypt_const_batch(pk, cw.ravel(), D, [seeds[0] + t for t in range(cw.size)], top)
         W1 = ctx.encrypt_const_batch(pk, f1.ravel(), D, [seeds[1] + t for t in range(f1.size)], top - 2)
         W2 = ctx.encrypt_const_batch(pk, f2.ravel(), D, [seeds[2] + t for t in range(f2.size)], top - 4)
-        return Wc, W1, W2
+        return CtArray(Wc), CtArray(W1), CtArray(W2)
 
     def forward(self, ctx, rlk, gks, X, weights):
         Wc, W1, W2 = weights
@@ -285,7 +287,7 @@ class PaperCNN:
         D = scale or ctx.scale
         Wc = ctx.encrypt_const_batch(pk, wc.ravel(), D, [seeds[0] + t for t in range(wc.size)], top)
         Wf = ctx.encrypt_const_batch(pk, wfc.ravel(), D, [seeds[1] + t for t in range(wfc.size)], 2)
-        return Wc, Wf
+        return CtArray(Wc), CtArray(Wf)
 
     def forward(self, ctx, rlk, gks, X, weights):
         Wc, Wf = weights

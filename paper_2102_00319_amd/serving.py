@@ -23,7 +23,7 @@ import time
 import numpy as np
 import torch
 
-from .fhe import Context
+from .fhe import Context, CtArray
 
 
 class Client:
@@ -50,6 +50,9 @@ class Client:
     def restore(self):
         for o in self.objs:
             o.data = o.data.to(self.device)
+        for grp in self.weights:   # packed descriptor arrays hold device addresses
+            if isinstance(grp, CtArray):
+                grp.refresh()
         self.resident = True
         self.loads += 1
 
