@@ -86,7 +86,7 @@ def parse():
                          "cnn4: within-image packed deep CNN images/s; batch3: 256 uneven jobs (mixed N and "
                          "level) per step")
     ap.add_argument("--fc1", type=int, default=100, help="cnn2: FC1 width (100 = the full network)")
-    ap.add_argument("--unbatched", action="store_true", help="cnn2: also time the one-ciphertext-per-call form")
+    ap.add_argument("--unbatched", action="store_true", help="cnn2 / cnn4: also time the one-ciphertext-per-call form")
     ap.add_argument("--rates", default="1,2,5,10,20,50,100,200", help="serve: Poisson arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=40, help="serve: requests per rate")
     ap.add_argument("--budget-gb", type=float, default=250.0, help="serve: HBM budget for admission (GB)")
@@ -243,6 +243,17 @@ def cnn4(args):
            "kernel_ms_per_batch": breakdown,
            "config": {"workload": "conv3x3x8 -> cubic -> avgpool -> conv3x3x16 -> cubic -> avgpool -> FC784x10, "
                                   "32 images of 28x28 per ciphertext, N=2^16, 24 limbs, dnum 3"}}
+    if args.unbatched:   # one ciphertext per library call
+        ou = net.forward_per_op(g, rlk, gks, X, Wt)
+        same = all(np.array_equal(g.export_ct(a), g.export_ct(b)) for a, b in zip(ou, out))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        net.forward_per_op(g, rlk, gks, X, Wt)
+        torch.cuda.synchronize()
+        du = time.perf_counter() - t0
+        rec["unbatched_images_per_s"] = round(B / du, 1)
+        rec["unbatched_ms_per_batch"] = round(du * 1e3, 2)
+        rec["unbatched_equals_batched_bitwise"] = bool(same)
     print(json.dumps(rec))
 
 

@@ -149,6 +149,42 @@ class PackedCNN:
         P = ctx.avgpool2x2(gks, A, 2, self.fw, self.pool_mask(ctx, 2, A[0].limbs))
         return ctx.fc_packed(rlk, gks, P, Wf, self.n_classes, self.frame)
 
+    def forward_per_op(self, ctx, rlk, gks, X, weights):
+        """The same network with one ciphertext per library call, the unbatched form that
+        batching is measured against: every rotation, every output's products +
+        relinearisation + rescale, every activation and pool, every rotate-and-sum step is
+        its own call.  Gives the same ciphertexts as forward()."""
+        W1, W2, Wf = weights
+
+        def conv(xs, wt, cout, dil):
+            steps = self.conv_steps(dil)
+            kk, cin = len(steps), len(xs)
+            rot = [[x if s == 0 else ctx.rotate(gks[s], x, s) for s in steps] for x in xs]
+            out = []
+            for co in range(cout):
+                a = [rot[ci][t] for ci in range(cin) for t in range(kk)]
+                b = [wt[(co * cin + ci) * kk + t] for ci in range(cin) for t in range(kk)]
+                out.append(ctx.rescale(ctx.relin(rlk, ctx.mul_acc(a, b))))
+            return out
+
+        def act(ys):
+            return [ctx.poly_act(rlk, [y], self.coef, self.deg)[0] for y in ys]
+
+        def pool(xs, dil):
+            return [ctx.avgpool2x2(gks, [x], dil, self.fw, self.pool_mask(ctx, dil, x.limbs))[0] for x in xs]
+
+        P = pool(act(conv(X, W1, self.c1, 1)), 1)
+        P = pool(act(conv(P, W2, self.c2, 2)), 2)
+        out = []
+        for r in range(self.n_classes):
+            z = ctx.rescale(ctx.relin(rlk, ctx.mul_acc(P, [Wf[r * self.c2 + c] for c in range(self.c2)])))
+            i = 1
+            while i < self.frame:
+                z = ctx.add(z, ctx.rotate(gks[i], z, i))
+                i *= 2
+            out.append(z)
+        return out
+
     # ---------------------------------------------- plain (unencrypted) model
     def plain_fc_weights(self, ctx, wfc, limbs):
         """FC weights as plaintexts at `limbs` limbs, scale q_(limbs-1) (the rescale keeps the scale)."""

@@ -65,10 +65,13 @@ def test_small_packed_network_bit_exact():
     ref = cnn.packed_cnn_fp64(imgs, w1, w2, wfc, COEF)
     got = net.decrypt_scores(g, sg, Z, B)
     assert np.abs(got - ref).max() < 1e-3
-    # the composed forward pass gives the same ciphertexts
+    # the composed forward pass, and the one-ciphertext-per-call form, give the same ciphertexts
     Z2 = net.forward(g, rlk, gks, X, (W1, W2, Wf))
-    for a, b in zip(Z2, Z):
+    Z3 = net.forward_per_op(g, rlk, gks, X, (W1, W2, Wf))
+    for a, b, c in zip(Z2, Z, Z3):
         assert np.array_equal(g.export_ct(a), g.export_ct(b))
+        assert np.array_equal(g.export_ct(c), g.export_ct(b))
+        assert c.scale == b.scale
 
 
 @pytest.mark.parametrize("coef,deg", [((0.3, -0.2, 0.7), 2), ((0.0, 1.0, 0.0, 0.0), 3)])
