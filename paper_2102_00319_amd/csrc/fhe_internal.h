@@ -246,8 +246,6 @@ size_t rescale_scratch_bytes_ragged(const fhe_ctx *c, uint32_t polys, uint32_t n
 fhe_status rescale_run_ragged(fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls, const uint64_t *const *in,
                               uint64_t *const *out, uint8_t *scr);
 void launch_automorph(fhe_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nlimbs, uint64_t g);
-fhe_status automorph_run(fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls, const uint32_t *gal,
-                         const uint64_t *const *in, uint64_t *const *out);
 
 // launchers (ntt.hip)
 void launch_ntt_fwd(fhe_ctx *c, const LimbSet &ls, uint32_t nlimbs);

@@ -99,25 +99,6 @@ __global__ void k_automorph(const uint64_t *__restrict__ in, uint64_t *__restric
     const uint32_t y = __brev((ey - 1u) >> 1) >> (32 - logN);
     out[i] = in[base + y];
 }
-// NTT-domain automorphism over a batch: table [in: n][out: n][lvl: n][gal: n][list]
-// with list entries (b*P + p) << 16 | limb; out[x] = in[galois_src(x)].
-__global__ void k_automorph_batch(uint64_t *const *__restrict__ tab, uint32_t n, uint32_t polys, uint32_t lst,
-                                  uint32_t logN, uint32_t y0)
-{
-    const uint32_t N = 1u << logN;
-    const uint32_t x = blockIdx.x * TPB + threadIdx.x;
-    if (x >= N) return;
-    const uint64_t e = (uint64_t)(uintptr_t)tab[lst + blockIdx.y + y0];
-    const uint32_t j = (uint32_t)(e >> 16), limb = (uint32_t)(e & 0xFFFF), b = j / polys, p = j % polys;
-    const uint32_t l = (uint32_t)(uintptr_t)tab[2 * n + b];
-    const uint32_t g = (uint32_t)(uintptr_t)tab[3 * n + b];
-    const size_t off = ((size_t)p * l + limb) * N;
-    const uint32_t ex = 2u * (__brev(x) >> (32 - logN)) + 1u;
-    const uint32_t ey = (uint32_t)(((uint64_t)ex * g) & (2u * N - 1));
-    const uint32_t y = __brev((ey - 1u) >> 1) >> (32 - logN);
-    gview(tab[n + b])[off + x] = gview(tab[b])[off + y];
-}
-
 }  // namespace
 
 // ============================================================ host helpers
@@ -130,38 +111,6 @@ static fhe_status chk_ct(const fhe_ctx *c, const fhe_ct *a, const char *what)
 }
 static bool scales_match(double a, double b) { return std::fabs(a / b - 1.0) <= 9.5367431640625e-07; }   // 2^-20
 
-template <typename F>
-static void in_pieces(uint32_t total, F f)
-{
-    for (uint32_t y0 = 0; y0 < total; y0 += 65535u) f(y0, std::min(65535u, total - y0));
-}
-// Batched NTT-domain automorphisms: out[b] = sigma_g[b](in[b]) over polys x ls[b] limbs.
-fhe_status automorph_run(fhe_ctx *c, uint32_t polys, uint32_t n, const uint32_t *ls, const uint32_t *gal,
-                         const uint64_t *const *in, uint64_t *const *out)
-{
-    if (!n) return FHE_OK;
-    std::vector<uint64_t *> tab;
-    for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)in[b]);
-    for (uint32_t b = 0; b < n; ++b) tab.push_back(out[b]);
-    for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)(uintptr_t)ls[b]);
-    for (uint32_t b = 0; b < n; ++b) tab.push_back((uint64_t *)(uintptr_t)gal[b]);
-    const uint32_t lst = (uint32_t)tab.size();
-    for (uint32_t b = 0; b < n; ++b)
-        for (uint32_t p = 0; p < polys; ++p)
-            for (uint32_t i = 0; i < ls[b]; ++i)
-                tab.push_back((uint64_t *)(uintptr_t)((((uint64_t)(b * polys + p)) << 16) | i));
-    const uint32_t cnt = (uint32_t)tab.size() - lst;
-    uint64_t **dt;
-    fhe_status s;
-    if ((s = ctx_ptr_table(c, tab, &dt))) return s;
-    ProfScope ps(c, "automorph");
-    in_pieces(cnt, [&](uint32_t y0, uint32_t k) {
-        hipLaunchKernelGGL(k_automorph_batch, dim3(blocks_for(c->N, TPB), k), dim3(TPB), 0, c->stream,
-                           (uint64_t *const *)dt, n, polys, lst, c->logN, y0);
-    });
-    HIPCHK(hipGetLastError());
-    return FHE_OK;
-}
 
 // ========================================================= C entry points
 extern "C" {
@@ -461,9 +410,9 @@ void launch_automorph(fhe_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nl
                        c->logN, (uint64_t)nlimbs, (uint32_t)g);
 }
 
-// n rotations (NTT-domain automorphism of the whole ciphertext, then a key
-// switch of the permuted c1 with the permuted c0 as addend), items at levels
-// ls[b], in chunks whose scratch stays near 4 GiB.  Outputs must not overlap inputs.
+// n rotations (a key switch of sigma_g(c1) with sigma_g(c0) as addend, both read
+// through the permutation), items at levels ls[b], in chunks whose scratch stays
+// near 4 GiB.  Outputs must not overlap inputs.
 fhe_status rotate_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *in,
                              const fhe_evk *const *keys, uint64_t *const *out)
 {
