@@ -130,7 +130,7 @@ class PackedCNN:
     # -------------------------------------------------------------- cloud
     def pool_mask(self, ctx, dil, limbs):
         """0.25 at the grid of step 2*dil, at scale q_(limbs-1) so that the rescale keeps the scale."""
-        key = (dil, limbs)
+        key = (ctx.N, tuple(ctx.q), dil, limbs)   # a network object may serve several parameter sets
         if key not in self._masks:
             v = np.zeros(ctx.N // 2)
             v[grid_slots(self.H, self.W, self.fh, self.fw, self.images_per_ct(ctx), 2 * dil)] = 0.25

@@ -370,3 +370,23 @@ def test_keyswitch_parity_n16_full_level(sets):
         d = workloads.uniform_residues(91 + l, o.q[:l], o.N)
         got = g.keyswitch(gk, g.import_limbs(d, list(range(l))))
         eq(g.export_ct(got), o.keyswitch(d, evk))
+
+
+def test_rotation_batch_as_benchmarked(sets):
+    """The benchmark's configuration: 8 fresh ciphertexts at N = 2^16, l = 24 rotated by
+    1..8 with 8 distinct Galois keys in one fhe_rotate_batch, with the default tuning.
+    Two sampled outputs are recomputed by the oracle from the same keys and inputs."""
+    g, o = sets("c4_n16")
+    s = g.keygen_secret(workloads.SEED_SECRET)
+    so = s.astype(np.int64)
+    pk = g.keygen_pk(s, workloads.SEED_PK)
+    steps = list(range(1, 9))
+    gks = [g.keygen_rot(s, r, workloads.SEED_EVK + r) for r in steps]
+    cts = [g.encrypt(pk, g.encode(workloads.slot_messages(workloads.SEED_DATA + b, 64), scale=g.scale, limbs=g.L),
+                     workloads.SEED_ENC + b) for b in range(8)]
+    outs = g.rotate_batch(gks, cts, steps)
+    for b in (0, 5):
+        gko = o.keygen_rot(so, steps[b], workloads.SEED_EVK + steps[b])
+        assert np.array_equal(g.export_evk(gks[b]), gko)
+        ref = o.rotate(ckks.Ct(g.export_ct(cts[b]), cts[b].scale), steps[b], gko)
+        eq(g.export_ct(outs[b]), ref.data)
