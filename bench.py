@@ -34,16 +34,27 @@ PROFILE_CATEGORIES = ["ntt_fwd", "ntt_fwd_col", "ntt_fwd_row", "ntt_inv", "ntt_i
                       "elementwise", "rescale"]
 
 
+def source_digest(path):
+    """sha256[:16] of a source file's code: // comments, trailing blanks and empty lines
+    removed, so that a comment edit does not count as a change of the kernel."""
+    import hashlib
+    lines = []
+    for line in open(path, encoding="utf-8").read().splitlines():
+        code = line.split("//", 1)[0].rstrip()
+        if code:
+            lines.append(code)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None when
-    there is none or the kernel's source changed since the counters were taken."""
-    import hashlib
+    there is none or the kernel's source code changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "%s_n16_l24_hbm_counters.md" % kernel)
     try:
         fields = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line
                       and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel", "source"))
-        src, digest = fields["source"].split(" sha256[:16] ")
-        now = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
+        src, digest = fields["source"].split(" code-sha256[:16] ")
+        now = source_digest(os.path.join(ROOT, src))
         if fields["kernel"].strip() != kernel or now != digest.strip():
             return None
         return int(fields["traffic_bytes_per_launch"])

@@ -16,7 +16,8 @@
 //   out_t  = ks_t + add_t.
 //
 // Kernel sequence (every transform split into a column pass and a row pass of at
-// most 2^8 elements, so that the fused row kernels run in 256-thread groups):
+// most 2^8 elements per row, so that the fused row kernels run in workgroups of at
+// most 256 threads, 128 by default):
 //   1 k_ks_intt_first   inverse row pass of d_b, gathered through gal_b  -> dc
 //     k_col_inv         inverse column pass, times (Q_j/q_a)^-1 mod q_a   -> dc (conversion sources)
 //   2 k_bconv           ModUp conversion of every digit, one thread per coefficient -> up
