@@ -46,7 +46,7 @@ def test_counter_lookup_needs_matching_source():
 
 def test_source_digest_ignores_comments(tmp_path):
     a, b, c = tmp_path / "a.hip", tmp_path / "b.hip", tmp_path / "c.hip"
-    a.write_text("int f(int x)\\n{\\n    return x + 1;\\n}\\n")
-    b.write_text("// a comment\\nint f(int x)   // trailing\\n{\\n\\n    return x + 1;\\n}\\n")
-    c.write_text("int f(int x)\\n{\\n    return x + 2;\\n}\\n")
+    a.write_text("int f(int x)\n{\n    return x + 1;\n}\n")
+    b.write_text("// a comment\nint f(int x)   // trailing\n{\n\n    return x + 1;\n}\n")
+    c.write_text("int f(int x)\n{\n    return x + 2;\n}\n")
     assert bench.source_digest(str(a)) == bench.source_digest(str(b)) != bench.source_digest(str(c))
