@@ -102,6 +102,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=40, help="serve: requests per rate")
     ap.add_argument("--budget-gb", type=float, default=250.0, help="serve: HBM budget for admission (GB)")
     ap.add_argument("--lanes", type=int, default=4, help="serve: concurrent execution lanes")
+    ap.add_argument("--cold-wait", type=float, default=2.0,
+                    help="serve: seconds a request of a client in host memory waits behind resident clients' ones")
     ap.add_argument("--packed-clients", type=int, default=4, help="serve: deep-CNN clients")
     ap.add_argument("--band", type=int, default=2, help="paper: pooled rows per conv/ActPool band")
     return ap.parse_args()
@@ -380,6 +382,8 @@ def serve(args):
     t_setup = time.perf_counter()
     sets = {"slot": "c2_n14", "packed": "c4_n16"}
     setup = {k: P.Context.from_set(v) for k, v in sets.items()}
+    srv = serving.Server(list(sets.values()), lanes=args.lanes, hbm_budget=args.budget_gb * 1e9,
+                         cold_wait=args.cold_wait)
     clients = []
     kinds = ["slot"] + ["packed"] * args.packed_clients
     for cid, kind in enumerate(kinds):
@@ -396,9 +400,10 @@ def serve(args):
         seeds = {"secret": base + 4, "pk": base + 5, "evk": base + 6, "weights": (base + 100, base + 200, base + 300)}
         clients.append(serving.Client(cid, net, g, sets[kind], w, seeds))
         torch.cuda.synchronize()
-    srv = serving.Server(list(sets.values()), lanes=args.lanes, hbm_budget=args.budget_gb * 1e9)
-    for c in clients:
-        srv.add_client(c)
+        srv.add_client(clients[-1])   # over the budget, older clients move to host memory
+        print("serve: client %d ready (%.1f GB), %d evicted so far" % (cid, clients[-1].nbytes / 1e9,
+                                                                        srv.stats["evictions"]),
+              file=sys.stderr, flush=True)
     # payload pools (client-side encryption happens before a request arrives)
     pools = []
     for c in clients:
@@ -428,7 +433,10 @@ def serve(args):
             pay, n, off = pools[cid][tag]
             reqs.append(serving.Request(i, clients[cid], pay, n, off, t, tag))
         srv.stats.clear()
-        srv.run(reqs, time_limit=600)
+
+        def progress(done, total, rate=rate):
+            print("serve: rate %g, %d/%d requests done" % (rate, done, total), file=sys.stderr, flush=True)
+        srv.run(reqs, time_limit=600, progress=progress)
         s = serving.summarize(reqs)
         s.update({"rate_req_s": rate, "evictions": srv.stats["evictions"], "cold_loads": srv.stats["cold_loads"],
                   "cold_load_s": round(srv.stats["cold_load_s"], 2)})

@@ -80,18 +80,27 @@ class Lane:
 
 class Server:
     def __init__(self, set_names, lanes=4, hbm_budget=250e9, merge=True, max_merge=64, scratch_bytes=4 << 30,
-                 device="cuda", lane_factory=None):
+                 device="cuda", lane_factory=None, cold_wait=None):
         self.device = torch.device(device)
         self.scratch = int(scratch_bytes)   # device scratch a lane may hold while it runs
         make = lane_factory or (lambda: Lane(set_names, self.device))
         self.lanes = [make() for _ in range(lanes)]
         self.budget, self.merge, self.max_merge = float(hbm_budget), merge, max_merge
+        # None: admission in arrival order.  A number of seconds: requests of resident
+        # clients go first, and a request whose client state sits in host memory is
+        # admitted (with its cold load) once it has waited that long or when no request
+        # of a resident client is queued, so that an over-budget client mix does not
+        # move client state back and forth on every request.
+        self.cold_wait = cold_wait
         self.clients = []
         self.stats = collections.Counter()
 
     # ------------------------------------------------------------ memory
     def add_client(self, client):
+        """Register a client; older idle clients move to host memory while the resident
+        state exceeds the budget (the new one stays)."""
         self.clients.append(client)
+        self._make_room(0, client)
 
     def resident_bytes(self):
         return sum(c.nbytes for c in self.clients if c.resident) + sum(l.ws for l in self.lanes)
@@ -108,25 +117,38 @@ class Server:
         net = req.client.net
         return int(len(req.payload) * ct * (4 + 2 * net.c2 + net.c1 * net.k * net.k) + self.scratch)
 
-    def _make_room(self, need, keep):
-        """Evict least-recently-used idle clients other than `keep` until `need` more bytes fit."""
+    def _make_room(self, need, keep, queue=()):
+        """Evict idle clients other than `keep` until `need` more bytes fit: first those
+        with no queued request, least recently used first, then the others."""
+        waiting = {id(r.client) for r in queue}
         while self.resident_bytes() + need > self.budget:
             idle = [c for c in self.clients if c.resident and c.inflight == 0 and c is not keep]
             if not idle:
                 return False
-            victim = min(idle, key=lambda c: c.last_used)
+            victim = min(idle, key=lambda c: (id(c) in waiting, c.last_used))
             victim.evict()
             self.stats["evictions"] += 1
             torch.cuda.empty_cache()
         return True
 
     # -------------------------------------------------------- scheduling
+    def _order(self, queue, now):
+        """Queue positions in the order admission tries them."""
+        if self.cold_wait is None:
+            return list(range(len(queue)))
+        warm = [i for i, r in enumerate(queue) if r.client.resident]
+        cold = [i for i, r in enumerate(queue) if not r.client.resident
+                and (not warm or now - r.t_arrival >= self.cold_wait)]
+        overdue = [i for i in cold if now - queue[i].t_arrival >= self.cold_wait]
+        return overdue + warm + [i for i in cold if i not in overdue]
+
     def _admit(self, lane, queue, now):
-        for i, req in enumerate(queue):
+        for i in self._order(queue, now):
+            req = queue[i]
             c = req.client
             ws = self.working_set(req, lane)
             need = ws + (0 if c.resident else c.nbytes)
-            if self.resident_bytes() + need > self.budget and not self._make_room(need, c):
+            if self.resident_bytes() + need > self.budget and not self._make_room(need, c, queue):
                 continue
             cold = not c.resident
             if cold:
@@ -206,8 +228,9 @@ class Server:
             lane.group, lane.thread, lane.ws = None, None, 0
         return done
 
-    def run(self, requests, time_limit=None):
-        """Serve `requests` (t_arrival in seconds from the start, sorted); returns them."""
+    def run(self, requests, time_limit=None, progress=None):
+        """Serve `requests` (t_arrival in seconds from the start, sorted); returns them.
+        progress(finished, total) is called whenever requests complete."""
         t0 = time.perf_counter()
 
         def now():
@@ -221,7 +244,11 @@ class Server:
                 raise TimeoutError("serving run exceeded its time limit")
             while pending and pending[0].t_arrival <= t:
                 queue.append(pending.popleft())
-            finished += self._poll()
+            done = self._poll()
+            if done:
+                finished += done
+                if progress is not None:
+                    progress(finished, total)
             busy = False
             for lane in self.lanes:
                 if lane.group is None and queue and self._admit(lane, queue, now()):

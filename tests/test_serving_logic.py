@@ -98,3 +98,40 @@ def test_request_that_cannot_fit_waits_for_running_work():
     srv.run(reqs, time_limit=10)
     assert [b for b in srv.batches] == [[0], [1]]
     assert c1.loads == 0 or c0.resident is False
+
+
+def test_registration_over_budget_moves_older_clients_to_host():
+    srv = FakeServer(lanes=1, hbm_budget=250, merge=False)
+    cs = [FakeClient(i, "packed", 100) for i in range(4)]
+    for c in cs:
+        srv.add_client(c)
+        assert c.resident                          # the new client stays
+        assert srv.resident_bytes() <= srv.budget
+    assert [c.resident for c in cs] == [False, False, True, True]
+    assert srv.stats["evictions"] == 2
+
+
+def test_warm_clients_first_then_overdue_cold_ones():
+    srv = FakeServer(lanes=1, hbm_budget=1e12, merge=False, cold_wait=1.0)
+    a, b = FakeClient(0, "packed", 100), FakeClient(1, "packed", 100)
+    srv.add_client(a)
+    srv.add_client(b)
+    b.evict()
+    q = [serving.Request(0, b, [None], 1, 0, 0.0, 0), serving.Request(1, a, [None], 1, 0, 0.1, 0)]
+    assert srv._order(q, 0.2) == [1]          # b's request waits behind the resident client's
+    assert srv._order(q, 1.5) == [0, 1]       # overdue: it goes first
+    assert srv._order(q[:1], 0.2) == [0]      # nothing warm queued: no reason to wait
+    srv.cold_wait = None
+    assert srv._order(q, 0.2) == [0, 1]       # arrival order
+
+
+def test_eviction_spares_clients_with_queued_requests():
+    srv = FakeServer(lanes=1, hbm_budget=1e12, merge=False)
+    a, b, c = (FakeClient(i, "packed", 100) for i in range(3))
+    for x in (a, b, c):
+        srv.add_client(x)
+    a.last_used, b.last_used, c.last_used = 1.0, 2.0, 3.0
+    srv.budget = 200
+    queued = [serving.Request(0, a, [None], 1, 0, 0.0, 0)]
+    assert srv._make_room(0, c, queued)
+    assert a.resident and not b.resident     # b is evicted although a was used less recently
