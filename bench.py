@@ -102,6 +102,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=40, help="serve: requests per rate")
     ap.add_argument("--budget-gb", type=float, default=250.0, help="serve: HBM budget for admission (GB)")
     ap.add_argument("--lanes", type=int, default=4, help="serve: concurrent execution lanes")
+    ap.add_argument("--host-budget-gb", type=float, default=160.0,
+                    help="serve: host memory for client state off the device; clients get host mirrors "
+                         "(smallest first; pinned while the system allows) within it; 0 for no mirrors")
     ap.add_argument("--cold-wait", type=float, default=2.0,
                     help="serve: seconds a request of a client in host memory waits behind resident clients' ones")
     ap.add_argument("--packed-clients", type=int, default=4, help="serve: deep-CNN clients")
@@ -383,7 +386,7 @@ def serve(args):
     sets = {"slot": "c2_n14", "packed": "c4_n16"}
     setup = {k: P.Context.from_set(v) for k, v in sets.items()}
     srv = serving.Server(list(sets.values()), lanes=args.lanes, hbm_budget=args.budget_gb * 1e9,
-                         cold_wait=args.cold_wait)
+                         cold_wait=args.cold_wait, host_budget=args.host_budget_gb * 1e9)
     clients = []
     kinds = ["slot"] + ["packed"] * args.packed_clients
     for cid, kind in enumerate(kinds):
@@ -404,6 +407,10 @@ def serve(args):
         print("serve: client %d ready (%.1f GB), %d evicted so far" % (cid, clients[-1].nbytes / 1e9,
                                                                         srv.stats["evictions"]),
               file=sys.stderr, flush=True)
+    if args.host_budget_gb > 0:
+        srv.make_mirrors(progress=lambda c: print("serve: client %d mirrored in %s host memory (%.1f GB)"
+                                                  % (c.cid, "pinned" if c.mirror_pinned else "pageable",
+                                                     c.mirror_bytes / 1e9), file=sys.stderr, flush=True))
     # payload pools (client-side encryption happens before a request arrives)
     pools = []
     for c in clients:
@@ -439,12 +446,15 @@ def serve(args):
         srv.run(reqs, time_limit=600, progress=progress)
         s = serving.summarize(reqs)
         s.update({"rate_req_s": rate, "evictions": srv.stats["evictions"], "cold_loads": srv.stats["cold_loads"],
-                  "cold_load_s": round(srv.stats["cold_load_s"], 2)})
+                  "cold_load_s": round(srv.stats["cold_load_s"], 2), "evict_s": round(srv.stats["evict_s"], 2)})
         print(json.dumps({"serve_rate": s}), flush=True)
         per_rate.append(s)
     rec = {"metric": "encrypted inference serving: p50/p99 latency and images/s per arrival rate",
            "unit": "ms / images/s", "per_rate": per_rate, "lanes": args.lanes, "hbm_budget_gb": args.budget_gb,
            "client_state_gb": state_gb, "setup_s": round(t_setup, 1),
+           "host_mirror_gb": {c.cid: [round(c.mirror_bytes / 1e9, 2), "pinned" if c.mirror_pinned else "pageable"]
+                              for c in clients if c.mirror is not None},
+           "pinned_refused": srv.mirror_error,
            "config": {"workload": "Poisson arrivals, 50/50 slot-packed CNN (N=2^14, FC1 %d) and deep within-image "
                                   "CNN (N=2^16), 1-64 images per request" % args.fc1,
                       "clients": {"slot": 1, "packed": args.packed_clients}}}

@@ -7,8 +7,11 @@ process holds, per client, the evaluation keys and the encrypted weights
   * admits requests in arrival order as soon as a lane (an execution slot with
     its own contexts and HIP stream) is free and the HBM budget covers the
     client's state plus the request's working set; client state not resident is
-    loaded (cold start), evicting least-recently-used idle clients to host
-    memory when the budget requires;
+    loaded (cold start), evicting idle clients to host memory when the budget
+    requires (those with no queued request first, then the smallest one that
+    frees enough, then the least recently used); client state is immutable while
+    served, so a client may keep a pinned host mirror, and its evictions then
+    free device memory without a copy back;
   * merges queued requests of one slot-packed client whose slot ranges are
     disjoint into one batch (ciphertext addition: each request's images sit in
     its own slots), up to max_merge requests;
@@ -24,6 +27,8 @@ import numpy as np
 import torch
 
 from .fhe import Context, CtArray
+
+PIN_BLOCK = 1 << 30   # pinned host mirrors are packed into blocks of this size
 
 
 class Client:
@@ -41,15 +46,68 @@ class Client:
         self.nbytes = sum(o.data.numel() * 8 for o in self.objs)
         self.resident, self.inflight, self.last_used, self.loads = True, 0, 0.0, 0
         self.device = ctx.device
+        self.mirror, self.mirror_bytes, self.mirror_pinned = None, 0, False
+
+    def host_bytes(self):
+        """Host memory the client holds: its pinned mirror, else the evicted copy."""
+        return self.mirror_bytes if self.mirror is not None else (0 if self.resident else self.nbytes)
+
+    @staticmethod
+    def mirror_size(nbytes_list):
+        """Pinned bytes make_mirror takes for objects of these sizes."""
+        total, used = 0, PIN_BLOCK
+        for nb in nbytes_list:
+            if nb > PIN_BLOCK:
+                total += nb
+                continue
+            if used + nb > PIN_BLOCK:
+                total, used = total + PIN_BLOCK, 0
+            used += (nb + 255) & ~255
+        return total
+
+    def make_mirror(self, pinned=True):
+        """Copy the client state once into host memory: pinned, packed into 1 GiB blocks
+        (the pinned allocator rounds each allocation up to a power of two), or pageable.
+        A resident client keeps its device copy; an evicted one swaps its host copy for
+        the mirror."""
+        if not pinned:
+            self.mirror = [o.data.to("cpu") for o in self.objs]
+            self.mirror_bytes, self.mirror_pinned = self.nbytes, False
+            return
+        views, size, cur, used = [], 0, None, PIN_BLOCK
+        for o in self.objs:
+            nb = o.data.numel() * o.data.element_size()
+            if nb > PIN_BLOCK:
+                blk, off = torch.empty(nb, dtype=torch.uint8, pin_memory=True), 0
+                size += nb
+            else:
+                if used + nb > PIN_BLOCK:
+                    cur, used = torch.empty(PIN_BLOCK, dtype=torch.uint8, pin_memory=True), 0
+                    size += PIN_BLOCK
+                blk, off = cur, used
+                used += (nb + 255) & ~255
+            h = blk[off:off + nb].view(o.data.dtype).view(o.data.shape)
+            h.copy_(o.data)
+            views.append(h)
+            if not self.resident:
+                o.data = h
+        self.mirror, self.mirror_bytes, self.mirror_pinned = views, size, True
 
     def evict(self):
-        for o in self.objs:
-            o.data = o.data.to("cpu")
+        if self.mirror is not None:
+            for o, h in zip(self.objs, self.mirror):
+                o.data = h
+        else:
+            for o in self.objs:
+                o.data = o.data.to("cpu")
         self.resident = False
 
     def restore(self):
+        pinned = self.mirror is not None and self.mirror_pinned
         for o in self.objs:
-            o.data = o.data.to(self.device)
+            o.data = o.data.to(self.device, non_blocking=pinned)
+        if pinned:
+            torch.cuda.current_stream(self.device).synchronize()
         for grp in self.weights:   # packed descriptor arrays hold device addresses
             if isinstance(grp, CtArray):
                 grp.refresh()
@@ -80,7 +138,7 @@ class Lane:
 
 class Server:
     def __init__(self, set_names, lanes=4, hbm_budget=250e9, merge=True, max_merge=64, scratch_bytes=4 << 30,
-                 device="cuda", lane_factory=None, cold_wait=None):
+                 device="cuda", lane_factory=None, cold_wait=None, host_budget=160e9):
         self.device = torch.device(device)
         self.scratch = int(scratch_bytes)   # device scratch a lane may hold while it runs
         make = lane_factory or (lambda: Lane(set_names, self.device))
@@ -92,18 +150,51 @@ class Server:
         # of a resident client is queued, so that an over-budget client mix does not
         # move client state back and forth on every request.
         self.cold_wait = cold_wait
+        # host memory for client state moved off the device (pinned mirrors and
+        # evicted copies); a client whose eviction would exceed it stays resident
+        self.host_budget = float(host_budget)
+        self.mirror_error = None
         self.clients = []
         self.stats = collections.Counter()
 
     # ------------------------------------------------------------ memory
     def add_client(self, client):
-        """Register a client; older idle clients move to host memory while the resident
-        state exceeds the budget (the new one stays)."""
+        """Register a client; idle clients move to host memory while the resident state
+        exceeds the budget (the new one stays)."""
         self.clients.append(client)
         self._make_room(0, client)
 
+    def make_mirrors(self, progress=None):
+        """Give registered clients host mirrors, smallest state first, while the host
+        budget holds them: pinned while pinned allocations succeed (the system may lock
+        less memory than the budget), pageable after that; returns the clients mirrored."""
+        done, pinned = [], True
+        for c in sorted(self.clients, key=lambda c: c.nbytes):
+            if c.mirror is not None:
+                continue
+            sizes = [o.data.numel() * o.data.element_size() for o in c.objs]
+            size = c.mirror_size(sizes) if pinned else c.nbytes
+            if self.host_bytes() - c.host_bytes() + size > self.host_budget:
+                continue
+            try:
+                c.make_mirror(pinned)
+            except RuntimeError as e:      # pinned allocation refused: pageable from here on
+                self.mirror_error = str(e).splitlines()[0]
+                torch._C._host_emptyCache()
+                pinned = False
+                if self.host_bytes() - c.host_bytes() + c.nbytes > self.host_budget:
+                    continue
+                c.make_mirror(False)
+            done.append(c)
+            if progress:
+                progress(c)
+        return done
+
     def resident_bytes(self):
         return sum(c.nbytes for c in self.clients if c.resident) + sum(l.ws for l in self.lanes)
+
+    def host_bytes(self):
+        return sum(c.host_bytes() for c in self.clients)
 
     def working_set(self, req, lane):
         """Device bytes of one batch of `req`'s network beyond the client state:
@@ -118,17 +209,27 @@ class Server:
         return int(len(req.payload) * ct * (4 + 2 * net.c2 + net.c1 * net.k * net.k) + self.scratch)
 
     def _make_room(self, need, keep, queue=()):
-        """Evict idle clients other than `keep` until `need` more bytes fit: first those
-        with no queued request, least recently used first, then the others."""
+        """Evict idle clients other than `keep` until `need` more bytes fit, keeping the
+        host memory they move to within the host budget."""
         waiting = {id(r.client) for r in queue}
         while self.resident_bytes() + need > self.budget:
-            idle = [c for c in self.clients if c.resident and c.inflight == 0 and c is not keep]
+            short = self.resident_bytes() + need - self.budget
+            idle = [c for c in self.clients if c.resident and c.inflight == 0 and c is not keep
+                    and (c.mirror is not None or self.host_bytes() + c.nbytes <= self.host_budget)]
             if not idle:
                 return False
-            victim = min(idle, key=lambda c: (id(c) in waiting, c.last_used))
+            # a client with a queued request is evicted last; of the others, the smallest
+            # one that frees enough on its own (its cold load costs least), one with a
+            # pinned mirror before one without, else the least recently used
+            victim = min(idle, key=lambda c: (id(c) in waiting, c.nbytes < short,
+                                              c.nbytes if c.nbytes >= short else 0, c.mirror is None,
+                                              c.last_used))
+            t0 = time.perf_counter()
             victim.evict()
-            self.stats["evictions"] += 1
+            # the library allocates its workspaces outside torch: return freed blocks
             torch.cuda.empty_cache()
+            self.stats["evict_s"] += time.perf_counter() - t0
+            self.stats["evictions"] += 1
         return True
 
     # -------------------------------------------------------- scheduling

@@ -41,6 +41,10 @@ def _setup(merge, budget_frac):
                          merge=merge, scratch_bytes=32 << 20)
     for c in clients:
         srv.add_client(c)
+    if not merge:   # pinned host mirrors for the two smallest clients, a pageable one for a third
+        srv.host_budget = 2 * serving.PIN_BLOCK + total
+        assert len(srv.make_mirrors()) == 2
+        next(c for c in clients if c.mirror is None).make_mirror(pinned=False)
     # payload pool: 3 per client (tag t: slots / frames from t * 64 on for slot clients)
     pools = []
     for c in clients:
@@ -105,3 +109,11 @@ def test_serving_mix_equals_alone(merge):
             assert np.abs(alone.scores - r.scores).max() < 1e-4, r.rid
     s = serving.summarize(reqs)
     assert s["requests"] == len(reqs) and s["p99_ms"] >= s["p50_ms"] > 0
+    if not merge:   # a mirrored client's cold load restores its state exactly
+        for pinned in (True, False):
+            r = next(r for r in reqs if r.client.mirror is not None and r.client.mirror_pinned == pinned)
+            if r.client.resident:
+                r.client.evict()
+            again = serving.Request(r.rid, r.client, r.payload, r.n, r.off, 0.0, r.tag)
+            srv.run([again], time_limit=60)
+            assert again.cold and np.array_equal(again.scores, r.scores), pinned

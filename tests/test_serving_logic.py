@@ -14,6 +14,10 @@ class FakeClient:
         self.cid, self.kind, self.nbytes, self.set_name = cid, kind, nbytes, "s"
         self.resident, self.inflight, self.last_used, self.loads = True, 0, 0.0, 0
         self.net = types.SimpleNamespace(H=4, W=4, Cout=1, Ho=2, Wo=2, c1=1, c2=1, k=3)
+        self.mirror, self.mirror_bytes = None, 0
+
+    def host_bytes(self):
+        return self.mirror_bytes if self.mirror is not None else (0 if self.resident else self.nbytes)
 
     def evict(self):
         assert self.inflight == 0, "evicted a client with work in flight"
@@ -135,3 +139,91 @@ def test_eviction_spares_clients_with_queued_requests():
     queued = [serving.Request(0, a, [None], 1, 0, 0.0, 0)]
     assert srv._make_room(0, c, queued)
     assert a.resident and not b.resident     # b is evicted although a was used less recently
+
+
+def test_eviction_prefers_the_smallest_sufficient_client():
+    srv = FakeServer(lanes=1, hbm_budget=1e12, merge=False)
+    big, s1, s2 = FakeClient(0, "slot", 400), FakeClient(1, "packed", 100), FakeClient(2, "packed", 100)
+    for x in (big, s1, s2):
+        srv.add_client(x)
+    big.last_used, s1.last_used, s2.last_used = 1.0, 3.0, 2.0
+    srv.budget = 550
+    new = FakeClient(3, "packed", 50)
+    srv.add_client(new)                      # 650 resident: 100 must go
+    assert big.resident and not s2.resident and s1.resident   # not the least recently used big one
+    assert srv.resident_bytes() == 550
+    srv.budget = 300                         # 250 short: no small client suffices alone
+    assert srv._make_room(0, new)
+    assert not big.resident and s1.resident
+
+
+def test_host_budget_keeps_a_client_resident():
+    srv = FakeServer(lanes=1, hbm_budget=1e12, merge=False, host_budget=150)
+    a, b = FakeClient(0, "packed", 100), FakeClient(1, "packed", 100)
+    srv.add_client(a)
+    srv.add_client(b)
+    srv.budget = 150
+    assert srv._make_room(0, b) and not a.resident     # 100 on the host
+    srv.budget = 50
+    assert not srv._make_room(0, None)                 # b's copy would exceed the host budget
+    assert b.resident
+    b.mirror, b.mirror_bytes = [], 0                   # a mirror needs no new host memory
+    assert srv._make_room(0, None) and not b.resident
+
+
+def test_mirror_size_packs_objects_into_pinned_blocks():
+    blk = serving.PIN_BLOCK
+    assert serving.Client.mirror_size([]) == 0
+    assert serving.Client.mirror_size([100, 200]) == blk
+    assert serving.Client.mirror_size([blk // 2, blk // 2 + 1]) == 2 * blk
+    assert serving.Client.mirror_size([blk + 8, 16]) == 2 * blk + 8
+
+
+def test_make_mirrors_smallest_first_within_host_budget():
+    class MirClient(FakeClient):
+        objs = ()
+
+        def mirror_size(self, sizes):
+            return self.nbytes
+
+        def make_mirror(self, pinned=True):
+            self.mirror, self.mirror_bytes = [], self.nbytes
+
+    srv = FakeServer(lanes=1, hbm_budget=1e12, merge=False, host_budget=250)
+    big, s1, s2 = MirClient(0, "slot", 200), MirClient(1, "packed", 100), MirClient(2, "packed", 100)
+    for x in (big, s1, s2):
+        srv.add_client(x)
+    assert srv.make_mirrors() == [s1, s2]
+    assert big.mirror is None and srv.host_bytes() == 200
+
+
+def test_mirrored_client_evicted_before_an_equal_one_without():
+    srv = FakeServer(lanes=1, hbm_budget=1e12, merge=False)
+    a, b, keep = FakeClient(0, "packed", 100), FakeClient(1, "packed", 100), FakeClient(2, "packed", 100)
+    for x in (a, b, keep):
+        srv.add_client(x)
+    a.last_used, b.last_used = 1.0, 2.0
+    b.mirror, b.mirror_bytes = [], 100
+    srv.budget = 200
+    assert srv._make_room(0, keep) and a.resident and not b.resident
+
+
+def test_refused_pinned_allocation_turns_to_pageable_mirrors():
+    class MirClient(FakeClient):
+        objs = ()
+
+        def mirror_size(self, sizes):
+            return self.nbytes
+
+        def make_mirror(self, pinned=True):
+            if self.cid == 1 and pinned:
+                raise RuntimeError("HIP error: out of memory\nmore")
+            self.mirror, self.mirror_bytes, self.mirror_pinned = [], self.nbytes, pinned
+
+    srv = FakeServer(lanes=1, hbm_budget=1e12, merge=False, host_budget=1000)
+    cs = [MirClient(i, "packed", 100 + i) for i in range(3)]
+    for x in cs:
+        srv.add_client(x)
+    assert srv.make_mirrors() == cs
+    assert srv.mirror_error == "HIP error: out of memory"
+    assert [c.mirror_pinned for c in cs] == [True, False, False]     # pageable after the refusal
