@@ -446,7 +446,8 @@ def serve(args):
         srv.run(reqs, time_limit=600, progress=progress)
         s = serving.summarize(reqs)
         s.update({"rate_req_s": rate, "evictions": srv.stats["evictions"], "cold_loads": srv.stats["cold_loads"],
-                  "cold_load_s": round(srv.stats["cold_load_s"], 2), "evict_s": round(srv.stats["evict_s"], 2)})
+                  "cold_load_s": round(srv.stats["cold_load_s"], 2), "evict_s": round(srv.stats["evict_s"], 2),
+                  "oom_retries": srv.stats["oom_retries"]})
         print(json.dumps({"serve_rate": s}), flush=True)
         per_rate.append(s)
     rec = {"metric": "encrypted inference serving: p50/p99 latency and images/s per arrival rate",

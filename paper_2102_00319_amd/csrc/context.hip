@@ -88,6 +88,7 @@ fhe_status fhe_fail(fhe_status code, const std::string &msg)
 fhe_status fhe_hip_check(hipError_t e, const char *what)
 {
     g_err = std::string(what) + ": " + hipGetErrorString(e);
+    (void)hipGetLastError();   // a refused allocation must not resurface at a later launch check
     return FHE_EDEVICE;
 }
 

@@ -26,9 +26,25 @@ import time
 import numpy as np
 import torch
 
-from .fhe import Context, CtArray
+from .fhe import FHE_EDEVICE, Context, CtArray, FheError
 
 PIN_BLOCK = 1 << 30   # pinned host mirrors are packed into blocks of this size
+
+
+def retry_out_of_memory(fn, release):
+    """fn(), and once more after release() if the device refused an allocation: the
+    library allocates its workspaces outside torch, so memory torch caches (blocks of
+    evicted client state) can leave it short.  A refused allocation comes before any
+    work of the call that needed it, and a forward pass writes only fresh outputs."""
+    try:
+        return fn()
+    except FheError as e:
+        if e.code != FHE_EDEVICE or "out of memory" not in str(e):
+            raise
+    except torch.OutOfMemoryError:
+        pass
+    release()
+    return fn()
 
 
 class Client:
@@ -45,6 +61,7 @@ class Client:
         self.objs = [self.rlk] + list(self.gks.values()) + [w for grp in self.weights for w in grp]
         self.nbytes = sum(o.data.numel() * 8 for o in self.objs)
         self.resident, self.inflight, self.last_used, self.loads = True, 0, 0.0, 0
+        self.ready = True        # resident and not still loading
         self.device = ctx.device
         self.mirror, self.mirror_bytes, self.mirror_pinned = None, 0, False
 
@@ -100,7 +117,7 @@ class Client:
         else:
             for o in self.objs:
                 o.data = o.data.to("cpu")
-        self.resident = False
+        self.resident = self.ready = False
 
     def restore(self):
         pinned = self.mirror is not None and self.mirror_pinned
@@ -113,6 +130,7 @@ class Client:
                 grp.refresh()
         self.resident = True
         self.loads += 1
+        self.ready = True
 
 
 class Request:
@@ -138,7 +156,7 @@ class Lane:
 
 class Server:
     def __init__(self, set_names, lanes=4, hbm_budget=250e9, merge=True, max_merge=64, scratch_bytes=4 << 30,
-                 device="cuda", lane_factory=None, cold_wait=None, host_budget=160e9):
+                 device="cuda", lane_factory=None, cold_wait=None, host_budget=160e9, async_loads=None):
         self.device = torch.device(device)
         self.scratch = int(scratch_bytes)   # device scratch a lane may hold while it runs
         make = lane_factory or (lambda: Lane(set_names, self.device))
@@ -150,6 +168,12 @@ class Server:
         # of a resident client is queued, so that an over-budget client mix does not
         # move client state back and forth on every request.
         self.cold_wait = cold_wait
+        # with the warm-first policy a cold load runs on a loader thread and its own
+        # stream (one at a time: they share the PCIe link) while lanes keep serving
+        # resident clients; in arrival order it runs before its request, in line
+        self.async_loads = (cold_wait is not None) if async_loads is None else bool(async_loads)
+        self.copy_stream = torch.cuda.Stream(device=self.device) if self.device.type == "cuda" else None
+        self.loading = None      # (client, thread, box) of the load in progress
         # host memory for client state moved off the device (pinned mirrors and
         # evicted copies); a client whose eviction would exceed it stays resident
         self.host_budget = float(host_budget)
@@ -225,9 +249,7 @@ class Server:
                                               c.nbytes if c.nbytes >= short else 0, c.mirror is None,
                                               c.last_used))
             t0 = time.perf_counter()
-            victim.evict()
-            # the library allocates its workspaces outside torch: return freed blocks
-            torch.cuda.empty_cache()
+            victim.evict()      # its device blocks stay in torch's cache for the next load
             self.stats["evict_s"] += time.perf_counter() - t0
             self.stats["evictions"] += 1
         return True
@@ -237,16 +259,59 @@ class Server:
         """Queue positions in the order admission tries them."""
         if self.cold_wait is None:
             return list(range(len(queue)))
-        warm = [i for i, r in enumerate(queue) if r.client.resident]
+        warm = [i for i, r in enumerate(queue) if r.client.resident and r.client.ready]
         cold = [i for i, r in enumerate(queue) if not r.client.resident
                 and (not warm or now - r.t_arrival >= self.cold_wait)]
         overdue = [i for i in cold if now - queue[i].t_arrival >= self.cold_wait]
         return overdue + warm + [i for i in cold if i not in overdue]
 
+    def _start_load(self, c, queue):
+        """Move c's state to the device on the loader thread; its queued requests wait."""
+        c.resident, c.ready = True, False
+        c.inflight += 1           # not evictable while it loads
+        for r in queue:
+            if r.client is c:
+                r.cold = True
+        box = {}
+
+        def work():
+            t0 = time.perf_counter()
+            try:
+                if self.copy_stream is not None:
+                    with torch.cuda.stream(self.copy_stream):
+                        c.restore()
+                else:
+                    c.restore()
+            except Exception as e:   # reported by the scheduler thread
+                box["error"] = e
+            box["seconds"] = time.perf_counter() - t0
+        th = threading.Thread(target=work, daemon=True)
+        self.loading = (c, th, box)
+        th.start()
+
+    def _poll_load(self):
+        if self.loading is None or self.loading[1].is_alive():
+            return
+        c, th, box = self.loading
+        th.join()
+        self.loading = None
+        if "error" in box:
+            raise box["error"]
+        c.hold = True             # stays unevictable until one of its requests is admitted
+        self.stats["cold_load_s"] += box["seconds"]
+        self.stats["cold_loads"] += 1
+
     def _admit(self, lane, queue, now):
         for i in self._order(queue, now):
             req = queue[i]
             c = req.client
+            if c.resident and not c.ready:      # its state is still loading
+                continue
+            if not c.resident and self.async_loads:
+                if self.loading is None and (self.resident_bytes() + c.nbytes <= self.budget
+                                             or self._make_room(c.nbytes, c, queue)):
+                    self._start_load(c, queue)
+                continue
             ws = self.working_set(req, lane)
             need = ws + (0 if c.resident else c.nbytes)
             if self.resident_bytes() + need > self.budget and not self._make_room(need, c, queue):
@@ -269,9 +334,12 @@ class Server:
             for r in group:
                 queue.remove(r)
                 r.t_admit = now
-                r.cold = cold
+                r.cold = r.cold or cold
                 r.merged = len(group)
             c.inflight += 1
+            if getattr(c, "hold", False):
+                c.hold = False
+                c.inflight -= 1
             c.last_used = now
             self._launch(lane, group, ws, self._now)
             return True
@@ -281,36 +349,44 @@ class Server:
         c = group[0].client
         ctx = lane.ctx[c.set_name]
 
+        def release():
+            lane.stream.synchronize()
+            torch.cuda.empty_cache()
+            self.stats["oom_retries"] += 1
+
         def work():
             try:
-                with torch.cuda.stream(lane.stream):
-                    if len(group) == 1:
-                        xs = group[0].payload
-                    else:   # slot merging: the requests' images occupy disjoint slots
-                        xs = []
-                        for k in range(len(group[0].payload)):
-                            acc = ctx.add(group[0].payload[k], group[1].payload[k])
-                            for r in group[2:]:
-                                acc = ctx.add(acc, r.payload[k], out=acc)
-                            xs.append(acc)
-                    if c.kind == "packed":
-                        out = [c.net.forward(ctx, c.rlk, c.gks, [x], c.weights) for x in xs]
-                    else:
-                        out = c.net.forward(ctx, c.rlk, c.gks, xs, c.weights)
-                    for r in group:   # the user decrypts (decode waits for the stream)
-                        if c.kind == "packed":
-                            parts, left = [], r.n
-                            for z in out:
-                                m = min(left, c.net.images_per_ct(ctx))
-                                parts.append(c.net.decrypt_scores(ctx, c.sk, z, m))
-                                left -= m
-                            r.scores = np.concatenate(parts)
-                        else:
-                            r.scores = c.net.decrypt_scores(ctx, c.sk, out, r.n, r.off)
-                        r.t_done = now_fn()
+                retry_out_of_memory(batch, release)
             except Exception as e:   # reported by the scheduler thread
                 lane.error = e
             lane.finished = True
+
+        def batch():
+            with torch.cuda.stream(lane.stream):
+                if len(group) == 1:
+                    xs = group[0].payload
+                else:   # slot merging: the requests' images occupy disjoint slots
+                    xs = []
+                    for k in range(len(group[0].payload)):
+                        acc = ctx.add(group[0].payload[k], group[1].payload[k])
+                        for r in group[2:]:
+                            acc = ctx.add(acc, r.payload[k], out=acc)
+                        xs.append(acc)
+                if c.kind == "packed":
+                    out = [c.net.forward(ctx, c.rlk, c.gks, [x], c.weights) for x in xs]
+                else:
+                    out = c.net.forward(ctx, c.rlk, c.gks, xs, c.weights)
+                for r in group:   # the user decrypts (decode waits for the stream)
+                    if c.kind == "packed":
+                        parts, left = [], r.n
+                        for z in out:
+                            m = min(left, c.net.images_per_ct(ctx))
+                            parts.append(c.net.decrypt_scores(ctx, c.sk, z, m))
+                            left -= m
+                        r.scores = np.concatenate(parts)
+                    else:
+                        r.scores = c.net.decrypt_scores(ctx, c.sk, out, r.n, r.off)
+                    r.t_done = now_fn()
 
         lane.group, lane.ws, lane.finished, lane.error = group, ws, False, None
         lane.thread = threading.Thread(target=work, daemon=True)
@@ -345,6 +421,7 @@ class Server:
                 raise TimeoutError("serving run exceeded its time limit")
             while pending and pending[0].t_arrival <= t:
                 queue.append(pending.popleft())
+            self._poll_load()
             done = self._poll()
             if done:
                 finished += done
@@ -356,6 +433,9 @@ class Server:
                     busy = True
             if not busy:
                 time.sleep(0.0002)
+        if self.loading is not None:      # a load no queued request waits for any more
+            self.loading[1].join()
+            self._poll_load()
         return requests
 
 

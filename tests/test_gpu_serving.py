@@ -16,7 +16,7 @@ SLOT = dict(H=6, W=6, K=3, Cout=2, stride=2, pad=1, fc1=3, n_classes=2)
 PACKED = dict(H=12, W=12, frame_h=16, frame_w=16, c1=2, c2=3, n_classes=2)
 
 
-def _setup(merge, budget_frac):
+def _setup(merge, budget_frac, cold_wait=None):
     import paper_2102_00319_amd as P
     from paper_2102_00319_amd import networks, serving
     sets = {"slot": "t_n12", "packed": "t4_n12"}
@@ -38,7 +38,7 @@ def _setup(merge, budget_frac):
         plain.append(w)
     total = sum(c.nbytes for c in clients)
     srv = serving.Server(list(sets.values()), lanes=2, hbm_budget=budget_frac * total + 2 * (64 << 20),
-                         merge=merge, scratch_bytes=32 << 20)
+                         merge=merge, scratch_bytes=32 << 20, cold_wait=cold_wait)
     for c in clients:
         srv.add_client(c)
     if not merge:   # pinned host mirrors for the two smallest clients, a pageable one for a third
@@ -89,10 +89,13 @@ def _fp64(c, w, imgs):
     return cnn.packed_cnn_fp64(imgs, w[0], w[1], w[2], c.net.coef)
 
 
-@pytest.mark.parametrize("merge", [False, True])
-def test_serving_mix_equals_alone(merge):
+@pytest.mark.parametrize("merge,cold_wait", [(False, None), (True, None), (False, 0.05)])
+def test_serving_mix_equals_alone(merge, cold_wait):
+    """Arrival-order admission with in-line cold loads (cold_wait None), or warm-first
+    admission with cold loads on the loader thread beside running lanes."""
     from paper_2102_00319_amd import serving
-    srv, clients, plain, pools = _setup(merge, 0.6)
+    srv, clients, plain, pools = _setup(merge, 0.6, cold_wait)
+    assert srv.async_loads == (cold_wait is not None)
     reqs = _requests(serving, clients, pools, burst=merge)
     srv.run(reqs, time_limit=120)
     assert srv.stats["evictions"] > 0 and srv.stats["cold_loads"] > 0

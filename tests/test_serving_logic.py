@@ -5,6 +5,7 @@ bookkeeping.  Lanes and clients are stand-ins; no device work is done."""
 import types
 
 import numpy as np
+import pytest
 
 from paper_2102_00319_amd import serving
 
@@ -12,7 +13,7 @@ from paper_2102_00319_amd import serving
 class FakeClient:
     def __init__(self, cid, kind, nbytes):
         self.cid, self.kind, self.nbytes, self.set_name = cid, kind, nbytes, "s"
-        self.resident, self.inflight, self.last_used, self.loads = True, 0, 0.0, 0
+        self.resident, self.inflight, self.last_used, self.loads, self.ready = True, 0, 0.0, 0, True
         self.net = types.SimpleNamespace(H=4, W=4, Cout=1, Ho=2, Wo=2, c1=1, c2=1, k=3)
         self.mirror, self.mirror_bytes = None, 0
 
@@ -21,11 +22,12 @@ class FakeClient:
 
     def evict(self):
         assert self.inflight == 0, "evicted a client with work in flight"
-        self.resident = False
+        self.resident = self.ready = False
 
     def restore(self):
         self.resident = True
         self.loads += 1
+        self.ready = True
 
 
 class FakeLane:
@@ -227,3 +229,82 @@ def test_refused_pinned_allocation_turns_to_pageable_mirrors():
     assert srv.make_mirrors() == cs
     assert srv.mirror_error == "HIP error: out of memory"
     assert [c.mirror_pinned for c in cs] == [True, False, False]     # pageable after the refusal
+
+
+def test_cold_load_runs_beside_warm_work():
+    import threading
+    gate = threading.Event()
+
+    class SlowClient(FakeClient):
+        def restore(self):
+            assert gate.wait(10)
+            super().restore()
+
+    srv = FakeServer(lanes=1, hbm_budget=1e12, merge=False, cold_wait=0.5)
+    assert srv.async_loads
+    warm, cold = FakeClient(0, "packed", 100), SlowClient(1, "packed", 100)
+    srv.add_client(warm)
+    srv.add_client(cold)
+    cold.evict()
+    q = [serving.Request(0, cold, [None], 1, 0, 0.0, 0), serving.Request(1, warm, [None], 1, 0, 0.1, 0),
+         serving.Request(2, cold, [None], 1, 0, 0.2, 0)]
+    srv._now = lambda: 1.0
+    assert srv._admit(srv.lanes[0], q, 1.0)            # overdue cold request: its load starts ...
+    assert srv.loading is not None and cold.resident and not cold.ready and cold.inflight == 1
+    assert srv.batches == [[1]]                        # ... and the warm request runs meanwhile
+    assert q[0].cold and q[-1].cold                    # both of the client's queued requests wait on it
+    srv._poll()
+    assert not srv._admit(srv.lanes[0], q, 1.0)        # nothing admissible while it loads
+    srv.budget = 100
+    assert srv._make_room(0, None) and cold.resident and not warm.resident   # a loading client stays
+    srv.budget = 1e12
+    gate.set()
+    srv.loading[1].join()
+    srv._poll_load()
+    assert srv.loading is None and cold.ready and srv.stats["cold_loads"] == 1
+    assert cold.inflight == 1 and cold.hold          # held for its queued requests
+    srv.budget = 100
+    assert not srv._make_room(100, None) and cold.resident
+    srv.budget = 1e12
+    assert srv._admit(srv.lanes[0], q, 1.0) and srv.batches[-1] == [0]
+    assert cold.inflight == 1 and not cold.hold      # now only the running batch holds it
+    srv._poll()
+    assert cold.inflight == 0
+
+
+def test_async_loads_serve_every_request():
+    srv = FakeServer(lanes=2, hbm_budget=0, merge=False, cold_wait=0.002)
+    cs = [FakeClient(i, "packed", 1000) for i in range(3)]
+    for c in cs:
+        srv.add_client(c)
+    srv.budget = 2 * 1000 + 2 * _ws(srv, serving.Request(99, cs[0], [None], 1, 0, 0.0, 0))
+    reqs = [serving.Request(i, cs[i % 3], [None], 1, 0, 0.001 * i, 0) for i in range(12)]
+    srv.run(reqs, time_limit=10)
+    assert all(r.t_done is not None for r in reqs)
+    assert srv.stats["cold_loads"] > 0 and srv.loading is None
+    assert srv.resident_bytes() <= srv.budget
+
+
+def test_retry_once_after_a_refused_allocation():
+    from paper_2102_00319_amd.fhe import FHE_EDEVICE, FHE_ELEVEL, FheError
+    calls, released = [], []
+
+    def flaky():
+        calls.append(1)
+        if len(calls) == 1:
+            raise FheError(FHE_EDEVICE, "hipMalloc((void **)&c->wksp, bytes): out of memory")
+        return "scores"
+    assert serving.retry_out_of_memory(flaky, lambda: released.append(1)) == "scores"
+    assert len(calls) == 2 and released == [1]
+
+    def level():
+        raise FheError(FHE_ELEVEL, "fhe_rescale: one limb left")
+    with pytest.raises(FheError):
+        serving.retry_out_of_memory(level, lambda: released.append(2))
+    assert released == [1]                       # other errors are not retried
+
+    def always():
+        raise FheError(FHE_EDEVICE, "hipMalloc(p, bytes): out of memory")
+    with pytest.raises(FheError):
+        serving.retry_out_of_memory(always, lambda: released.append(3))
+    assert released == [1, 3]                    # one retry only
