@@ -215,8 +215,10 @@ def cnn4(args):
     import paper_2102_00319_amd as P
     from paper_2102_00319_amd import networks
 
+    from paper_2102_00319_amd import runtime
+
     torch.cuda.set_device(0)
-    g = P.Context.from_set("c4_n16")
+    g = P.Context.from_set("c4_n16", stream=torch.cuda.Stream())   # a stream of its own: graphs capture it
     g.set_tuning("row_wg", args.row_wg)
     net = networks.PackedCNN()
     B = net.images_per_ct(g)
@@ -252,11 +254,25 @@ def cnn4(args):
     prof = {c: g.profile_read(c)[0] for c in PROFILE_CATEGORIES}
     g.profile_enable(None)
     breakdown = {k: round(v, 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1]) if v > 0}
+    # the same forward pass captured once into a HIP graph and replayed
+    gf = runtime.GraphedForward(g, lambda xs: net.forward(g, rlk, gks, xs, Wt), X)
+    for _ in range(max(1, args.warmup)):
+        gf.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        zg = gf.run()
+    torch.cuda.synchronize()
+    dg = (time.perf_counter() - t0) / args.steps
+    graph_same = all(np.array_equal(g.export_ct(a), g.export_ct(b)) for a, b in zip(zg, out))
+    gf.close()
     rec = {"metric": "encrypted-CNN images/s (within-image packing, N=2^16)", "value": round(B / dt, 1),
            "unit": "images/s", "ms_per_batch": round(dt * 1e3, 3), "images_per_batch": B, "steps": args.steps,
            "max_abs_logit_error_vs_fp64": err, "setup_s": round(t_setup, 1),
            "ops_per_batch": {k: ops[k] for k in ("ct_mult", "relin", "rotate", "rescale")},
            "kernel_ms_per_batch": breakdown,
+           "graph_images_per_s": round(B / dg, 1), "graph_ms_per_batch": round(dg * 1e3, 3),
+           "graph_equals_eager_bitwise": bool(graph_same),
            "config": {"workload": "conv3x3x8 -> cubic -> avgpool -> conv3x3x16 -> cubic -> avgpool -> FC784x10, "
                                   "32 images of 28x28 per ciphertext, N=2^16, 24 limbs, dnum 3"}}
     if args.unbatched:   # one ciphertext per library call
@@ -651,8 +667,10 @@ def latency(args):
     import paper_2102_00319_amd as P
     from paper_2102_00319_amd import networks
 
+    from paper_2102_00319_amd import runtime
+
     torch.cuda.set_device(0)
-    g = P.Context.from_set("c4_n16")
+    g = P.Context.from_set("c4_n16", stream=torch.cuda.Stream())   # a stream of its own: graphs capture it
     net = networks.PackedCNN()
     img = workloads.images(workloads.SEED_DATA, 1, 28, 28)
     w1 = workloads.weights(workloads.SEED_DATA + 1, (8, 1, 3, 3))
@@ -667,8 +685,13 @@ def latency(args):
     Wpt = net.plain_fc_weights(g, wfc, g.L - 8)
     ref = _packed_cnn_fp64(img, w1, w2, wfc, net.coef)
     res = {}
+    # graph forms: each forward pass captured once; a run copies the image's ciphertext in
+    g_enc = runtime.GraphedForward(g, lambda xs: net.forward(g, rlk, gks, xs, Wenc), X)
+    g_pt = runtime.GraphedForward(g, lambda xs: net.forward_plain(g, rlk, gks, xs, w1, w2, Wpt), X)
     for name, run in [("encrypted_model", lambda: net.forward(g, rlk, gks, X, Wenc)),
-                      ("plain_model", lambda: net.forward_plain(g, rlk, gks, X, w1, w2, Wpt))]:
+                      ("plain_model", lambda: net.forward_plain(g, rlk, gks, X, w1, w2, Wpt)),
+                      ("encrypted_model_graph", lambda: g_enc.run(X)),
+                      ("plain_model_graph", lambda: g_pt.run(X))]:
         out = run()
         err = float(np.abs(net.decrypt_scores(g, s, out, 1) - ref).max())
         times = []
@@ -681,6 +704,8 @@ def latency(args):
         times.sort()
         res[name] = {"median_ms": round(times[len(times) // 2] * 1e3, 2), "min_ms": round(times[0] * 1e3, 2),
                      "max_abs_logit_error_vs_fp64": err}
+    g_enc.close()
+    g_pt.close()
     print(json.dumps({"metric": "single-image encrypted inference latency (deep CNN, one 28x28 image per "
                                 "ciphertext, N=2^16)", "unit": "ms", "results": res,
                       "paper_context": "8.8 s (encrypted model) and 2.5 s (plain model) on the paper's CPU, "

@@ -259,6 +259,7 @@ class Context:
             _check(_lib.fhe_ctx_create(C.byref(prm), C.c_void_p(st.cuda_stream), int(hbm_budget), C.byref(h)))
         self._h = h
         self.alpha = (self.L + self.dnum - 1) // self.dnum
+        self._kept = None      # list receiving every buffer empty() allocates, when set
 
     @classmethod
     def from_set(cls, name, **kw):
@@ -282,9 +283,19 @@ class Context:
         # allocate on the context's stream, so that the caching allocator orders
         # the reuse of freed blocks after this stream's kernels
         if self.stream == torch.cuda.current_stream(self.device):
-            return torch.empty(shape, dtype=torch.int64, device=self.device)
-        with torch.cuda.stream(self.stream):
-            return torch.empty(shape, dtype=torch.int64, device=self.device)
+            t = torch.empty(shape, dtype=torch.int64, device=self.device)
+        else:
+            with torch.cuda.stream(self.stream):
+                t = torch.empty(shape, dtype=torch.int64, device=self.device)
+        if self._kept is not None:
+            self._kept.append(t)
+        return t
+
+    def keep_allocations(self, kept):
+        """From now on every buffer this context allocates is also appended to `kept`
+        (None stops): a captured launch sequence must find its intermediates where the
+        capture put them, so none may return to torch's cache while the graph lives."""
+        self._kept = kept
 
     def use_stream(self, stream):
         """Enqueue this context's work on another torch stream from now on."""

@@ -17,7 +17,7 @@ import time
 
 import torch
 
-from .fhe import OP_MUL_RELIN_RESCALE, OP_ROTATE, BatchOp, capture_graph
+from .fhe import OP_MUL_RELIN_RESCALE, OP_ROTATE, BatchOp, Ciphertext, capture_graph
 
 
 class Autotuner:
@@ -144,3 +144,61 @@ class UnevenBatch:
             lv = sorted(op.a.limbs for op in self.ops[n] if op.kind == OP_MUL_RELIN_RESCALE)
             parts.append("%s:%s" % (n, ",".join(map(str, lv))))
         return "uneven|" + "|".join(parts) + "|" + torch.cuda.get_device_name(0)
+
+
+class GraphedForward:
+    """A layer sequence captured once into a HIP graph and replayed.
+
+    fn(X) enqueues the whole sequence on `ctx` (its own stream, not the default one)
+    and returns its output ciphertexts.  The constructor runs fn once eagerly (sizing
+    the context's scratch and workspace and filling torch's cache with blocks of the
+    right sizes), then captures a second run.  Every buffer allocated during the
+    capture is kept for the graph's lifetime, so replays write the same intermediates
+    and outputs.  The graph reads its own copies of X, made at construction; run(X2)
+    copies new inputs (same levels and scales) into them first.  One replay is one
+    launch for the whole sequence: the host work between layer kernels (tables,
+    chunking) is done once, at capture."""
+
+    def __init__(self, ctx, fn, X, table_bytes=256 << 20):
+        if ctx.stream == torch.cuda.default_stream(ctx.device):
+            raise ValueError("GraphedForward: the context needs a stream of its own (use_stream)")
+        self.ctx = ctx
+        self.X = []                           # the graph's own input buffers
+        with torch.cuda.stream(ctx.stream):
+            for x in X:
+                t = ctx.empty(*x.data.shape)
+                t.copy_(x.data)
+                self.X.append(Ciphertext(t, x.scale))
+        warm = []
+        ctx.keep_allocations(warm)
+        try:
+            fn(self.X)
+        finally:
+            ctx.keep_allocations(None)
+        torch.cuda.synchronize(ctx.device)
+        del warm                              # back to torch's cache, sized for the capture
+        self._kept, out = [], []
+        ctx.keep_allocations(self._kept)
+        try:
+            self.graph = capture_graph([ctx], lambda: out.append(fn(self.X)), table_bytes)
+        finally:
+            ctx.keep_allocations(None)
+        self.out = out[0]
+
+    def run(self, X=None):
+        """Replay (asynchronous on the context's stream); returns the output ciphertexts."""
+        if X is not None:
+            X = list(X)
+            if len(X) != len(self.X):
+                raise ValueError("GraphedForward.run: %d inputs, captured with %d" % (len(X), len(self.X)))
+            with torch.cuda.stream(self.ctx.stream):
+                for dst, src in zip(self.X, X):
+                    if src.data.shape != dst.data.shape or src.scale != dst.scale:
+                        raise ValueError("GraphedForward.run: inputs must match the captured levels and scales")
+                    dst.data.copy_(src.data)
+        self.graph.launch()
+        return self.out
+
+    def close(self):
+        self.graph.close()
+        self._kept = []

@@ -1,5 +1,6 @@
-"""HIP graph capture of ragged work lists over several contexts: every replay
-equals the eager result, with eager work and synchronisations in between."""
+"""HIP graph capture of ragged work lists over several contexts, and of a whole
+network's layer sequence: every replay equals the eager result, with eager work
+and synchronisations in between."""
 import numpy as np
 import pytest
 import torch
@@ -108,3 +109,44 @@ def test_capture_needs_sized_scratch():
     for o, r in zip(outs, ref):
         assert torch.equal(o.data, r)
     gr.close()
+
+
+def test_graphed_layer_sequence_matches_eager():
+    """The deep CNN's whole forward pass captured once into a graph: three replays
+    (captured inputs, new inputs copied in, the first inputs again), with eager
+    forward passes and synchronisations in between, each equal bit for bit to the
+    eager pass over the same inputs."""
+    import paper_2102_00319_amd as P
+    from paper_2102_00319_amd import networks, runtime
+    g = P.Context.from_set("t4_n12", stream=torch.cuda.Stream())
+    net = networks.PackedCNN(H=12, W=12, frame_h=16, frame_w=16, c1=2, c2=3, n_classes=2)
+    B = net.images_per_ct(g)
+    w1 = workloads.weights(workloads.SEED_DATA + 1, (2, 1, 3, 3))
+    w2 = workloads.weights(workloads.SEED_DATA + 2, (3, 2, 3, 3))
+    wfc = workloads.weights(workloads.SEED_DATA + 3, (2, 27))
+    s = g.keygen_secret(workloads.SEED_SECRET)
+    pk = g.keygen_pk(s, workloads.SEED_PK)
+    rlk, gks = net.keygen(g, s, workloads.SEED_EVK)
+    W = net.encrypt_weights(g, pk, w1, w2, wfc, (workloads.SEED_ENC + 100000, workloads.SEED_ENC + 200000,
+                                                 workloads.SEED_ENC + 300000))
+    ia = workloads.images(workloads.SEED_DATA + 10, B, 12, 12)
+    ib = workloads.images(workloads.SEED_DATA + 11, B, 12, 12)
+    Xa = net.encrypt_images(g, pk, ia, workloads.SEED_ENC)
+    Xb = net.encrypt_images(g, pk, ib, workloads.SEED_ENC + 5000)
+
+    def fwd(X):
+        return net.forward(g, rlk, gks, X, W)
+    ea = [g.export_ct(z) for z in fwd(Xa)]
+    eb = [g.export_ct(z) for z in fwd(Xb)]
+    gf = runtime.GraphedForward(g, fwd, [x for x in Xa])
+    try:
+        for k, (X, ref) in enumerate([(None, ea), (Xb, eb), (Xa, ea)]):
+            out = gf.run(X)
+            torch.cuda.synchronize()
+            assert all(np.array_equal(g.export_ct(z), r) for z, r in zip(out, ref)), "replay %d" % k
+            fwd(Xb if k % 2 == 0 else Xa)          # eager work on the same context between replays
+            torch.cuda.synchronize()
+        scores = net.decrypt_scores(g, s, gf.run(Xa), B)
+        assert np.abs(scores - net.decrypt_scores(g, s, fwd(Xa), B)).max() == 0.0
+    finally:
+        gf.close()
