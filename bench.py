@@ -98,6 +98,9 @@ def parse():
                          "level) per step")
     ap.add_argument("--fc1", type=int, default=100, help="cnn2: FC1 width (100 = the full network)")
     ap.add_argument("--unbatched", action="store_true", help="cnn2 / cnn4: also time the one-ciphertext-per-call form")
+    ap.add_argument("--graph-streams", type=int, default=2,
+                    help="cnn4: also replay this many graphed forward passes at once, each on its own "
+                         "context and stream (0: skip)")
     ap.add_argument("--rates", default="1,2,5,10,20,50,100,200", help="serve: Poisson arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=40, help="serve: requests per rate")
     ap.add_argument("--budget-gb", type=float, default=250.0, help="serve: HBM budget for admission (GB)")
@@ -266,13 +269,38 @@ def cnn4(args):
     dg = (time.perf_counter() - t0) / args.steps
     graph_same = all(np.array_equal(g.export_ct(a), g.export_ct(b)) for a, b in zip(zg, out))
     gf.close()
+    # several ciphertext batches in flight: one graph per context, each context on its own
+    # stream (keys and weights are shared device buffers), replayed together
+    conc = None
+    if args.graph_streams > 1:
+        ctxs = [P.Context.from_set("c4_n16", stream=torch.cuda.Stream()) for _ in range(args.graph_streams)]
+        gfs = []
+        for c in ctxs:
+            c.set_tuning("row_wg", args.row_wg)
+            gfs.append(runtime.GraphedForward(c, lambda xs, c=c: net.forward(c, rlk, gks, xs, Wt), X))
+        for _ in range(max(1, args.warmup)):
+            for f in gfs:
+                f.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for f in gfs:
+                f.run()
+        torch.cuda.synchronize()
+        dc = (time.perf_counter() - t0) / args.steps
+        conc_same = all(np.array_equal(c.export_ct(a), g.export_ct(b))
+                        for c, f in zip(ctxs, gfs) for a, b in zip(f.out, out))
+        for f in gfs:
+            f.close()
+        conc = {"streams": args.graph_streams, "images_per_s": round(len(gfs) * B / dc, 1),
+                "ms_per_step": round(dc * 1e3, 3), "equal_to_eager_bitwise": bool(conc_same)}
     rec = {"metric": "encrypted-CNN images/s (within-image packing, N=2^16)", "value": round(B / dt, 1),
            "unit": "images/s", "ms_per_batch": round(dt * 1e3, 3), "images_per_batch": B, "steps": args.steps,
            "max_abs_logit_error_vs_fp64": err, "setup_s": round(t_setup, 1),
            "ops_per_batch": {k: ops[k] for k in ("ct_mult", "relin", "rotate", "rescale")},
            "kernel_ms_per_batch": breakdown,
            "graph_images_per_s": round(B / dg, 1), "graph_ms_per_batch": round(dg * 1e3, 3),
-           "graph_equals_eager_bitwise": bool(graph_same),
+           "graph_equals_eager_bitwise": bool(graph_same), "graph_concurrent": conc,
            "config": {"workload": "conv3x3x8 -> cubic -> avgpool -> conv3x3x16 -> cubic -> avgpool -> FC784x10, "
                                   "32 images of 28x28 per ciphertext, N=2^16, 24 limbs, dnum 3"}}
     if args.unbatched:   # one ciphertext per library call
