@@ -61,7 +61,7 @@ class Client:
         self.objs = [self.rlk] + list(self.gks.values()) + [w for grp in self.weights for w in grp]
         self.nbytes = sum(o.data.numel() * 8 for o in self.objs)
         self.resident, self.inflight, self.last_used, self.loads = True, 0, 0.0, 0
-        self.ready = True        # resident and not still loading
+        self.hold = False        # loaded for queued requests: kept until one is admitted
         self.device = ctx.device
         self.mirror, self.mirror_bytes, self.mirror_pinned = None, 0, False
 
@@ -117,7 +117,7 @@ class Client:
         else:
             for o in self.objs:
                 o.data = o.data.to("cpu")
-        self.resident = self.ready = False
+        self.resident = False
 
     def restore(self):
         pinned = self.mirror is not None and self.mirror_pinned
@@ -130,7 +130,6 @@ class Client:
                 grp.refresh()
         self.resident = True
         self.loads += 1
-        self.ready = True
 
 
 class Request:
@@ -259,15 +258,17 @@ class Server:
         """Queue positions in the order admission tries them."""
         if self.cold_wait is None:
             return list(range(len(queue)))
-        warm = [i for i, r in enumerate(queue) if r.client.resident and r.client.ready]
+        loading = self.loading[0] if self.loading is not None else None
+        warm = [i for i, r in enumerate(queue) if r.client.resident and r.client is not loading]
         cold = [i for i, r in enumerate(queue) if not r.client.resident
                 and (not warm or now - r.t_arrival >= self.cold_wait)]
         overdue = [i for i in cold if now - queue[i].t_arrival >= self.cold_wait]
         return overdue + warm + [i for i in cold if i not in overdue]
 
     def _start_load(self, c, queue):
-        """Move c's state to the device on the loader thread; its queued requests wait."""
-        c.resident, c.ready = True, False
+        """Move c's state to the device on the loader thread; its queued requests wait
+        until the scheduler thread has seen the load finish (_poll_load)."""
+        c.resident = True         # counts against the budget from now on
         c.inflight += 1           # not evictable while it loads
         for r in queue:
             if r.client is c:
@@ -305,7 +306,7 @@ class Server:
         for i in self._order(queue, now):
             req = queue[i]
             c = req.client
-            if c.resident and not c.ready:      # its state is still loading
+            if self.loading is not None and self.loading[0] is c:   # its state is still loading
                 continue
             if not c.resident and self.async_loads:
                 if self.loading is None and (self.resident_bytes() + c.nbytes <= self.budget
@@ -337,7 +338,7 @@ class Server:
                 r.cold = r.cold or cold
                 r.merged = len(group)
             c.inflight += 1
-            if getattr(c, "hold", False):
+            if c.hold:
                 c.hold = False
                 c.inflight -= 1
             c.last_used = now
@@ -436,6 +437,10 @@ class Server:
         if self.loading is not None:      # a load no queued request waits for any more
             self.loading[1].join()
             self._poll_load()
+        for c in self.clients:            # nothing is queued any more: release the holds
+            if c.hold:
+                c.hold = False
+                c.inflight -= 1
         return requests
 
 

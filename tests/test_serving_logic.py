@@ -13,7 +13,7 @@ from paper_2102_00319_amd import serving
 class FakeClient:
     def __init__(self, cid, kind, nbytes):
         self.cid, self.kind, self.nbytes, self.set_name = cid, kind, nbytes, "s"
-        self.resident, self.inflight, self.last_used, self.loads, self.ready = True, 0, 0.0, 0, True
+        self.resident, self.inflight, self.last_used, self.loads, self.hold = True, 0, 0.0, 0, False
         self.net = types.SimpleNamespace(H=4, W=4, Cout=1, Ho=2, Wo=2, c1=1, c2=1, k=3)
         self.mirror, self.mirror_bytes = None, 0
 
@@ -22,12 +22,11 @@ class FakeClient:
 
     def evict(self):
         assert self.inflight == 0, "evicted a client with work in flight"
-        self.resident = self.ready = False
+        self.resident = False
 
     def restore(self):
         self.resident = True
         self.loads += 1
-        self.ready = True
 
 
 class FakeLane:
@@ -250,7 +249,7 @@ def test_cold_load_runs_beside_warm_work():
          serving.Request(2, cold, [None], 1, 0, 0.2, 0)]
     srv._now = lambda: 1.0
     assert srv._admit(srv.lanes[0], q, 1.0)            # overdue cold request: its load starts ...
-    assert srv.loading is not None and cold.resident and not cold.ready and cold.inflight == 1
+    assert srv.loading is not None and srv.loading[0] is cold and cold.resident and cold.inflight == 1
     assert srv.batches == [[1]]                        # ... and the warm request runs meanwhile
     assert q[0].cold and q[-1].cold                    # both of the client's queued requests wait on it
     srv._poll()
@@ -260,8 +259,9 @@ def test_cold_load_runs_beside_warm_work():
     srv.budget = 1e12
     gate.set()
     srv.loading[1].join()
+    assert not srv._admit(srv.lanes[0], q, 1.0)        # finished, but not yet seen by the scheduler
     srv._poll_load()
-    assert srv.loading is None and cold.ready and srv.stats["cold_loads"] == 1
+    assert srv.loading is None and srv.stats["cold_loads"] == 1
     assert cold.inflight == 1 and cold.hold          # held for its queued requests
     srv.budget = 100
     assert not srv._make_room(100, None) and cold.resident
@@ -283,6 +283,7 @@ def test_async_loads_serve_every_request():
     assert all(r.t_done is not None for r in reqs)
     assert srv.stats["cold_loads"] > 0 and srv.loading is None
     assert srv.resident_bytes() <= srv.budget
+    assert all(c.inflight == 0 and not c.hold for c in cs)     # every client evictable again
 
 
 def test_retry_once_after_a_refused_allocation():
