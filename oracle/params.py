@@ -93,10 +93,10 @@ def build_all():
     sets = [
         make_set("c1_n12", 12, 40, 2, None, 1, 50, 30, 3,
                  "primitives: 3 x ~40-bit primes, 1 special ~50-bit, scale 2^30"),
-        make_set("c2_n14", 14, 40, 7, 40, 1, 41, 40, 8,
-                 "slot-packed CNN: 8 primes of ~40 bits (q0 below 2^40, q1..q7 nearest 2^40), 1 special "
-                 "~2^41, scale 2^40 (scale 2^30 misses the 1e-3 logit bound: fresh noise of inputs and "
-                 "weights)"),
+        make_set("c2_n14", 14, 40, 7, 40, 2, 41, 40, 4,
+                 "slot-packed CNN: 8 primes of ~40 bits (q0 below 2^40, q1..q7 nearest 2^40), 2 special "
+                 "~2^41, dnum 4 (digits of 2 limbs under P ~ 2^82; log QP ~ 402 bits), scale 2^40 (scale "
+                 "2^30 misses the 1e-3 logit bound: fresh noise of inputs and weights)"),
         make_set("c3_n13", 13, 45, 3, 40, 1, 46, 40, 4,
                  "uneven batch N=2^13: q0 ~2^45, 3 primes nearest 2^40, 1 special"),
         make_set("c3_n15", 15, 45, 15, 40, 4, 46, 40, 4,
