@@ -95,6 +95,83 @@ __global__ __launch_bounds__(TPB) void k_tensor_tile(uint64_t *const *__restrict
 }
 constexpr int MAC_TILE = 8;
 
+// Two-group tiles: TG groups whose outputs pair the same B lists with their own A
+// lists (conv positions next to each other: one window each, the same weights per
+// channel).  Group g has its A list at a_off + g*P; output u of every group uses the
+// B list at b_off + u*P; output (g, u) is tab[nA + nB + o0 + g*k + u].  Each B
+// element loaded serves all TG groups.  One coefficient per thread.  Tile words
+// (after the single-group tiles, from tile0 on): a_off | P << 32 | tg << 56,
+// b_off | o0 << 32 | k << 56.
+template <int TG, int TO>
+__global__ __launch_bounds__(TPB) void k_tensor_tile2(uint64_t *const *__restrict__ tab, uint32_t nA, uint32_t nB,
+                                                      uint32_t n_out, uint32_t tile0, const ModQ *__restrict__ mods,
+                                                      uint32_t logN, uint32_t limbs)
+{
+    const uint64_t e = (uint64_t)blockIdx.x * TPB + threadIdx.x;   // limb * N + k
+    if (e >= ((uint64_t)limbs << logN)) return;
+    const uint64_t w0 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * (tile0 + blockIdx.y)];
+    const uint64_t w1 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * (tile0 + blockIdx.y) + 1];
+    const uint32_t a_off = (uint32_t)w0, P = (uint32_t)(w0 >> 32) & 0xFFFFFF, tg = (uint32_t)(w0 >> 56);
+    const uint32_t b_off = (uint32_t)w1, o0 = (uint32_t)(w1 >> 32) & 0xFFFFFF, k = (uint32_t)(w1 >> 56);
+    uint64_t *const *ap = tab + a_off, *const *bp = tab + nA + b_off;
+    const uint32_t limb = (uint32_t)(e >> logN);
+    const uint64_t off1 = (uint64_t)limbs << logN;
+    const double q = mods[limb].q, qi = mods[limb].qinv;
+    double d0[TG][TO], d1[TG][TO], d2[TG][TO];
+#pragma unroll
+    for (int g = 0; g < TG; ++g)
+#pragma unroll
+        for (int u = 0; u < TO; ++u) d0[g][u] = d1[g][u] = d2[g][u] = 0.0;
+    for (uint32_t p = 0; p < P; ++p) {
+        double a0[TG], a1[TG];
+#pragma unroll
+        for (int g = 0; g < TG; ++g) {
+            a0[g] = a1[g] = 0.0;
+            if (g < (int)tg) {
+                const gu64 *A = gview(ap[(size_t)g * P + p]);
+                a0[g] = u64_to_f64(A[e]);
+                a1[g] = u64_to_f64(A[e + off1]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < TO; ++u) {
+            if (u < (int)k) {
+                const gu64 *Bp = gview(bp[(size_t)u * P + p]);
+                const double b0 = u64_to_f64(Bp[e]), b1 = u64_to_f64(Bp[e + off1]);
+#pragma unroll
+                for (int g = 0; g < TG; ++g) {
+                    d0[g][u] += mulmod(a0[g], b0, q, qi);
+                    d1[g][u] += mulmod(a0[g], b1, q, qi) + mulmod(a1[g], b0, q, qi);
+                    d2[g][u] += mulmod(a1[g], b1, q, qi);
+                }
+            }
+        }
+        // |mulmod| <= 0.75 q + 2^46: four pairs keep every sum below 2^53 (q < 2^50)
+        if ((p & 3) == 3) {
+#pragma unroll
+            for (int g = 0; g < TG; ++g)
+#pragma unroll
+                for (int u = 0; u < TO; ++u) {
+                    d0[g][u] = redc(d0[g][u], q, qi);
+                    d1[g][u] = redc(d1[g][u], q, qi);
+                    d2[g][u] = redc(d2[g][u], q, qi);
+                }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < TG; ++g)
+#pragma unroll
+        for (int u = 0; u < TO; ++u) {
+            if (g < (int)tg && u < (int)k) {
+                gu64 *out = gview(tab[nA + nB + o0 + g * k + u]);
+                out[e] = f64_to_u64(canon(d0[g][u], q, qi));
+                out[e + off1] = f64_to_u64(canon(d1[g][u], q, qi));
+                out[e + 2 * off1] = f64_to_u64(canon(d2[g][u], q, qi));
+            }
+        }
+}
+constexpr int MAC_GROUPS = 2;
+
 // ---- batched encryption of constant (slot-replicated) plaintexts
 __global__ void k_small_batch(int64_t *out, const uint64_t *__restrict__ seeds, const uint64_t *__restrict__ cdt,
                               uint32_t ncdt, uint32_t N)
@@ -171,7 +248,9 @@ __global__ void k_encrypt_const(const uint64_t *__restrict__ pk, uint32_t L, con
 
 // Y[o] = Rescale(Relin(sum over CSR pairs)) for every output; all inputs at l limbs, 2 polys.
 // Outputs whose first factors are the same list (conv channels over one window,
-// FC rows over one input vector) are grouped into tiles of up to MAC_TILE.
+// FC rows over one input vector) are grouped into tiles of up to MAC_TILE; two such
+// groups next to each other whose outputs share their second factors (neighbouring
+// conv windows) form one two-group tile that loads each second factor once.
 fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const std::vector<uint64_t *> &A,
                              const std::vector<uint64_t *> &B, const std::vector<uint32_t> &off,
                              const std::vector<uint64_t *> &Y)
@@ -217,23 +296,47 @@ fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const s
     uint64_t pairs = 0;
     for (uint32_t o0 = 0; o0 < n_out; o0 += C) {
         const uint32_t cn = std::min(C, n_out - o0);
-        // tiles inside this chunk: runs of one group, at most MAC_TILE outputs
-        std::vector<uint64_t *> ta, tb, tout, tt;
-        for (uint32_t t = 0; t < cn;) {
+        // tiles inside this chunk: runs of one group, at most MAC_TILE outputs; two runs
+        // of different groups next to each other whose outputs have the same B lists
+        // (and the same pair count) form one two-group tile
+        std::vector<uint64_t *> ta, tb, tout, tt, tt2;
+        auto run_len = [&](uint32_t t) {
             uint32_t k = 1;
             while (t + k < cn && k < (uint32_t)MAC_TILE && gid[o0 + t + k] == gid[o0 + t]) ++k;
+            return k;
+        };
+        auto same_b = [&](uint32_t t, uint32_t t2, uint32_t k) {
+            for (uint32_t u = 0; u < k; ++u) {
+                const uint32_t o = order[o0 + t + u], o2 = order[o0 + t2 + u];
+                if (off[o + 1] - off[o] != off[o2 + 1] - off[o2] ||
+                    !std::equal(B.begin() + off[o], B.begin() + off[o + 1], B.begin() + off[o2]))
+                    return false;
+            }
+            return true;
+        };
+        for (uint32_t t = 0; t < cn;) {
+            const uint32_t k = run_len(t);
             const uint32_t first = order[o0 + t];
             const uint32_t P = off[first + 1] - off[first];
+            const uint32_t t2 = t + k;
+            const bool pair = t2 < cn && gid[o0 + t2] != gid[o0 + t] && run_len(t2) == k && same_b(t, t2, k) &&
+                              P < (1u << 24);
+            const uint32_t tg = pair ? 2 : 1;
             const uint64_t a_off = ta.size(), b_off = tb.size();
-            ta.insert(ta.end(), A.begin() + off[first], A.begin() + off[first + 1]);
+            for (uint32_t g = 0; g < tg; ++g) {
+                const uint32_t fg = order[o0 + t + g * k];
+                ta.insert(ta.end(), A.begin() + off[fg], A.begin() + off[fg + 1]);
+                for (uint32_t u = 0; u < k; ++u) pairs += P;
+            }
             for (uint32_t u = 0; u < k; ++u) {
                 const uint32_t o = order[o0 + t + u];
                 tb.insert(tb.end(), B.begin() + off[o], B.begin() + off[o + 1]);
-                pairs += P;
             }
-            tt.push_back((uint64_t *)(uintptr_t)(a_off | ((uint64_t)P << 32)));
-            tt.push_back((uint64_t *)(uintptr_t)(b_off | ((uint64_t)t << 32) | ((uint64_t)k << 56)));
-            t += k;
+            auto &dst = pair ? tt2 : tt;
+            // single-group tile words carry P in all 32 high bits; two-group ones P < 2^24 and tg
+            dst.push_back((uint64_t *)(uintptr_t)(a_off | ((uint64_t)P << 32) | (pair ? (uint64_t)tg << 56 : 0)));
+            dst.push_back((uint64_t *)(uintptr_t)(b_off | ((uint64_t)t << 32) | ((uint64_t)k << 56)));
+            t += tg * k;
         }
         for (uint32_t t = 0; t < cn; ++t) tout.push_back(acc3 + (size_t)t * 3 * l * N);
         std::vector<uint64_t *> tab;
@@ -242,15 +345,21 @@ fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const s
         tab.insert(tab.end(), tb.begin(), tb.end());
         tab.insert(tab.end(), tout.begin(), tout.end());
         tab.insert(tab.end(), tt.begin(), tt.end());
+        tab.insert(tab.end(), tt2.begin(), tt2.end());
         uint64_t **dt;
         if ((s = ctx_ptr_table(c, tab, &dt))) return s;
-        const uint32_t ntiles = (uint32_t)(tt.size() / 2);
+        const uint32_t ntiles = (uint32_t)(tt.size() / 2), ntiles2 = (uint32_t)(tt2.size() / 2);
         {
             ProfScope ps(c, "tensor");
-            if (ntiles > 65535u) return fhe_fail(FHE_EINVAL, "layer: too many tiles in one chunk");
-            hipLaunchKernelGGL(k_tensor_tile<MAC_TILE>, dim3(blocks_for((uint64_t)l * N / 2, TPB), ntiles), dim3(TPB), 0,
-                               c->stream, (uint64_t *const *)dt, (uint32_t)ta.size(), (uint32_t)tb.size(), cn,
-                               (const ModQ *)c->d_mod, c->logN, l);
+            if (ntiles > 65535u || ntiles2 > 65535u) return fhe_fail(FHE_EINVAL, "layer: too many tiles in one chunk");
+            if (ntiles)
+                hipLaunchKernelGGL(k_tensor_tile<MAC_TILE>, dim3(blocks_for((uint64_t)l * N / 2, TPB), ntiles), dim3(TPB),
+                                   0, c->stream, (uint64_t *const *)dt, (uint32_t)ta.size(), (uint32_t)tb.size(), cn,
+                                   (const ModQ *)c->d_mod, c->logN, l);
+            if (ntiles2)
+                hipLaunchKernelGGL((k_tensor_tile2<MAC_GROUPS, MAC_TILE>), dim3(blocks_for((uint64_t)l * N, TPB), ntiles2),
+                                   dim3(TPB), 0, c->stream, (uint64_t *const *)dt, (uint32_t)ta.size(),
+                                   (uint32_t)tb.size(), cn, ntiles, (const ModQ *)c->d_mod, c->logN, l);
         }
         for (uint32_t t = 0; t < cn; ++t) {
             uint64_t *a3 = acc3 + (size_t)t * 3 * l * N;
