@@ -35,10 +35,12 @@ __global__ __launch_bounds__(TPB) void k_tensor_tile(uint64_t *const *__restrict
 {
     // two consecutive coefficients per thread (16-byte loads and stores)
     const uint32_t N = 1u << logN;
-    const uint64_t e = 2 * ((uint64_t)blockIdx.x * TPB + threadIdx.x);   // limb * N + k, k even
+    // blockIdx.x = tile, blockIdx.y = coefficient block: the tiles of one block are
+    // dispatched together, so their shared factors are read while still in cache
+    const uint64_t e = 2 * ((uint64_t)blockIdx.y * TPB + threadIdx.x);   // limb * N + k, k even
     if (e >= ((uint64_t)limbs << logN)) return;
-    const uint64_t w0 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * blockIdx.y];
-    const uint64_t w1 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * blockIdx.y + 1];
+    const uint64_t w0 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * blockIdx.x];
+    const uint64_t w1 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * blockIdx.x + 1];
     const uint32_t a_off = (uint32_t)w0, P = (uint32_t)(w0 >> 32), b_off = (uint32_t)w1;
     const uint32_t o0 = (uint32_t)(w1 >> 32) & 0xFFFFFF, k = (uint32_t)(w1 >> 56);
     uint64_t *const *ap = tab + a_off, *const *bp = tab + nA + b_off;
@@ -107,10 +109,10 @@ __global__ __launch_bounds__(TPB) void k_tensor_tile2(uint64_t *const *__restric
                                                       uint32_t n_out, uint32_t tile0, const ModQ *__restrict__ mods,
                                                       uint32_t logN, uint32_t limbs)
 {
-    const uint64_t e = (uint64_t)blockIdx.x * TPB + threadIdx.x;   // limb * N + k
+    const uint64_t e = (uint64_t)blockIdx.y * TPB + threadIdx.x;   // limb * N + k; blockIdx.x = tile
     if (e >= ((uint64_t)limbs << logN)) return;
-    const uint64_t w0 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * (tile0 + blockIdx.y)];
-    const uint64_t w1 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * (tile0 + blockIdx.y) + 1];
+    const uint64_t w0 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * (tile0 + blockIdx.x)];
+    const uint64_t w1 = (uint64_t)(uintptr_t)tab[nA + nB + n_out + 2 * (tile0 + blockIdx.x) + 1];
     const uint32_t a_off = (uint32_t)w0, P = (uint32_t)(w0 >> 32) & 0xFFFFFF, tg = (uint32_t)(w0 >> 56);
     const uint32_t b_off = (uint32_t)w1, o0 = (uint32_t)(w1 >> 32) & 0xFFFFFF, k = (uint32_t)(w1 >> 56);
     uint64_t *const *ap = tab + a_off, *const *bp = tab + nA + b_off;
@@ -352,12 +354,13 @@ fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const s
         {
             ProfScope ps(c, "tensor");
             if (ntiles > 65535u || ntiles2 > 65535u) return fhe_fail(FHE_EINVAL, "layer: too many tiles in one chunk");
+            if (blocks_for((uint64_t)l * N, TPB) > 65535u) return fhe_fail(FHE_EINVAL, "layer: ciphertexts too large");
             if (ntiles)
-                hipLaunchKernelGGL(k_tensor_tile<MAC_TILE>, dim3(blocks_for((uint64_t)l * N / 2, TPB), ntiles), dim3(TPB),
+                hipLaunchKernelGGL(k_tensor_tile<MAC_TILE>, dim3(ntiles, blocks_for((uint64_t)l * N / 2, TPB)), dim3(TPB),
                                    0, c->stream, (uint64_t *const *)dt, (uint32_t)ta.size(), (uint32_t)tb.size(), cn,
                                    (const ModQ *)c->d_mod, c->logN, l);
             if (ntiles2)
-                hipLaunchKernelGGL((k_tensor_tile2<MAC_GROUPS, MAC_TILE>), dim3(blocks_for((uint64_t)l * N, TPB), ntiles2),
+                hipLaunchKernelGGL((k_tensor_tile2<MAC_GROUPS, MAC_TILE>), dim3(ntiles2, blocks_for((uint64_t)l * N, TPB)),
                                    dim3(TPB), 0, c->stream, (uint64_t *const *)dt, (uint32_t)ta.size(),
                                    (uint32_t)tb.size(), cn, ntiles, (const ModQ *)c->d_mod, c->logN, l);
         }
