@@ -130,3 +130,31 @@ def test_config2_cnn_logits_reduced_fc1():
                 pairs.append((Ct(g.export_ct(X[y * W + x]), D), Ct(g.export_ct(Wc[p * K + q]), D)))
     y0 = cnn._mac_relin_rescale(o, rlko, pairs, cnt)
     assert np.array_equal(g.export_ct(Y[0]), y0.data)
+
+
+@pytest.mark.parametrize("H,W,Cin,Cout,K,stride,pad", [(3, 4, 2, 9, 2, 1, 0), (6, 6, 1, 3, 3, 2, 1)])
+def test_conv_tiles_bit_exact(H, W, Cin, Cout, K, stride, pad):
+    """Conv shapes whose outputs fill the multiply-accumulate tiles in every way:
+    runs of 8 channels and of 1, two neighbouring windows per tile, windows cut by
+    padding (single-group tiles), several input channels per window."""
+    P = _P()
+    g, o = P.Context.from_set("t_n12"), OracleCtx.from_set("t_n12")
+    D, L, B = o.scale, o.L, o.N // 2
+    Ho, Wo = (H + pad - K) // stride + 1, (W + pad - K) // stride + 1
+    imgs = workloads.images(workloads.SEED_DATA + 7, B, Cin * H, W)
+    cw = workloads.weights(workloads.SEED_DATA + 8, (Cout, Cin, K, K))
+    s = g.keygen_secret(workloads.SEED_SECRET)
+    so = s.astype(np.int64)
+    pk, pko = g.keygen_pk(s, workloads.SEED_PK), o.keygen_pk(so, workloads.SEED_PK)
+    rlk, rlko = g.keygen_relin(s, workloads.SEED_EVK), o.keygen_relin(so, workloads.SEED_EVK)
+    X = encrypt_images_gpu(g, pk, imgs, D)
+    Xo = [o.encrypt(pko, o.encode_rns(imgs[:, y, x], D, L), workloads.SEED_ENC + y * W + x, D)
+          for y in range(Cin * H) for x in range(W)]
+    Wc = g.encrypt_const_batch(pk, cw.ravel(), D, [workloads.SEED_ENC + S_CONV + t for t in range(cw.size)], L)
+    Wco = [cnn.encrypt_const(o, pko, v, D, L, workloads.SEED_ENC + S_CONV + t) for t, v in enumerate(cw.ravel())]
+    Y = g.conv2d_slot(rlk, X, H, W, Cin, Wc, Cout, K, K, stride, pad, pad, Ho, Wo)
+    Yo = cnn.enc_conv2d_slot(o, rlko, Xo, H, W, Cin, Wco, Cout, K, K, stride, pad, pad, Ho, Wo, cnn.Counter())
+    assert len(Y) == len(Yo) == Cout * Ho * Wo
+    for i, (a, b) in enumerate(zip(Y, Yo)):
+        assert np.array_equal(g.export_ct(a), b.data), "output %d differs" % i
+        assert a.scale == b.scale
