@@ -165,6 +165,26 @@ def test_add_sub_mulconst_parity(sets):
     eq(g.export_ct(g.add_pt(ga, gp)), o.add_pt(ckks.Ct(a, 1.0), p).data)
 
 
+def test_sum_pool_and_drop_level_parity(sets):
+    """The 2x2 sum pooling over slot-packed maps (three additions per output, the
+    paper network's pool with 1/4 folded into the activation) and the level drop,
+    against the oracle's additions and limb slicing: 2 channels of 4 x 6 maps."""
+    from oracle import cnn
+    g, o = sets("c1_n12")
+    C_, H, W = 2, 4, 6
+    xs = [rand_ct(o, 3, 2, 900 + i) for i in range(C_ * H * W)]
+    gx = [g.import_ct(x, 1.0) for x in xs]
+    got = g.pool2x2_sum_slot(gx, C_, H, W)
+    ref = cnn.enc_sum_pool2x2_slot(o, [ckks.Ct(x, 1.0) for x in xs], C_, H, W, cnn.Counter())
+    assert len(got) == len(ref) == C_ * (H // 2) * (W // 2)
+    for a, b in zip(got, ref):
+        eq(g.export_ct(a), b.data)
+    for lim in (1, 2):
+        d = g.drop_level(gx[5], lim)
+        assert d.limbs == lim and d.scale == gx[5].scale
+        eq(g.export_ct(d), xs[5][:, :lim])
+
+
 @pytest.mark.parametrize("n", [1, 5, 25])
 def test_tensor_mac_parity(sets, n):
     g, o = sets("c2_n14")
