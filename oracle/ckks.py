@@ -323,6 +323,16 @@ class OracleCtx:
         lib().or_keyswitch(self._h, _p(d), C.c_uint32(l), _p(np.ascontiguousarray(evk)), _p(ks))
         return ks
 
+    def keyswitch_galois(self, d, evk, g):
+        """Key switch of sigma_g(d) in the form rotations use: d's digits extended,
+        then every extended limb mapped by X -> X^g (see or_keyswitch_galois)."""
+        d = np.ascontiguousarray(d, dtype=np.uint64)
+        l = d.shape[0]
+        ks = np.empty((2, l, self.N), dtype=np.uint64)
+        lib().or_keyswitch_galois(self._h, _p(d), C.c_uint32(l), _p(np.ascontiguousarray(evk)), C.c_uint64(int(g)),
+                                  _p(ks))
+        return ks
+
     def relin(self, ct3, rlk):
         out = np.empty((2, ct3.level, self.N), dtype=np.uint64)
         lib().or_relin(self._h, _p(np.ascontiguousarray(ct3.data)), C.c_uint32(ct3.level),

@@ -552,12 +552,24 @@ void or_bconv(const or_ctx *c, const u64 *x, const uint32_t *src, uint32_t nsrc,
     }
 }
 
+/* X -> X^g on one coefficient-domain polynomial modulo q (g odd): coefficient i moves
+ * to i*g mod 2N, negated when that lands in [N, 2N). */
+static void automorph_mod(uint32_t N, const u64 *a, u64 q, u64 g, u64 *out)
+{
+    for (uint32_t i = 0; i < N; i++) {
+        u64 t = ((u64)i * g) % (2ull * N), v = a[i];
+        if (t < N) out[t] = v;
+        else out[t - N] = v ? q - v : 0;
+    }
+}
+
 /* Hybrid key switch of d (l limbs) with evk [dnum][2][L+K][N]:
  *   ModUp:  D_j = [d]_{Q_j} extended to Q_l u P by basis conversion (original limbs kept);
+ *           with g != 1 every limb of D_j then goes through X -> X^g (see or_keyswitch_galois);
  *   inner:  u_t = sum_j D_j * evk_{j,t}  over Q_l u P;
  *   ModDown: ks_t = (u'_t - Conv_{P->Q_l}([u'_t]_P)) * P^-1 mod q_i,  u'_t = u_t + (P-1)/2,
  *            i.e. u_t / P rounded (up to the fast-conversion error). */
-void or_keyswitch(const or_ctx *c, const u64 *d, uint32_t l, const u64 *evk, u64 *ks)
+static void keyswitch_core(const or_ctx *c, const u64 *d, uint32_t l, const u64 *evk, u64 g, u64 *ks)
 {
     uint32_t N = c->N, L = c->L, K = c->K, nx = l + K, nevk = L + K;
     uint32_t ext[OR_MAXMOD], pidx[OR_MAXMOD], qidx[OR_MAXMOD];
@@ -575,6 +587,11 @@ void or_keyswitch(const or_ctx *c, const u64 *d, uint32_t l, const u64 *evk, u64
         or_bconv(c, d + (size_t)lo * N, src, ns, dst, ndst, tmp);
         for (uint32_t i = lo; i < hi; i++) memcpy(D + (size_t)i * N, d + (size_t)i * N, sizeof(u64) * N);
         for (uint32_t t = 0; t < ndst; t++) memcpy(D + (size_t)dpos[t] * N, tmp + (size_t)t * N, sizeof(u64) * N);
+        if (g != 1)
+            for (uint32_t x = 0; x < nx; x++) {
+                automorph_mod(N, D + (size_t)x * N, c->mod[ext[x]], g, tmp);
+                memcpy(D + (size_t)x * N, tmp, sizeof(u64) * N);
+            }
         const u64 *ej = evk + (size_t)j * 2 * nevk * N;
         for (uint32_t t = 0; t < 2; t++)
             for (uint32_t x = 0; x < nx; x++) {
@@ -608,6 +625,21 @@ void or_keyswitch(const or_ctx *c, const u64 *d, uint32_t l, const u64 *evk, u64
         }
     }
     free(u); free(D); free(tmp);
+}
+void or_keyswitch(const or_ctx *c, const u64 *d, uint32_t l, const u64 *evk, u64 *ks)
+{
+    keyswitch_core(c, d, l, evk, 1, ks);
+}
+/* The key switch of sigma_g(d) that a rotation uses: the digits of d itself are
+ * extended, and X -> X^g is applied to every extended digit limb before the inner
+ * product.  The automorphism commutes with the digit decomposition, but the fast
+ * conversion of a negated coefficient differs from the negated conversion by a
+ * multiple of Q_j, so the result is another valid key switch of sigma_g(d) than
+ * or_keyswitch(sigma_g(d)); its extension does not depend on g, so rotations of
+ * one ciphertext by several steps can share it. */
+void or_keyswitch_galois(const or_ctx *c, const u64 *d, uint32_t l, const u64 *evk, u64 g, u64 *ks)
+{
+    keyswitch_core(c, d, l, evk, g, ks);
 }
 void or_relin(const or_ctx *c, const u64 *ct3, uint32_t l, const u64 *rlk, u64 *out2)
 {
@@ -649,21 +681,20 @@ void or_automorph(const or_ctx *c, const u64 *a, uint32_t nlimbs, u64 g, u64 *ou
         }
     }
 }
-/* Left rotation by r slots: (sigma_g c0 + ks0, ks1), ks = KS_{sigma_g(s) -> s}(sigma_g c1). */
+/* Left rotation by r slots: (sigma_g c0 + ks0, ks1), ks = KS_{sigma_g(s) -> s}(sigma_g c1)
+ * in the form of or_keyswitch_galois (c1's digits extended, then permuted). */
 void or_rotate(const or_ctx *c, const u64 *ct, uint32_t l, int64_t r, const u64 *gk, u64 *out)
 {
     size_t n = (size_t)l * c->N;
     u64 g = or_galois_elt(c, r);
-    u64 *a0 = (u64 *)malloc(sizeof(u64) * n), *a1 = (u64 *)malloc(sizeof(u64) * n),
-        *ks = (u64 *)malloc(sizeof(u64) * 2 * n);
+    u64 *a0 = (u64 *)malloc(sizeof(u64) * n), *ks = (u64 *)malloc(sizeof(u64) * 2 * n);
     or_automorph(c, ct, l, g, a0);
-    or_automorph(c, ct + n, l, g, a1);
-    or_keyswitch(c, a1, l, gk, ks);
+    keyswitch_core(c, ct + n, l, gk, g, ks);
     for (uint32_t i = 0; i < l; i++)
         for (uint32_t k = 0; k < c->N; k++) {
             size_t x = (size_t)i * c->N + k;
             out[x] = addm(a0[x], ks[x], c->mod[i]);
             out[n + x] = ks[n + x];
         }
-    free(a0); free(a1); free(ks);
+    free(a0); free(ks);
 }

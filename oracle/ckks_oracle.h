@@ -100,6 +100,8 @@ void or_mul_acc(const or_ctx *c, const uint64_t *const *a, const uint64_t *const
 void or_bconv(const or_ctx *c, const uint64_t *x, const uint32_t *src, uint32_t nsrc,
               const uint32_t *dst, uint32_t ndst, uint64_t *y);
 void or_keyswitch(const or_ctx *c, const uint64_t *d, uint32_t l, const uint64_t *evk, uint64_t *ks);
+void or_keyswitch_galois(const or_ctx *c, const uint64_t *d, uint32_t l, const uint64_t *evk, uint64_t g,
+                         uint64_t *ks);
 void or_relin(const or_ctx *c, const uint64_t *ct3, uint32_t l, const uint64_t *rlk, uint64_t *out2);
 int  or_rescale(const or_ctx *c, const uint64_t *ct, uint32_t npolys, uint32_t l, uint64_t *out);
 void or_automorph(const or_ctx *c, const uint64_t *a, uint32_t nlimbs, uint64_t g, uint64_t *out);

@@ -2,15 +2,18 @@
 // a batch of inputs, the operation under relinearisation and slot rotation
 // (the CT-CT multiplications of Sec. 3 and the rotations of its packing).
 //
-// For each item b: input d_b (l_b limbs, NTT domain) read through a Galois
-// permutation gal_b (0 = none), key evk_b [dnum][2][L+K][N], output out_b
-// (2 polys of l_b limbs), optional addends add[2b], add[2b+1] (read through
-// gal_b).  Items may sit at different levels l_b: every launch walks flat lists
-// of (item, limb) or (item, digit) entries built on the host, so that one launch
-// sequence serves a whole ragged batch.
-//   ModUp:   digits D_j = limbs [j alpha, min((j+1) alpha, l)); each converted to
-//            Q_l u P by fast basis conversion (canonical representatives);
-//   inner:   u_t = sum_j D_j * evk_{j,t} over Q_l u P;
+// For each item b: input d_b (l_b limbs, NTT domain), Galois element gal_b (0 =
+// none), key evk_b [dnum][2][L+K][N], output out_b (2 polys of l_b limbs), optional
+// addends add[2b], add[2b+1] (read through gal_b).  Items may sit at different
+// levels l_b: every launch walks flat lists of (item, limb) or (item, digit) entries
+// built on the host, so that one launch sequence serves a whole ragged batch.
+// Items with the same input and level share one ModUp (rotations of one ciphertext
+// by several steps).
+//   ModUp:   digits D_j = limbs [j alpha, min((j+1) alpha, l)) of d_b itself; each
+//            converted to Q_l u P by fast basis conversion (canonical representatives);
+//   inner:   u_t = sum_j sigma_g(D_j) * evk_{j,t} over Q_l u P, every limb of D_j read
+//            through the permutation of gal_b (the key switch of sigma_g(d_b) that a
+//            rotation needs, with the extension done once for all g);
 //   ModDown: ks_t = (u_t + (P-1)/2 - Conv_{P->Q}([u_t + (P-1)/2]_P)) * P^-1,
 //            i.e. u_t / P rounded (up to the fast-conversion error);
 //   out_t  = ks_t + add_t.
@@ -18,7 +21,7 @@
 // Kernel sequence (every transform split into a column pass and a row pass of at
 // most 2^8 elements per row, so that the fused row kernels run in workgroups of at
 // most 256 threads, 128 by default):
-//   1 k_ks_intt_first   inverse row pass of d_b, gathered through gal_b  -> dc
+//   1 k_ks_intt_first   inverse row pass of d_b                           -> dc
 //     k_col_inv         inverse column pass, times (Q_j/q_a)^-1 mod q_a   -> dc (conversion sources)
 //   2 k_bconv           ModUp conversion of every digit, one thread per coefficient -> up
 //     k_col_fwd         forward column pass of up
@@ -95,8 +98,8 @@ __device__ __forceinline__ uint64_t tab_word(uint64_t *const *tab, uint32_t off,
     return (uint64_t)(uintptr_t)tab[off + y];
 }
 
-// 1. First (row) pass of the inverse transform of d_b, gathered through gal_b,
-//    into dc as lazy FP64 bits.  blockIdx.y + y0 = entry of the la list.
+// 1. First (row) pass of the inverse transform of d_b into dc as lazy FP64 bits.
+//    blockIdx.y + y0 = entry of the la list.
 template <int LOGG, int WG>
 __global__ __launch_bounds__(WG) void k_ks_intt_first(uint64_t *const *__restrict__ tab, KsTab t, uint32_t y0,
                                                       uint64_t *__restrict__ dc, const ModQ *__restrict__ mods,
@@ -110,12 +113,11 @@ __global__ __launch_bounds__(WG) void k_ks_intt_first(uint64_t *const *__restric
     const uint64_t e = tab_word(tab, t.la, y);
     const uint32_t b = (uint32_t)((e >> 16) & 0xFFFF), i = (uint32_t)(e & 0xFFFF);
     const gu64 *src = gview(tab[b] + (size_t)i * N);
-    const uint32_t gal = (uint32_t)tab_word(tab, 5 * t.n, b);
     const double q = mods[i].q, qinv = mods[i].qinv;
     const Gm gm(logN, blockIdx.x);
     double x[R];
 #pragma unroll
-    for (int k = 0; k < R; k++) x[k] = u64_to_f64(src[galois_src(gm.coal(k), gal, logN)]);
+    for (int k = 0; k < R; k++) x[k] = u64_to_f64(src[gm.coal(k)]);
     gm.coal_to_inv_in(x, lds);
     gm.template inv<false>(x, lds, itwt + (size_t)i * N, q, qinv, 0.0, logN, sigma0);
     uint64_t *dst = dc + (size_t)y * N;
@@ -125,9 +127,9 @@ __global__ __launch_bounds__(WG) void k_ks_intt_first(uint64_t *const *__restric
 
 // 4b. Key inner product, one thread per pair of coefficients (16-byte loads) of
 //     one limb x of Q_l u P for the TI (or fewer) items of one group, which share
-//     the key: u_t[x] = sum_j D_j[x] * evk_{j,t}[x]; D_j[x] is the item's input limb
-//     itself (read through gal_b) inside digit j, else its converted limb.  blockIdx.y + y0 = entry of
-//     the inner list.
+//     the key: u_t[x] = sum_j sigma_g(D_j[x]) * evk_{j,t}[x]; D_j[x] is the item's input
+//     limb itself inside digit j, else its converted limb, both read through the
+//     group's Galois permutation.  blockIdx.y + y0 = entry of the inner list.
 __device__ __forceinline__ void ld2(const uint64_t *p, double &a, double &b)
 {
     // p comes from the pointer table: a generic pointer to device memory, loaded as
@@ -155,8 +157,8 @@ __global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ 
     const double q = mods[mx].q, qi = mods[mx].qinv;
     const uint64_t *ev = tab[t.n + gr.it[0]];
     const size_t ML = t.L + t.K;
-    // the input limb is read through the Galois permutation of the group's key, which
-    // maps the pair (k, k+1) onto the pair (y, y^1): one 16-byte load, swapped when y is odd
+    // every limb is read through the Galois permutation of the group's key, which maps
+    // the pair (k, k+1) onto the pair (y, y^1): one 16-byte load, swapped when y is odd
     const uint32_t gal = (uint32_t)tab_word(tab, 5 * t.n, gr.it[0]);
     const uint32_t ys = galois_src(k, gal, logN), yk = ys & ~1u;
     const bool swp = ys & 1u;
@@ -177,14 +179,14 @@ __global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ 
                 double D0, D1;
                 if (inside) {
                     ld2(tab[b] + (size_t)x * N + yk, D0, D1);
-                    if (swp) {
-                        const double t0 = D0;
-                        D0 = D1;
-                        D1 = t0;
-                    }
                 } else {
                     const KsItem &it = tab_item(tab, t, b);
-                    ld2(up + ((size_t)it.up_off + it.upoff[j] + pos) * N + k, D0, D1);
+                    ld2(up + ((size_t)it.up_off + it.upoff[j] + pos) * N + yk, D0, D1);
+                }
+                if (swp) {
+                    const double t0 = D0;
+                    D0 = D1;
+                    D1 = t0;
                 }
                 a0[u] += mulmod(D0, e00, q, qi);
                 c0[u] += mulmod(D1, e01, q, qi);
@@ -224,7 +226,9 @@ __global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ 
 }
 
 // 3+4. The forward row pass of the converted digits fused with the key inner
-//     product, for items with their own key (groups of one): one block covers the
+//     product, for items with their own key (groups of one) and no Galois element
+//     (the converted limbs are transformed here, so they cannot be read through a
+//     permutation): one block covers the
 //     rows of limb x of Q_l u P that the row pass gives it, in the row-pass geometry;
 //     per digit j, D_j[x] is the input limb (canonical) or the converted limb,
 //     transformed in registers and redistributed to the coalesced order, then
@@ -611,19 +615,22 @@ void in_pieces(uint32_t total, F f)
 
 // Host plan of one ragged batch.
 struct KsPlan {
-    uint32_t n, sum_l, sum_nd, sum_ups, sum_inner, max_grp;
+    uint32_t n, sum_l, sum_dc, sum_nd, sum_ups, sum_inner, max_grp;
     std::vector<KsItem> items;
     std::vector<BcJob> upjobs, dnjobs;
     std::vector<KsGrp> groups;
     std::vector<uint64_t> la, upmods, inner, fl, pl;
 };
 
-fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *evk, KsPlan &pl)
+fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *d,
+                   const uint64_t *const *evk, KsPlan &pl)
 {
     const uint32_t K = c->K, alpha = c->alpha;
     pl.n = n;
     pl.items.assign(n, KsItem{});
     uint32_t dc = 0, up = 0, uq = 0;
+    // items with the same input and level share the first one's ModUp (dc and up rows)
+    std::map<std::pair<const uint64_t *, uint32_t>, uint32_t> first;
     for (uint32_t b = 0; b < n; ++b) {
         const uint32_t l = ls[b];
         if (l < 1 || l > c->L) return fhe_fail(FHE_ELEVEL, "key switch: limb count out of range");
@@ -633,9 +640,28 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
         KsItem &it = pl.items[b];
         it.l = l;
         it.nd = nd;
+        it.uq_off = uq;
+        for (uint32_t tt = 0; tt < 2; ++tt) {
+            const BconvTab &md = c->moddown[l];
+            pl.dnjobs.push_back(BcJob{md.off, md.nsrc, md.ndst, (2 * b + tt) * K, uq + tt * l, 0});
+            for (uint32_t i = 0; i < l; ++i)
+                pl.fl.push_back(((uint64_t)b << 17) | ((uint64_t)tt << 16) | i | ((uint64_t)(uq + tt * l + i) << 32));
+            for (uint32_t k = 0; k < K; ++k)
+                pl.pl.push_back((uint64_t)(c->L + k) | ((uint64_t)(md.off + k) << 32));
+        }
+        uq += 2 * l;
+        const auto key = std::make_pair(d[b], l);
+        const auto f = first.find(key);
+        if (f != first.end()) {
+            const KsItem &src = pl.items[f->second];
+            it.dc_off = src.dc_off;
+            it.up_off = src.up_off;
+            for (uint32_t j = 0; j < nd; ++j) it.upoff[j] = src.upoff[j];
+            continue;
+        }
+        first.emplace(key, b);
         it.dc_off = dc;
         it.up_off = up;
-        it.uq_off = uq;
         uint32_t u = 0;
         for (uint32_t j = 0; j < nd; ++j) {
             const BconvTab &t = c->modup[(size_t)l * c->dnum + j];
@@ -648,17 +674,8 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
             const BconvTab &t = c->modup[(size_t)l * c->dnum + i / alpha];
             pl.la.push_back(((uint64_t)b << 16) | i | ((uint64_t)(t.off + i % alpha) << 32));
         }
-        for (uint32_t tt = 0; tt < 2; ++tt) {
-            const BconvTab &md = c->moddown[l];
-            pl.dnjobs.push_back(BcJob{md.off, md.nsrc, md.ndst, (2 * b + tt) * K, uq + tt * l, 0});
-            for (uint32_t i = 0; i < l; ++i)
-                pl.fl.push_back(((uint64_t)b << 17) | ((uint64_t)tt << 16) | i | ((uint64_t)(uq + tt * l + i) << 32));
-            for (uint32_t k = 0; k < K; ++k)
-                pl.pl.push_back((uint64_t)(c->L + k) | ((uint64_t)(md.off + k) << 32));
-        }
         dc += l;
         up += u;
-        uq += 2 * l;
     }
     // the ModUp digits' forward passes in modulus order (their row-pass twiddles are then
     // read once per modulus: 22% less HBM traffic for the row pass, at the same speed);
@@ -683,7 +700,8 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     if (pl.groups.size() >= 65536) return fhe_fail(FHE_EINVAL, "key-switch batch too large");
     for (uint32_t g = 0; g < pl.groups.size(); ++g)
         for (uint32_t x = 0; x < ls[pl.groups[g].it[0]] + K; ++x) pl.inner.push_back(((uint64_t)g << 16) | x);
-    pl.sum_l = dc;
+    pl.sum_l = uq / 2;
+    pl.sum_dc = dc;
     pl.sum_ups = up;
     pl.sum_nd = (uint32_t)pl.upjobs.size();
     pl.sum_inner = (uint32_t)pl.inner.size();
@@ -779,12 +797,13 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     if (2ull * n > GRID_Y) return fhe_fail(FHE_EINVAL, "key-switch batch too large");
     KsPlan pl;
     fhe_status s;
-    if ((s = ks_plan(c, n, ls, evk, pl))) return s;
+    if ((s = ks_plan(c, n, ls, d, evk, pl))) return s;
 
-    // scratch: dc [sum l], up [sum ups], uQ [sum 2l], uP [n][2][K], z [sum 2l]
+    // scratch: dc [sum l of distinct inputs], up [their ups], uQ [sum 2l], uP [n][2][K],
+    // z [sum 2l] (ks_scratch_bytes_ragged counts every input as distinct)
     uint8_t *scr = scr_in;
     if (!scr && (s = ctx_scratch(c, ks_scratch_bytes_ragged(c, n, ls), &scr))) return s;
-    uint64_t *dc = (uint64_t *)scr, *up = dc + (size_t)pl.sum_l * N, *uQ = up + (size_t)pl.sum_ups * N,
+    uint64_t *dc = (uint64_t *)scr, *up = dc + (size_t)pl.sum_dc * N, *uQ = up + (size_t)pl.sum_ups * N,
              *uP = uQ + 2 * (size_t)pl.sum_l * N, *z = uP + 2 * (size_t)n * K * N;
 
     // one table: pointers, then the plan's lists
@@ -826,24 +845,26 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     hipStream_t st = c->stream;
     const uint32_t sum2l = 2 * pl.sum_l;
 
-    // 1. coefficients of the (permuted) inputs
+    // 1. coefficients of the distinct inputs
     {
         ProfScope ps(c, "ks_intt_first");
         dispatch_logn(c, [&](auto sh) {
             using S = decltype(sh);
-            in_pieces(pl.sum_l, [&](uint32_t y0, uint32_t cnt) {
+            in_pieces(pl.sum_dc, [&](uint32_t y0, uint32_t cnt) {
                 hipLaunchKernelGGL((k_ks_intt_first<S::LOGB, S::WB>), dim3(S::GB, cnt), dim3(S::WB), 0, st,
                                    (uint64_t *const *)dt, kt, y0, dc, (const ModQ *)c->d_mod, (const double *)c->d_itw,
                                    c->logN, (uint32_t)S::LOGA);
             });
         });
     }
-    ks_col_inv<1>(c, dc, dwords + kt.la, pl.sum_l, "ntt_inv_col");
+    ks_col_inv<1>(c, dc, dwords + kt.la, pl.sum_dc, "ntt_inv_col");
     // 2-3. ModUp conversion, the forward column pass of the converted limbs, then
     //      their row pass (alone, or inside the inner product)
     ks_bconv<false>(c, dc, up, dwords + kt.uj, pl.sum_nd, "bconv_up");
     ks_col_fwd(c, up, dwords + kt.um, pl.sum_ups);
-    if (pl.max_grp == 1 && c->tune_fuse_row_inner) {
+    bool permuted = false;
+    for (uint32_t b = 0; gal && b < n; ++b) permuted = permuted || gal[b] != 0;
+    if (pl.max_grp == 1 && c->tune_fuse_row_inner && !permuted) {
         // 3+4. row pass of the converted digits fused with the key inner product
         ProfScope ps(c, "ks_inner");
         dispatch_logn(c, [&](auto sh) {

@@ -330,22 +330,20 @@ fhe_status fhe_rotate(fhe_ctx *c, const fhe_evk *gk, const fhe_ct *in, int32_t s
     if (gk->galois != g) return fhe_fail(FHE_ENOKEY, "fhe_rotate: Galois key is for another step");
     const uint32_t l = in->limbs;
     const size_t per = (size_t)l * c->N;
-    // sigma_g of both polynomials into scratch (one pass; the permutation gathers,
-    // the writes are coalesced), then the key switch of sigma_g(c1) adds sigma_g(c0).
+    // the input copied to scratch first, so that out may alias in; then the key switch
+    // of sigma_g(c1) (c1's digits extended, read through the permutation) adds
+    // sigma_g(c0), read through the permutation as well
     const size_t ksb = ks_scratch_bytes(c, l, 1);
     uint8_t *scr;
     if ((s = ctx_scratch(c, ksb + 2 * per * sizeof(uint64_t), &scr))) return s;
-    uint64_t *perm = (uint64_t *)(scr + ksb);
-    {
-        ProfScope ps(c, "automorph");
-        hipLaunchKernelGGL(k_automorph, dim3(blocks_for(2 * per, TPB)), dim3(TPB), 0, c->stream,
-                           (const uint64_t *)in->d, perm, c->logN, (uint64_t)2 * l, (uint32_t)g);
-    }
-    const uint64_t *dd[1] = {perm + per};
+    uint64_t *cp = (uint64_t *)(scr + ksb);
+    HIPCHK(hipMemcpyAsync(cp, in->d, 2 * per * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->stream));
+    const uint64_t *dd[1] = {cp + per};
+    const uint32_t ga[1] = {(uint32_t)g};
     const uint64_t *ek[1] = {gk->d};
     uint64_t *oo[1] = {out->d};
-    const uint64_t *ad[2] = {perm, nullptr};   // (sigma_g(c0) + ks0, ks1)
-    fhe_status r = ks_run(c, l, 1, dd, nullptr, ek, oo, ad, scr);
+    const uint64_t *ad[2] = {cp, nullptr};   // (sigma_g(c0) + ks0, ks1)
+    fhe_status r = ks_run(c, l, 1, dd, ga, ek, oo, ad, scr);
     out->scale = in->scale;
     c->ops[OP_ROTATE] += 1;
     return r;
@@ -411,15 +409,17 @@ void launch_automorph(fhe_ctx *c, const uint64_t *in, uint64_t *out, uint32_t nl
 }
 
 // n rotations (a key switch of sigma_g(c1) with sigma_g(c0) as addend, both read
-// through the permutation), items at levels ls[b], in chunks whose scratch stays
-// near 4 GiB.  Outputs must not overlap inputs.
+// through the permutation; rotations of one input share its digit extension), items
+// at levels ls[b], in chunks whose scratch stays near 4 GiB.  Outputs must not
+// overlap inputs.
 fhe_status rotate_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *in,
                              const fhe_evk *const *keys, uint64_t *const *out)
 {
-    // The key switch reads c1 through the Galois permutation in its first pass and
-    // adds sigma_g(c0) in its last one: a wavefront's 64 consecutive outputs gather
-    // from one aligned block of 64 inputs (the permutation is affine in bit-reversed
-    // index order), so the gathers stay coalesced and no permuted copy is made.
+    // The key switch extends the digits of c1 itself, reads them through the Galois
+    // permutation in its inner product and adds sigma_g(c0) in its last pass: a
+    // wavefront's 64 consecutive outputs gather from one aligned block of 64 inputs
+    // (the permutation is affine in bit-reversed index order), so the gathers stay
+    // coalesced and no permuted copy is made.
     const size_t N = c->N, cap = (size_t)4 << 30;
     fhe_status s;
     for (uint32_t b0 = 0; b0 < n;) {

@@ -336,6 +336,32 @@ def test_keyswitch_invariant(tiny):
         assert max(abs(x) for x in err) <= bound
 
 
+def test_keyswitch_galois_identity_and_invariant(tiny):
+    """The rotation form of the key switch: with g = 1 it is the plain key switch;
+    with a Galois element it is a key switch of sigma_g(d) (same invariant and error
+    bound as the plain one, with sigma_g(d) for d); and it is another valid result
+    than the plain key switch of sigma_g(d), since the fast conversion of a negated
+    coefficient differs from the negated conversion by a multiple of the digit modulus."""
+    s = tiny.sample_ternary(2, ckks.TAG_SECRET, 0)
+    rs = np.random.default_rng(17)
+    for l in [3, 2]:
+        d = np.array([rs.integers(0, q, size=tiny.N, dtype=np.uint64) for q in tiny.q[:l]])
+        s_from = tiny.square_small(s)
+        evk = tiny.keygen_evk(s, s_from, 9)
+        assert np.array_equal(tiny.keyswitch_galois(d, evk, 1), tiny.keyswitch(d, evk))
+        for r in (1, -3):
+            g = tiny.galois_elt(r)
+            sg = tiny.automorph_small(s, g)
+            gk = tiny.keygen_evk(s, sg, 30 + r)
+            dg = tiny.automorph(d, g)
+            ks = tiny.keyswitch_galois(d, gk, g)
+            err = _ks_error(tiny, ks, dg, sg, s)
+            maxQj = max(math.prod(tiny.q[j * tiny.alpha:(j + 1) * tiny.alpha]) for j in range(tiny.dnum))
+            bound = tiny.dnum * tiny.alpha * tiny.N * 19 * maxQj / math.prod(tiny.p) + (tiny.K + 1) * (tiny.N + 1)
+            assert max(abs(x) for x in err) <= bound
+            assert not np.array_equal(ks, tiny.keyswitch(dg, gk))
+
+
 def test_relin_preserves_decryption(c1):
     s = c1.keygen_secret(1)
     rlk = c1.keygen_relin(s, 4)
