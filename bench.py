@@ -633,10 +633,11 @@ def paper(args):
 
 
 def kssweep(args):
-    """Key switches per second against batch size B in {1, 8, 32, 64}, with B distinct
-    Galois keys and with B ciphertexts sharing one key (N = 2^16, l = 24, K = 8,
-    dnum = 3); the compulsory bytes per key switch are the input, the output and the
-    key's share: (3 l + 2 dnum (L + K) / k) limbs with k items per key."""
+    """Key switches per second against batch size B in {1, 8, 32, 64}: B ciphertexts
+    with B distinct Galois keys, B ciphertexts sharing one key, and one ciphertext
+    rotated by B steps (N = 2^16, l = 24, K = 8, dnum = 3); the compulsory bytes per key
+    switch are the input's share, the output and the key's share:
+    (l / m + 2 l + 2 dnum (L + K) / k) limbs with k items per key and m per input."""
     import numpy as np
     import torch
 
@@ -656,29 +657,35 @@ def kssweep(args):
     z0 = workloads.slot_messages(workloads.SEED_DATA, 64)
     rows = []
     for B in (1, 8, 32, 64):
-        for mode in ("distinct", "shared"):
-            keys = gks[:B] if mode == "distinct" else [gks[0]] * B
-            steps = list(range(1, B + 1)) if mode == "distinct" else [1] * B
-            g.rotate_batch(keys, cts[:B], steps, outs[:B])
+        for mode in ("distinct", "shared", "one_input"):
+            # distinct: B ciphertexts, each with its own key; shared: B ciphertexts, one
+            # key; one_input: one ciphertext rotated by B steps (B keys), which share
+            # the extension of its digits
+            keys = [gks[0]] * B if mode == "shared" else gks[:B]
+            steps = [1] * B if mode == "shared" else list(range(1, B + 1))
+            ins = [cts[0]] * B if mode == "one_input" else cts[:B]
+            g.rotate_batch(keys, ins, steps, outs[:B])
             got, _ = g.decode(g.decrypt(s, outs[0]), n=63)
             assert np.abs(got - z0[1:64]).max() < 1e-6, "rotation result is wrong"
             reps = max(2, min(args.steps, 256 // B))
             for _ in range(2):
-                g.rotate_batch(keys, cts[:B], steps, outs[:B])
+                g.rotate_batch(keys, ins, steps, outs[:B])
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(reps):
-                g.rotate_batch(keys, cts[:B], steps, outs[:B])
+                g.rotate_batch(keys, ins, steps, outs[:B])
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / reps
             per_key = B if mode == "shared" else 1
-            ks_bytes = (3 * l + 2 * g.dnum * (g.L + g.K) / per_key) * N * 8
+            per_input = B if mode == "one_input" else 1
+            ks_bytes = (l / per_input + 2 * l + 2 * g.dnum * (g.L + g.K) / per_key) * N * 8
             rate = B / dt
             rows.append({"batch": B, "keys": mode, "key_switch_per_s": round(rate, 1), "ms_per_batch": round(dt * 1e3, 3),
                          "compulsory_MiB_per_ks": round(ks_bytes / 2 ** 20, 1),
                          "hbm_frac_compulsory": round(rate * ks_bytes / (HBM_PEAK_GBS * 1e9), 4)})
             print(json.dumps({"kssweep_row": rows[-1]}), file=sys.stderr, flush=True)
-    print(json.dumps({"metric": "key-switch ops/s at N=2^16,L=24 against batch size, distinct or shared keys",
+    print(json.dumps({"metric": "key-switch ops/s at N=2^16,L=24 against batch size: distinct keys, shared key, "
+                                "one input",
                       "unit": "key-switch/s", "rows": rows,
                       "config": {"workload": "rotation key switch, N=2^16, l=24, K=8, dnum=3"}}))
 
