@@ -162,12 +162,16 @@ fhe_status fhe_mul_acc(fhe_ctx *ctx, const fhe_ct *a, const fhe_ct *b, uint32_t 
 fhe_status fhe_relin(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *in3, fhe_ct *out2);
 fhe_status fhe_rescale(fhe_ctx *ctx, const fhe_ct *in, fhe_ct *out);
 fhe_status fhe_drop_level(fhe_ctx *ctx, const fhe_ct *in, uint32_t limbs, fhe_ct *out);
-/* Left rotation by step slots with the Galois key of that step; out may equal in
- * (the permuted input is staged in the context's scratch). */
+/* Left rotation by step slots with the Galois key of that step (the slot rotation of
+ * Sec. 3 / Fig. 2, computed as sigma_g(c0) + KS(sigma_g(c1)) with g = 5^step mod 2N).
+ * The key switch extends the digits of c1 itself and applies sigma_g to the extended
+ * digits before the key inner product, the same result the oracle defines; out may
+ * equal in (the input is copied to the context's scratch first). */
 fhe_status fhe_rotate(fhe_ctx *ctx, const fhe_evk *gk, const fhe_ct *in, int32_t step, fhe_ct *out);
 /* n independent rotations in one launch sequence: out[t] = rotate(in[t], steps[t])
- * with Galois key gk[t]; gk, in, steps, out are host arrays of n entries.
- * Outputs must not overlap any input (FHE_EINVAL). */
+ * with Galois key gk[t]; gk, in, steps, out are host arrays of n entries.  Entries
+ * with the same input ciphertext share one extension of its digits.  Outputs must
+ * not overlap any input (FHE_EINVAL). */
 fhe_status fhe_rotate_batch(fhe_ctx *ctx, const fhe_evk *gk, const fhe_ct *in, const int32_t *steps, uint32_t n,
                             fhe_ct *out);
 /* Hybrid key switch of d (limbs x N, evaluation form): out = (ks0, ks1), polys 2. */
