@@ -265,11 +265,15 @@ fhe_status fhe_square_act(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *x, uin
  *   s_pq = dilation * ((p - k/2) * frame_w + (q - k/2)), taps row-major, k odd;
  *   W[(co*Cin + ci)*k*k + p*k + q] are slot-replicated weights (Eq. (enc_conv)
  *   with the window sum done by rotations); X, W at level l, Y at l - 1.
- * fhe_poly_act: polynomial activation at depth 2 (Sec. 3 "Activation"):
- *   deg 3: y = (c3 u + c2) u^2 + (c1 u + c0); deg 2: y = (c2 u + c1) u + c0,
- *   coef = {c0, c1, c2, c3}; constants c multiply as the integer round(c * s):
- *   c3 (deg 3) or c2 (deg 2) at s = q_(l-1), the linear term at the scale that
- *   lands on the product's scale.  Inputs at l >= 3, one scale; outputs at l - 2.
+ * fhe_poly_act: polynomial activation (Sec. 3 "Activation", Eq. (approxReLU)),
+ *   coef = {c0, c1, c2, c3}; constants c multiply as the integer round(c * s).
+ *   deg 3, depth 2: y = (c3 u + c2) u^2 + (c1 u + c0), c3 at s = q_(l-1), the
+ *   linear term at the scale that lands on the product's scale; inputs at l >= 3,
+ *   outputs at l - 2, output scale S^3 / (q_(l-1) q_(l-2)) up to the constants.
+ *   deg 2, depth 1 (the paper's count): Relin(u (x) u) is taken as c2 u^2 at scale
+ *   S' = S^2 / c2, plus round(c1 S / c2) u and round(c0 S'), then one rescale;
+ *   c2 must be nonzero; inputs at l >= 2, outputs at l - 1, scale S' / q_(l-1).
+ *   Inputs share one scale S.
  * fhe_avgpool2x2 (Sec. 3 "Pooling", mean of a 2x2 window): t = x + rot(x, d);
  *   t = t + rot(t, frame_w d); y = Rescale(t * mask).  mask is a plaintext at
  *   level l (0.25 on the positions that survive, zero elsewhere; its scale sets

@@ -157,10 +157,12 @@ def conv_steps(k, dil, frame_w):
 
 
 def add_const(o, ct, value):
-    """ct + value: the constant polynomial round(value * ct.scale) added to c0."""
-    m = np.zeros(o.N, dtype=np.int64)
-    m[0] = int(np.rint(value * ct.scale))
-    return o.add_pt(ct, o.small_to_rns(m, ct.level))
+    """ct + value: the constant polynomial round(value * ct.scale) added to c0.
+    The integer is exact at any size (a Python int), reduced per limb."""
+    m = int(np.rint(value * ct.scale))
+    pt = np.zeros((ct.level, o.N), dtype=np.uint64)
+    pt[:, 0] = [m % int(q) for q in o.q[:ct.level]]
+    return o.add_pt(ct, pt)
 
 
 def enc_conv2d_packed(o, rlk, gks, X, Cin, Wt, Cout, k, dil, frame_w, cnt):
@@ -185,11 +187,15 @@ def enc_conv2d_packed(o, rlk, gks, X, Cin, Wt, Cout, k, dil, frame_w, cnt):
 
 
 def enc_poly_act(o, rlk, xs, coef, deg, cnt):
-    """Polynomial activation at depth 2.
-    deg 3: (c3 u + c2) u^2 + (c1 u + c0); deg 2: (c2 u + c1) u + c0.
-    A constant multiplier c at plaintext scale s is the integer round(c s); the
-    branch c3 u (c2 u) uses s = q_(l-1) so that its rescale keeps u's scale, and
-    the linear branch's scale is chosen so that it lands on the product's scale."""
+    """Polynomial activation; deg 3 at depth 2, deg 2 at depth 1 (Sec. 3).
+    deg 3: (c3 u + c2) u^2 + (c1 u + c0).  A constant multiplier c at plaintext
+    scale s is the integer round(c s); the branch c3 u uses s = q_(l-1) so that
+    its rescale keeps u's scale, and the linear branch's scale is chosen so that
+    it lands on the product's scale.
+    deg 2: Relin(u (x) u), whose plain value is u^2 at scale S^2, is read as c2 u^2
+    at scale S' = S^2 / c2, so the leading coefficient costs no multiplication;
+    c1 u joins at that scale as round(c1 S / c2) u, c0 as round(c0 S'), and one
+    rescale ends it."""
     out = []
     for x in xs:
         l = x.level
@@ -208,13 +214,21 @@ def enc_poly_act(o, rlk, xs, coef, deg, cnt):
             cnt.ct_add += 1
             out.append(o.add(p, b))
         elif deg == 2:
-            a = o.rescale(o.mul_const(x, int(np.rint(coef[2] * float(ql))), float(ql)))
-            a = add_const(o, a, coef[1])
-            p = _mac_relin_rescale(o, rlk, [(a, o.drop_level(x, l - 1))], cnt)
+            if coef[2] == 0:
+                raise ValueError("deg 2 needs a nonzero quadratic coefficient")
+            S = x.scale
+            Sp = S * S / coef[2]
+            t = o.relin(o.tensor(x, x), rlk)
+            b = o.mul_const(x, int(np.rint(coef[1] * S / coef[2])))
+            u = o.add(ckks.Ct(t.data, Sp), ckks.Ct(b.data, Sp))
+            u = add_const(o, u, coef[0])
+            out.append(o.rescale(u))
+            cnt.ct_mult += 1
+            cnt.relin += 1
             cnt.pt_mult += 1
-            cnt.pt_add += 2
+            cnt.pt_add += 1
+            cnt.ct_add += 1
             cnt.rescale += 1
-            out.append(add_const(o, p, coef[0]))
         else:
             raise ValueError("deg must be 2 or 3")
     return out

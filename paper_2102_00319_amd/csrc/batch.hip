@@ -42,6 +42,8 @@ __global__ __launch_bounds__(TPB) void k_tensor_batch(uint64_t *const *__restric
     out[x + 2 * off1] = f64_to_u64(canon(mulmod(a1, b1, q, qi), q, qi));
 }
 
+}  // namespace
+
 fhe_status tensor_run(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *a, const uint64_t *const *b,
                       uint64_t *const *out)
 {
@@ -64,6 +66,8 @@ fhe_status tensor_run(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t
     HIPCHK(hipGetLastError());
     return FHE_OK;
 }
+
+namespace {
 
 bool overlaps(const fhe_ct *x, const fhe_ct *y, size_t N)
 {

@@ -210,6 +210,9 @@ fhe_status mac_relin_rescale(fhe_ctx *c, const fhe_evk *rlk, uint32_t l, const s
                              const std::vector<uint64_t *> &B, const std::vector<uint32_t> &off,
                              const std::vector<uint64_t *> &Y);
 fhe_status ctx_ptr_table(fhe_ctx *c, const std::vector<uint64_t *> &ptrs, uint64_t ***dev);
+// Tensor products a[t] (x) b[t] -> out[t] = (a0 b0, a0 b1 + a1 b0, a1 b1), item t at ls[t] limbs.
+fhe_status tensor_run(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *a, const uint64_t *const *b,
+                      uint64_t *const *out);
 
 // Kernel timing: when enabled for a category (or "*"), launches of that
 // category are bracketed by HIP events on the context's stream.

@@ -460,15 +460,35 @@ fhe_status rotate_run(fhe_ctx *c, uint32_t l, uint32_t n, const uint64_t *const 
 }
 
 // Residues of the integer round(v) (|round(v)| < 2^62) on limbs 0..limbs-1.
+// Residues of the integer nearest to v (ties to even).  Beyond 2^62 the double is an
+// integer m * 2^e with m < 2^53: its residues are (m mod q) (2^e mod q) mod q, exact.
 fhe_status const_residues(const fhe_ctx *c, double v, uint32_t limbs, Consts64 *out)
 {
     const double r = std::nearbyint(v);
-    if (!(std::fabs(r) < 4611686018427387904.0)) return fhe_fail(FHE_EINVAL, "constant out of range");
+    if (!std::isfinite(r)) return fhe_fail(FHE_EINVAL, "constant out of range");
     std::memset(out, 0, sizeof(*out));
-    const int64_t iv = (int64_t)r;
+    if (std::fabs(r) < 4611686018427387904.0) {
+        const int64_t iv = (int64_t)r;
+        for (uint32_t i = 0; i < limbs; ++i) {
+            int64_t m = iv % (int64_t)c->mod[i];
+            out->v[i] = (double)(m < 0 ? m + (int64_t)c->mod[i] : m);
+        }
+        return FHE_OK;
+    }
+    int ex;
+    const double f = std::frexp(std::fabs(r), &ex);                 // |r| = f 2^ex, f in [0.5, 1)
+    const uint64_t m = (uint64_t)std::ldexp(f, 53);                  // exact: 53 significant bits
+    const int e = ex - 53;                                           // > 0 here
     for (uint32_t i = 0; i < limbs; ++i) {
-        int64_t m = iv % (int64_t)c->mod[i];
-        out->v[i] = (double)(m < 0 ? m + (int64_t)c->mod[i] : m);
+        const uint64_t q = c->mod[i];
+        unsigned __int128 p2 = 1, b = 2 % q;
+        for (int k = e; k; k >>= 1) {
+            if (k & 1) p2 = p2 * b % q;
+            b = b * b % q;
+        }
+        uint64_t res = (uint64_t)((unsigned __int128)(m % q) * p2 % q);
+        if (r < 0 && res) res = q - res;
+        out->v[i] = (double)res;
     }
     return FHE_OK;
 }

@@ -186,6 +186,60 @@ fhe_status plain_mac_rescale(fhe_ctx *c, uint32_t l, const std::vector<uint64_t 
 
 }  // namespace
 
+// Quadratic activation at depth 1 (the paper's count for g): T = Relin(x (x) x) is read
+// as c2 x^2 at scale S' = S*S/c2, so c2 costs no level; c1 x joins as the integer
+// multiple round(c1 S / c2) of x, c0 as round(c0 S'), and one rescale ends it.
+static fhe_status poly_act2(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_t n, const double *coef, fhe_ct *y)
+{
+    fhe_status s;
+    const uint32_t l = x[0].limbs;
+    if (l < 2) return fhe_fail(FHE_ELEVEL, "fhe_poly_act: degree 2 needs two limbs (depth 1)");
+    if (!(coef[2] != 0.0)) return fhe_fail(FHE_EINVAL, "fhe_poly_act: degree 2 needs a nonzero quadratic coefficient");
+    const double S = x[0].scale;
+    for (uint32_t i = 0; i < n; ++i) {
+        if ((s = chk2(&x[i], l, "fhe_poly_act")) || (s = chk2(&y[i], l - 1, "fhe_poly_act"))) return s;
+        if (x[i].scale != S) return fhe_fail(FHE_ESCALE, "fhe_poly_act: input scales differ");
+    }
+    const size_t N = c->N, w3 = 3 * (size_t)l * N, w2 = 2 * (size_t)l * N;
+    // workspace: T3 [n][3][l], U [n][2][l], B [n][2][l]
+    uint8_t *ws;
+    if ((s = ctx_workspace(c, (size_t)n * (w3 + 2 * w2) * sizeof(uint64_t), &ws))) return s;
+    uint64_t *T3 = (uint64_t *)ws, *U = T3 + n * w3, *Bw = U + n * w2;
+    std::vector<const uint64_t *> xin(n), d2(n), ad(2 * (size_t)n), Uc(n), Bc(n);
+    std::vector<uint64_t *> Tp(n), Up(n), Bp(n), Yp(n);
+    std::vector<uint32_t> ls(n, l);
+    for (uint32_t i = 0; i < n; ++i) {
+        xin[i] = x[i].d;
+        Tp[i] = T3 + i * w3;
+        Up[i] = U + i * w2;
+        Bp[i] = Bw + i * w2;
+        d2[i] = Tp[i] + 2 * (size_t)l * N;
+        ad[2 * i] = Tp[i];
+        ad[2 * i + 1] = Tp[i] + (size_t)l * N;
+        Uc[i] = Up[i];
+        Bc[i] = Bp[i];
+        Yp[i] = y[i].d;
+    }
+    if ((s = tensor_run(c, n, ls.data(), xin.data(), xin.data(), Tp.data()))) return s;
+    std::vector<const uint64_t *> ek(n, rlk->d);
+    if ((s = ks_run(c, l, n, d2.data(), nullptr, ek.data(), Up.data(), ad.data(), nullptr))) return s;
+    const double Sp = S * S / coef[2];
+    Consts64 k1, k0;
+    if ((s = const_residues(c, coef[1] * S / coef[2], l, &k1))) return s;
+    if ((s = ew_batch(c, EW_MULC, l, l, 2, n, xin.data(), nullptr, Bp.data(), k1))) return s;
+    if ((s = ew_batch(c, EW_ADD, l, l, 2, n, Uc.data(), Bc.data(), Up.data(), zero_consts()))) return s;
+    if ((s = const_residues(c, coef[0] * Sp, l, &k0))) return s;
+    if ((s = ew_batch(c, EW_ADDC, l, l, 2, n, Uc.data(), nullptr, Up.data(), k0))) return s;
+    if ((s = rescale_many(c, l, n, Uc, Yp))) return s;
+    for (uint32_t i = 0; i < n; ++i) y[i].scale = Sp / (double)c->mod[l - 1];
+    c->ops[OP_CT_MULT] += n;
+    c->ops[OP_RELIN] += n;
+    c->ops[OP_PT_MULT] += n;
+    c->ops[OP_PT_ADD] += n;
+    c->ops[OP_CT_ADD] += n;
+    return FHE_OK;
+}
+
 extern "C" {
 
 fhe_status fhe_conv2d_packed(fhe_ctx *c, const fhe_evk *rlk, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *X,
@@ -268,6 +322,7 @@ fhe_status fhe_poly_act(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_
     if (!c || !rlk || !rlk->d || !x || !y || !coef || !n) return fhe_fail(FHE_EINVAL, "fhe_poly_act: null or empty");
     if (rlk->galois != 0) return fhe_fail(FHE_ENOKEY, "fhe_poly_act: needs the relinearisation key");
     if (deg != 2 && deg != 3) return fhe_fail(FHE_EINVAL, "fhe_poly_act: degree must be 2 or 3");
+    if (deg == 2) return poly_act2(c, rlk, x, n, coef, y);
     const uint32_t l = x[0].limbs;
     if (l < 3) return fhe_fail(FHE_ELEVEL, "fhe_poly_act: inputs need three limbs (depth 2)");
     const double S = x[0].scale;

@@ -651,7 +651,7 @@ class Context:
         return Y
 
     def poly_act(self, rlk, xs, coef, deg):
-        y = [self.new_ct(v.limbs - 2, 2) for v in xs]
+        y = [self.new_ct(v.limbs - (1 if deg == 2 else 2), 2) for v in xs]
         cf = (C.c_double * 4)(*[float(v) for v in (list(coef) + [0.0] * 4)[:4]])
         XA, YA = self._arr(xs), self._arr(y)
         _check(_lib.fhe_poly_act(self._h, C.byref(rlk.s()), XA, len(xs), cf, deg, YA))

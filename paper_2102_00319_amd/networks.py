@@ -11,7 +11,8 @@ each in a frame_h x frame_w frame of slots (zero guard right and below):
     -> conv k x k same (c2 channels, dilation 2) -> poly act -> 2x2 avg pool
     -> fully connected (flatten order (c, y, x)) -> score in slot 0 of each frame.
 Every CT x CT product is followed by relinearisation and one rescale, so a
-forward pass takes 9 levels: conv 1, act 2, pool 1, conv 1, act 2, pool 1, fc 1.
+forward pass takes 9 levels with the cubic activation: conv 1, act 2, pool 1,
+conv 1, act 2, pool 1, fc 1 (7 with the quadratic one, whose depth is 1).
 """
 import numpy as np
 
@@ -75,8 +76,12 @@ class PackedCNN:
         return (ctx.N // 2) // self.frame
 
     @property
+    def act_depth(self):
+        return 2 if self.deg == 3 else 1
+
+    @property
     def depth(self):
-        return 9
+        return 2 * (self.act_depth + 2) + 1
 
     # -------------------------------------------------------------- user
     def keygen(self, ctx, s, seed):
@@ -101,7 +106,8 @@ class PackedCNN:
 
     # ------------------------------------------------------- model owner
     def weight_levels(self, top):
-        return top, top - 4, top - 8
+        d = self.act_depth + 2
+        return top, top - d, top - 2 * d
 
     def fc_slots(self, ctx, wrow):
         """One FC weight ciphertext's slots: weight (y, x) of a channel at frame position (4y, 4x)."""

@@ -35,9 +35,8 @@ def test_conv_count_formula():
 
 
 def test_depth_of_conv_and_activation():
-    """Levels the oracle's recipe consumes: one for the conv, as the paper states, and
-    two for the quadratic activation (one more than the paper's count): one 3x3
-    window and one filter at N = 2^12."""
+    """Levels the oracle's recipe consumes: one for the conv and one for the quadratic
+    activation, as the paper states: one 3x3 window and one filter at N = 2^12."""
     import numpy as np
     from oracle import OracleCtx
     o = OracleCtx.from_set("t_n12")
@@ -53,6 +52,4 @@ def test_depth_of_conv_and_activation():
     A = cnn.enc_poly_act(o, rlk, Y, GOLD["activation"]["coefficients"], 2, cnn.Counter())
     d = GOLD["depth"]
     assert Y[0].data.shape[1] == L - d["conv"]
-    # the paper's depth 1 for g rests on HElib's plaintext scaling; here a non-integer
-    # constant multiplies as round(c * q_(l-1)) and its rescale costs one more level
-    assert A[0].data.shape[1] == L - d["conv"] - (d["activation"] + 1)
+    assert A[0].data.shape[1] == L - d["conv"] - d["activation"]
