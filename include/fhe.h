@@ -272,7 +272,8 @@ fhe_status fhe_square_act(fhe_ctx *ctx, const fhe_evk *rlk, const fhe_ct *x, uin
  *   outputs at l - 2, output scale S^3 / (q_(l-1) q_(l-2)) up to the constants.
  *   deg 2, depth 1 (the paper's count): Relin(u (x) u) is taken as c2 u^2 at scale
  *   S' = S^2 / c2, plus round(c1 S / c2) u and round(c0 S'), then one rescale;
- *   c2 must be nonzero; inputs at l >= 2, outputs at l - 1, scale S' / q_(l-1).
+ *   c2 must be positive (FHE_EINVAL otherwise: it becomes a factor of the scale);
+ *   inputs at l >= 2, outputs at l - 1, scale S' / q_(l-1).
  *   Inputs share one scale S.
  * fhe_avgpool2x2 (Sec. 3 "Pooling", mean of a 2x2 window): t = x + rot(x, d);
  *   t = t + rot(t, frame_w d); y = Rescale(t * mask).  mask is a plaintext at

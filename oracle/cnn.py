@@ -214,8 +214,8 @@ def enc_poly_act(o, rlk, xs, coef, deg, cnt):
             cnt.ct_add += 1
             out.append(o.add(p, b))
         elif deg == 2:
-            if coef[2] == 0:
-                raise ValueError("deg 2 needs a nonzero quadratic coefficient")
+            if not coef[2] > 0:
+                raise ValueError("deg 2 needs a positive quadratic coefficient (a factor of the scale)")
             S = x.scale
             Sp = S * S / coef[2]
             t = o.relin(o.tensor(x, x), rlk)

@@ -194,7 +194,8 @@ static fhe_status poly_act2(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uin
     fhe_status s;
     const uint32_t l = x[0].limbs;
     if (l < 2) return fhe_fail(FHE_ELEVEL, "fhe_poly_act: degree 2 needs two limbs (depth 1)");
-    if (!(coef[2] != 0.0)) return fhe_fail(FHE_EINVAL, "fhe_poly_act: degree 2 needs a nonzero quadratic coefficient");
+    if (!(coef[2] > 0.0))   // it becomes a factor of the output scale
+        return fhe_fail(FHE_EINVAL, "fhe_poly_act: degree 2 needs a positive quadratic coefficient");
     const double S = x[0].scale;
     for (uint32_t i = 0; i < n; ++i) {
         if ((s = chk2(&x[i], l, "fhe_poly_act")) || (s = chk2(&y[i], l - 1, "fhe_poly_act"))) return s;

@@ -74,7 +74,7 @@ def test_small_packed_network_bit_exact():
         assert c.scale == b.scale
 
 
-@pytest.mark.parametrize("coef,deg", [((0.3, -0.2, 0.7), 2), ((0.0, 1.0, 0.0, 0.0), 3)])
+@pytest.mark.parametrize("coef,deg", [((0.3, -0.2, 0.7), 2), ((-0.3, 0.2, 0.05), 2), ((0.0, 1.0, 0.0, 0.0), 3)])
 def test_poly_act_forms_bit_exact(coef, deg):
     P, _ = _P()
     g, o = P.Context.from_set("t4_n12"), OracleCtx.from_set("t4_n12")
@@ -112,6 +112,8 @@ def test_packed_layer_errors():
         g.fc_packed(rlk, {}, [x], [x], 1, 24)
     with pytest.raises(P.FheError):   # degree 4
         g.poly_act(rlk, [x], (0, 1, 0, 0, 1), 4)
+    with pytest.raises(P.FheError):   # degree 2 with a quadratic coefficient that is not positive
+        g.poly_act(rlk, [x], (0.1, 1.0, -0.5), 2)
     net = networks.PackedCNN(H=H, W=W, frame_h=FH, frame_w=FW, c1=1, c2=1, n_classes=1)
     with pytest.raises(P.FheError):   # mask at another level
         g.avgpool2x2({}, [x], 1, FW, net.pool_mask(g, 1, g.L - 1))

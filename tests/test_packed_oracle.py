@@ -111,10 +111,12 @@ def test_packed_network_logits_and_counts():
     assert cnt.rotate == (kk - 1) * (1 + c1) + 2 * (c1 + c2) + ncls * 8
 
 
-@pytest.mark.parametrize("coef,deg", [((0.0, 1.0, 0.0, 0.0), 3), ((0.3, -0.2, 0.7, 0.0), 3), ((0.3, -0.2, 0.7), 2)])
+@pytest.mark.parametrize("coef,deg", [((0.0, 1.0, 0.0, 0.0), 3), ((0.3, -0.2, 0.7, 0.0), 3), ((0.3, -0.2, 0.7), 2),
+                                      ((-0.3, 0.2, 0.05), 2)])
 def test_poly_act_special_cases(coef, deg):
     """(0, 1, 0, 0) is the identity up to noise; a zero cubic term reduces to the
-    quadratic, and the degree-2 form agrees with it."""
+    quadratic, and the degree-2 form agrees with it (its constant term is an integer
+    near 2^79, or a negative one near 2^82 for the last case)."""
     o = OracleCtx.from_set("t4_n12")
     n = o.N // 2
     s = o.keygen_secret(workloads.SEED_SECRET)
