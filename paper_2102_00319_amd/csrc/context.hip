@@ -274,8 +274,8 @@ extern "C" fhe_status fhe_ctx_create(const fhe_params *pp, void *hip_stream, uin
         for (uint32_t a = 0; a < t.nsrc; ++a) bc.push_back(1.0 / (double)c->mod[src[a]]);
         for (uint32_t d = 0; d < t.ndst; ++d) bc.push_back((double)c->mod[dst[d]]);
         for (uint32_t d = 0; d < t.ndst; ++d) bc.push_back(1.0 / (double)c->mod[dst[d]]);
-        for (uint32_t a = 0; a < t.nsrc; ++a)
-            for (uint32_t d = 0; d < t.ndst; ++d) {
+        for (uint32_t d = 0; d < t.ndst; ++d)
+            for (uint32_t a = 0; a < t.nsrc; ++a) {
                 uint64_t cm = c->mod[dst[d]], h = 1;
                 for (uint32_t o = 0; o < t.nsrc; ++o)
                     if (o != a) h = hmul(h, c->mod[src[o]] % cm, cm);

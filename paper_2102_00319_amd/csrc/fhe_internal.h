@@ -125,7 +125,7 @@ struct BconvTab {                 // one fast basis conversion S -> T
     uint32_t nsrc, ndst;
     uint32_t off;                 // offset into ctx->d_bconv (doubles)
     // layout at off: [nsrc] (B/b_i)^-1 mod b_i, [nsrc] b_i, [nsrc] 1/b_i, [ndst] c_t,
-    // [ndst] 1/c_t, then [nsrc][ndst] (B/b_i) mod c_t
+    // [ndst] 1/c_t, then [ndst][nsrc] (B/b_i) mod c_t (one target's constants adjacent)
     uint8_t src[FHE_MAXMOD], dst[FHE_MAXMOD];
 };
 

@@ -435,8 +435,9 @@ __global__ __launch_bounds__(WG) void k_row_inv(uint64_t *__restrict__ base, con
 //   y_t = sum_a v_a (B/b_a mod c_t) mod c_t,  v_a the prepared sources (FP64 bits of
 //   [x_a (B/b_a)^-1]_{b_a}, written by the inverse column pass), all nsrc of them
 //   loaded at once; SUB_HALF subtracts hdst[t] (the rounding shift of ModDown).
-//   Canonical targets out, for the forward column pass.
-template <bool SUB_HALF>
+//   Canonical targets out, for the forward column pass.  NS > 0: every job of the
+//   launch has NS sources (unguarded loops, one target's constants in one wide load).
+template <bool SUB_HALF, int NS>
 __global__ __launch_bounds__(TPB) void k_bconv(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
                                                const double *__restrict__ ctab, const BcJob *__restrict__ jobs,
                                                uint32_t y0, uint32_t logN, const double *__restrict__ hdst)
@@ -445,21 +446,23 @@ __global__ __launch_bounds__(TPB) void k_bconv(const uint64_t *__restrict__ src,
     const uint32_t k = blockIdx.x * TPB + threadIdx.x;
     if (k >= N) return;
     const BcJob jb = jobs[blockIdx.y + y0];
+    const uint32_t ns = NS > 0 ? (uint32_t)NS : jb.nsrc;
     const double *T = ctab + jb.off;
-    const double *dq = T + 3 * jb.nsrc, *dqi = T + 3 * jb.nsrc + jb.ndst, *qh = T + 3 * jb.nsrc + 2 * jb.ndst;
+    const double *dq = T + 3 * ns, *dqi = T + 3 * ns + jb.ndst, *qh = T + 3 * ns + 2 * jb.ndst;
     const uint64_t *S = src + (size_t)jb.src0 * N + k;
     uint64_t *D = dst + (size_t)jb.dst0 * N + k;
-    double v[16];
+    constexpr int NV = NS > 0 ? NS : 16;
+    double v[NV];
 #pragma unroll
-    for (int a = 0; a < 16; ++a)
-        if (a < (int)jb.nsrc) v[a] = bits_to_f64(S[(size_t)a * N]);
+    for (int a = 0; a < NV; ++a)
+        if (a < (int)ns) v[a] = bits_to_f64(S[(size_t)a * N]);
     for (uint32_t t = 0; t < jb.ndst; ++t) {
         const double q = dq[t], qi = dqi[t];
         double acc = 0.0;
 #pragma unroll
-        for (int a = 0; a < 16; ++a) {
-            if (a < (int)jb.nsrc) {
-                acc += mulmod(v[a], qh[(size_t)a * jb.ndst + t], q, qi);
+        for (int a = 0; a < NV; ++a) {
+            if (a < (int)ns) {
+                acc += mulmod(v[a], qh[(size_t)t * ns + a], q, qi);
                 if ((a & 3) == 3) acc = redc(acc, q, qi);
             }
         }
@@ -616,6 +619,7 @@ void in_pieces(uint32_t total, F f)
 // Host plan of one ragged batch.
 struct KsPlan {
     uint32_t n, sum_l, sum_dc, sum_nd, sum_ups, sum_inner, max_grp;
+    uint32_t up_ns, dn_ns;   // sources of every ModUp (ModDown) conversion job, 0 if they differ
     std::vector<KsItem> items;
     std::vector<BcJob> upjobs, dnjobs;
     std::vector<KsGrp> groups;
@@ -677,6 +681,14 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
         dc += l;
         up += u;
     }
+    auto common_ns = [](const std::vector<BcJob> &js) {
+        const uint32_t ns = js.empty() ? 0u : js[0].nsrc;
+        for (const BcJob &j : js)
+            if (j.nsrc != ns) return 0u;
+        return ns;
+    };
+    pl.up_ns = common_ns(pl.upjobs);
+    pl.dn_ns = common_ns(pl.dnjobs);
     // the ModUp digits' forward passes in modulus order (their row-pass twiddles are then
     // read once per modulus: 22% less HBM traffic for the row pass, at the same speed);
     // the ModDown finish keeps item order, which measured faster than modulus order
@@ -746,14 +758,24 @@ static void ks_row_inv(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t
         });
     });
 }
+// ns: the number of sources of every job, or 0 when they differ
 template <bool SUB_HALF>
 static void ks_bconv(fhe_ctx *c, const uint64_t *src, uint64_t *dst, const uint64_t *jobs, uint32_t njobs,
-                     const char *cat)
+                     uint32_t ns, const char *cat)
 {
     ProfScope ps(c, cat);
     in_pieces(njobs, [&](uint32_t y0, uint32_t cnt) {
-        hipLaunchKernelGGL(k_bconv<SUB_HALF>, dim3(blocks_for(c->N, TPB), cnt), dim3(TPB), 0, c->stream, src, dst,
-                           (const double *)c->d_bconv, (const BcJob *)jobs, y0, c->logN, (const double *)c->d_phalf);
+        const dim3 grid(blocks_for(c->N, TPB), cnt);
+#define BCONV_GO(NSV)                                                                                           \
+    hipLaunchKernelGGL((k_bconv<SUB_HALF, NSV>), grid, dim3(TPB), 0, c->stream, src, dst,                       \
+                       (const double *)c->d_bconv, (const BcJob *)jobs, y0, c->logN, (const double *)c->d_phalf)
+        switch (ns) {
+        case 2: BCONV_GO(2); break;
+        case 4: BCONV_GO(4); break;
+        case 8: BCONV_GO(8); break;
+        default: BCONV_GO(0); break;
+        }
+#undef BCONV_GO
     });
 }
 static void ks_col_fwd(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs)
@@ -860,7 +882,7 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     ks_col_inv<1>(c, dc, dwords + kt.la, pl.sum_dc, "ntt_inv_col");
     // 2-3. ModUp conversion, the forward column pass of the converted limbs, then
     //      their row pass (alone, or inside the inner product)
-    ks_bconv<false>(c, dc, up, dwords + kt.uj, pl.sum_nd, "bconv_up");
+    ks_bconv<false>(c, dc, up, dwords + kt.uj, pl.sum_nd, pl.up_ns, "bconv_up");
     ks_col_fwd(c, up, dwords + kt.um, pl.sum_ups);
     bool permuted = false;
     for (uint32_t b = 0; gal && b < n; ++b) permuted = permuted || gal[b] != 0;
@@ -896,7 +918,7 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     //      rounded conversion to Q_l, the forward column pass of z
     ks_row_inv(c, uP, dwords + kt.pl, n * 2 * K);
     ks_col_inv<2>(c, uP, dwords + kt.pl, n * 2 * K, "ntt_inv_col");
-    ks_bconv<true>(c, uP, z, dwords + kt.dj, 2 * n, "bconv_down");
+    ks_bconv<true>(c, uP, z, dwords + kt.dj, 2 * n, pl.dn_ns, "bconv_down");
     ks_col_fwd(c, z, dwords + kt.fl, sum2l);
     // 7. row pass of z fused with the finish
     {
