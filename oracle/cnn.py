@@ -330,7 +330,7 @@ def enc_sum_pool2x2_slot(o, xs, C, H, W, cnt):
 
 
 def enc_paper_cnn(o, rlk, X, Wc, Wf, C, K, H, W, n_classes, cnt, coef=G_PAPER):
-    """The paper's network on the oracle: conv, g/4 on every output (depth 2), sum
+    """The paper's network on the oracle: conv, g/4 on every output (depth 1), sum
     pooling (= the mean of g), drop to two limbs, FC; returns (stages, scores)."""
     Ho, Wo = H - K + 1, W - K + 1
     Y = enc_conv2d_slot(o, rlk, X, H, W, 1, Wc, C, K, K, 1, 0, 0, Ho, Wo, cnt)
