@@ -8,7 +8,7 @@ import pytest
 import workloads
 from oracle import OracleCtx, cnn
 from oracle.ckks import Ct
-from test_packed_oracle import COEF, FH, FW, H, K, W, _setup, run_packed_oracle
+from test_packed_oracle import COEF, FH, FW, G_PAPER, H, K, W, _setup, run_packed_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -26,17 +26,20 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def test_small_packed_network_bit_exact():
+@pytest.mark.parametrize("coef,deg", [(COEF, 3), (G_PAPER, 2)])
+def test_small_packed_network_bit_exact(coef, deg):
     """N = 2^12, 8 images of 12 x 12 in 16 x 16 frames: every stage's ciphertexts
-    equal the oracle's, operation counts match, scores within 1e-3 of FP64."""
+    equal the oracle's, operation counts match, scores within 1e-3 of FP64; with the
+    cubic activation and with the paper's quadratic g (depth 1, weights two levels higher)."""
     P, networks = _P()
     g, o = P.Context.from_set("t4_n12"), OracleCtx.from_set("t4_n12")
     c1, c2, ncls = 2, 3, 2
     B, imgs, w1, w2, wfc, s, pk_o = _setup(o, c1, c2, ncls)
     cnt = cnn.Counter()
-    Zo, st, (Xo, W1o, W2o, Wfo) = run_packed_oracle(o, imgs, w1, w2, wfc, s, pk_o, COEF, 3, cnt)
-    _say("oracle network done")
-    net = networks.PackedCNN(H=H, W=W, frame_h=FH, frame_w=FW, k=K, c1=c1, c2=c2, n_classes=ncls, coef=COEF)
+    Zo, st, (Xo, W1o, W2o, Wfo) = run_packed_oracle(o, imgs, w1, w2, wfc, s, pk_o, coef, deg, cnt)
+    _say("oracle network done (deg %d)" % deg)
+    net = networks.PackedCNN(H=H, W=W, frame_h=FH, frame_w=FW, k=K, c1=c1, c2=c2, n_classes=ncls, coef=coef,
+                             deg=deg)
     sg = g.keygen_secret(workloads.SEED_SECRET)
     assert np.array_equal(sg.astype(np.int64), s)
     pk = g.keygen_pk(sg, workloads.SEED_PK)
@@ -47,10 +50,10 @@ def test_small_packed_network_bit_exact():
         assert np.array_equal(g.export_ct(a), b.data)
     g.op_counts()
     Y = g.conv2d_packed(rlk, gks, X, W1, c1, K, 1, FW)
-    A = g.poly_act(rlk, Y, COEF, 3)
+    A = g.poly_act(rlk, Y, coef, deg)
     Pl = g.avgpool2x2(gks, A, 1, FW, net.pool_mask(g, 1, A[0].limbs))
     Y2 = g.conv2d_packed(rlk, gks, Pl, W2, c2, K, 2, FW)
-    A2 = g.poly_act(rlk, Y2, COEF, 3)
+    A2 = g.poly_act(rlk, Y2, coef, deg)
     P2 = g.avgpool2x2(gks, A2, 2, FW, net.pool_mask(g, 2, A2[0].limbs))
     Z = g.fc_packed(rlk, gks, P2, Wf, ncls, FH * FW)
     ops = g.op_counts()
@@ -62,7 +65,7 @@ def test_small_packed_network_bit_exact():
     assert (ops["ct_mult"], ops["relin"], ops["rotate"], ops["rescale"], ops["pt_mult"], ops["pt_add"],
             ops["ct_add"]) == (cnt.ct_mult, cnt.relin, cnt.rotate, cnt.rescale, cnt.pt_mult, cnt.pt_add, cnt.ct_add)
     assert (ops["ct_mult"], ops["relin"], ops["rotate"]) == net.op_counts()
-    ref = cnn.packed_cnn_fp64(imgs, w1, w2, wfc, COEF)
+    ref = cnn.packed_cnn_fp64(imgs, w1, w2, wfc, coef)
     got = net.decrypt_scores(g, sg, Z, B)
     assert np.abs(got - ref).max() < 1e-3
     # the composed forward pass, and the one-ciphertext-per-call form, give the same ciphertexts

@@ -13,6 +13,7 @@ FH = FW = 16
 H = W = 12
 K = 3
 COEF = (0.47, 0.5, 0.09, -0.005)
+G_PAPER = (0.47, 0.50, 0.09)   # g of Eq. (approxReLU)
 
 
 def test_fp64_blocks_against_library_routines():
@@ -62,16 +63,17 @@ def run_packed_oracle(o, imgs, w1, w2, wfc, s, pk, coef, deg, cnt):
     steps = cnn.packed_rotation_steps(K, FW, FH * FW)
     gks = {r: o.keygen_rot(s, r, workloads.SEED_EVK + 1 + i) for i, r in enumerate(steps)}
     L = o.L
+    d = (2 if deg == 3 else 1) + 2   # levels of one conv, activation and pool
     X = [o.encrypt(pk, o.encode_rns(cnn.frame_pack(imgs, FH, FW), D, L), workloads.SEED_ENC, D)]
     W1 = [cnn.encrypt_const(o, pk, v, D, L, workloads.SEED_ENC + 100000 + t) for t, v in enumerate(w1.ravel())]
-    W2 = [cnn.encrypt_const(o, pk, v, D, L - 4, workloads.SEED_ENC + 200000 + t) for t, v in enumerate(w2.ravel())]
+    W2 = [cnn.encrypt_const(o, pk, v, D, L - d, workloads.SEED_ENC + 200000 + t) for t, v in enumerate(w2.ravel())]
     hp = H // 4
     Wf = []
     for r in range(ncls):
         rows = wfc[r].reshape(c2, hp * hp)
         for c in range(c2):
             v = cnn.fc_weight_slots(rows[c], hp, hp, FH, FW, B, 4)
-            Wf.append(o.encrypt(pk, o.encode_rns(v, D, L - 8), workloads.SEED_ENC + 300000 + r * c2 + c, D))
+            Wf.append(o.encrypt(pk, o.encode_rns(v, D, L - 2 * d), workloads.SEED_ENC + 300000 + r * c2 + c, D))
     stages = {}
     Y = cnn.enc_conv2d_packed(o, rlk, gks, X, 1, W1, c1, K, 1, FW, cnt)
     A = cnn.enc_poly_act(o, rlk, Y, coef, deg, cnt)
@@ -90,24 +92,27 @@ def run_packed_oracle(o, imgs, w1, w2, wfc, s, pk, coef, deg, cnt):
     return Z, stages, (X, W1, W2, Wf)
 
 
-def test_packed_network_logits_and_counts():
+@pytest.mark.parametrize("coef,deg", [(COEF, 3), (G_PAPER, 2)])
+def test_packed_network_logits_and_counts(coef, deg):
     """Small within-image network (N = 2^12, 8 images of 12 x 12 in 16 x 16 frames,
     2 and 3 channels, 2 classes, 11 limbs at scale 2^49): decrypted scores equal the
-    FP64 network to 1e-3, and the operation counts follow the recipe."""
+    FP64 network to 1e-3, and the operation counts follow the recipe; with the
+    paper's quadratic g each activation takes one level instead of two."""
     o = OracleCtx.from_set("t4_n12")
     c1, c2, ncls = 2, 3, 2
     B, imgs, w1, w2, wfc, s, pk = _setup(o, c1, c2, ncls)
     cnt = cnn.Counter()
-    Z, _, _ = run_packed_oracle(o, imgs, w1, w2, wfc, s, pk, COEF, 3, cnt)
-    assert Z[0].level == o.L - 9
-    ref = cnn.packed_cnn_fp64(imgs, w1, w2, wfc, COEF)
+    Z, _, _ = run_packed_oracle(o, imgs, w1, w2, wfc, s, pk, coef, deg, cnt)
+    assert Z[0].level == o.L - (9 if deg == 3 else 7)
+    ref = cnn.packed_cnn_fp64(imgs, w1, w2, wfc, coef)
     F = FH * FW
     for r in range(ncls):
         re, _ = o.decode(o.decrypt(Z[r], s), Z[r].scale)
         assert np.abs(re[np.arange(B) * F] - ref[:, r]).max() < 1e-3
     kk = K * K
-    assert cnt.ct_mult == c1 * kk + c2 * c1 * kk + 2 * (c1 + c2) + ncls * c2
-    assert cnt.relin == c1 + c2 + 2 * (c1 + c2) + ncls
+    act = 2 if deg == 3 else 1
+    assert cnt.ct_mult == c1 * kk + c2 * c1 * kk + act * (c1 + c2) + ncls * c2
+    assert cnt.relin == c1 + c2 + act * (c1 + c2) + ncls
     assert cnt.rotate == (kk - 1) * (1 + c1) + 2 * (c1 + c2) + ncls * 8
 
 
