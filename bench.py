@@ -98,6 +98,8 @@ def parse():
                          "level) per step")
     ap.add_argument("--fc1", type=int, default=100, help="cnn2: FC1 width (100 = the full network)")
     ap.add_argument("--unbatched", action="store_true", help="cnn2 / cnn4: also time the one-ciphertext-per-call form")
+    ap.add_argument("--act", choices=("cubic", "g"), default="cubic",
+                    help="cnn4: activation, the cubic (depth 2) or the paper's quadratic g (depth 1)")
     ap.add_argument("--graph-streams", type=int, default=2,
                     help="cnn4: also replay this many graphed forward passes at once, each on its own "
                          "context and stream (0: skip)")
@@ -196,8 +198,10 @@ def _slot_cnn_fp64(imgs, cw, f1, f2):
 
 
 def _packed_cnn_fp64(imgs, w1, w2, wfc, coef):
+    c = tuple(coef) + (0.0,) * (4 - len(coef))   # a quadratic has no cubic term
+
     def act(x):
-        return coef[0] + coef[1] * x + coef[2] * x * x + coef[3] * x * x * x
+        return c[0] + c[1] * x + c[2] * x * x + c[3] * x * x * x
 
     def pool(x):
         B, C, H, W = x.shape
@@ -223,7 +227,7 @@ def cnn4(args):
     torch.cuda.set_device(0)
     g = P.Context.from_set("c4_n16", stream=torch.cuda.Stream())   # a stream of its own: graphs capture it
     g.set_tuning("row_wg", args.row_wg)
-    net = networks.PackedCNN()
+    net = networks.PackedCNN() if args.act == "cubic" else networks.PackedCNN(coef=(0.47, 0.50, 0.09), deg=2)
     B = net.images_per_ct(g)
     imgs = workloads.images(workloads.SEED_DATA, B, 28, 28)
     w1 = workloads.weights(workloads.SEED_DATA + 1, (8, 1, 3, 3))
@@ -301,8 +305,9 @@ def cnn4(args):
            "kernel_ms_per_batch": breakdown,
            "graph_images_per_s": round(B / dg, 1), "graph_ms_per_batch": round(dg * 1e3, 3),
            "graph_equals_eager_bitwise": bool(graph_same), "graph_concurrent": conc,
-           "config": {"workload": "conv3x3x8 -> cubic -> avgpool -> conv3x3x16 -> cubic -> avgpool -> FC784x10, "
-                                  "32 images of 28x28 per ciphertext, N=2^16, 24 limbs, dnum 3"}}
+           "config": {"workload": "conv3x3x8 -> {a} -> avgpool -> conv3x3x16 -> {a} -> avgpool -> FC784x10, "
+                                  "32 images of 28x28 per ciphertext, N=2^16, 24 limbs, dnum 3".format(
+                                      a="cubic" if args.act == "cubic" else "g (quadratic, depth 1)")}}
     if args.unbatched:   # one ciphertext per library call
         ou = net.forward_per_op(g, rlk, gks, X, Wt)
         same = all(np.array_equal(g.export_ct(a), g.export_ct(b)) for a, b in zip(ou, out))
