@@ -72,3 +72,43 @@ def test_paper_network_on_oracle():
         assert np.abs(re - ref[:, r]).max() < 1e-3
     assert cnt.ct_mult == 2 * 4 * 4 * 9 + 2 * 4 * 4 + 8 * 2
     assert cnt.relin == 2 * 16 + 2 * 16 + 2   # conv outputs, one product each in g, FC outputs
+
+
+def test_slot_cnn_on_oracle():
+    """The slot CNN's recipe (conv with stride 2 and padding 1 on top and left,
+    padded taps skipped; x^2; FC; x^2; FC) shrunk to N = 2^12 with 6x6 images, two
+    filters, FC 18 -> 3 -> 2: scores within 1e-3 of the FP64 network, and the
+    operation counts of the recipe (one product per in-bounds tap and input,
+    one relinearisation and one rescale per output)."""
+    o = OracleCtx.from_set("t_n12")
+    D, B = o.scale, o.N // 2
+    H = W = 6
+    C, K, S = 2, 3, 2
+    Ho = Wo = (H + 1 - K) // S + 1
+    imgs = workloads.images(workloads.SEED_DATA, B, H, W)
+    wc = workloads.weights(workloads.SEED_DATA + 1, (C, 1, K, K))
+    f1 = workloads.weights(workloads.SEED_DATA + 2, (3, C * Ho * Wo))
+    f2 = workloads.weights(workloads.SEED_DATA + 3, (2, 3))
+    s = o.keygen_secret(workloads.SEED_SECRET)
+    pk = o.keygen_pk(s, workloads.SEED_PK)
+    rlk = o.keygen_relin(s, workloads.SEED_EVK)
+    L = o.L
+    X = [o.encrypt(pk, o.encode_rns(imgs[:, y, x], D, L), workloads.SEED_ENC + y * W + x, D)
+         for y in range(H) for x in range(W)]
+    Wc = [cnn.encrypt_const(o, pk, v, D, L, workloads.SEED_ENC + 100 + t) for t, v in enumerate(wc.ravel())]
+    W1 = [cnn.encrypt_const(o, pk, v, D, L - 2, workloads.SEED_ENC + 200 + t) for t, v in enumerate(f1.ravel())]
+    W2 = [cnn.encrypt_const(o, pk, v, D, L - 4, workloads.SEED_ENC + 300 + t) for t, v in enumerate(f2.ravel())]
+    cnt = cnn.Counter()
+    Y = cnn.enc_conv2d_slot(o, rlk, X, H, W, 1, Wc, C, K, K, S, 1, 1, Ho, Wo, cnt)
+    A = cnn.enc_square(o, rlk, Y, cnt)
+    Z = cnn.enc_fc_slot(o, rlk, A, W1, 3, cnt)
+    A2 = cnn.enc_square(o, rlk, Z, cnt)
+    out = cnn.enc_fc_slot(o, rlk, A2, W2, 2, cnt)
+    ref = cnn.slot_cnn_fp64(imgs, wc, f1, f2, S, 1, 1, Ho, Wo)
+    for r in range(2):
+        assert out[r].level == L - 5
+        re, _ = o.decode(o.decrypt(out[r], s), out[r].scale, n=B)
+        assert np.abs(re - ref[:, r]).max() < 1e-3
+    taps = cnn.conv_op_count(H, W, K, K, S, 1, 1, Ho, Wo, 1, C)
+    assert cnt.ct_mult == taps + C * Ho * Wo + 3 * C * Ho * Wo + 3 + 2 * 3
+    assert cnt.relin == cnt.rescale == C * Ho * Wo * 2 + 3 * 2 + 2
