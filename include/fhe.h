@@ -38,11 +38,18 @@ typedef int32_t fhe_status;
 #define FHE_OK 0
 #define FHE_EINVAL (-1)   /* null pointer, shape or size mismatch */
 #define FHE_ELEVEL (-2)   /* limb-count mismatch, or rescale at one limb */
-#define FHE_ESCALE (-3)   /* add of operands whose scales differ by more than 2^-20 relative */
+#define FHE_ESCALE (-3)   /* add of operands whose scales differ by more than 2^-40 relative, or a layer
+                             output whose scale leaves fewer than FHE_SCALE_ROOM_BITS bits below Q/2 */
 #define FHE_ENOKEY (-4)   /* evaluation key does not match the requested rotation */
 #define FHE_EPARAM (-5)   /* invalid parameter set */
 #define FHE_ENOMEM (-6)   /* the context's HBM budget would be exceeded */
 #define FHE_EDEVICE (-7)  /* HIP runtime error */
+
+/* Layer entry points (convolution, activation, fully connected) refuse outputs whose
+ * scale S at l limbs has log2(S) > log2(q_0 ... q_(l-1)) - 1 - FHE_SCALE_ROOM_BITS:
+ * slot values up to 2^(FHE_SCALE_ROOM_BITS - 1) in magnitude must decrypt without
+ * wrapping around the modulus. */
+#define FHE_SCALE_ROOM_BITS 4
 
 /* Parameter set (all arrays host memory, copied by fhe_ctx_create).
  * Requirements: 10 <= log_n <= 16; every prime is distinct, below 2^50 and

@@ -16,22 +16,20 @@ from . import ckks
 
 # ------------------------------------------------------------ FP64 network
 def conv2d_fp64(x, w, stride, pad_t, pad_l, Ho, Wo):
-    """x: [B][Cin][H][W], w: [Cout][Cin][kh][kw] -> [B][Cout][Ho][Wo] (zero padding)."""
+    """x: [B][Cin][H][W], w: [Cout][Cin][kh][kw] -> [B][Cout][Ho][Wo] (zero padding).
+    out[b, co, i, j] = sum over (ci, p, q) of x[b, ci, i*stride + p - pad_t, j*stride + q - pad_l]
+    * w[co, ci, p, q], taps outside the image counting as zero: the windows of a
+    zero-padded copy of x, contracted with the weights by one matrix product."""
     B, Cin, H, W = x.shape
     Cout, _, kh, kw = w.shape
-    out = np.zeros((B, Cout, Ho, Wo))
-    for co in range(Cout):
-        for i in range(Ho):
-            for j in range(Wo):
-                acc = np.zeros(B)
-                for ci in range(Cin):
-                    for p in range(kh):
-                        for q in range(kw):
-                            y, xx = i * stride + p - pad_t, j * stride + q - pad_l
-                            if 0 <= y < H and 0 <= xx < W:
-                                acc += x[:, ci, y, xx] * w[co, ci, p, q]
-                out[:, co, i, j] = acc
-    return out
+    pb = max(0, (Ho - 1) * stride + kh - pad_t - H)
+    pr = max(0, (Wo - 1) * stride + kw - pad_l - W)
+    xp = np.zeros((B, Cin, pad_t + H + pb, pad_l + W + pr))
+    xp[:, :, pad_t:pad_t + H, pad_l:pad_l + W] = x
+    win = np.lib.stride_tricks.sliding_window_view(xp, (kh, kw), axis=(2, 3))   # [B][Cin][y][x][p][q]
+    win = win[:, :, :(Ho - 1) * stride + 1:stride, :(Wo - 1) * stride + 1:stride]
+    out = np.tensordot(win, w, axes=([1, 4, 5], [1, 2, 3]))                     # [B][Ho][Wo][Cout]
+    return np.ascontiguousarray(out.transpose(0, 3, 1, 2))
 
 
 def slot_cnn_fp64(images, conv_w, fc1_w, fc2_w, stride, pad_t, pad_l, Ho, Wo):
@@ -303,15 +301,18 @@ def packed_rotation_steps(k, frame_w, frame_slots, n_pools=2):
 G_PAPER = (0.47, 0.50, 0.09)   # Eq. (approxReLU)
 
 
-def paper_cnn_fp64(images, wc, wfc, coef=G_PAPER):
-    """conv KxK stride 1 no padding -> g -> 2x2 mean (Eq. (ActPool)) -> flatten (c, y, x) -> FC."""
+def paper_cnn_fp64(images, wc, wfc, coef=G_PAPER, chunk=512):
+    """conv KxK stride 1 no padding -> g -> 2x2 mean (Eq. (ActPool)) -> flatten (c, y, x) -> FC.
+    Images are independent; they go through in chunks so that the intermediates stay small."""
     x = images[:, None] if images.ndim == 3 else images
     K = wc.shape[2]
     H, W = x.shape[2], x.shape[3]
-    y = conv2d_fp64(x, wc, 1, 0, 0, H - K + 1, W - K + 1)
-    a = poly_fp64(y, coef)
-    p = avgpool2_fp64(a)
-    return p.reshape(p.shape[0], -1) @ wfc.T
+    out = np.empty((x.shape[0], wfc.shape[0]))
+    for b0 in range(0, x.shape[0], chunk):
+        y = conv2d_fp64(x[b0:b0 + chunk], wc, 1, 0, 0, H - K + 1, W - K + 1)
+        p = avgpool2_fp64(poly_fp64(y, coef))
+        out[b0:b0 + chunk] = p.reshape(p.shape[0], -1) @ wfc.T
+    return out
 
 
 def enc_sum_pool2x2_slot(o, xs, C, H, W, cnt):

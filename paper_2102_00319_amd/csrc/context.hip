@@ -85,6 +85,11 @@ fhe_status fhe_fail(fhe_status code, const std::string &msg)
     g_err = msg;
     return code;
 }
+fhe_status scale_room_error(const char *what)
+{
+    return fhe_fail(FHE_ESCALE, std::string(what) + ": the output scale leaves fewer than " +
+                                    std::to_string(FHE_SCALE_ROOM_BITS) + " bits below Q/2 (lower an input scale)");
+}
 fhe_status fhe_hip_check(hipError_t e, const char *what)
 {
     g_err = std::string(what) + ": " + hipGetErrorString(e);

@@ -12,6 +12,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <cmath>
 #include <string>
 #include <deque>
 #include <vector>
@@ -192,6 +193,20 @@ fhe_status fhe_hip_check(hipError_t e, const char *what);
         hipError_t _e = (x);                                                       \
         if (_e != hipSuccess) return fhe_hip_check(_e, #x);                        \
     } while (0)
+
+// Scales of operands that are added must agree to 2^-40 relative (doubles carry
+// 53 bits; scales computed along different branches differ by a few ulps).
+inline bool scales_match(double a, double b) { return std::fabs(a / b - 1.0) <= 0x1p-40; }
+// A layer output at `limbs` limbs and scale `scale` must leave FHE_SCALE_ROOM_BITS bits
+// between the scale and Q_limbs / 2, so that slot values of magnitude below
+// 2^(FHE_SCALE_ROOM_BITS - 1) decrypt without wrapping around the modulus.
+inline bool scale_has_room(const fhe_ctx *c, uint32_t limbs, double scale)
+{
+    double lq = 0.0;
+    for (uint32_t i = 0; i < limbs; ++i) lq += std::log2((double)c->mod[i]);
+    return std::log2(scale) <= lq - 1.0 - FHE_SCALE_ROOM_BITS;
+}
+fhe_status scale_room_error(const char *what);
 
 // scratch / pointer tables
 fhe_status ctx_scratch(fhe_ctx *c, size_t bytes, uint8_t **out);

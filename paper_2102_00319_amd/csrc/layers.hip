@@ -390,7 +390,6 @@ static fhe_status chk_in(const fhe_ct *x, uint32_t l, const char *what)
         return fhe_fail(FHE_EINVAL, std::string(what) + ": every input must be a 2-poly ciphertext at the same level");
     return FHE_OK;
 }
-static bool same_scale(double a, double b) { return std::fabs(a / b - 1.0) <= 9.5367431640625e-07; }
 
 extern "C" {
 
@@ -477,11 +476,11 @@ fhe_status fhe_conv2d_slot(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *X, uint
     const double sx = X[0].scale, sw = Wt[0].scale;
     for (uint32_t i = 0; i < H * W * Cin; ++i) {
         if ((s = chk_in(&X[i], l, "fhe_conv2d_slot"))) return s;
-        if (!same_scale(X[i].scale, sx)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_slot: input scales differ");
+        if (!scales_match(X[i].scale, sx)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_slot: input scales differ");
     }
     for (uint32_t i = 0; i < Cout * Cin * kh * kw; ++i) {
         if ((s = chk_in(&Wt[i], l, "fhe_conv2d_slot"))) return s;
-        if (!same_scale(Wt[i].scale, sw)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_slot: weight scales differ");
+        if (!scales_match(Wt[i].scale, sw)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_slot: weight scales differ");
     }
     std::vector<uint64_t *> A, B, Yp;
     std::vector<uint32_t> off{0};
@@ -503,8 +502,9 @@ fhe_status fhe_conv2d_slot(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *X, uint
                     return fhe_fail(FHE_EINVAL, "fhe_conv2d_slot: outputs must be 2 x (l-1)");
                 Yp.push_back(y.d);
             }
-    if ((s = mac_relin_rescale(c, rlk, l, A, B, off, Yp))) return s;
     const double so = sx * sw / (double)c->mod[l - 1];
+    if (!scale_has_room(c, l - 1, so)) return scale_room_error("fhe_conv2d_slot");
+    if ((s = mac_relin_rescale(c, rlk, l, A, B, off, Yp))) return s;
     for (uint32_t o = 0; o < Cout * Ho * Wo; ++o) Y[o].scale = so;
     return FHE_OK;
 }
@@ -518,7 +518,7 @@ fhe_status fhe_fc_slot(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_t
     const uint32_t l = x[0].limbs;
     for (uint32_t i = 0; i < n_in; ++i) {
         if ((s = chk_in(&x[i], l, "fhe_fc_slot"))) return s;
-        if (!same_scale(x[i].scale, x[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_slot: input scales differ");
+        if (!scales_match(x[i].scale, x[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_slot: input scales differ");
     }
     std::vector<uint64_t *> A, B, Yp;
     std::vector<uint32_t> off{0};
@@ -526,7 +526,7 @@ fhe_status fhe_fc_slot(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_t
         for (uint32_t i = 0; i < n_in; ++i) {
             const fhe_ct &w = Wt[(size_t)o * n_in + i];
             if ((s = chk_in(&w, l, "fhe_fc_slot"))) return s;
-            if (!same_scale(w.scale, Wt[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_slot: weight scales differ");
+            if (!scales_match(w.scale, Wt[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_slot: weight scales differ");
             A.push_back(x[i].d);
             B.push_back(w.d);
         }
@@ -534,8 +534,9 @@ fhe_status fhe_fc_slot(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_t
         if (!y[o].d || y[o].polys != 2 || y[o].limbs != l - 1) return fhe_fail(FHE_EINVAL, "fhe_fc_slot: bad output");
         Yp.push_back(y[o].d);
     }
-    if ((s = mac_relin_rescale(c, rlk, l, A, B, off, Yp))) return s;
     const double so = x[0].scale * Wt[0].scale / (double)c->mod[l - 1];
+    if (!scale_has_room(c, l - 1, so)) return scale_room_error("fhe_fc_slot");
+    if ((s = mac_relin_rescale(c, rlk, l, A, B, off, Yp))) return s;
     for (uint32_t o = 0; o < n_out; ++o) y[o].scale = so;
     return FHE_OK;
 }
@@ -550,6 +551,8 @@ fhe_status fhe_square_act(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint3
     std::vector<uint32_t> off{0};
     for (uint32_t i = 0; i < n; ++i) {
         if ((s = chk_in(&x[i], l, "fhe_square_act"))) return s;
+        if (!scale_has_room(c, l - 1, x[i].scale * x[i].scale / (double)c->mod[l - 1]))
+            return scale_room_error("fhe_square_act");
         if (!y[i].d || y[i].polys != 2 || y[i].limbs != l - 1) return fhe_fail(FHE_EINVAL, "fhe_square_act: bad output");
         A.push_back(x[i].d);
         B.push_back(x[i].d);
@@ -568,7 +571,7 @@ fhe_status fhe_pool2x2_sum_slot(fhe_ctx *c, const fhe_ct *x, uint32_t C, uint32_
     const uint32_t l = x[0].limbs, Hp = H / 2, Wp = W / 2, n = C * Hp * Wp;
     for (uint32_t i = 0; i < C * H * W; ++i) {
         if ((s = chk_in(&x[i], l, "fhe_pool2x2_sum_slot"))) return s;
-        if (!same_scale(x[i].scale, x[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_pool2x2_sum_slot: scales differ");
+        if (!scales_match(x[i].scale, x[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_pool2x2_sum_slot: scales differ");
     }
     std::vector<const uint64_t *> a(n), b(n), cc(n), d(n), yc(n);
     std::vector<uint64_t *> yo(n);

@@ -109,7 +109,6 @@ static fhe_status chk_ct(const fhe_ctx *c, const fhe_ct *a, const char *what)
     if (a->polys < 2 || a->polys > 3) return fhe_fail(FHE_EINVAL, std::string(what) + ": polys must be 2 or 3");
     return FHE_OK;
 }
-static bool scales_match(double a, double b) { return std::fabs(a / b - 1.0) <= 9.5367431640625e-07; }   // 2^-20
 
 
 // ========================================================= C entry points

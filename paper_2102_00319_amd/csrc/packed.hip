@@ -38,7 +38,6 @@ fhe_status chk2(const fhe_ct *x, uint32_t l, const char *what)
         return fhe_fail(FHE_EINVAL, std::string(what) + ": ciphertexts must be 2 x limbs at the expected level");
     return FHE_OK;
 }
-bool same_scale(double a, double b) { return std::fabs(a / b - 1.0) <= 9.5367431640625e-07; }
 
 fhe_status rescale_many(fhe_ctx *c, uint32_t l, uint32_t n, const std::vector<const uint64_t *> &in,
                         const std::vector<uint64_t *> &out)
@@ -189,18 +188,15 @@ fhe_status plain_mac_rescale(fhe_ctx *c, uint32_t l, const std::vector<uint64_t 
 // Quadratic activation at depth 1 (the paper's count for g): T = Relin(x (x) x) is read
 // as c2 x^2 at scale S' = S*S/c2, so c2 costs no level; c1 x joins as the integer
 // multiple round(c1 S / c2) of x, c0 as round(c0 S'), and one rescale ends it.
+static size_t poly_act2_item_bytes(const fhe_ctx *c, uint32_t l)
+{
+    return 7 * (size_t)l * c->N * sizeof(uint64_t) + ks_scratch_bytes(c, l, 1) + rescale_scratch_bytes(c, l, 2, 1);
+}
 static fhe_status poly_act2(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_t n, const double *coef, fhe_ct *y)
 {
     fhe_status s;
     const uint32_t l = x[0].limbs;
-    if (l < 2) return fhe_fail(FHE_ELEVEL, "fhe_poly_act: degree 2 needs two limbs (depth 1)");
-    if (!(coef[2] > 0.0))   // it becomes a factor of the output scale
-        return fhe_fail(FHE_EINVAL, "fhe_poly_act: degree 2 needs a positive quadratic coefficient");
     const double S = x[0].scale;
-    for (uint32_t i = 0; i < n; ++i) {
-        if ((s = chk2(&x[i], l, "fhe_poly_act")) || (s = chk2(&y[i], l - 1, "fhe_poly_act"))) return s;
-        if (x[i].scale != S) return fhe_fail(FHE_ESCALE, "fhe_poly_act: input scales differ");
-    }
     const size_t N = c->N, w3 = 3 * (size_t)l * N, w2 = 2 * (size_t)l * N;
     // workspace: T3 [n][3][l], U [n][2][l], B [n][2][l]
     uint8_t *ws;
@@ -257,14 +253,16 @@ fhe_status fhe_conv2d_packed(fhe_ctx *c, const fhe_evk *rlk, const fhe_evk *keys
     if (l < 2) return fhe_fail(FHE_ELEVEL, "fhe_conv2d_packed: inputs need two limbs");
     for (uint32_t i = 0; i < Cin; ++i) {
         if ((s = chk2(&X[i], l, "fhe_conv2d_packed"))) return s;
-        if (!same_scale(X[i].scale, X[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_packed: input scales differ");
+        if (!scales_match(X[i].scale, X[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_packed: input scales differ");
     }
     for (uint32_t i = 0; i < Cout * Cin * kk; ++i) {
         if ((s = chk2(&Wt[i], l, "fhe_conv2d_packed"))) return s;
-        if (!same_scale(Wt[i].scale, Wt[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_packed: weight scales differ");
+        if (!scales_match(Wt[i].scale, Wt[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_packed: weight scales differ");
     }
     for (uint32_t o = 0; o < Cout; ++o)
         if ((s = chk2(&Y[o], l - 1, "fhe_conv2d_packed"))) return s;
+    if (!scale_has_room(c, l - 1, X[0].scale * Wt[0].scale / (double)c->mod[l - 1]))
+        return scale_room_error("fhe_conv2d_packed");
     // rotation step of tap t = (p, q), row-major
     const int64_t half = k / 2;
     std::vector<int64_t> step(kk);
@@ -316,21 +314,20 @@ fhe_status fhe_conv2d_packed(fhe_ctx *c, const fhe_evk *rlk, const fhe_evk *keys
     return FHE_OK;
 }
 
-fhe_status fhe_poly_act(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_t n, const double *coef, uint32_t deg,
-                        fhe_ct *y)
+}  // extern "C"
+
+static size_t poly_act3_item_bytes(const fhe_ctx *c, uint32_t l)
+{
+    // workspace T, U, A, Bq; the products inside bound their own scratch
+    return (2 * (size_t)l + 4 * ((size_t)l - 1) + 2 * ((size_t)l - 2)) * c->N * sizeof(uint64_t) +
+           rescale_scratch_bytes(c, l, 2, 1);
+}
+static fhe_status poly_act3(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_t n, const double *coef,
+                            uint32_t deg, fhe_ct *y)
 {
     fhe_status s;
-    if (!c || !rlk || !rlk->d || !x || !y || !coef || !n) return fhe_fail(FHE_EINVAL, "fhe_poly_act: null or empty");
-    if (rlk->galois != 0) return fhe_fail(FHE_ENOKEY, "fhe_poly_act: needs the relinearisation key");
-    if (deg != 2 && deg != 3) return fhe_fail(FHE_EINVAL, "fhe_poly_act: degree must be 2 or 3");
-    if (deg == 2) return poly_act2(c, rlk, x, n, coef, y);
     const uint32_t l = x[0].limbs;
-    if (l < 3) return fhe_fail(FHE_ELEVEL, "fhe_poly_act: inputs need three limbs (depth 2)");
     const double S = x[0].scale;
-    for (uint32_t i = 0; i < n; ++i) {
-        if ((s = chk2(&x[i], l, "fhe_poly_act")) || (s = chk2(&y[i], l - 2, "fhe_poly_act"))) return s;
-        if (x[i].scale != S) return fhe_fail(FHE_ESCALE, "fhe_poly_act: input scales differ");
-    }
     const size_t N = c->N, w1 = 2 * (size_t)(l - 1) * N, w2 = 2 * (size_t)(l - 2) * N;
     // workspace: T [n][2][l], U [n][2][l-1], A [n][2][l-1], Bq [n][2][l-2]
     uint8_t *ws;
@@ -402,6 +399,42 @@ fhe_status fhe_poly_act(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_
     return FHE_OK;
 }
 
+extern "C" {
+
+// Every input is validated first; the items then go through in chunks whose layer
+// workspace and scratch stay near 2 GiB, so the memory a call takes does not grow
+// with the number of ciphertexts.
+fhe_status fhe_poly_act(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_t n, const double *coef, uint32_t deg,
+                        fhe_ct *y)
+{
+    fhe_status s;
+    if (!c || !rlk || !rlk->d || !x || !y || !coef || !n) return fhe_fail(FHE_EINVAL, "fhe_poly_act: null or empty");
+    if (rlk->galois != 0) return fhe_fail(FHE_ENOKEY, "fhe_poly_act: needs the relinearisation key");
+    if (deg != 2 && deg != 3) return fhe_fail(FHE_EINVAL, "fhe_poly_act: degree must be 2 or 3");
+    const uint32_t l = x[0].limbs, depth = deg == 2 ? 1 : 2;
+    if (l < depth + 1)
+        return fhe_fail(FHE_ELEVEL, deg == 2 ? "fhe_poly_act: degree 2 needs two limbs (depth 1)"
+                                             : "fhe_poly_act: inputs need three limbs (depth 2)");
+    if (deg == 2 && !(coef[2] > 0.0))   // it becomes a factor of the output scale
+        return fhe_fail(FHE_EINVAL, "fhe_poly_act: degree 2 needs a positive quadratic coefficient");
+    const double S = x[0].scale;
+    for (uint32_t i = 0; i < n; ++i) {
+        if ((s = chk2(&x[i], l, "fhe_poly_act")) || (s = chk2(&y[i], l - depth, "fhe_poly_act"))) return s;
+        if (x[i].scale != S) return fhe_fail(FHE_ESCALE, "fhe_poly_act: input scales differ");
+    }
+    // output scale: depth 1, S^2 / c2 / q_(l-1); depth 2, about S (each branch lands on S q_(l-1) / q_(l-1))
+    const double so = deg == 2 ? S * S / coef[2] / (double)c->mod[l - 1] : S;
+    if (!scale_has_room(c, l - depth, so)) return scale_room_error("fhe_poly_act");
+    const size_t per = deg == 2 ? poly_act2_item_bytes(c, l) : poly_act3_item_bytes(c, l);
+    const uint32_t C = (uint32_t)std::max<size_t>(1, std::min<size_t>(n, ((size_t)2 << 30) / per));
+    for (uint32_t t0 = 0; t0 < n; t0 += C) {
+        const uint32_t cn = std::min(C, n - t0);
+        s = deg == 2 ? poly_act2(c, rlk, x + t0, cn, coef, y + t0) : poly_act3(c, rlk, x + t0, cn, coef, deg, y + t0);
+        if (s) return s;
+    }
+    return FHE_OK;
+}
+
 fhe_status fhe_avgpool2x2(fhe_ctx *c, const fhe_evk *keys, uint32_t nkeys, const fhe_ct *x, uint32_t n,
                           uint32_t dil, uint32_t frame_w, const fhe_pt *mask, fhe_ct *y)
 {
@@ -460,14 +493,16 @@ fhe_status fhe_fc_packed(fhe_ctx *c, const fhe_evk *rlk, const fhe_evk *keys, ui
     if (l < 2) return fhe_fail(FHE_ELEVEL, "fhe_fc_packed: inputs need two limbs");
     for (uint32_t i = 0; i < n_in; ++i) {
         if ((s = chk2(&x[i], l, "fhe_fc_packed"))) return s;
-        if (!same_scale(x[i].scale, x[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_packed: input scales differ");
+        if (!scales_match(x[i].scale, x[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_packed: input scales differ");
     }
     for (uint32_t i = 0; i < n_in * n_out; ++i) {
         if ((s = chk2(&Wt[i], l, "fhe_fc_packed"))) return s;
-        if (!same_scale(Wt[i].scale, Wt[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_packed: weight scales differ");
+        if (!scales_match(Wt[i].scale, Wt[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_packed: weight scales differ");
     }
     for (uint32_t o = 0; o < n_out; ++o)
         if ((s = chk2(&y[o], l - 1, "fhe_fc_packed"))) return s;
+    if (!scale_has_room(c, l - 1, x[0].scale * Wt[0].scale / (double)c->mod[l - 1]))
+        return scale_room_error("fhe_fc_packed");
     std::vector<const fhe_evk *> sumkey;
     for (uint32_t i = 1; i < frame_slots; i *= 2) {
         const fhe_evk *kk = find_key(keys, nkeys, fhe_galois_elt(c, (int32_t)i));
@@ -524,10 +559,12 @@ fhe_status fhe_conv2d_packed_pw(fhe_ctx *c, const fhe_evk *keys, uint32_t nkeys,
     if (l < 2) return fhe_fail(FHE_ELEVEL, "fhe_conv2d_packed_pw: inputs need two limbs");
     for (uint32_t i = 0; i < Cin; ++i) {
         if ((s = chk2(&X[i], l, "fhe_conv2d_packed_pw"))) return s;
-        if (!same_scale(X[i].scale, X[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_packed_pw: input scales differ");
+        if (!scales_match(X[i].scale, X[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_conv2d_packed_pw: input scales differ");
     }
     for (uint32_t o = 0; o < Cout; ++o)
         if ((s = chk2(&Y[o], l - 1, "fhe_conv2d_packed_pw"))) return s;
+    if (!scale_has_room(c, l - 1, X[0].scale * wscale / (double)c->mod[l - 1]))
+        return scale_room_error("fhe_conv2d_packed_pw");
     const int64_t half = k / 2;
     std::vector<int64_t> step(kk);
     std::vector<const fhe_evk *> tapkey(kk, nullptr);
@@ -581,16 +618,18 @@ fhe_status fhe_fc_packed_pw(fhe_ctx *c, const fhe_evk *keys, uint32_t nkeys, con
     if (l < 2) return fhe_fail(FHE_ELEVEL, "fhe_fc_packed_pw: inputs need two limbs");
     for (uint32_t i = 0; i < n_in; ++i) {
         if ((s = chk2(&x[i], l, "fhe_fc_packed_pw"))) return s;
-        if (!same_scale(x[i].scale, x[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_packed_pw: input scales differ");
+        if (!scales_match(x[i].scale, x[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_packed_pw: input scales differ");
     }
     std::vector<const uint64_t *> pts((size_t)n_in * n_out);
     for (uint32_t i = 0; i < n_in * n_out; ++i) {
         if (!Wt[i].d || Wt[i].limbs != l) return fhe_fail(FHE_ELEVEL, "fhe_fc_packed_pw: weights must have l limbs");
-        if (!same_scale(Wt[i].scale, Wt[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_packed_pw: weight scales differ");
+        if (!scales_match(Wt[i].scale, Wt[0].scale)) return fhe_fail(FHE_ESCALE, "fhe_fc_packed_pw: weight scales differ");
         pts[i] = Wt[i].d;
     }
     for (uint32_t o = 0; o < n_out; ++o)
         if ((s = chk2(&y[o], l - 1, "fhe_fc_packed_pw"))) return s;
+    if (!scale_has_room(c, l - 1, x[0].scale * Wt[0].scale / (double)c->mod[l - 1]))
+        return scale_room_error("fhe_fc_packed_pw");
     std::vector<const fhe_evk *> sumkey;
     for (uint32_t i = 1; i < frame_slots; i *= 2) {
         const fhe_evk *kk = find_key(keys, nkeys, fhe_galois_elt(c, (int32_t)i));

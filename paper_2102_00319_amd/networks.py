@@ -14,6 +14,8 @@ Every CT x CT product is followed by relinearisation and one rescale, so a
 forward pass takes 9 levels with the cubic activation: conv 1, act 2, pool 1,
 conv 1, act 2, pool 1, fc 1 (7 with the quadratic one, whose depth is 1).
 """
+import math
+
 import numpy as np
 
 from .fhe import CtArray
@@ -294,7 +296,13 @@ class PaperCNN:
     into g's coefficients, so that pooling is three additions.  The conv and ActPool
     run in bands of pooled rows (the conv outputs of one band are freed before the
     next), and the pooled maps drop to two limbs before the FC, whose weights the
-    model owner encrypts at that level."""
+    model owner encrypts at that level.
+
+    Scales: the depth-1 activation reads Relin(u (x) u) as c2 u^2 at scale S^2 / c2,
+    so its output scale is 1/c2 times that of u^2 (44x for g/4).  The conv weights
+    are therefore encrypted at scale D * sqrt(c2), which puts the conv output at
+    about D sqrt(c2) and the activation output back at about D; the FC output then
+    sits near D at one limb, with log2(q0 / D) bits of room for the scores."""
 
     def __init__(self, H=28, W=28, K=3, C=28, n_classes=10, coef=(0.47, 0.50, 0.09), band=1):
         self.H, self.W, self.K, self.C, self.n_classes = H, W, K, C, n_classes
@@ -310,10 +318,14 @@ class PaperCNN:
     def n_in_fc(self):
         return self.C * self.Hp * self.Wp
 
+    def conv_weight_scale(self, D):
+        """Scale of the conv weight ciphertexts for input scale D (see the class note)."""
+        return D * math.sqrt(self.coef4[2])
+
     def keygen(self, ctx, s, seed):
         return ctx.keygen_relin(s, seed), {}
 
-    def encrypt_images(self, ctx, pk, images, seed, slot_offset=0, scale=None):
+    def encrypt_images(self, ctx, pk, images, seed, slot_offset=0, scale=None, progress=None):
         B = images.shape[0]
         out = []
         for y in range(self.H):
@@ -321,17 +333,21 @@ class PaperCNN:
                 v = np.zeros(slot_offset + B)
                 v[slot_offset:] = images[:, y, x]
                 out.append(ctx.encrypt(pk, ctx.encode(v, scale=scale or ctx.scale), seed + y * self.W + x))
+            if progress:
+                progress("images: row %d of %d encrypted" % (y + 1, self.H))
         return out
 
     def encrypt_weights(self, ctx, pk, wc, wfc, seeds, top=None, scale=None):
-        """wc [C][1][K][K] at the top level, wfc [classes][C*Hp*Wp] at two limbs."""
+        """wc [C][1][K][K] at the top level and scale conv_weight_scale(D); wfc
+        [classes][C*Hp*Wp] at two limbs and scale D."""
         top = ctx.L if top is None else top
         D = scale or ctx.scale
-        Wc = ctx.encrypt_const_batch(pk, wc.ravel(), D, [seeds[0] + t for t in range(wc.size)], top)
+        Wc = ctx.encrypt_const_batch(pk, wc.ravel(), self.conv_weight_scale(D),
+                                     [seeds[0] + t for t in range(wc.size)], top)
         Wf = ctx.encrypt_const_batch(pk, wfc.ravel(), D, [seeds[1] + t for t in range(wfc.size)], 2)
         return CtArray(Wc), CtArray(Wf)
 
-    def forward(self, ctx, rlk, gks, X, weights):
+    def forward(self, ctx, rlk, gks, X, weights, progress=None):
         Wc, Wf = weights
         pooled = [None] * self.n_in_fc
         for i0 in range(0, self.Hp, self.band):
@@ -349,6 +365,8 @@ class PaperCNN:
                     for j in range(self.Wp):
                         p = Pb[(c * (i1 - i0) + i) * self.Wp + j]
                         pooled[(c * self.Hp + i0 + i) * self.Wp + j] = ctx.drop_level(p, 2)
+            if progress:
+                progress("forward: pooled rows %d..%d of %d enqueued" % (i0, i1 - 1, self.Hp))
         return ctx.fc_slot(rlk, pooled, Wf, self.n_classes)
 
     def decrypt_scores(self, ctx, s, Z, B, slot_offset=0):

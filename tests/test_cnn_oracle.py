@@ -1,5 +1,7 @@
 """CPU checks of the CNN layer definitions used by the encrypted recipes:
 the op-count formula of the paper and the FP64 network shape arithmetic."""
+import math
+
 import numpy as np
 
 import workloads
@@ -62,10 +64,14 @@ def test_paper_network_on_oracle():
     rlk = o.keygen_relin(s, workloads.SEED_EVK)
     X = [o.encrypt(pk, o.encode_rns(imgs[:, y, x], D, o.L), workloads.SEED_ENC + y * 6 + x, D)
          for y in range(6) for x in range(6)]
-    Wc = [cnn.encrypt_const(o, pk, v, D, o.L, workloads.SEED_ENC + 100000 + t) for t, v in enumerate(wc.ravel())]
+    # conv weights at D sqrt(c2 / 4): the depth-1 activation's output scale (S^2 / c2 per
+    # rescale) then returns to about D, leaving the scores room below q0
+    swc = D * math.sqrt(0.09 / 4.0)
+    Wc = [cnn.encrypt_const(o, pk, v, swc, o.L, workloads.SEED_ENC + 100000 + t) for t, v in enumerate(wc.ravel())]
     Wf = [cnn.encrypt_const(o, pk, v, D, 2, workloads.SEED_ENC + 200000 + t) for t, v in enumerate(wfc.ravel())]
     cnt = cnn.Counter()
     _, Z = cnn.enc_paper_cnn(o, rlk, X, Wc, Wf, 2, 3, 6, 6, 2, cnt)
+    assert abs(math.log2(Z[0].scale) - math.log2(D)) < 1.0
     ref = cnn.paper_cnn_fp64(imgs, wc, wfc)
     for r in range(2):
         re, _ = o.decode(o.decrypt(Z[r], s), Z[r].scale, n=B)

@@ -211,3 +211,23 @@ def test_packed_network_plain_model():
         assert np.abs(re[np.arange(B) * FH * FW] - ref[:, r]).max() < 1e-3
     assert cnt.relin == 2 * (c1 + c2) and cnt.ct_mult == 2 * (c1 + c2)
     assert cnt.rotate == (K * K - 1) * (1 + c1) + 2 * (c1 + c2) + ncls * 8
+
+
+def test_strided_padded_conv_against_scipy():
+    """The FP64 convolution with stride and one-sided padding against scipy's
+    correlate2d of the zero-padded image, sampled at the strided positions."""
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((2, 2, 9, 7))
+    w = rng.standard_normal((3, 2, 3, 3))
+    for stride, pt, pl in [(1, 0, 0), (2, 1, 1), (2, 0, 1), (3, 2, 0)]:
+        Ho = (9 + pt - 3) // stride + 1
+        Wo = (7 + pl - 3) // stride + 1
+        got = cnn.conv2d_fp64(x, w, stride, pt, pl, Ho, Wo)
+        for b in range(2):
+            for co in range(3):
+                ref = 0.0
+                for ci in range(2):
+                    xp = np.pad(x[b, ci], ((pt, 3), (pl, 3)))
+                    full = scipy.signal.correlate2d(xp, w[co, ci], mode="valid")
+                    ref = ref + full[::stride, ::stride][:Ho, :Wo]
+                assert np.allclose(got[b, co], ref, atol=1e-12)
