@@ -62,6 +62,39 @@ def measured_traffic(kernel):
         return None
 
 
+def measured_step_traffic(param_set, batch):
+    """HBM bytes of one step (all kernels of `batch` key switches) from the committed
+    per-kernel counter summary, or None when there is none for this shape or the
+    key-switch source changed since the counters were taken."""
+    if param_set != "c4_n16":
+        return None
+    path = os.path.join(ROOT, "profiles", "keyswitch_n16_l24_step_hbm_counters.md")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
+        for src in fields["sources"].split(";"):
+            name, digest = src.strip().split(" code-sha256[:16] ")
+            if source_digest(os.path.join(ROOT, name)) != digest.strip():
+                return None
+        if int(fields["batch"]) != batch:
+            return None
+        return int(fields["traffic_bytes_per_step"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def _host_cpu():
+    """CPU model and logical CPU count of this host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
 def _oracle_keyswitch_once(arg):
     """One oracle key switch on random data (a separate process per host core)."""
     name, seed = arg
@@ -84,6 +117,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=8, help="rotations (distinct keys) per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-procs", type=int, default=16,
+                    help="oracle processes for the CPU baseline (one GPU's share of the host)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB copy kernel (reference for HBM byte counters)")
     ap.add_argument("--param-set", default="c4_n16")
@@ -118,10 +153,9 @@ def parse():
 
 
 def ks_shape(logN):
-    """Split of each transform in the key-switching path: a column pass of LOGA
-    stages and a row pass of LOGB <= 8 stages."""
-    logB = min(8, logN - 4)
-    return logN - logB, logB
+    """Split of each transform in the key-switching path: 3 column stages (run inside
+    the basis conversions) and a row pass of logN - 3 stages."""
+    return 3, logN - 3
 
 
 def kernel_model(cat, N, l, K, alpha, B, dnum, L, fused=False):
@@ -134,18 +168,12 @@ def kernel_model(cat, N, l, K, alpha, B, dnum, L, fused=False):
     ups = sum(l + K - min(alpha, l - j * alpha) for j in range(nd))
     logA, logB = ks_shape(logN)
     bfly = (N // 2) * FLOPS_PER_BUTTERFLY     # flops of one stage over one limb
-    if cat == "ntt_fwd_col":   # the converted ModUp digits and the ModDown conversions z
-        n = B * (ups + 2 * l)
-        return 2 * n * limb, n * logA * bfly
-    if cat == "ntt_fwd_row":
+    if cat == "ntt_fwd_row":   # the converted ModUp limbs (split form)
         if fused:
             return 0, 0
         n = B * ups
         return 2 * n * limb, n * logB * bfly
-    if cat == "ntt_inv_col":
-        n = B * (l + 2 * K)
-        return 2 * n * limb, n * logA * bfly
-    if cat == "ntt_inv_row":
+    if cat == "ntt_inv_row":   # the P limbs of u
         n = B * 2 * K
         return 2 * n * limb, n * logB * bfly
     if cat == "ks_intt_first":
@@ -157,15 +185,16 @@ def kernel_model(cat, N, l, K, alpha, B, dnum, L, fused=False):
         return (3 * n + B * l) * limb, n * logB * bfly + n * N * 8
     if cat == "ks_inner":
         # D_j and both key polynomials per digit in, u out (2 products per element per
-        # digit); fused: D_j of the converted limbs enters in column-pass form and gets
+        # digit); fused: D_j of the converted limbs enters in column-stage form and gets
         # its row pass here
         return (B * (3 * nd * (l + K) + 2 * (l + K)) * limb,
                 B * 2 * nd * (l + K) * N * 9 + (B * ups * logB * bfly if fused else 0))
     if cat == "bconv_up":
-        # the digit sources in, the converted limbs out (alpha products per target element)
-        return B * (l + ups) * limb, B * ups * alpha * N * 9
+        # the row-inverted digit limbs in, the converted limbs out (alpha products per
+        # target element), with the sources' last 3 inverse stages and the targets' first 3
+        return B * (l + ups) * limb, B * ups * alpha * N * 9 + B * (l + ups) * logA * bfly
     if cat == "bconv_down":
-        return B * (2 * K + 2 * l) * limb, B * 2 * l * K * N * 9
+        return B * (2 * K + 2 * l) * limb, B * 2 * l * K * N * 9 + B * (2 * K + 2 * l) * logA * bfly
     if cat == "automorph":
         return B * 4 * l * limb, 0
     return 0, 0
@@ -496,7 +525,7 @@ def serve(args):
         s = serving.summarize(reqs)
         s.update({"rate_req_s": rate, "evictions": srv.stats["evictions"], "cold_loads": srv.stats["cold_loads"],
                   "cold_load_s": round(srv.stats["cold_load_s"], 2), "evict_s": round(srv.stats["evict_s"], 2),
-                  "oom_retries": srv.stats["oom_retries"]})
+                  "library_gib_held": round(sum(l.library_bytes() for l in srv.lanes) / 2 ** 30, 2)})
         print(json.dumps({"serve_rate": s}), flush=True)
         per_rate.append(s)
     rec = {"metric": "encrypted inference serving: p50/p99 latency and images/s per arrival rate",
@@ -873,14 +902,19 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import multiprocessing as mp
-        cores = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+        # the processes this job may run at once: the CPUs it is allowed on, at most
+        # --cpu-procs (one GPU's share of its host)
+        allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        cores = max(1, min(args.cpu_procs, allowed))
+        model, nproc = _host_cpu()
         c0 = time.perf_counter()
         with mp.get_context("spawn").Pool(cores) as pool:
             per = pool.map(_oracle_keyswitch_once, [(args.param_set, 90 + 2 * i) for i in range(cores)])
         c1 = time.perf_counter()
         cpu = {"value": round(cores / (c1 - c0), 4), "unit": "key-switch/s", "cores": cores, "kind": "oracle",
+               "host_cpu": model, "host_logical_cpus": nproc, "allowed_cpus": allowed,
                "sample": "%d key switches at N=2^16, l=24, K=8, dnum=3 (random inputs and keys), one per process, "
-                         "%.1f s wall (%.1f s per key switch)" % (cores, c1 - c0, sum(per) / len(per))}
+                         "%.1f s wall (%.1f s per key switch on one core)" % (cores, c1 - c0, sum(per) / len(per))}
         print("cpu baseline: %s" % cpu["sample"], file=sys.stderr, flush=True)
     import numpy as np
     import torch
@@ -925,8 +959,8 @@ def main():
     torch.cuda.synchronize()
 
     # untimed profiling pass to find the dominant kernel category
-    cats = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_col", "ntt_inv_row", "ntt_fwd", "ntt_inv", "bconv_up",
-            "bconv_down", "ks_intt_first", "ks_inner", "ks_moddown_final", "automorph"]
+    cats = ["ntt_fwd_row", "ntt_inv_row", "ntt_fwd", "ntt_inv", "bconv_up", "bconv_down", "ks_intt_first",
+            "ks_inner", "ks_moddown_final", "automorph"]
     g.profile_enable("*")
     for _ in range(3):
         step()
@@ -952,25 +986,28 @@ def main():
     ks_bytes = (l + g.dnum * 2 * (g.L + g.K) + 2 * l) * N * 8
     hbm_frac = ks_per_s * ks_bytes / (HBM_PEAK_GBS * 1e9)
 
+    # Roofline of the whole key switch: the compulsory bytes counted per key switch
+    # (input, key, output) times the key switches of a step, over the timed step.
+    step_gbs = B * ks_bytes / (ms_per_step * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(step_gbs / HBM_PEAK_GBS, 4), "traffic": measured_step_traffic(args.param_set, B),
+            "scope": "whole key switch: %d key switches per step, all kernels, step time" % B,
+            "algorithmic_bytes_per_step": int(B * ks_bytes)}
+    # the dominant kernel on its own, live-timed with HIP events on the library's stream
     bytes_step, flops_step = kernel_model(dominant, N, l, K, alpha, B, g.dnum, g.L, fused=bool(args.ks_fuse))
     avg_ms = dom_ms / max(dom_cnt, 1)
     launches_per_step = dom_cnt / args.steps
     per_launch_b = bytes_step / max(launches_per_step, 1)
     per_launch_f = flops_step / max(launches_per_step, 1)
-    gbs = per_launch_b / (avg_ms * 1e-3) / 1e9
-    tfl = per_launch_f / (avg_ms * 1e-3) / 1e12
-    if gbs / HBM_PEAK_GBS >= tfl / FP64_PEAK_TFLOPS:
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
-    else:
-        roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tfl / FP64_PEAK_TFLOPS, 4), "traffic": None}
-    roof["traffic"] = measured_traffic(dominant)
-    roof["algorithmic_bytes_per_launch"] = int(per_launch_b)
-    roof["algorithmic_flops_per_launch"] = int(per_launch_f)
-    roof["kernel"] = dominant
-    roof["avg_launch_ms"] = round(avg_ms, 5)
-
+    own_gbs = per_launch_b / (avg_ms * 1e-3) / 1e9
+    compulsory_gbs = B * ks_bytes / max(launches_per_step, 1) / (avg_ms * 1e-3) / 1e9
+    roof["dominant_kernel"] = {
+        "kernel": dominant, "avg_launch_ms": round(avg_ms, 5), "launches_per_step": round(launches_per_step, 2),
+        "frac_compulsory": round(compulsory_gbs / HBM_PEAK_GBS, 4),
+        "frac_own_io": round(own_gbs / HBM_PEAK_GBS, 4),
+        "own_io_bytes_per_launch": int(per_launch_b),
+        "own_io_traffic": measured_traffic(dominant),
+        "tflops": round(per_launch_f / (avg_ms * 1e-3) / 1e12, 2)}
 
     rec = {
         "metric": "key-switch ops/s at N=2^16,L=24",

@@ -102,6 +102,20 @@ uint64_t fhe_modulus(const fhe_ctx *ctx, uint32_t idx);          /* 0..n_q-1: q_
 size_t fhe_evk_bytes(const fhe_ctx *ctx);
 uint64_t fhe_galois_elt(const fhe_ctx *ctx, int32_t step);        /* 5^(step mod N/2) mod 2N */
 uint64_t fhe_scratch_bytes(const fhe_ctx *ctx);                   /* scratch currently held */
+uint64_t fhe_workspace_bytes(const fhe_ctx *ctx);                 /* layer workspace currently held */
+
+/* Device memory for the context's growable scratch and layer workspace (the only
+ * device memory it allocates after creation) from the caller's allocator instead of
+ * hipMalloc, e.g. a framework's caching allocator, so that one budget and one cache
+ * cover the caller's buffers and the library's.  alloc_fn(bytes, stream, user)
+ * returns device memory usable on `stream` (the context's) or null (the call that
+ * needed it fails with FHE_ENOMEM before any work); free_fn(ptr, user) returns it,
+ * called once the context's stream has drained.  Both or neither (null, null:
+ * hipMalloc again).  Buffers held from the previous allocator are released first;
+ * fhe_ctx_destroy releases the rest.  Not while capturing (FHE_EINVAL). */
+typedef void *(*fhe_alloc_fn)(size_t bytes, void *hip_stream, void *user);
+typedef void (*fhe_free_fn)(void *ptr, void *user);
+fhe_status fhe_ctx_set_allocator(fhe_ctx *ctx, fhe_alloc_fn alloc_fn, fhe_free_fn free_fn, void *user);
 
 /* Kernel timing for measurement: after fhe_profile_enable(ctx, cat) every
  * launch of kernel category cat ("*" = all; categories: ntt_fwd, ntt_inv,
@@ -187,6 +201,7 @@ fhe_status fhe_keyswitch(fhe_ctx *ctx, const fhe_evk *evk, const uint64_t *d, ui
  * d, evk, out are host arrays of n entries.  One launch sequence for all. */
 fhe_status fhe_keyswitch_batch(fhe_ctx *ctx, const fhe_evk *evk, const uint64_t *const *d, uint32_t limbs,
                                uint32_t n, fhe_ct *out);
+
 
 /* Work list of independent or chained operations at mixed levels (one ring).
  * Operations run as if in list order; those whose inputs are ready are grouped

@@ -181,6 +181,12 @@ extern "C" fhe_status fhe_profile_read(fhe_ctx *c, const char *category, double 
 static void ctx_free_all(fhe_ctx *c)
 {
     if (c->prof) (void)fhe_profile_enable(c, nullptr);
+    if (c->alloc_fn) {   // the growable buffers came from the caller's allocator
+        if (c->stream) (void)hipStreamSynchronize(c->stream);
+        if (c->scratch) c->free_fn(c->scratch, c->alloc_user);
+        if (c->wksp) c->free_fn(c->wksp, c->alloc_user);
+        c->scratch = c->wksp = nullptr;
+    }
     void *ptrs[] = {c->d_mod, c->d_tw, c->d_itw, c->d_ninv, c->d_cdt, c->d_cos, c->d_sin, c->d_g5,
                     c->d_bconv, c->d_pinv, c->d_phalf, c->d_pmod, c->d_qlinv, c->scratch, c->wksp, c->tbl_dev, c->d_big};
     for (void *p : ptrs)
@@ -207,6 +213,7 @@ extern "C" fhe_status fhe_ctx_create(const fhe_params *pp, void *hip_stream, uin
     const uint32_t N = 1u << logN;
     fhe_ctx *c = new fhe_ctx();   // value-initialised: plain fields zero, containers constructed
     c->tune_row_wg = 128;
+    c->tune_fuse_row_inner = 1;
     c->logN = logN; c->N = N; c->L = L; c->K = K; c->dnum = pp->dnum;
     c->alpha = (L + pp->dnum - 1) / pp->dnum;
     c->stream = (hipStream_t)hip_stream;
@@ -385,25 +392,54 @@ extern "C" uint64_t fhe_galois_elt(const fhe_ctx *c, int32_t step)
 }
 extern "C" uint64_t fhe_scratch_bytes(const fhe_ctx *c) { return c ? c->scratch_bytes : 0; }
 
-fhe_status ctx_scratch(fhe_ctx *c, size_t bytes, uint8_t **out)
+// Device memory of the context's growable buffers: from the caller's allocator when
+// one is set (fhe_ctx_set_allocator), else hipMalloc.
+static fhe_status ctx_dev_alloc(fhe_ctx *c, size_t bytes, uint8_t **p)
+{
+    if (c->alloc_fn) {
+        *p = (uint8_t *)c->alloc_fn(bytes, (void *)c->stream, c->alloc_user);
+        if (!*p) return fhe_fail(FHE_ENOMEM, "the caller's allocator refused " + std::to_string(bytes) + " bytes");
+        return FHE_OK;
+    }
+    HIPCHK(hipMalloc((void **)p, bytes));
+    return FHE_OK;
+}
+static fhe_status ctx_dev_free(fhe_ctx *c, uint8_t *p)
+{
+    if (!p) return FHE_OK;
+    if (c->alloc_fn) {
+        c->free_fn(p, c->alloc_user);
+        return FHE_OK;
+    }
+    HIPCHK(hipFree(p));
+    return FHE_OK;
+}
+// Grow one of the buffers to `bytes` (its contents are not kept).
+static fhe_status ctx_grow(fhe_ctx *c, uint8_t **buf, size_t *held, size_t bytes, const char *what)
 {
     bytes = (bytes + 255) & ~(size_t)255;
-    if (bytes > c->scratch_bytes && c->capturing) {
+    if (bytes <= *held) return FHE_OK;
+    if (c->capturing) {
         c->cap_error = FHE_ENOMEM;
         return fhe_fail(FHE_ENOMEM, "graph capture: device memory must be sized by an eager run first");
     }
-    if (bytes > c->scratch_bytes) {
-        size_t grow = bytes - c->scratch_bytes;
-        if (c->used + grow > c->budget) return fhe_fail(FHE_ENOMEM, "scratch exceeds the HBM budget");
-        HIPCHK(hipStreamSynchronize(c->stream));
-        if (c->scratch) HIPCHK(hipFree(c->scratch));
-        c->scratch = nullptr;
-        c->used -= c->scratch_bytes;
-        c->scratch_bytes = 0;
-        HIPCHK(hipMalloc((void **)&c->scratch, bytes));
-        c->scratch_bytes = bytes;
-        c->used += bytes;
-    }
+    if (c->used + (bytes - *held) > c->budget) return fhe_fail(FHE_ENOMEM, std::string(what) + " exceeds the HBM budget");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    fhe_status s = ctx_dev_free(c, *buf);
+    *buf = nullptr;
+    c->used -= *held;
+    *held = 0;
+    if (s) return s;
+    if ((s = ctx_dev_alloc(c, bytes, buf))) return s;
+    *held = bytes;
+    c->used += bytes;
+    return FHE_OK;
+}
+
+fhe_status ctx_scratch(fhe_ctx *c, size_t bytes, uint8_t **out)
+{
+    fhe_status s = ctx_grow(c, &c->scratch, &c->scratch_bytes, bytes, "scratch");
+    if (s) return s;
     *out = c->scratch;
     return FHE_OK;
 }
@@ -412,26 +448,29 @@ fhe_status ctx_scratch(fhe_ctx *c, size_t bytes, uint8_t **out)
 // intermediates survive the scratch use of the operations it calls).
 fhe_status ctx_workspace(fhe_ctx *c, size_t bytes, uint8_t **out)
 {
-    bytes = (bytes + 255) & ~(size_t)255;
-    if (bytes > c->wksp_bytes && c->capturing) {
-        c->cap_error = FHE_ENOMEM;
-        return fhe_fail(FHE_ENOMEM, "graph capture: device memory must be sized by an eager run first");
-    }
-    if (bytes > c->wksp_bytes) {
-        size_t grow = bytes - c->wksp_bytes;
-        if (c->used + grow > c->budget) return fhe_fail(FHE_ENOMEM, "layer workspace exceeds the HBM budget");
-        HIPCHK(hipStreamSynchronize(c->stream));
-        if (c->wksp) HIPCHK(hipFree(c->wksp));
-        c->wksp = nullptr;
-        c->used -= c->wksp_bytes;
-        c->wksp_bytes = 0;
-        HIPCHK(hipMalloc((void **)&c->wksp, bytes));
-        c->wksp_bytes = bytes;
-        c->used += bytes;
-    }
+    fhe_status s = ctx_grow(c, &c->wksp, &c->wksp_bytes, bytes, "layer workspace");
+    if (s) return s;
     *out = c->wksp;
     return FHE_OK;
 }
+
+extern "C" fhe_status fhe_ctx_set_allocator(fhe_ctx *c, fhe_alloc_fn alloc_fn, fhe_free_fn free_fn, void *user)
+{
+    if (!c || (!alloc_fn) != (!free_fn)) return fhe_fail(FHE_EINVAL, "fhe_ctx_set_allocator: need both functions or none");
+    if (c->capturing) return fhe_fail(FHE_EINVAL, "fhe_ctx_set_allocator: context is capturing");
+    // release what the previous allocator gave
+    HIPCHK(hipStreamSynchronize(c->stream));
+    fhe_status s = ctx_dev_free(c, c->scratch);
+    if (!s) s = ctx_dev_free(c, c->wksp);
+    c->used -= c->scratch_bytes + c->wksp_bytes;
+    c->scratch = c->wksp = nullptr;
+    c->scratch_bytes = c->wksp_bytes = 0;
+    c->alloc_fn = alloc_fn;
+    c->free_fn = free_fn;
+    c->alloc_user = user;
+    return s;
+}
+extern "C" uint64_t fhe_workspace_bytes(const fhe_ctx *c) { return c ? c->wksp_bytes : 0; }
 
 // Upload a list of device pointers for the next launch(es) on the context's
 // stream.  Tables live in a ring over a device arena (copied from its pinned

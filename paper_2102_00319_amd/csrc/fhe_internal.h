@@ -178,6 +178,9 @@ struct fhe_ctx {
     int cap_error;
     uint8_t *cap_host, *cap_dev;
     size_t cap_bytes, cap_used;
+    fhe_alloc_fn alloc_fn;   // caller's allocator for scratch and workspace (null: hipMalloc)
+    fhe_free_fn free_fn;
+    void *alloc_user;
     uint32_t tune_chunk;     // most items per ragged launch sequence (0: no limit)
     uint32_t tune_fuse_row_inner;   // key switch: fuse the digits' row pass into the inner product
     uint32_t tune_row_wg;    // key switch and rescale: row-pass workgroup cap (128 or 256)

@@ -18,6 +18,12 @@ struct fhe_graph {
     hipGraphExec_t exec;
     hipStream_t stream;
     std::vector<void *> dev;     // device memory owned by the graph
+    struct Lent {                // buffers from a context's caller-supplied allocator
+        void *p;
+        fhe_free_fn free_fn;
+        void *user;
+    };
+    std::vector<Lent> lent;
     std::vector<void *> host;    // pinned staging
     std::vector<hipEvent_t> events;
 };
@@ -29,6 +35,7 @@ static void graph_free(fhe_graph *g)
     if (g->graph) (void)hipGraphDestroy(g->graph);
     for (void *p : g->dev)
         if (p) (void)hipFree(p);
+    for (const fhe_graph::Lent &b : g->lent) b.free_fn(b.p, b.user);
     for (void *p : g->host)
         if (p) (void)hipHostFree(p);
     for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
@@ -147,8 +154,11 @@ fhe_status fhe_graph_end(fhe_ctx *const *ctxs, uint32_t n, fhe_graph *g)
             return fhe_hip_check(e, "hipMemcpy");
         }
         fhe_ctx *c = ctxs[i];
-        if (c->scratch) g->dev.push_back(c->scratch);
-        if (c->wksp) g->dev.push_back(c->wksp);
+        for (uint8_t *b : {c->scratch, c->wksp}) {
+            if (!b) continue;
+            if (c->alloc_fn) g->lent.push_back(fhe_graph::Lent{b, c->free_fn, c->alloc_user});
+            else g->dev.push_back(b);
+        }
         c->used -= c->scratch_bytes + c->wksp_bytes;
         c->scratch = c->wksp = nullptr;
         c->scratch_bytes = c->wksp_bytes = 0;

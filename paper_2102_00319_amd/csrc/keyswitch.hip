@@ -18,23 +18,25 @@
 //            i.e. u_t / P rounded (up to the fast-conversion error);
 //   out_t  = ks_t + add_t.
 //
-// Kernel sequence (every transform split into a column pass and a row pass of at
-// most 2^8 elements per row, so that the fused row kernels run in workgroups of at
-// most 256 threads, 128 by default):
-//   1 k_ks_intt_first   inverse row pass of d_b                           -> dc
-//     k_col_inv         inverse column pass, times (Q_j/q_a)^-1 mod q_a   -> dc (conversion sources)
-//   2 k_bconv           ModUp conversion of every digit, one thread per coefficient -> up
-//     k_col_fwd         forward column pass of up
-//   3 k_row_fwd         forward row pass of up
-//   4 k_ks_inner        key inner product over the digits                -> uQ, uP
-//     (3 and 4 as one kernel, k_ks_row_inner, when the fusion is switched on)
-//   5 k_row_inv, k_col_inv  inverse transform of uP, plus (P-1)/2, times (P/p_a)^-1
-//   6 k_bconv           rounded conversion P -> Q_l, minus (P-1)/2        -> z
-//     k_col_fwd         forward column pass of z
-//   7 k_ks_moddown_final forward row pass of z fused with (u - z) P^-1 + add -> out
-// A conversion thread loads all sources of its coefficient at once and writes every
-// target: fusing the conversion into the column pass of each target instead re-reads
-// the digit's sources once per target and measured 1.6x slower on MI355X.
+// Transforms are split into rows of N/8 elements (the last logN - 3 forward stages,
+// the first inverse ones: one workgroup per row, radix-16 register rounds through
+// LDS) and columns of 8 elements at stride N/8 (the other 3 stages).  A column fits
+// in one thread's registers, so the column stages run inside the basis conversions:
+// a conversion thread finishes the inverse transform of its digit's sources on its
+// column, converts, and starts the forward transform of every target on it.
+// Kernel sequence:
+//   1 k_ks_intt_first   inverse row pass of d_b                         -> dc
+//   2 k_conv_cols<up>   inverse column stages of the digit's limbs, times
+//                       (Q_j/q_a)^-1, conversion to every other limb of Q_l u P,
+//                       forward column stages                          -> up
+//   3 k_ks_row_inner    forward row pass of the converted limbs fused with the key
+//                       inner product (items with their own key), or k_row_fwd then
+//                       k_ks_inner (items that share a key read it once per group)
+//                                                                       -> uQ, uP
+//   4 k_row_inv         inverse row pass of uP
+//   5 k_conv_cols<down> inverse column stages, plus (P-1)/2, times (P/p_a)^-1,
+//                       conversion P -> Q_l minus (P-1)/2, forward column stages -> z
+//   6 k_ks_moddown_final forward row pass of z fused with (u - z) P^-1 + add -> out
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -56,17 +58,21 @@ struct KsItem {
     uint32_t dc_off;    // first limb of the item in dc
     uint32_t up_off;    // first limb of the item in up
     uint32_t uq_off;    // first limb of the item in uQ and z ([2][l] each)
-    uint32_t pad;
+    uint32_t ginv;      // inverse of the item's Galois element mod 2N (0: none)
     uint16_t upoff[16]; // first converted limb of digit j, relative to up_off
 };
 static_assert(sizeof(KsItem) == 56, "KsItem is 7 table words");
-struct BcJob {          // one basis conversion: nsrc source limbs -> ndst destination limbs
-    uint32_t off;       // constants in the conversion table
-    uint32_t nsrc, ndst;
-    uint32_t src0, dst0;   // absolute first limbs in the source and destination buffers
+// One basis conversion with its column stages: nsrc source limbs (moduli smod0 ..)
+// -> ndst target limbs; target t has modulus t (t < glo), t + gn (t < l - gn) or
+// L + t - (l - gn) (the special primes): Q_l u P without the digit's own limbs.
+struct CvJob {
+    uint32_t off;          // constants in the conversion table (BconvTab layout)
+    uint16_t nsrc, ndst;
+    uint32_t src0, dst0;   // first source / target limb in their buffers
+    uint8_t smod0, glo, gn, l;
     uint32_t pad;
 };
-static_assert(sizeof(BcJob) == 24, "BcJob is 3 table words");
+static_assert(sizeof(CvJob) == 24, "CvJob is 3 table words");
 // Items of one batch that use the same key at the same level share the key reads
 // of the inner product: up to KS_GRP of them form a group.
 constexpr uint32_t KS_GRP = 8;
@@ -80,11 +86,10 @@ static_assert(sizeof(KsGrp) == 24, "KsGrp is 3 table words");
 //   [d: n][evk: n][out: n][add: 2n][gal: n][items: 7n][la: sum l][upjobs: 3 sum nd]
 //   [upmods: sum ups][inner: sum over groups (l + K)][dnjobs: 3 * 2n][fl: sum 2l]
 //   [pl: 2nK][groups: 3 per group]
-// la entries: item << 16 | limb, plus the offset of the limb's (Q_j/q_a)^-1 in the
-// conversion constants << 32 (dc order); inner: group << 16 | x (x < l: Q limb,
+// la entries: item << 16 | limb (dc order); inner: group << 16 | x (x < l: Q limb,
 // else special prime x - l); fl: item << 17 | poly << 16 | limb (z and uQ order);
-// pl (uP limbs): modulus | offset of (P/p_a)^-1 << 32.  upmods and fl also carry the
-// limb of up / z (and uQ) in bits 32..; upmods is sorted by modulus.
+// pl (uP limbs): modulus.  upmods and fl also carry the limb of up / z (and uQ) in
+// bits 32..; upmods is sorted by modulus.
 struct KsTab {
     uint32_t n, K, L;
     uint32_t it, la, uj, um, il, dj, fl, pl, gr;
@@ -225,14 +230,18 @@ __global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ 
     }
 }
 
-// 3+4. The forward row pass of the converted digits fused with the key inner
-//     product, for items with their own key (groups of one) and no Galois element
-//     (the converted limbs are transformed here, so they cannot be read through a
-//     permutation): one block covers the
-//     rows of limb x of Q_l u P that the row pass gives it, in the row-pass geometry;
-//     per digit j, D_j[x] is the input limb (canonical) or the converted limb,
-//     transformed in registers and redistributed to the coalesced order, then
-//     multiplied by both key polynomials.  blockIdx.y + y0 = entry of the inner list.
+// 3 (items with their own key). The forward row pass of the converted limbs fused
+//     with the key inner product: one block per row of limb x of Q_l u P.  Per digit
+//     j, D_j[x] is the item's input limb (x inside the digit, already in the NTT
+//     domain) or its converted limb, whose row stages run here; both are taken at
+//     positions y' in coalesced order.  With Galois element g (permutation pi of the
+//     NTT positions, out[y] = in[pi(y)]) the sum lands at y = pi^-1(y'):
+//       u_t[y] = sum_j D_j[pi(y)] evk_{j,t}[y],
+//     so the key is read at y and u stored at y; pi^-1 maps an aligned block of 64
+//     positions onto another one, so both stay coalesced.  Lazy values below 2.7 q
+//     enter the products (|v e / q| < 2^52) and three digits' products sum below 2^53
+//     (the sums are reduced every four digits).  blockIdx.y + y0 = entry of the
+//     inner list.
 template <int LOGG, int WG>
 __global__ __launch_bounds__(WG) void k_ks_row_inner(uint64_t *const *__restrict__ tab, KsTab t, uint32_t y0,
                                                      const uint64_t *__restrict__ up, uint64_t *__restrict__ uQ,
@@ -247,39 +256,49 @@ __global__ __launch_bounds__(WG) void k_ks_row_inner(uint64_t *const *__restrict
     const uint32_t g = (uint32_t)(e >> 16), x = (uint32_t)(e & 0xFFFF);
     const uint32_t b = reinterpret_cast<const KsGrp *>(tab + t.gr)[g].it[0];
     const KsItem &it = tab_item(tab, t, b);
-    const uint32_t l = it.l, nd = it.nd;
+    const uint32_t l = it.l, nd = it.nd, ginv = it.ginv;
     const uint32_t mx = x < l ? x : t.L + (x - l);
     const double q = mods[mx].q, qi = mods[mx].qinv;
     const uint64_t *ev = tab[t.n + b];
-    const uint32_t gal = (uint32_t)tab_word(tab, 5 * t.n, b);
     const size_t ML = t.L + t.K;
     const Gm gm(logN, blockIdx.x);
     double a0[R], a1[R];
 #pragma unroll
     for (int k = 0; k < R; k++) a0[k] = a1[k] = 0.0;
+#pragma unroll 1
     for (uint32_t j = 0; j < nd; ++j) {
         const uint32_t lo = j * alpha, hi = min(lo + alpha, l);
         double v[R];
-        if (x >= lo && x < hi) {   // block-uniform branch; the input limb through the permutation
+        if (x >= lo && x < hi) {   // block-uniform branch
             const gu64 *src = gview(tab[b] + (size_t)x * N);
 #pragma unroll
-            for (int k = 0; k < R; k++) v[k] = u64_to_f64(src[galois_src(gm.coal(k), gal, logN)]);
+            for (int k = 0; k < R; k++) v[k] = u64_to_f64(src[gm.coal(k)]);
         } else {
             const uint32_t pos = x < lo ? x : x - (hi - lo);
             const uint64_t *src = up + ((size_t)it.up_off + it.upoff[j] + pos) * N;
 #pragma unroll
             for (int k = 0; k < R; k++) v[k] = bits_to_f64(src[gm.fwd_in(k)]);
-            gm.fwd(v, lds, twt + (size_t)mx * N, q, qi, logN, sigma0);
-            gm.fwd_out_to_coal(v, lds);
-#pragma unroll
-            for (int k = 0; k < R; k++) v[k] = canon(v[k], q, qi);
+            // the transform's addresses are the same for every digit: an opaque copy of
+            // the thread index keeps the compiler from computing all of them once before
+            // the loop and holding them (about 150 registers)
+            uint32_t tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            const Gm gj(logN, blockIdx.x, tid);
+            gj.fwd(v, lds, twt + (size_t)mx * N, q, qi, logN, sigma0);
+            gj.fwd_out_to_coal(v, lds);
         }
-        const gu64 *e0 = gview(ev + (((size_t)j * 2 + 0) * ML + mx) * N), *e1 = gview(ev + (((size_t)j * 2 + 1) * ML + mx) * N);
+        const gu64 *e0 = gview(ev + (((size_t)j * 2 + 0) * ML + mx) * N);
+        const gu64 *e1 = gview(ev + (((size_t)j * 2 + 1) * ML + mx) * N);
+        // the key products in quarters, so that few key loads are in flight at once
 #pragma unroll
-        for (int k = 0; k < R; k++) {
-            const uint32_t idx = gm.coal(k);
-            a0[k] += mulmod(v[k], u64_to_f64(e0[idx]), q, qi);
-            a1[k] += mulmod(v[k], u64_to_f64(e1[idx]), q, qi);
+        for (int h = 0; h < R; h += 4) {
+#pragma unroll
+            for (int k = h; k < h + 4; k++) {
+                const uint32_t y = galois_src(gm.coal(k), ginv, logN);
+                a0[k] += mulmod(v[k], u64_to_f64(e0[y]), q, qi);
+                a1[k] += mulmod(v[k], u64_to_f64(e1[y]), q, qi);
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
         if ((j & 3) == 3) {
 #pragma unroll
@@ -289,19 +308,19 @@ __global__ __launch_bounds__(WG) void k_ks_row_inner(uint64_t *const *__restrict
             }
         }
     }
-    uint64_t *o0, *o1;
+    gu64 *o0, *o1;
     if (x < l) {
-        o0 = uQ + ((size_t)it.uq_off + x) * N;
-        o1 = uQ + ((size_t)it.uq_off + l + x) * N;
+        o0 = gview(uQ + ((size_t)it.uq_off + x) * N);
+        o1 = gview(uQ + ((size_t)it.uq_off + l + x) * N);
     } else {
-        o0 = uP + ((size_t)b * 2 * t.K + (x - l)) * N;
-        o1 = uP + ((size_t)b * 2 * t.K + t.K + (x - l)) * N;
+        o0 = gview(uP + ((size_t)b * 2 * t.K + (x - l)) * N);
+        o1 = gview(uP + ((size_t)b * 2 * t.K + t.K + (x - l)) * N);
     }
 #pragma unroll
     for (int k = 0; k < R; k++) {
-        const uint32_t idx = gm.coal(k);
-        o0[idx] = f64_to_u64(canon(a0[k], q, qi));
-        o1[idx] = f64_to_u64(canon(a1[k], q, qi));
+        const uint32_t y = galois_src(gm.coal(k), ginv, logN);
+        o0[y] = f64_to_u64(canon(a0[k], q, qi));
+        o1[y] = f64_to_u64(canon(a1[k], q, qi));
     }
 }
 
@@ -346,14 +365,11 @@ __global__ __launch_bounds__(WG, 3) void k_ks_moddown_final(uint64_t *const *__r
     }
 }
 
-// Passes of the key-switching path (split_ks) over a flat limb buffer.  The inverse
-// passes treat entry y of lst as limb y, reduced modulo mods[lst[y] & 0xFFFF]; the
-// forward passes read the limb index from bits 32.. of the entry, so that their lists
-// can be ordered by modulus (consecutive blocks then share the row-pass twiddles in
-// L2).  Kernels: the forward row pass (lazy bits in,
-// canonical out, coalesced stores), the inverse column pass (bits in, N^-1
-// folded, canonical or prepared-source out), the inverse row pass, and the
-// forward column pass fused with a basis conversion.
+// Row passes of the key-switching path over a flat limb buffer.  The inverse pass
+// treats entry y of lst as limb y, reduced modulo mods[lst[y] & 0xFFFF]; the forward
+// pass reads the limb index from bits 32.. of the entry, so that its list can be
+// ordered by modulus (consecutive blocks then share the row-pass twiddles in L2).
+// The forward row pass: lazy bits in, canonical out, coalesced stores.
 template <int LOGG, int WG>
 __global__ __launch_bounds__(WG) void k_row_fwd(uint64_t *__restrict__ base, const uint64_t *__restrict__ lst,
                                                 uint32_t y0, const ModQ *__restrict__ mods,
@@ -374,40 +390,6 @@ __global__ __launch_bounds__(WG) void k_row_fwd(uint64_t *__restrict__ base, con
     gm.fwd_out_to_coal(x, lds);
 #pragma unroll
     for (int k = 0; k < R; k++) p[gm.coal(k)] = f64_to_u64(canon(x[k], q, qinv));
-}
-// EPI 0: canonical out; EPI 1: times ctab[lst[y] >> 32]; EPI 2: plus half[m], then
-// times ctab[lst[y] >> 32] (the conversion sources of ModUp and ModDown, stored as
-// FP64 bits of their canonical values: every target limb reads them again).
-template <int LOGG, int WG, int EPI>
-__global__ __launch_bounds__(WG) void k_col_inv(uint64_t *__restrict__ base, const uint64_t *__restrict__ lst,
-                                                uint32_t y0, const ModQ *__restrict__ mods,
-                                                const double *__restrict__ itwt, const double *__restrict__ ninvt,
-                                                uint32_t logN, const double *__restrict__ ctab,
-                                                const double *__restrict__ half)
-{
-    using Gm = Geom<LOGG, WG, true>;
-    __shared__ double lds[Gm::LDS];
-    const uint32_t N = 1u << logN;
-    const uint32_t b = blockIdx.y + y0;
-    const uint64_t e = lst[b];
-    const uint32_t m = (uint32_t)(e & 0xFFFF);
-    const double q = mods[m].q, qinv = mods[m].qinv;
-    uint64_t *p = base + (size_t)b * N;
-    const Gm gm(logN, blockIdx.x);
-    double x[R];
-#pragma unroll
-    for (int k = 0; k < R; k++) x[k] = bits_to_f64(p[gm.inv_in(k)]);
-    gm.template inv<true>(x, lds, itwt + (size_t)m * N, q, qinv, ninvt[m], logN, 0);
-    double mul = 0.0, h = 0.0;
-    if (EPI) mul = ctab[e >> 32];
-    if (EPI == 2) h = half[m];
-#pragma unroll
-    for (int k = 0; k < R; k++) {
-        double v = canon(x[k], q, qinv);
-        if (EPI == 2) v += h;
-        if (EPI) v = canon(mulmod(v, mul, q, qinv), q, qinv);
-        p[gm.inv_out(k)] = EPI ? f64_to_bits(v) : f64_to_u64(v);
-    }
 }
 // Inverse row pass over a flat buffer (canonical in, coalesced loads; lazy bits out).
 template <int LOGG, int WG>
@@ -431,65 +413,121 @@ __global__ __launch_bounds__(WG) void k_row_inv(uint64_t *__restrict__ base, con
 #pragma unroll
     for (int k = 0; k < R; k++) p[gm.inv_out(k)] = f64_to_bits(x[k]);
 }
-// Fast basis conversion, one thread per coefficient, blockIdx.y + y0 = job:
-//   y_t = sum_a v_a (B/b_a mod c_t) mod c_t,  v_a the prepared sources (FP64 bits of
-//   [x_a (B/b_a)^-1]_{b_a}, written by the inverse column pass), all nsrc of them
-//   loaded at once; SUB_HALF subtracts hdst[t] (the rounding shift of ModDown).
-//   Canonical targets out, for the forward column pass.  NS > 0: every job of the
-//   launch has NS sources (unguarded loops, one target's constants in one wide load).
-template <bool SUB_HALF, int NS>
-__global__ __launch_bounds__(TPB) void k_bconv(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
-                                               const double *__restrict__ ctab, const BcJob *__restrict__ jobs,
-                                               uint32_t y0, uint32_t logN, const double *__restrict__ hdst)
+// 2 and 5. Fast basis conversion with the column stages of its transforms.  One thread
+//     per column {c + i N/8 : i < 8} of one job (blockIdx.y + y0); lazy FP64 bits of the
+//     row-inverted sources in, lazy bits of the column-transformed targets out.
+//   * each source a (modulus smod0 + a): the last three inverse stages on the column
+//     (Gentleman-Sande, twiddles itw[1..7] of its modulus), N^-1 and the conversion
+//     factor (B/b_a)^-1 folded into the last stage, DOWN: plus ((P-1)/2) (B/b_a)^-1,
+//     then canonical: v_a = [x_a (B/b_a)^-1]_{b_a} (of x_a + (P-1)/2 for ModDown);
+//   * each target t: y = sum_a v_a (B/b_a mod c_t) reduced every four terms, DOWN: minus
+//     (P-1)/2, canonical, then the first three forward stages (Cooley-Tukey, twiddles
+//     tw[1..7] of c_t; the upper inputs reduced on the first and third) .
+//   NS > 0: every job of the launch has NS sources; NS < 0: at most -NS (else 16).
+constexpr int CV_WG = 128;
+template <int NS, bool DOWN>
+__global__ __launch_bounds__(CV_WG) void k_conv_cols(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
+                                                     const CvJob *__restrict__ jobs, uint32_t y0,
+                                                     const ModQ *__restrict__ mods, const double *__restrict__ twt,
+                                                     const double *__restrict__ itwt, const double *__restrict__ ninvt,
+                                                     const double *__restrict__ ctab, const double *__restrict__ half,
+                                                     uint32_t L, uint32_t logN)
 {
-    const uint32_t N = 1u << logN;
-    const uint32_t k = blockIdx.x * TPB + threadIdx.x;
-    if (k >= N) return;
-    const BcJob jb = jobs[blockIdx.y + y0];
-    const uint32_t ns = NS > 0 ? (uint32_t)NS : jb.nsrc;
+    const uint32_t N = 1u << logN, S = N >> 3;
+    const uint32_t c = blockIdx.x * CV_WG + threadIdx.x;
+    if (c >= S) return;
+    const CvJob jb = jobs[blockIdx.y + y0];
+    const uint32_t ns = NS > 0 ? (uint32_t)NS : jb.nsrc, nt = jb.ndst;
     const double *T = ctab + jb.off;
-    const double *dq = T + 3 * ns, *dqi = T + 3 * ns + jb.ndst, *qh = T + 3 * ns + 2 * jb.ndst;
-    const uint64_t *S = src + (size_t)jb.src0 * N + k;
-    uint64_t *D = dst + (size_t)jb.dst0 * N + k;
-    constexpr int NV = NS > 0 ? NS : 16;
-    double v[NV];
+    const double *hq = T + 3 * ns + 2 * nt;   // [nt][ns] (B/b_a) mod c_t
+    constexpr int NV = NS > 0 ? NS : (NS < 0 ? -NS : 16);
+    double v[NV][8];
 #pragma unroll
-    for (int a = 0; a < NV; ++a)
-        if (a < (int)ns) v[a] = bits_to_f64(S[(size_t)a * N]);
-    for (uint32_t t = 0; t < jb.ndst; ++t) {
-        const double q = dq[t], qi = dqi[t];
-        double acc = 0.0;
+    for (int a = 0; a < NV; ++a) {
+        if (a >= (int)ns) break;
+        const uint32_t m = jb.smod0 + a;
+        const double q = mods[m].q, qi = mods[m].qinv;
+        const double *w = itwt + (size_t)m * N;
+        const uint64_t *s = src + (size_t)(jb.src0 + a) * N + c;
+        double x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = bits_to_f64(s[(size_t)i * S]);
+        // inverse stage on bit 0 (pairs i, i+1), then bit 1 (i, i+2)
+#pragma unroll
+        for (int i = 0; i < 8; i += 2) {
+            const double U = x[i], V = x[i + 1];
+            x[i] = redc(U + V, q, qi);
+            x[i + 1] = mulmod(U - V, w[4 + (i >> 1)], q, qi);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (i & 2) continue;
+            const double U = x[i], V = x[i + 2];
+            x[i] = redc(U + V, q, qi);
+            x[i + 2] = mulmod(U - V, w[2 + (i >> 2)], q, qi);
+        }
+        // last stage (bit 2) with N^-1 (B/b_a)^-1 folded in
+        const double f = canon(mulmod(ninvt[m], T[a], q, qi), q, qi);
+        const double fw = canon(mulmod(w[1], f, q, qi), q, qi);
+        double h = 0.0;
+        if (DOWN) h = canon(mulmod(half[m], T[a], q, qi), q, qi);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double U = x[i], V = x[i + 4];
+            double r0 = mulmod(U + V, f, q, qi), r1 = mulmod(U - V, fw, q, qi);
+            if (DOWN) {
+                r0 += h;
+                r1 += h;
+            }
+            v[a][i] = canon(r0, q, qi);
+            v[a][i + 4] = canon(r1, q, qi);
+        }
+    }
+    for (uint32_t tt = 0; tt < nt; ++tt) {
+        const uint32_t m = tt < jb.glo ? tt : (tt < (uint32_t)jb.l - jb.gn ? tt + jb.gn : L + tt - (jb.l - jb.gn));
+        const double q = mods[m].q, qi = mods[m].qinv;
+        const double *h = hq + (size_t)tt * ns;
+        double y[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) y[i] = 0.0;
 #pragma unroll
         for (int a = 0; a < NV; ++a) {
-            if (a < (int)ns) {
-                acc += mulmod(v[a], qh[(size_t)t * ns + a], q, qi);
-                if ((a & 3) == 3) acc = redc(acc, q, qi);
+            if (a >= (int)ns) break;
+            const double ha = h[a];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                y[i] += mulmod(v[a][i], ha, q, qi);
+                if ((a & 3) == 3) y[i] = redc(y[i], q, qi);
             }
         }
-        if (SUB_HALF) acc -= hdst[t];
-        D[(size_t)t * N] = f64_to_u64(canon(acc, q, qi));
+        const double hd = DOWN ? half[m] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) y[i] = canon(DOWN ? y[i] - hd : y[i], q, qi);
+        // forward stages on bit 2 (pairs i, i+4), bit 1 (i, i+2), bit 0 (i, i+1)
+        const double *w = twt + (size_t)m * N;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double X = redc(y[i], q, qi), V = mulmod(y[i + 4], w[1], q, qi);
+            y[i] = X + V;
+            y[i + 4] = X - V;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (i & 2) continue;
+            const double X = y[i], V = mulmod(y[i + 2], w[2 + (i >> 2)], q, qi);
+            y[i] = X + V;
+            y[i + 2] = X - V;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; i += 2) {
+            const double X = redc(y[i], q, qi), V = mulmod(y[i + 1], w[4 + (i >> 1)], q, qi);
+            y[i] = X + V;
+            y[i + 1] = X - V;
+        }
+        uint64_t *o = dst + (size_t)(jb.dst0 + tt) * N + c;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[(size_t)i * S] = f64_to_bits(y[i]);
     }
-}
-// Forward column pass over a flat buffer (canonical in, lazy bits out).
-template <int LOGG, int WG>
-__global__ __launch_bounds__(WG) void k_col_fwd(uint64_t *__restrict__ base, const uint64_t *__restrict__ lst,
-                                                uint32_t y0, const ModQ *__restrict__ mods,
-                                                const double *__restrict__ twt, uint32_t logN)
-{
-    using Gm = Geom<LOGG, WG, true>;
-    __shared__ double lds[Gm::LDS];
-    const uint32_t N = 1u << logN;
-    const uint64_t e = lst[blockIdx.y + y0];
-    const uint32_t m = (uint32_t)(e & 0xFFFF);
-    const double q = mods[m].q, qinv = mods[m].qinv;
-    uint64_t *p = base + (size_t)(e >> 32) * N;
-    const Gm gm(logN, blockIdx.x);
-    double x[R];
-#pragma unroll
-    for (int k = 0; k < R; k++) x[k] = u64_to_f64(p[gm.fwd_in(k)]);
-    gm.fwd(x, lds, twt + (size_t)m * N, q, qinv, logN, 0);
-#pragma unroll
-    for (int k = 0; k < R; k++) p[gm.fwd_out(k)] = f64_to_bits(x[k]);
 }
 
 // ---- rescale over a ragged batch (item b: l_b limbs, P polys).  Table:
@@ -616,20 +654,57 @@ void in_pieces(uint32_t total, F f)
     for (uint32_t y0 = 0; y0 < total; y0 += GRID_Y) f(y0, std::min(GRID_Y, total - y0));
 }
 
+// Geometry of the key-switching transforms: rows of 2^LOGW = N/8 elements (T lanes
+// each, RPB rows per WG-thread block, GB blocks per limb) and the 3 column stages in
+// the conversions.  A row of 2^13 elements takes one 512-thread block and 69.6 KB of LDS.
+template <int LOGN>
+struct KsRow {
+    static constexpr int LOGW = LOGN - 3, T = 1 << (LOGW - 4);
+    static constexpr int WG0 = T < 256 ? 256 : T;
+    static constexpr int WG = WG0 < T * 8 ? WG0 : T * 8;
+    static constexpr int GB = 8 * T / WG;
+};
+template <typename F>
+void dispatch_row(const fhe_ctx *c, F f)
+{
+    switch (c->logN) {
+    case 10: f(KsRow<10>{}); break;
+    case 11: f(KsRow<11>{}); break;
+    case 12: f(KsRow<12>{}); break;
+    case 13: f(KsRow<13>{}); break;
+    case 14: f(KsRow<14>{}); break;
+    case 15: f(KsRow<15>{}); break;
+    case 16: f(KsRow<16>{}); break;
+    default: break;
+    }
+}
+
 // Host plan of one ragged batch.
 struct KsPlan {
     uint32_t n, sum_l, sum_dc, sum_nd, sum_ups, sum_inner, max_grp;
     uint32_t up_ns, dn_ns;   // sources of every ModUp (ModDown) conversion job, 0 if they differ
+    uint32_t up_max, dn_max; // most sources of a job
     std::vector<KsItem> items;
-    std::vector<BcJob> upjobs, dnjobs;
+    std::vector<CvJob> upjobs, dnjobs;
     std::vector<KsGrp> groups;
     std::vector<uint64_t> la, upmods, inner, fl, pl;
 };
 
-fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *d,
+// g^-1 mod 2N for odd g (the units mod 2N form a group of order N, so g^-1 = g^(N-1))
+uint32_t galois_inverse(uint32_t g, uint32_t N)
+{
+    if (!g) return 0;
+    const uint64_t m = 2ull * N;
+    uint64_t r = 1, b = g % m;
+    for (uint64_t e = N - 1; e; e >>= 1, b = b * b % m)
+        if (e & 1) r = r * b % m;
+    return (uint32_t)r;
+}
+
+fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint64_t *const *d, const uint32_t *gal,
                    const uint64_t *const *evk, KsPlan &pl)
 {
-    const uint32_t K = c->K, alpha = c->alpha;
+    const uint32_t K = c->K, L = c->L, alpha = c->alpha;
     pl.n = n;
     pl.items.assign(n, KsItem{});
     uint32_t dc = 0, up = 0, uq = 0;
@@ -637,7 +712,7 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     std::map<std::pair<const uint64_t *, uint32_t>, uint32_t> first;
     for (uint32_t b = 0; b < n; ++b) {
         const uint32_t l = ls[b];
-        if (l < 1 || l > c->L) return fhe_fail(FHE_ELEVEL, "key switch: limb count out of range");
+        if (l < 1 || l > L) return fhe_fail(FHE_ELEVEL, "key switch: limb count out of range");
         const uint32_t nd = (l + alpha - 1) / alpha;
         if (nd > 16) return fhe_fail(FHE_EPARAM, "key switching supports at most 16 digits");
         if (b >= 32768) return fhe_fail(FHE_EINVAL, "key-switch batch too large");
@@ -645,13 +720,14 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
         it.l = l;
         it.nd = nd;
         it.uq_off = uq;
+        it.ginv = galois_inverse(gal ? gal[b] : 0u, c->N);
         for (uint32_t tt = 0; tt < 2; ++tt) {
             const BconvTab &md = c->moddown[l];
-            pl.dnjobs.push_back(BcJob{md.off, md.nsrc, md.ndst, (2 * b + tt) * K, uq + tt * l, 0});
+            pl.dnjobs.push_back(CvJob{md.off, (uint16_t)md.nsrc, (uint16_t)md.ndst, (2 * b + tt) * K, uq + tt * l,
+                                      (uint8_t)L, (uint8_t)l, 0, (uint8_t)l, 0});
             for (uint32_t i = 0; i < l; ++i)
                 pl.fl.push_back(((uint64_t)b << 17) | ((uint64_t)tt << 16) | i | ((uint64_t)(uq + tt * l + i) << 32));
-            for (uint32_t k = 0; k < K; ++k)
-                pl.pl.push_back((uint64_t)(c->L + k) | ((uint64_t)(md.off + k) << 32));
+            for (uint32_t k = 0; k < K; ++k) pl.pl.push_back((uint64_t)(L + k));
         }
         uq += 2 * l;
         const auto key = std::make_pair(d[b], l);
@@ -669,29 +745,34 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
         uint32_t u = 0;
         for (uint32_t j = 0; j < nd; ++j) {
             const BconvTab &t = c->modup[(size_t)l * c->dnum + j];
+            const uint32_t lo = j * alpha;
             it.upoff[j] = (uint16_t)u;
-            pl.upjobs.push_back(BcJob{t.off, t.nsrc, t.ndst, dc + j * alpha, up + u, 0});
+            pl.upjobs.push_back(CvJob{t.off, (uint16_t)t.nsrc, (uint16_t)t.ndst, dc + lo, up + u, (uint8_t)lo,
+                                      (uint8_t)lo, (uint8_t)t.nsrc, (uint8_t)l, 0});
             for (uint32_t a = 0; a < t.ndst; ++a) pl.upmods.push_back(t.dst[a] | ((uint64_t)(up + u + a) << 32));
             u += t.ndst;
         }
-        for (uint32_t i = 0; i < l; ++i) {
-            const BconvTab &t = c->modup[(size_t)l * c->dnum + i / alpha];
-            pl.la.push_back(((uint64_t)b << 16) | i | ((uint64_t)(t.off + i % alpha) << 32));
-        }
+        for (uint32_t i = 0; i < l; ++i) pl.la.push_back(((uint64_t)b << 16) | i);
         dc += l;
         up += u;
     }
-    auto common_ns = [](const std::vector<BcJob> &js) {
+    auto common_ns = [](const std::vector<CvJob> &js) {
         const uint32_t ns = js.empty() ? 0u : js[0].nsrc;
-        for (const BcJob &j : js)
+        for (const CvJob &j : js)
             if (j.nsrc != ns) return 0u;
         return ns;
     };
+    auto max_ns = [](const std::vector<CvJob> &js) {
+        uint32_t m = 0;
+        for (const CvJob &j : js) m = std::max<uint32_t>(m, j.nsrc);
+        return m;
+    };
     pl.up_ns = common_ns(pl.upjobs);
     pl.dn_ns = common_ns(pl.dnjobs);
-    // the ModUp digits' forward passes in modulus order (their row-pass twiddles are then
-    // read once per modulus: 22% less HBM traffic for the row pass, at the same speed);
-    // the ModDown finish keeps item order, which measured faster than modulus order
+    pl.up_max = max_ns(pl.upjobs);
+    pl.dn_max = max_ns(pl.dnjobs);
+    // the ModUp digits' forward row passes (grouped path) in modulus order: their
+    // twiddles are then read once per modulus
     std::stable_sort(pl.upmods.begin(), pl.upmods.end(),
                      [](uint64_t a, uint64_t b) { return (a & 0xFFFF) < (b & 0xFFFF); });
     // groups of items with the same key and level, in order of first appearance
@@ -723,70 +804,53 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
 }  // namespace
 
 // ---- launchers of the key-switching path
-template <int EPI>
-static void ks_col_inv(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs, const char *cat)
-{
-    ProfScope ps(c, cat);
-    dispatch_logn(c, [&](auto sh) {
-        using S = decltype(sh);
-        in_pieces(nlimbs, [&](uint32_t y0, uint32_t cnt) {
-            hipLaunchKernelGGL((k_col_inv<S::LOGA, S::WA, EPI>), dim3(S::GA, cnt), dim3(S::WA), 0, c->stream, base, lst,
-                               y0, (const ModQ *)c->d_mod, (const double *)c->d_itw, (const double *)c->d_ninv, c->logN,
-                               (const double *)c->d_bconv, (const double *)c->d_phalf);
-        });
-    });
-}
 static void ks_row_fwd(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs)
 {
     ProfScope ps(c, "ntt_fwd_row");
-    dispatch_logn(c, [&](auto sh) {
+    dispatch_row(c, [&](auto sh) {
         using S = decltype(sh);
         in_pieces(nlimbs, [&](uint32_t y0, uint32_t cnt) {
-            hipLaunchKernelGGL((k_row_fwd<S::LOGB, S::WB>), dim3(S::GB, cnt), dim3(S::WB), 0, c->stream, base, lst, y0,
-                               (const ModQ *)c->d_mod, (const double *)c->d_tw, c->logN, (uint32_t)S::LOGA);
+            hipLaunchKernelGGL((k_row_fwd<S::LOGW, S::WG>), dim3(S::GB, cnt), dim3(S::WG), 0, c->stream, base, lst, y0,
+                               (const ModQ *)c->d_mod, (const double *)c->d_tw, c->logN, 3u);
         });
     });
 }
 static void ks_row_inv(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs)
 {
     ProfScope ps(c, "ntt_inv_row");
-    dispatch_logn(c, [&](auto sh) {
+    dispatch_row(c, [&](auto sh) {
         using S = decltype(sh);
         in_pieces(nlimbs, [&](uint32_t y0, uint32_t cnt) {
-            hipLaunchKernelGGL((k_row_inv<S::LOGB, S::WB>), dim3(S::GB, cnt), dim3(S::WB), 0, c->stream, base, lst, y0,
-                               (const ModQ *)c->d_mod, (const double *)c->d_itw, c->logN, (uint32_t)S::LOGA);
+            hipLaunchKernelGGL((k_row_inv<S::LOGW, S::WG>), dim3(S::GB, cnt), dim3(S::WG), 0, c->stream, base, lst, y0,
+                               (const ModQ *)c->d_mod, (const double *)c->d_itw, c->logN, 3u);
         });
     });
 }
-// ns: the number of sources of every job, or 0 when they differ
-template <bool SUB_HALF>
-static void ks_bconv(fhe_ctx *c, const uint64_t *src, uint64_t *dst, const uint64_t *jobs, uint32_t njobs,
-                     uint32_t ns, const char *cat)
+// ns: the number of sources of every job, or 0 when they differ (then mx: the most)
+template <bool DOWN>
+static void ks_conv(fhe_ctx *c, const uint64_t *src, uint64_t *dst, const uint64_t *jobs, uint32_t njobs,
+                    uint32_t ns, uint32_t mx, const char *cat)
 {
     ProfScope ps(c, cat);
     in_pieces(njobs, [&](uint32_t y0, uint32_t cnt) {
-        const dim3 grid(blocks_for(c->N, TPB), cnt);
-#define BCONV_GO(NSV)                                                                                           \
-    hipLaunchKernelGGL((k_bconv<SUB_HALF, NSV>), grid, dim3(TPB), 0, c->stream, src, dst,                       \
-                       (const double *)c->d_bconv, (const BcJob *)jobs, y0, c->logN, (const double *)c->d_phalf)
+        const dim3 grid(blocks_for(c->N / 8, CV_WG), cnt);
+#define CONV_GO(NSV)                                                                                          \
+    hipLaunchKernelGGL((k_conv_cols<NSV, DOWN>), grid, dim3(CV_WG), 0, c->stream, src, dst, (const CvJob *)jobs, \
+                       y0, (const ModQ *)c->d_mod, (const double *)c->d_tw, (const double *)c->d_itw,          \
+                       (const double *)c->d_ninv, (const double *)c->d_bconv, (const double *)c->d_phalf, c->L,   \
+                       c->logN)
         switch (ns) {
-        case 2: BCONV_GO(2); break;
-        case 4: BCONV_GO(4); break;
-        case 8: BCONV_GO(8); break;
-        default: BCONV_GO(0); break;
+        case 1: CONV_GO(1); break;
+        case 2: CONV_GO(2); break;
+        case 3: CONV_GO(3); break;
+        case 4: CONV_GO(4); break;
+        case 8: CONV_GO(8); break;
+        default:
+            if (mx <= 8) CONV_GO(-8);
+            else CONV_GO(0);
+            break;
         }
-#undef BCONV_GO
-    });
-}
-static void ks_col_fwd(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs)
-{
-    ProfScope ps(c, "ntt_fwd_col");
-    dispatch_logn(c, [&](auto sh) {
-        using S = decltype(sh);
-        in_pieces(nlimbs, [&](uint32_t y0, uint32_t cnt) {
-            hipLaunchKernelGGL((k_col_fwd<S::LOGA, S::WA>), dim3(S::GA, cnt), dim3(S::WA), 0, c->stream, base, lst, y0,
-                               (const ModQ *)c->d_mod, (const double *)c->d_tw, c->logN);
-        });
+#undef CONV_GO
     });
 }
 
@@ -819,7 +883,7 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     if (2ull * n > GRID_Y) return fhe_fail(FHE_EINVAL, "key-switch batch too large");
     KsPlan pl;
     fhe_status s;
-    if ((s = ks_plan(c, n, ls, d, evk, pl))) return s;
+    if ((s = ks_plan(c, n, ls, d, gal, evk, pl))) return s;
 
     // scratch: dc [sum l of distinct inputs], up [their ups], uQ [sum 2l], uP [n][2][K],
     // z [sum 2l] (ks_scratch_bytes_ragged counts every input as distinct)
@@ -848,13 +912,13 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     kt.la = (uint32_t)tab.size();
     push_words(pl.la.data(), pl.la.size() * 8);
     kt.uj = (uint32_t)tab.size();
-    push_words(pl.upjobs.data(), pl.upjobs.size() * sizeof(BcJob));
+    push_words(pl.upjobs.data(), pl.upjobs.size() * sizeof(CvJob));
     kt.um = (uint32_t)tab.size();
     push_words(pl.upmods.data(), pl.upmods.size() * 8);
     kt.il = (uint32_t)tab.size();
     push_words(pl.inner.data(), pl.inner.size() * 8);
     kt.dj = (uint32_t)tab.size();
-    push_words(pl.dnjobs.data(), pl.dnjobs.size() * sizeof(BcJob));
+    push_words(pl.dnjobs.data(), pl.dnjobs.size() * sizeof(CvJob));
     kt.fl = (uint32_t)tab.size();
     push_words(pl.fl.data(), pl.fl.size() * 8);
     kt.pl = (uint32_t)tab.size();
@@ -867,40 +931,33 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     hipStream_t st = c->stream;
     const uint32_t sum2l = 2 * pl.sum_l;
 
-    // 1. coefficients of the distinct inputs
+    // 1. inverse row pass of the distinct inputs
     {
         ProfScope ps(c, "ks_intt_first");
-        dispatch_logn(c, [&](auto sh) {
+        dispatch_row(c, [&](auto sh) {
             using S = decltype(sh);
             in_pieces(pl.sum_dc, [&](uint32_t y0, uint32_t cnt) {
-                hipLaunchKernelGGL((k_ks_intt_first<S::LOGB, S::WB>), dim3(S::GB, cnt), dim3(S::WB), 0, st,
+                hipLaunchKernelGGL((k_ks_intt_first<S::LOGW, S::WG>), dim3(S::GB, cnt), dim3(S::WG), 0, st,
                                    (uint64_t *const *)dt, kt, y0, dc, (const ModQ *)c->d_mod, (const double *)c->d_itw,
-                                   c->logN, (uint32_t)S::LOGA);
+                                   c->logN, 3u);
             });
         });
     }
-    ks_col_inv<1>(c, dc, dwords + kt.la, pl.sum_dc, "ntt_inv_col");
-    // 2-3. ModUp conversion, the forward column pass of the converted limbs, then
-    //      their row pass (alone, or inside the inner product)
-    ks_bconv<false>(c, dc, up, dwords + kt.uj, pl.sum_nd, pl.up_ns, "bconv_up");
-    ks_col_fwd(c, up, dwords + kt.um, pl.sum_ups);
-    bool permuted = false;
-    for (uint32_t b = 0; gal && b < n; ++b) permuted = permuted || gal[b] != 0;
-    if (pl.max_grp == 1 && c->tune_fuse_row_inner && !permuted) {
-        // 3+4. row pass of the converted digits fused with the key inner product
+    // 2. ModUp: column stages and conversion of every digit
+    ks_conv<false>(c, dc, up, dwords + kt.uj, pl.sum_nd, pl.up_ns, pl.up_max, "bconv_up");
+    // 3. forward row pass of the converted limbs and the key inner product
+    if (pl.max_grp == 1 && c->tune_fuse_row_inner) {
         ProfScope ps(c, "ks_inner");
-        dispatch_logn(c, [&](auto sh) {
+        dispatch_row(c, [&](auto sh) {
             using S = decltype(sh);
             in_pieces(pl.sum_inner, [&](uint32_t y0, uint32_t cnt) {
-                hipLaunchKernelGGL((k_ks_row_inner<S::LOGB, S::WB>), dim3(S::GB, cnt), dim3(S::WB), 0, st,
+                hipLaunchKernelGGL((k_ks_row_inner<S::LOGW, S::WG>), dim3(S::GB, cnt), dim3(S::WG), 0, st,
                                    (uint64_t *const *)dt, kt, y0, (const uint64_t *)up, uQ, uP, (const ModQ *)c->d_mod,
-                                   (const double *)c->d_tw, c->alpha, c->logN, (uint32_t)S::LOGA);
+                                   (const double *)c->d_tw, c->alpha, c->logN, 3u);
             });
         });
     } else {
-    ks_row_fwd(c, up, dwords + kt.um, pl.sum_ups);
-    // 4. key inner product over the digits
-    {
+        ks_row_fwd(c, up, dwords + kt.um, pl.sum_ups);
         ProfScope ps(c, "ks_inner");
         in_pieces(pl.sum_inner, [&](uint32_t y0, uint32_t cnt) {
             if (pl.max_grp > 1)
@@ -913,23 +970,20 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
                                    (const ModQ *)c->d_mod, c->alpha, c->logN);
         });
     }
-    }
-    // 5-6. ModDown: P limbs to coefficients (prepared as conversion sources), the
-    //      rounded conversion to Q_l, the forward column pass of z
+    // 4-5. ModDown: inverse row pass of the P limbs, then their column stages and the
+    //      rounded conversion to Q_l with the first forward column stages of z
     ks_row_inv(c, uP, dwords + kt.pl, n * 2 * K);
-    ks_col_inv<2>(c, uP, dwords + kt.pl, n * 2 * K, "ntt_inv_col");
-    ks_bconv<true>(c, uP, z, dwords + kt.dj, 2 * n, pl.dn_ns, "bconv_down");
-    ks_col_fwd(c, z, dwords + kt.fl, sum2l);
-    // 7. row pass of z fused with the finish
+    ks_conv<true>(c, uP, z, dwords + kt.dj, 2 * n, pl.dn_ns, pl.dn_max, "bconv_down");
+    // 6. row pass of z fused with the finish
     {
         ProfScope ps(c, "ks_moddown_final");
-        dispatch_logn(c, [&](auto sh) {
+        dispatch_row(c, [&](auto sh) {
             using S = decltype(sh);
             in_pieces(sum2l, [&](uint32_t y0, uint32_t cnt) {
-                hipLaunchKernelGGL((k_ks_moddown_final<S::LOGB, S::WB>), dim3(S::GB, cnt), dim3(S::WB), 0, st,
+                hipLaunchKernelGGL((k_ks_moddown_final<S::LOGW, S::WG>), dim3(S::GB, cnt), dim3(S::WG), 0, st,
                                    (uint64_t *const *)dt, kt, y0, (const uint64_t *)z, (const uint64_t *)uQ,
                                    (const ModQ *)c->d_mod, (const double *)c->d_tw, (const double *)c->d_pinv,
-                                   c->logN, (uint32_t)S::LOGA);
+                                   c->logN, 3u);
             });
         });
     }

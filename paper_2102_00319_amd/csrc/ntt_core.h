@@ -32,9 +32,12 @@ struct Geom {
     static constexpr int LDS = GPW * GS;
     int grp, tau;
     uint32_t gi, N2;
-    __device__ __forceinline__ Geom(uint32_t logN, uint32_t block)
+    __device__ __forceinline__ Geom(uint32_t logN, uint32_t block) : Geom(logN, block, threadIdx.x) {}
+    // tid: this lane's thread index (passed through an opaque copy, it keeps the compiler
+    // from holding every derived address across an outer loop)
+    __device__ __forceinline__ Geom(uint32_t logN, uint32_t block, uint32_t tid_)
     {
-        const int tid = threadIdx.x;
+        const int tid = (int)tid_;
         grp = COL ? (tid % GPW) : (tid / T);
         tau = COL ? (tid / GPW) : (tid % T);
         gi = block * GPW + grp;

@@ -322,8 +322,10 @@ static size_t poly_act3_item_bytes(const fhe_ctx *c, uint32_t l)
     return (2 * (size_t)l + 4 * ((size_t)l - 1) + 2 * ((size_t)l - 2)) * c->N * sizeof(uint64_t) +
            rescale_scratch_bytes(c, l, 2, 1);
 }
+// Cubic activation at depth 2: (c3 u + c2) u^2 + (c1 u + c0), each constant an integer
+// multiple chosen so that the branches meet at one scale.
 static fhe_status poly_act3(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_t n, const double *coef,
-                            uint32_t deg, fhe_ct *y)
+                            fhe_ct *y)
 {
     fhe_status s;
     const uint32_t l = x[0].limbs;
@@ -347,55 +349,41 @@ static fhe_status poly_act3(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uin
         Bc[i] = Bp[i];
     }
     const double ql = (double)c->mod[l - 1], ql2 = (double)c->mod[l - 2];
-    const uint32_t cl = deg == 3 ? 3 : 2;   // coefficient of the branch that is multiplied by u (or u^2)
-    // a = Rescale(round(coef[cl] * q_(l-1)) * x) + coef[cl-1]
+    // a = Rescale(round(c3 * q_(l-1)) * x) + c2
     Consts64 k1, k2;
-    if ((s = const_residues(c, coef[cl] * ql, l, &k1))) return s;
+    if ((s = const_residues(c, coef[3] * ql, l, &k1))) return s;
     if ((s = ew_batch(c, EW_MULC, l, l, 2, n, xin.data(), nullptr, Tp.data(), k1))) return s;
     if ((s = rescale_many(c, l, n, Tc, Ap))) return s;
     const double sA = S * ql / ql;
-    if ((s = const_residues(c, coef[cl - 1] * sA, l - 1, &k2))) return s;
+    if ((s = const_residues(c, coef[2] * sA, l - 1, &k2))) return s;
     if ((s = ew_batch(c, EW_ADDC, l - 1, l - 1, 2, n, Ac.data(), nullptr, Ap.data(), k2))) return s;
     c->ops[OP_PT_MULT] += n;
     c->ops[OP_PT_ADD] += n;
     std::vector<uint64_t *> A1(Ap.begin(), Ap.end()), B1;
     std::vector<uint32_t> off(n + 1);
     for (uint32_t i = 0; i <= n; ++i) off[i] = i;
-    if (deg == 3) {
-        // u^2, then p = Rescale(Relin(a (x) u^2))
-        std::vector<uint64_t *> X2(n);
-        for (uint32_t i = 0; i < n; ++i) X2[i] = x[i].d;
-        if ((s = mac_relin_rescale(c, rlk, l, X2, X2, off, Up))) return s;
-        const double sU = S * S / ql;
-        if ((s = mac_relin_rescale(c, rlk, l - 1, A1, Up, off, Yp))) return s;
-        const double sp = sA * sU / ql2;
-        // b = Rescale(round(c1 * s1) * x at l-1 limbs) + c0, s1 chosen so that b lands on sp
-        const double s1 = sp * ql2 / S;
-        Consts64 k3, k4;
-        if ((s = const_residues(c, coef[1] * s1, l - 1, &k3))) return s;
-        if ((s = ew_batch(c, EW_MULC, l - 1, l, 2, n, xin.data(), nullptr, Tp.data(), k3))) return s;
-        if ((s = rescale_many(c, l - 1, n, Tc, Bp))) return s;
-        const double sB = S * s1 / ql2;
-        if ((s = const_residues(c, coef[0] * sB, l - 2, &k4))) return s;
-        if ((s = ew_batch(c, EW_ADDC, l - 2, l - 2, 2, n, Bc.data(), nullptr, Bp.data(), k4))) return s;
-        std::vector<const uint64_t *> Yc(Yp.begin(), Yp.end());
-        if ((s = ew_batch(c, EW_ADD, l - 2, l - 2, 2, n, Yc.data(), Bc.data(), Yp.data(), zero_consts()))) return s;
-        c->ops[OP_PT_MULT] += n;
-        c->ops[OP_PT_ADD] += n;
-        c->ops[OP_CT_ADD] += n;
-        for (uint32_t i = 0; i < n; ++i) y[i].scale = sp;
-    } else {
-        // p = Rescale(Relin(a (x) x at l-1 limbs)) + c0
-        if ((s = ew_batch(c, EW_COPY, l - 1, l, 2, n, xin.data(), nullptr, Up.data(), zero_consts()))) return s;
-        if ((s = mac_relin_rescale(c, rlk, l - 1, A1, Up, off, Yp))) return s;
-        const double sp = sA * S / ql2;
-        Consts64 k4;
-        if ((s = const_residues(c, coef[0] * sp, l - 2, &k4))) return s;
-        std::vector<const uint64_t *> Yc(Yp.begin(), Yp.end());
-        if ((s = ew_batch(c, EW_ADDC, l - 2, l - 2, 2, n, Yc.data(), nullptr, Yp.data(), k4))) return s;
-        c->ops[OP_PT_ADD] += n;
-        for (uint32_t i = 0; i < n; ++i) y[i].scale = sp;
-    }
+    // u^2, then p = Rescale(Relin(a (x) u^2))
+    std::vector<uint64_t *> X2(n);
+    for (uint32_t i = 0; i < n; ++i) X2[i] = x[i].d;
+    if ((s = mac_relin_rescale(c, rlk, l, X2, X2, off, Up))) return s;
+    const double sU = S * S / ql;
+    if ((s = mac_relin_rescale(c, rlk, l - 1, A1, Up, off, Yp))) return s;
+    const double sp = sA * sU / ql2;
+    // b = Rescale(round(c1 * s1) * x at l-1 limbs) + c0, s1 chosen so that b lands on sp
+    const double s1 = sp * ql2 / S;
+    Consts64 k3, k4;
+    if ((s = const_residues(c, coef[1] * s1, l - 1, &k3))) return s;
+    if ((s = ew_batch(c, EW_MULC, l - 1, l, 2, n, xin.data(), nullptr, Tp.data(), k3))) return s;
+    if ((s = rescale_many(c, l - 1, n, Tc, Bp))) return s;
+    const double sB = S * s1 / ql2;
+    if ((s = const_residues(c, coef[0] * sB, l - 2, &k4))) return s;
+    if ((s = ew_batch(c, EW_ADDC, l - 2, l - 2, 2, n, Bc.data(), nullptr, Bp.data(), k4))) return s;
+    std::vector<const uint64_t *> Yc(Yp.begin(), Yp.end());
+    if ((s = ew_batch(c, EW_ADD, l - 2, l - 2, 2, n, Yc.data(), Bc.data(), Yp.data(), zero_consts()))) return s;
+    c->ops[OP_PT_MULT] += n;
+    c->ops[OP_PT_ADD] += n;
+    c->ops[OP_CT_ADD] += n;
+    for (uint32_t i = 0; i < n; ++i) y[i].scale = sp;
     return FHE_OK;
 }
 
@@ -422,14 +410,15 @@ fhe_status fhe_poly_act(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *x, uint32_
         if ((s = chk2(&x[i], l, "fhe_poly_act")) || (s = chk2(&y[i], l - depth, "fhe_poly_act"))) return s;
         if (x[i].scale != S) return fhe_fail(FHE_ESCALE, "fhe_poly_act: input scales differ");
     }
-    // output scale: depth 1, S^2 / c2 / q_(l-1); depth 2, about S (each branch lands on S q_(l-1) / q_(l-1))
-    const double so = deg == 2 ? S * S / coef[2] / (double)c->mod[l - 1] : S;
+    // output scale: depth 1, S^2 / c2 / q_(l-1); depth 2, S (S^2 / q_(l-1)) / q_(l-2)
+    const double so = deg == 2 ? S * S / coef[2] / (double)c->mod[l - 1]
+                               : S * (S * S / (double)c->mod[l - 1]) / (double)c->mod[l - 2];
     if (!scale_has_room(c, l - depth, so)) return scale_room_error("fhe_poly_act");
     const size_t per = deg == 2 ? poly_act2_item_bytes(c, l) : poly_act3_item_bytes(c, l);
     const uint32_t C = (uint32_t)std::max<size_t>(1, std::min<size_t>(n, ((size_t)2 << 30) / per));
     for (uint32_t t0 = 0; t0 < n; t0 += C) {
         const uint32_t cn = std::min(C, n - t0);
-        s = deg == 2 ? poly_act2(c, rlk, x + t0, cn, coef, y + t0) : poly_act3(c, rlk, x + t0, cn, coef, deg, y + t0);
+        s = deg == 2 ? poly_act2(c, rlk, x + t0, cn, coef, y + t0) : poly_act3(c, rlk, x + t0, cn, coef, y + t0);
         if (s) return s;
     }
     return FHE_OK;

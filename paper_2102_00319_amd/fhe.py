@@ -5,8 +5,10 @@ tensors used as raw 64-bit residue storage) and the current HIP stream.  If
 the library is missing this module raises at import time: there is no CPU
 fallback.
 """
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -91,6 +93,7 @@ _sig = {
     "fhe_rotate": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), C.c_int32, C.POINTER(fhe_ct)],
     "fhe_keyswitch": [_P, C.POINTER(fhe_evk), _P, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_keyswitch_batch": [_P, C.POINTER(fhe_evk), _P, C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
+    "fhe_ctx_set_allocator": [_P, _P, _P, _P],
     "fhe_rotate_batch": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), _P, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_profile_enable": [_P, C.c_char_p],
     "fhe_op_counts": [_P, _P],
@@ -134,13 +137,26 @@ _lib.fhe_last_error.restype = C.c_char_p
 _lib.fhe_graph_destroy.argtypes = [_P]
 _lib.fhe_graph_destroy.restype = None
 for _n, _r in [("fhe_ring_degree", C.c_uint32), ("fhe_modulus", C.c_uint64), ("fhe_evk_bytes", C.c_size_t),
-               ("fhe_galois_elt", C.c_uint64), ("fhe_scratch_bytes", C.c_uint64)]:
+               ("fhe_galois_elt", C.c_uint64), ("fhe_scratch_bytes", C.c_uint64), ("fhe_workspace_bytes", C.c_uint64)]:
     getattr(_lib, _n).restype = _r
+_lib.fhe_workspace_bytes.argtypes = [_P]
 _lib.fhe_ring_degree.argtypes = [_P]
 _lib.fhe_modulus.argtypes = [_P, C.c_uint32]
 _lib.fhe_evk_bytes.argtypes = [_P]
 _lib.fhe_galois_elt.argtypes = [_P, C.c_int32]
 _lib.fhe_scratch_bytes.argtypes = [_P]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+# contexts whose buffers come from torch: closed before the interpreter tears torch down
+_TORCH_ALLOC_CTXS = weakref.WeakSet()
+
+
+@atexit.register
+def _close_torch_alloc_ctxs():
+    for ctx in list(_TORCH_ALLOC_CTXS):
+        ctx.close()
 
 
 def lib():
@@ -149,7 +165,7 @@ def lib():
 
 def exported_symbols():
     return sorted(_sig) + ["fhe_ctx_destroy", "fhe_last_error", "fhe_ring_degree", "fhe_modulus", "fhe_evk_bytes",
-                           "fhe_galois_elt", "fhe_scratch_bytes", "fhe_graph_destroy"]
+                           "fhe_galois_elt", "fhe_scratch_bytes", "fhe_workspace_bytes", "fhe_graph_destroy"]
 
 
 def _check(rc):
@@ -320,6 +336,33 @@ class Context:
 
     def scratch_bytes(self):
         return int(_lib.fhe_scratch_bytes(self._h))
+
+    def library_bytes(self):
+        """Device memory the context's growable buffers hold (scratch and layer workspace)."""
+        return int(_lib.fhe_scratch_bytes(self._h)) + int(_lib.fhe_workspace_bytes(self._h))
+
+    def use_torch_allocator(self):
+        """Take the context's scratch and layer workspace from torch's caching allocator
+        (fhe_ctx_set_allocator), on the context's stream: the library's memory then shares
+        torch's cache and its accounting.  A refused allocation fails the call that needed
+        it (FHE_ENOMEM) before any work."""
+        dev = self.device.index if self.device.index is not None else torch.cuda.current_device()
+        me = weakref.ref(self)
+
+        def alloc(nbytes, hip_stream, user):
+            ctx = me()
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, ctx.stream if ctx else None)
+            except torch.OutOfMemoryError:
+                return None
+
+        def free(ptr, user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc_cbs = (_ALLOC_FN(alloc), _FREE_FN(free))   # kept alive with the context
+        _check(_lib.fhe_ctx_set_allocator(self._h, C.cast(self._alloc_cbs[0], C.c_void_p),
+                                          C.cast(self._alloc_cbs[1], C.c_void_p), None))
+        _TORCH_ALLOC_CTXS.add(self)
 
     # ---------------------------------------------------- limbs / IO
     @staticmethod

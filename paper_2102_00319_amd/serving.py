@@ -26,25 +26,9 @@ import time
 import numpy as np
 import torch
 
-from .fhe import FHE_EDEVICE, Context, CtArray, FheError
+from .fhe import Context, CtArray
 
 PIN_BLOCK = 1 << 30   # pinned host mirrors are packed into blocks of this size
-
-
-def retry_out_of_memory(fn, release):
-    """fn(), and once more after release() if the device refused an allocation: the
-    library allocates its workspaces outside torch, so memory torch caches (blocks of
-    evicted client state) can leave it short.  A refused allocation comes before any
-    work of the call that needed it, and a forward pass writes only fresh outputs."""
-    try:
-        return fn()
-    except FheError as e:
-        if e.code != FHE_EDEVICE or "out of memory" not in str(e):
-            raise
-    except torch.OutOfMemoryError:
-        pass
-    release()
-    return fn()
 
 
 class Client:
@@ -150,7 +134,13 @@ class Lane:
     def __init__(self, set_names, device):
         self.stream = torch.cuda.Stream(device=device)
         self.ctx = {n: Context.from_set(n, stream=self.stream) for n in set_names}
+        for ctx in self.ctx.values():   # the library's buffers come from torch's cache and budget
+            ctx.use_torch_allocator()
         self.group, self.thread, self.finished, self.error, self.ws = None, None, False, None, 0
+
+    def library_bytes(self):
+        """Device memory the lane's contexts hold for their scratch and workspaces."""
+        return sum(ctx.library_bytes() for ctx in self.ctx.values())
 
 
 class Server:
@@ -214,7 +204,16 @@ class Server:
         return done
 
     def resident_bytes(self):
-        return sum(c.nbytes for c in self.clients if c.resident) + sum(l.ws for l in self.lanes)
+        """Client state on the device, plus per lane the larger of its running batch's
+        working set (which reserves the scratch the batch may grow to) and the library
+        memory its contexts hold."""
+        return sum(c.nbytes for c in self.clients if c.resident) + sum(
+            max(l.ws, self._library_bytes(l)) for l in self.lanes)
+
+    @staticmethod
+    def _library_bytes(lane):
+        f = getattr(lane, "library_bytes", None)
+        return f() if f else 0
 
     def host_bytes(self):
         return sum(c.host_bytes() for c in self.clients)
@@ -350,14 +349,9 @@ class Server:
         c = group[0].client
         ctx = lane.ctx[c.set_name]
 
-        def release():
-            lane.stream.synchronize()
-            torch.cuda.empty_cache()
-            self.stats["oom_retries"] += 1
-
         def work():
             try:
-                retry_out_of_memory(batch, release)
+                batch()
             except Exception as e:   # reported by the scheduler thread
                 lane.error = e
             lane.finished = True

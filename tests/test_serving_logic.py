@@ -286,26 +286,20 @@ def test_async_loads_serve_every_request():
     assert all(c.inflight == 0 and not c.hold for c in cs)     # every client evictable again
 
 
-def test_retry_once_after_a_refused_allocation():
-    from paper_2102_00319_amd.fhe import FHE_EDEVICE, FHE_ELEVEL, FheError
-    calls, released = [], []
-
-    def flaky():
-        calls.append(1)
-        if len(calls) == 1:
-            raise FheError(FHE_EDEVICE, "hipMalloc((void **)&c->wksp, bytes): out of memory")
-        return "scores"
-    assert serving.retry_out_of_memory(flaky, lambda: released.append(1)) == "scores"
-    assert len(calls) == 2 and released == [1]
-
-    def level():
-        raise FheError(FHE_ELEVEL, "fhe_rescale: one limb left")
-    with pytest.raises(FheError):
-        serving.retry_out_of_memory(level, lambda: released.append(2))
-    assert released == [1]                       # other errors are not retried
-
-    def always():
-        raise FheError(FHE_EDEVICE, "hipMalloc(p, bytes): out of memory")
-    with pytest.raises(FheError):
-        serving.retry_out_of_memory(always, lambda: released.append(3))
-    assert released == [1, 3]                    # one retry only
+def test_library_memory_of_lanes_counts_against_the_budget():
+    """Memory a lane's contexts hold for their scratch and workspace (from torch's
+    allocator) is resident: an idle lane counts what it holds, a running one the
+    larger of that and its batch's working set."""
+    srv = FakeServer(hbm_budget=1000)
+    held = {"bytes": 0}
+    for lane in srv.lanes:
+        lane.library_bytes = lambda: held["bytes"]
+    c = FakeClient(0, "slot", 300)
+    srv.add_client(c)
+    base = srv.resident_bytes()
+    held["bytes"] = 50
+    assert srv.resident_bytes() == base + 50 * len(srv.lanes)
+    srv.lanes[0].ws = 120
+    assert srv.resident_bytes() == base + 120 + 50 * (len(srv.lanes) - 1)
+    srv.lanes[0].ws = 20
+    assert srv.resident_bytes() == base + 50 * len(srv.lanes)
