@@ -34,6 +34,11 @@ PROFILE_CATEGORIES = ["ntt_fwd", "ntt_fwd_col", "ntt_fwd_row", "ntt_inv", "ntt_i
                       "elementwise", "rescale"]
 
 
+def say(msg):
+    """A progress line on stderr (the JSON record alone goes to stdout)."""
+    print(msg, file=sys.stderr, flush=True)
+
+
 def source_digest(path):
     """sha256[:16] of a source file's code: // comments, trailing blanks and empty lines
     removed, so that a comment edit does not count as a change of the kernel."""
@@ -110,6 +115,53 @@ def _oracle_keyswitch_once(arg):
     return time.perf_counter() - t0
 
 
+def _oracle_units(arg):
+    """Oracle timings on one core for the CPU baselines of the primitives (config 1's
+    ops at N = 2^12) and of the networks (per-unit costs at the networks' shapes)."""
+    what, seed = arg
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import workloads
+    from oracle import OracleCtx
+    from oracle.ckks import Ct
+
+    def clock(fn):
+        t0 = time.perf_counter()
+        r = fn()
+        return time.perf_counter() - t0, r
+    if what == "config1":
+        o = OracleCtx.from_set("c1_n12")
+        n, D = o.N // 2, o.scale
+        s = o.keygen_secret(workloads.SEED_SECRET)
+        pk = o.keygen_pk(s, workloads.SEED_PK)
+        rlk = o.keygen_relin(s, workloads.SEED_EVK)
+        gk = o.keygen_rot(s, 1, workloads.SEED_EVK + 1)
+        a, b = workloads.slot_messages(1, n), workloads.slot_messages(2, n)
+        out = {}
+        out["encode"], pa = clock(lambda: o.encode_rns(a, D, o.L))
+        pb = o.encode_rns(b, D, o.L)
+        out["encrypt"], ca = clock(lambda: o.encrypt(pk, pa, workloads.SEED_ENC, D))
+        cb = o.encrypt(pk, pb, workloads.SEED_ENC + 1, D)
+        out["hmult_relin_rescale"], m = clock(lambda: o.mul_relin_rescale(ca, cb, rlk))
+        out["rotate"], r = clock(lambda: o.rotate(m, 1, gk))
+        out["decrypt"], pt = clock(lambda: o.decrypt(r, s))
+        out["decode"], _ = clock(lambda: o.decode(pt, r.scale))
+        return what, {k: round(v * 1e3, 3) for k, v in out.items()}
+    # one tensor product (and for config 2 one relinearisation) at a network's shape
+    name, l = {"tensor_c4": ("c4_n16", 24), "units_c2": ("c2_n14", 8)}[what]
+    o = OracleCtx.from_set(name)
+    x = Ct(np.stack([workloads.uniform_residues(seed + i, o.q[:l], o.N) for i in range(2)]), 1.0)
+    y = Ct(np.stack([workloads.uniform_residues(seed + 2 + i, o.q[:l], o.N) for i in range(2)]), 1.0)
+    t_t, t3 = clock(lambda: o.tensor(x, y))
+    res = {"tensor_ms": round(t_t * 1e3, 1)}
+    if what == "units_c2":
+        M = o.L + o.K
+        evk = workloads.uniform_residues(seed + 9, o.moduli * (2 * o.dnum), o.N).reshape(o.dnum, 2, M, o.N)
+        t_r, _ = clock(lambda: o.relin(t3, evk))
+        res["relin_ms"] = round(t_r * 1e3, 1)
+    return what, res
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,15 +169,18 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=8, help="rotations (distinct keys) per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="key switch only: skip the short encrypted-CNN runs added to the line")
     ap.add_argument("--cpu-procs", type=int, default=16,
                     help="oracle processes for the CPU baseline (one GPU's share of the host)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB copy kernel (reference for HBM byte counters)")
     ap.add_argument("--param-set", default="c4_n16")
     ap.add_argument("--row-wg", type=int, default=128, choices=[128, 256],
-                    help="keyswitch / cnn4: workgroup size of the row passes")
-    ap.add_argument("--ks-fuse", type=int, default=0, choices=[0, 1],
-                    help="keyswitch: fuse the digits' row pass into the key inner product (1) or not (0)")
+                    help="cnn4: workgroup size of the rescale's row pass")
+    ap.add_argument("--ks-fuse", type=int, default=None, choices=[0, 1],
+                    help="keyswitch: fuse the converted limbs' row pass into the key inner product (1) or not "
+                         "(0); default: chosen by the autotuner on the step")
     ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "kssweep", "cnn2", "cnn4", "batch3", "serve", "fig3", "paper",
                                                            "latency"],
                     help="keyswitch: the headline metric; cnn2: slot-packed encrypted CNN images/s; "
@@ -241,6 +296,10 @@ def _packed_cnn_fp64(imgs, w1, w2, wfc, coef):
 
 
 def cnn4(args):
+    print(json.dumps(run_cnn4(args)))
+
+
+def run_cnn4(args):
     """Within-image packed deep CNN (32 images of 28 x 28 per ciphertext, N = 2^16,
     24 limbs): conv 3x3 x 8 -> cubic -> pool -> conv 3x3 x 16 -> cubic -> pool -> FC 784->10,
     images and weights encrypted; one step = one forward pass over one ciphertext batch."""
@@ -271,6 +330,12 @@ def cnn4(args):
                                                   workloads.SEED_ENC + 300000))
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
+    # kernel knobs chosen by measurement on the forward pass itself
+    key = "cnn4|%s|%s" % (args.act, torch.cuda.get_device_name(0))
+    say("cnn4: keys, images and weights ready (%.1f s)" % t_setup)
+    tuned, _ = runtime.tune_knobs(runtime.Autotuner(), key, [g], lambda: net.forward(g, rlk, gks, X, Wt),
+                                  ["ks_fuse_row_inner"], reps=2)
+    say("cnn4: knobs %s" % tuned)
     g.op_counts()
     out = net.forward(g, rlk, gks, X, Wt)
     ops = g.op_counts()
@@ -283,6 +348,7 @@ def cnn4(args):
         out = net.forward(g, rlk, gks, X, Wt)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    say("cnn4: %.1f ms per batch, max error %.2e" % (dt * 1e3, err))
     # per-category kernel time of one forward pass
     g.profile_enable("*")
     net.forward(g, rlk, gks, X, Wt)
@@ -302,6 +368,7 @@ def cnn4(args):
     dg = (time.perf_counter() - t0) / args.steps
     graph_same = all(np.array_equal(g.export_ct(a), g.export_ct(b)) for a, b in zip(zg, out))
     gf.close()
+    say("cnn4: %.1f ms per batch as one graph" % (dg * 1e3))
     # several ciphertext batches in flight: one graph per context, each context on its own
     # stream (keys and weights are shared device buffers), replayed together
     conc = None
@@ -310,6 +377,7 @@ def cnn4(args):
         gfs = []
         for c in ctxs:
             c.set_tuning("row_wg", args.row_wg)
+            runtime.apply_knobs([c], tuned)
             gfs.append(runtime.GraphedForward(c, lambda xs, c=c: net.forward(c, rlk, gks, xs, Wt), X))
         for _ in range(max(1, args.warmup)):
             for f in gfs:
@@ -333,11 +401,12 @@ def cnn4(args):
            "ops_per_batch": {k: ops[k] for k in ("ct_mult", "relin", "rotate", "rescale")},
            "kernel_ms_per_batch": breakdown,
            "graph_images_per_s": round(B / dg, 1), "graph_ms_per_batch": round(dg * 1e3, 3),
-           "graph_equals_eager_bitwise": bool(graph_same), "graph_concurrent": conc,
+           "graph_equals_eager_bitwise": bool(graph_same), "graph_concurrent": conc, "autotuned": tuned,
            "config": {"workload": "conv3x3x8 -> {a} -> avgpool -> conv3x3x16 -> {a} -> avgpool -> FC784x10, "
                                   "32 images of 28x28 per ciphertext, N=2^16, 24 limbs, dnum 3".format(
                                       a="cubic" if args.act == "cubic" else "g (quadratic, depth 1)")}}
     if args.unbatched:   # one ciphertext per library call
+        say("cnn4: one ciphertext per call")
         ou = net.forward_per_op(g, rlk, gks, X, Wt)
         same = all(np.array_equal(g.export_ct(a), g.export_ct(b)) for a, b in zip(ou, out))
         torch.cuda.synchronize()
@@ -348,7 +417,7 @@ def cnn4(args):
         rec["unbatched_images_per_s"] = round(B / du, 1)
         rec["unbatched_ms_per_batch"] = round(du * 1e3, 2)
         rec["unbatched_equals_batched_bitwise"] = bool(same)
-    print(json.dumps(rec))
+    return rec
 
 
 def batch3(args):
@@ -405,6 +474,10 @@ def batch3(args):
     t_unb = time.perf_counter() - t0
 
     tuner = runtime.Autotuner()
+    # the kernel knobs first (on the eager schedule), then the schedule with them applied
+    knobs, _ = runtime.tune_knobs(tuner, ub.signature() + "|knobs", list(ctxs.values()),
+                                  lambda: ub.run({"graph": False, "concurrent": True, "chunk": 0}),
+                                  ["ks_fuse_row_inner", "row_wg"], reps=2)
     best, times = tuner.tune(ub.signature(), ub.candidates(), lambda c: ub.time(c, reps=3))
     for _ in range(args.warmup):
         ub.run(best)
@@ -437,7 +510,7 @@ def batch3(args):
            "unbatched_jobs_per_s": round(len(jobs) / t_unb, 1), "unbatched_ms": round(t_unb * 1e3, 2),
            "speedup_vs_unbatched": round(t_unb / dt, 2), "batched_equals_unbatched_bitwise": bool(same),
            "hbm_frac_algorithmic": round(nbytes / dt / (HBM_PEAK_GBS * 1e9), 4),
-           "algorithmic_bytes_per_step": nbytes, "autotuned": best,
+           "algorithmic_bytes_per_step": nbytes, "autotuned": best, "autotuned_knobs": knobs,
            "autotune_ms": {k: round(v * 1e3, 3) for k, v in times.items()}, "setup_s": round(t_setup, 1),
            "config": {"workload": "256 jobs, N in {2^13, 2^14, 2^15}, levels uniform 2..L, steps +-1, +-28",
                       "jobs_per_ring": {n: sum(1 for s_, _ in spec if s_ == n) for n in ctxs}}}
@@ -612,13 +685,15 @@ def _paper_cnn_fp64(imgs, wc, wfc, coef):
 
 
 def paper(args):
+    print(json.dumps(run_paper(args)))
+
+
+def run_paper(args):
     """The paper's network at its ring (m = 2^16: N = 2^15, 16384 images per batch,
     Sec. 4.3): conv 3x3 x 28 without padding, ActPool (g and 2x2 mean), FC 4732 -> 10,
     images and weights encrypted.  One step = one forward pass over the batch.  The
     paper's own run takes 561 s for the batch on 112 POWER9 threads (Sec. 4.4), quoted
     as context only."""
-    raise SystemExit("the paper-network run is switched off: its first GPU run was killed for silence with a "
-                     "process left blocked in the GPU driver, and the cause is not yet found")
     import numpy as np
     import torch
 
@@ -637,11 +712,12 @@ def paper(args):
     s = g.keygen_secret(workloads.SEED_SECRET)
     pk = g.keygen_pk(s, workloads.SEED_PK)
     rlk, _ = net.keygen(g, s, workloads.SEED_EVK)
-    X = net.encrypt_images(g, pk, imgs, workloads.SEED_ENC)
+    X = net.encrypt_images(g, pk, imgs, workloads.SEED_ENC, progress=lambda m: say("paper: " + m))
     W = net.encrypt_weights(g, pk, wc, wfc, (workloads.SEED_ENC + 100000, workloads.SEED_ENC + 200000))
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
-    out = net.forward(g, rlk, {}, X, W)
+    say("paper: keys, images and weights ready (%.1f s)" % t_setup)
+    out = net.forward(g, rlk, {}, X, W, progress=lambda m: say("paper: " + m))
     err = float(np.abs(net.decrypt_scores(g, s, out, B) - _paper_cnn_fp64(imgs, wc, wfc, net.coef)).max())
     del out
     torch.cuda.synchronize()
@@ -651,6 +727,7 @@ def paper(args):
         del out
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    say("paper: %.3f s per batch, max error %.2e" % (dt, err))
     g.profile_enable("*")
     out = net.forward(g, rlk, {}, X, W)
     torch.cuda.synchronize()
@@ -663,7 +740,7 @@ def paper(args):
            "kernel_ms_per_batch": {k: round(v, 1) for k, v in sorted(prof.items(), key=lambda kv: -kv[1]) if v > 0},
            "config": {"workload": "conv3x3x28 (no pad) -> ActPool(g, 2x2 mean) -> FC4732x10, N=2^15, 16 limbs "
                                   "(q0 ~2^50, 15 x ~2^40), scale 2^40, 16384 images, band %d" % args.band}}
-    print(json.dumps(rec))
+    return rec
 
 
 def kssweep(args):
@@ -782,6 +859,10 @@ def latency(args):
 
 
 def cnn2(args):
+    print(json.dumps(run_cnn2(args)))
+
+
+def run_cnn2(args):
     """Slot-packed encrypted CNN (8192 images per ciphertext): conv 5x5 stride 2 x 5
     channels -> x^2 -> FC 845->fc1 -> x^2 -> FC fc1->10; images and weights encrypted."""
     import numpy as np
@@ -817,6 +898,12 @@ def cnn2(args):
         Y = g.conv2d_slot(rlk, X, H, W, 1, Wc, Cout, K, K, 2, 1, 1, Ho, Wo)
         return g.fc_slot(rlk, g.square_act(rlk, g.fc_slot(rlk, g.square_act(rlk, Y), W1, n1)), W2, n2)
 
+    from paper_2102_00319_amd import runtime
+    key = "cnn2|fc1=%d|%s" % (n1, torch.cuda.get_device_name(0))
+    say("cnn2: keys, images and weights ready (%.1f s)" % t_setup)
+    tuned, _ = runtime.tune_knobs(runtime.Autotuner(), key, [g], forward, ["ks_fuse_row_inner", "row_wg"], reps=2)
+    say("cnn2: knobs %s" % tuned)
+
     out = forward()
     ref = _slot_cnn_fp64(imgs, cw, f1, f2)
     err = max(float(np.abs(g.decode(g.decrypt(s, out[r]), n=B)[0] - ref[:, r]).max()) for r in range(n2))
@@ -828,6 +915,7 @@ def cnn2(args):
         out = forward()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    say("cnn2: %.1f ms per batch, max error %.2e" % (dt * 1e3, err))
     # per-category kernel time of one forward pass
     g.profile_enable("*")
     forward()
@@ -842,7 +930,7 @@ def cnn2(args):
     rec = {"metric": "encrypted-CNN images/s (slot packing, batched layers)", "value": round(B / dt, 1),
            "unit": "images/s", "ms_per_batch": round(dt * 1e3, 3), "images_per_batch": B, "steps": args.steps,
            "max_abs_logit_error_vs_fp64": err, "setup_s": round(t_setup, 1), "kernel_ms_per_batch": breakdown,
-           "compulsory_GB_per_batch": round((wbytes + xbytes) / 1e9, 2),
+           "compulsory_GB_per_batch": round((wbytes + xbytes) / 1e9, 2), "autotuned": tuned,
            "hbm_frac_compulsory": round((wbytes + xbytes) / dt / (HBM_PEAK_GBS * 1e9), 4),
            "config": {"workload": "conv5x5s2x5 -> x^2 -> FC845x%d -> x^2 -> FC%dx10, N=2^14, 8 x ~40-bit primes, "
                                   "scale 2^40" % (n1, n1), "weight_ciphertexts": int(cw.size + f1.size + f2.size)}}
@@ -863,6 +951,7 @@ def cnn2(args):
             Z = [mrr([(A[i], W1[r * len(A) + i]) for i in range(len(A))]) for r in range(n1)]
             A2 = [mrr([(z, z)]) for z in Z]
             return [mrr([(A2[i], W2[r * n1 + i]) for i in range(n1)]) for r in range(n2)]
+        say("cnn2: one ciphertext per call")
         ou = forward_unbatched()
         same = all(np.array_equal(g.export_ct(a), g.export_ct(b)) for a, b in zip(ou, out))
         torch.cuda.synchronize()
@@ -873,7 +962,7 @@ def cnn2(args):
         rec["unbatched_images_per_s"] = round(B / du, 1)
         rec["unbatched_ms_per_batch"] = round(du * 1e3, 2)
         rec["unbatched_equals_batched_bitwise"] = bool(same)
-    print(json.dumps(rec))
+    return rec
 
 
 def main():
@@ -910,9 +999,26 @@ def main():
         c0 = time.perf_counter()
         with mp.get_context("spawn").Pool(cores) as pool:
             per = pool.map(_oracle_keyswitch_once, [(args.param_set, 90 + 2 * i) for i in range(cores)])
-        c1 = time.perf_counter()
+            c1 = time.perf_counter()
+            units = dict(pool.map(_oracle_units, [("config1", 0), ("tensor_c4", 500), ("units_c2", 600)]))
+        t_ks = sum(per) / len(per)
+        # whole-network times on one core, from the per-unit costs and the networks' op
+        # counts (tensor products at the full level, an upper bound for the deeper ones):
+        # deep CNN 1432 tensor products + 302 key switches; slot CNN 106,925 tensor
+        # products + 1900 relinearisations
+        t4 = 1432 * units["tensor_c4"]["tensor_ms"] / 1e3 + 302 * t_ks
+        t2 = (106925 * units["units_c2"]["tensor_ms"] + 1900 * units["units_c2"]["relin_ms"]) / 1e3
         cpu = {"value": round(cores / (c1 - c0), 4), "unit": "key-switch/s", "cores": cores, "kind": "oracle",
                "host_cpu": model, "host_logical_cpus": nproc, "allowed_cpus": allowed,
+               "config1_ms_per_op_one_core": units["config1"],
+               "network_estimates_one_core": {
+                   "deep_cnn_n16_s_per_32_images": round(t4, 1),
+                   "slot_cnn_n14_fc1_100_s_per_8192_images": round(t2, 1),
+                   "units": {"tensor_n16_l24_ms": units["tensor_c4"]["tensor_ms"],
+                             "tensor_n14_l8_ms": units["units_c2"]["tensor_ms"],
+                             "relin_n14_l8_ms": units["units_c2"]["relin_ms"], "keyswitch_n16_l24_s": round(t_ks, 2)},
+                   "how": "per-unit oracle times on one core times the networks' operation counts (an estimate; "
+                          "divide by the cores for a parallel run)"},
                "sample": "%d key switches at N=2^16, l=24, K=8, dnum=3 (random inputs and keys), one per process, "
                          "%.1f s wall (%.1f s per key switch on one core)" % (cores, c1 - c0, sum(per) / len(per))}
         print("cpu baseline: %s" % cpu["sample"], file=sys.stderr, flush=True)
@@ -923,8 +1029,8 @@ def main():
     import paper_2102_00319_amd as P
 
     torch.cuda.set_device(0)
+    say("keyswitch: context %s, %d rotation keys" % (args.param_set, args.batch))
     g = P.Context.from_set(args.param_set)
-    g.set_tuning("ks_fuse_row_inner", args.ks_fuse)
     g.set_tuning("row_wg", args.row_wg)
     N, l, K, alpha = g.N, g.L, g.K, g.alpha
     B = args.batch
@@ -954,6 +1060,20 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
+    # the kernel knob of this path: chosen by measurement on the step itself (or fixed)
+    from paper_2102_00319_amd import runtime
+    tuned = None
+    if args.ks_fuse is None:
+        tuner = runtime.Autotuner()
+        key = "keyswitch|%s|B%d|%s" % (args.param_set, B, torch.cuda.get_device_name(0))
+        best, times = runtime.tune_knobs(tuner, key, [g], step, ["ks_fuse_row_inner"], reps=5)
+        args.ks_fuse = best["ks_fuse_row_inner"]
+        tuned = {"choice": best, "ms_per_step": None if times is None else
+                 {k: round(v * 1e3, 4) for k, v in times.items()}}
+    else:
+        g.set_tuning("ks_fuse_row_inner", args.ks_fuse)
+
+    say("keyswitch: ks_fuse_row_inner %d%s" % (args.ks_fuse, " (tuned)" if tuned else ""))
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -981,6 +1101,7 @@ def main():
 
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     ks_per_s = B * args.steps / (t1 - t0)
+    say("keyswitch: %.1f key switches/s (%.4f ms per step)" % (ks_per_s, ms_per_step))
     # compulsory bytes of one key switch with its own key: input l limbs, key
     # dnum*2*(L+K) limbs, output 2*l limbs (8 bytes per residue)
     ks_bytes = (l + g.dnum * 2 * (g.L + g.K) + 2 * l) * N * 8
@@ -1025,13 +1146,58 @@ def main():
         "config": {"workload": "rotation key switch, N=2^16, l=24 limbs (~49-bit), K=8 special primes, dnum=3, "
                                "%d distinct Galois keys per step" % B,
                    "batch": B, "ring_degree": N, "limbs": l, "special_primes": K, "dnum": g.dnum,
-                   "ks_fuse_row_inner": args.ks_fuse, "row_wg": args.row_wg},
+                   "ks_fuse_row_inner": args.ks_fuse, "autotuned": tuned},
         "hbm_frac_compulsory": round(hbm_frac, 4),
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernel_ms_per_step": {c: round(v[0] / 3, 4) for c, v in per_cat.items() if v[1]},
     }
+    if not args.no_extras:
+        del outs, cts, gks, g
+        rec["cnn"] = cnn_extras(args)
     print(json.dumps(rec))
+
+
+def cnn_extras(args):
+    """The encrypted-CNN part of the metric, from short runs after the key-switch
+    measurement: the deep CNN (N = 2^16) batched and one ciphertext per call, the slot
+    CNN (N = 2^14, FC1 = 100) batched and one ciphertext per call, and the paper's
+    network at its ring; images/s and the largest score error against FP64 each."""
+    import gc
+    import types
+
+    import torch
+
+    def free():
+        gc.collect()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+    out = {}
+    common = dict(steps=3, warmup=1, row_wg=args.row_wg, graph_streams=0, unbatched=True)
+    runs = [("deep_cnn_n16", run_cnn4, dict(act="cubic")),
+            ("slot_cnn_n14_fc1_100", run_cnn2, dict(fc1=100)),
+            ("paper_cnn_n15", run_paper, dict(band=2, unbatched=False))]
+    for name, fn, kw in runs:
+        say("extras: %s" % name)
+        t0 = time.perf_counter()
+        a = types.SimpleNamespace(**{**common, **kw})
+        try:
+            r = fn(a)
+        except Exception as e:   # reported in the record; the key-switch line still prints
+            out[name] = {"error": "%s: %s" % (type(e).__name__, e)}
+            free()
+            continue
+        keep = {k: r[k] for k in ("value", "unit", "ms_per_batch", "s_per_batch", "images_per_batch",
+                                  "max_abs_logit_error_vs_fp64", "unbatched_images_per_s",
+                                  "unbatched_equals_batched_bitwise", "setup_s") if k in r}
+        keep["wall_s"] = round(time.perf_counter() - t0, 1)
+        keep["workload"] = r["config"]["workload"]
+        out[name] = keep
+        print("extras: %s %s images/s (%.1f s)" % (name, r["value"], keep["wall_s"]), file=sys.stderr, flush=True)
+        del r
+        free()
+    return out
 
 
 if __name__ == "__main__":

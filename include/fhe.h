@@ -116,6 +116,9 @@ uint64_t fhe_workspace_bytes(const fhe_ctx *ctx);                 /* layer works
 typedef void *(*fhe_alloc_fn)(size_t bytes, void *hip_stream, void *user);
 typedef void (*fhe_free_fn)(void *ptr, void *user);
 fhe_status fhe_ctx_set_allocator(fhe_ctx *ctx, fhe_alloc_fn alloc_fn, fhe_free_fn free_fn, void *user);
+/* Return the context's scratch and layer workspace (after its stream drains); the
+ * next call that needs them allocates again.  Not while capturing (FHE_EINVAL). */
+fhe_status fhe_ctx_release_buffers(fhe_ctx *ctx);
 
 /* Kernel timing for measurement: after fhe_profile_enable(ctx, cat) every
  * launch of kernel category cat ("*" = all; categories: ntt_fwd, ntt_inv,
@@ -240,13 +243,13 @@ fhe_status fhe_graph_end(fhe_ctx *const *ctxs, uint32_t n, fhe_graph *g);
 fhe_status fhe_graph_launch(fhe_graph *g, void *hip_stream);   /* null: the first context's stream */
 void fhe_graph_destroy(fhe_graph *g);                          /* waits for the device first */
 
-/* Tuning knobs read by the batched drivers (autotuned by the Python layer):
+/* Tuning knobs read by the batched drivers; the Python runtime's autotuner measures
+ * their combinations on a workload and keeps the fastest.  None changes a result.
  *   "chunk_items": most items per ragged launch sequence (0 = no limit);
- *   "ks_fuse_row_inner": 1 fuses the forward row pass of the converted digits into
- *     the key inner product when every item has its own key; 0 (default) runs them
- *     as two kernels.  Results are the same;
- *   "row_wg": 128 (default) or 256, the workgroup size of the row passes of the key
- *     switch and the rescale (same results). */
+ *   "ks_fuse_row_inner": 1 (default) fuses the forward row pass of the converted limbs
+ *     into the key inner product when every item of a key switch has its own key;
+ *     0 runs them as two kernels;
+ *   "row_wg": 128 (default) or 256, the workgroup size of the rescale's row pass. */
 fhe_status fhe_ctx_set_tuning(fhe_ctx *ctx, const char *key, uint64_t value);
 
 /* Batched relinearisation and rescale of n ciphertexts (host descriptor arrays;

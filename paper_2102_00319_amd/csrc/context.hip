@@ -214,6 +214,7 @@ extern "C" fhe_status fhe_ctx_create(const fhe_params *pp, void *hip_stream, uin
     fhe_ctx *c = new fhe_ctx();   // value-initialised: plain fields zero, containers constructed
     c->tune_row_wg = 128;
     c->tune_fuse_row_inner = 1;
+
     c->logN = logN; c->N = N; c->L = L; c->K = K; c->dnum = pp->dnum;
     c->alpha = (L + pp->dnum - 1) / pp->dnum;
     c->stream = (hipStream_t)hip_stream;
@@ -471,6 +472,18 @@ extern "C" fhe_status fhe_ctx_set_allocator(fhe_ctx *c, fhe_alloc_fn alloc_fn, f
     return s;
 }
 extern "C" uint64_t fhe_workspace_bytes(const fhe_ctx *c) { return c ? c->wksp_bytes : 0; }
+extern "C" fhe_status fhe_ctx_release_buffers(fhe_ctx *c)
+{
+    if (!c) return fhe_fail(FHE_EINVAL, "null context");
+    if (c->capturing) return fhe_fail(FHE_EINVAL, "fhe_ctx_release_buffers: context is capturing");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    fhe_status s = ctx_dev_free(c, c->scratch);
+    if (!s) s = ctx_dev_free(c, c->wksp);
+    c->used -= c->scratch_bytes + c->wksp_bytes;
+    c->scratch = c->wksp = nullptr;
+    c->scratch_bytes = c->wksp_bytes = 0;
+    return s;
+}
 
 // Upload a list of device pointers for the next launch(es) on the context's
 // stream.  Tables live in a ring over a device arena (copied from its pinned

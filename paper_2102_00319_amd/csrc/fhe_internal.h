@@ -182,8 +182,8 @@ struct fhe_ctx {
     fhe_free_fn free_fn;
     void *alloc_user;
     uint32_t tune_chunk;     // most items per ragged launch sequence (0: no limit)
-    uint32_t tune_fuse_row_inner;   // key switch: fuse the digits' row pass into the inner product
-    uint32_t tune_row_wg;    // key switch and rescale: row-pass workgroup cap (128 or 256)
+    uint32_t tune_fuse_row_inner;   // key switch: fuse the converted limbs' row pass into the inner product
+    uint32_t tune_row_wg;    // rescale: row-pass workgroup cap (128 or 256)
     struct Prof *prof;       // kernel timing (HIP events), null until enabled
     uint64_t ops[8];         // operation counters, see OP_* (read and reset by fhe_op_counts)
 };

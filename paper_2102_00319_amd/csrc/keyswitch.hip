@@ -267,38 +267,33 @@ __global__ __launch_bounds__(WG) void k_ks_row_inner(uint64_t *const *__restrict
     for (int k = 0; k < R; k++) a0[k] = a1[k] = 0.0;
 #pragma unroll 1
     for (uint32_t j = 0; j < nd; ++j) {
+        // every address below is the same for every digit: an opaque copy of the thread
+        // index keeps the compiler from computing all of them once before the loop and
+        // holding them in registers
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const Gm gj(logN, blockIdx.x, tid);
         const uint32_t lo = j * alpha, hi = min(lo + alpha, l);
         double v[R];
         if (x >= lo && x < hi) {   // block-uniform branch
             const gu64 *src = gview(tab[b] + (size_t)x * N);
 #pragma unroll
-            for (int k = 0; k < R; k++) v[k] = u64_to_f64(src[gm.coal(k)]);
+            for (int k = 0; k < R; k++) v[k] = u64_to_f64(src[gj.coal(k)]);
         } else {
             const uint32_t pos = x < lo ? x : x - (hi - lo);
             const uint64_t *src = up + ((size_t)it.up_off + it.upoff[j] + pos) * N;
 #pragma unroll
-            for (int k = 0; k < R; k++) v[k] = bits_to_f64(src[gm.fwd_in(k)]);
-            // the transform's addresses are the same for every digit: an opaque copy of
-            // the thread index keeps the compiler from computing all of them once before
-            // the loop and holding them (about 150 registers)
-            uint32_t tid = threadIdx.x;
-            asm volatile("" : "+v"(tid));
-            const Gm gj(logN, blockIdx.x, tid);
+            for (int k = 0; k < R; k++) v[k] = bits_to_f64(src[gj.fwd_in(k)]);
             gj.fwd(v, lds, twt + (size_t)mx * N, q, qi, logN, sigma0);
             gj.fwd_out_to_coal(v, lds);
         }
         const gu64 *e0 = gview(ev + (((size_t)j * 2 + 0) * ML + mx) * N);
         const gu64 *e1 = gview(ev + (((size_t)j * 2 + 1) * ML + mx) * N);
-        // the key products in quarters, so that few key loads are in flight at once
 #pragma unroll
-        for (int h = 0; h < R; h += 4) {
-#pragma unroll
-            for (int k = h; k < h + 4; k++) {
-                const uint32_t y = galois_src(gm.coal(k), ginv, logN);
-                a0[k] += mulmod(v[k], u64_to_f64(e0[y]), q, qi);
-                a1[k] += mulmod(v[k], u64_to_f64(e1[y]), q, qi);
-            }
-            __builtin_amdgcn_sched_barrier(0);
+        for (int k = 0; k < R; k++) {
+            const uint32_t y = galois_src(gj.coal(k), ginv, logN);
+            a0[k] += mulmod(v[k], u64_to_f64(e0[y]), q, qi);
+            a1[k] += mulmod(v[k], u64_to_f64(e1[y]), q, qi);
         }
         if ((j & 3) == 3) {
 #pragma unroll

@@ -16,12 +16,16 @@ constexpr int R = 1 << LOGR;
 
 // Local index of register k of lane tau in a round covering bits [blo, blo+rho).
 template <int LOGT>
-__device__ __forceinline__ int elem_local(int tau, int k, int blo, int rho)
+__host__ __device__ constexpr int elem_local(int tau, int k, int blo, int rho)
 {
-    int fr = ((k >> rho) << LOGT) | tau;
+    const int fr = ((k >> rho) << LOGT) | tau;
     return ((fr >> blo) << (blo + rho)) | ((k & ((1 << rho) - 1)) << blo) | (fr & ((1 << blo) - 1));
 }
-__device__ __forceinline__ int lds_pad(int g) { return g + (g >> LOGR); }
+// The lane's part and the register's part of elem_local have disjoint bits, so
+// elem_local(tau, k) = elem_local(tau, 0) + elem_local(0, k), and the same holds for
+// their right shifts and for lds_pad: a lane computes its part once per round and
+// every register adds a compile-time constant (an immediate offset of its load).
+__host__ __device__ constexpr int lds_pad(int g) { return g + (g >> LOGR); }
 
 template <int LOGG, int WG, bool COL>
 struct Geom {
@@ -47,41 +51,84 @@ struct Geom {
     {
         return COL ? gi + (uint32_t)g * N2 : (gi << LOGG) + (uint32_t)g;
     }
+    __device__ __forceinline__ uint32_t gidx2(int gt, int gk) const   // gidx(gt + gk), disjoint bits
+    {
+        return COL ? gi + (uint32_t)gt * N2 + (uint32_t)gk * N2 : (gi << LOGG) + (uint32_t)gt + (uint32_t)gk;
+    }
+    __device__ __forceinline__ int lt(int blo, int rho) const { return elem_local<LOGT>(tau, 0, blo, rho); }
+    static constexpr int lk(int k, int blo, int rho) { return elem_local<LOGT>(0, k, blo, rho); }
     // forward: registers hold round-0 elements on entry, last-round elements on exit
-    __device__ __forceinline__ uint32_t fwd_in(int k) const { return gidx(elem_local<LOGT>(tau, k, LOGG - LOGR, LOGR)); }
-    __device__ __forceinline__ uint32_t fwd_out(int k) const { return gidx(elem_local<LOGT>(tau, k, 0, RL)); }
+    __device__ __forceinline__ uint32_t fwd_in(int k) const
+    {
+        return gidx2(lt(LOGG - LOGR, LOGR), lk(k, LOGG - LOGR, LOGR));
+    }
+    __device__ __forceinline__ uint32_t fwd_out(int k) const { return gidx2(lt(0, RL), lk(k, 0, RL)); }
     // inverse: the opposite round order
     __device__ __forceinline__ uint32_t inv_in(int k) const
     {
-        return gidx(elem_local<LOGT>(tau, k, 0, LOGG < LOGR ? LOGG : LOGR));
+        constexpr int r0 = LOGG < LOGR ? LOGG : LOGR;
+        return gidx2(lt(0, r0), lk(k, 0, r0));
     }
     __device__ __forceinline__ uint32_t inv_out(int k) const
     {
-        return gidx(elem_local<LOGT>(tau, k, (NR - 1) * LOGR, RL));
+        return gidx2(lt((NR - 1) * LOGR, RL), lk(k, (NR - 1) * LOGR, RL));
     }
 
     // Coalesced order: register k of lane tau holds local element k*T + tau, so that
     // for a fixed k consecutive lanes touch consecutive addresses (ROW groups).
-    __device__ __forceinline__ uint32_t coal(int k) const { return gidx((k << LOGT) | tau); }
-    // Redistribute through LDS: from the forward output order to the coalesced order.
+    __device__ __forceinline__ uint32_t coal(int k) const { return gidx2(tau, k << LOGT); }
+    // Exchange through LDS: register k goes to the slot of round (wb, wr) and comes
+    // back from the slot of round (rb, rr).
+    __device__ __forceinline__ void exchange(double (&x)[R], double *lds, int wb, int wr, int rb, int rr) const
+    {
+        double *w = lds + grp * GS + lds_pad(lt(wb, wr));
+#pragma unroll
+        for (int k = 0; k < R; k++) w[lds_pad(lk(k, wb, wr))] = x[k];
+        __syncthreads();
+        const double *r = lds + grp * GS + lds_pad(lt(rb, rr));
+#pragma unroll
+        for (int k = 0; k < R; k++) x[k] = r[lds_pad(lk(k, rb, rr))];
+        __syncthreads();
+    }
+    // coalesced order <-> the slot of a round (the coalesced index k*T + tau is the
+    // local index of register k in round (LOGT, 4) when the group has LOGT + 4 bits)
     __device__ __forceinline__ void fwd_out_to_coal(double (&x)[R], double *lds) const
     {
+        double *w = lds + grp * GS + lds_pad(lt(0, RL));
 #pragma unroll
-        for (int k = 0; k < R; k++) lds[grp * GS + lds_pad(elem_local<LOGT>(tau, k, 0, RL))] = x[k];
+        for (int k = 0; k < R; k++) w[lds_pad(lk(k, 0, RL))] = x[k];
         __syncthreads();
+        const double *r = lds + grp * GS + lds_pad(tau);
 #pragma unroll
-        for (int k = 0; k < R; k++) x[k] = lds[grp * GS + lds_pad((k << LOGT) | tau)];
+        for (int k = 0; k < R; k++) x[k] = r[lds_pad(k << LOGT)];
         __syncthreads();
     }
     // From the coalesced order to the inverse input order.
     __device__ __forceinline__ void coal_to_inv_in(double (&x)[R], double *lds) const
     {
+        constexpr int r0 = LOGG < LOGR ? LOGG : LOGR;
+        double *w = lds + grp * GS + lds_pad(tau);
 #pragma unroll
-        for (int k = 0; k < R; k++) lds[grp * GS + lds_pad((k << LOGT) | tau)] = x[k];
+        for (int k = 0; k < R; k++) w[lds_pad(k << LOGT)] = x[k];
         __syncthreads();
+        const double *r = lds + grp * GS + lds_pad(lt(0, r0));
 #pragma unroll
-        for (int k = 0; k < R; k++) x[k] = lds[grp * GS + lds_pad(elem_local<LOGT>(tau, k, 0, LOGG < LOGR ? LOGG : LOGR))];
+        for (int k = 0; k < R; k++) x[k] = r[lds_pad(lk(k, 0, r0))];
         __syncthreads();
+    }
+    // Twiddle base of a stage on local bit lb (sigma = sigma0 + LOGG - 1 - lb).  A ROW
+    // pass holds the last LOGG stages (sigma0 = logN - LOGG) and a COL pass the first
+    // (sigma0 = 0), so in both the table index (1 << sigma) + (j >> (logN - sigma))
+    // of element j = gidx(local) is (1 << sigma) + [ROW: gi << (LOGG - lb - 1)] +
+    // (local >> (lb + 1)), and local >> (lb + 1) splits into the lane's part and the
+    // register's constant.
+    __device__ __forceinline__ const double *tw_stage(const double *tw, uint32_t sigma0, int lb, int blo,
+                                                      int rho) const
+    {
+        const uint32_t sigma = sigma0 + (uint32_t)(LOGG - 1 - lb);
+        uint32_t base = (1u << sigma) + ((uint32_t)lt(blo, rho) >> (lb + 1));
+        if (!COL) base += gi << (LOGG - lb - 1);
+        return tw + base;
     }
 
     // Cooley-Tukey stages sigma0 .. sigma0 + LOGG - 1 (table psi^brv).  The upper input
@@ -96,25 +143,17 @@ struct Geom {
             const int bhi = LOGG - r * LOGR;
             const int rho = bhi < LOGR ? bhi : LOGR;
             const int blo = bhi - rho;
-            if (r > 0) {
-#pragma unroll
-                for (int k = 0; k < R; k++) lds[grp * GS + lds_pad(elem_local<LOGT>(tau, k, bhi, LOGR))] = x[k];
-                __syncthreads();
-#pragma unroll
-                for (int k = 0; k < R; k++) x[k] = lds[grp * GS + lds_pad(elem_local<LOGT>(tau, k, blo, rho))];
-                __syncthreads();
-            }
+            if (r > 0) exchange(x, lds, bhi, LOGR, blo, rho);
 #pragma unroll
             for (int s = 0; s < rho; s++) {
                 const int bit = rho - 1 - s;
                 const int lb = blo + bit;
-                const uint32_t sigma = sigma0 + (uint32_t)(LOGG - 1 - lb);
+                const double *tws = tw_stage(tw, sigma0, lb, blo, rho);
 #pragma unroll
                 for (int k = 0; k < R; k++) {
                     if (k & (1 << bit)) continue;
                     const int kt = k & ~((2 << bit) - 1);
-                    const uint32_t j = gidx(elem_local<LOGT>(tau, kt, blo, rho));
-                    const double W = tw[(1u << sigma) + (j >> (logN - sigma))];
+                    const double W = tws[lk(kt, blo, rho) >> (lb + 1)];
                     const double X = (s & 1) ? x[k] : redc(x[k], q, qinv);
                     const double V = mulmod(x[k | (1 << bit)], W, q, qinv);
                     x[k] = X + V;
@@ -133,26 +172,18 @@ struct Geom {
         for (int r = 0; r < NR; r++) {
             const int blo = r * LOGR;
             const int rho = (LOGG - blo) < LOGR ? (LOGG - blo) : LOGR;
-            if (r > 0) {
-#pragma unroll
-                for (int k = 0; k < R; k++) lds[grp * GS + lds_pad(elem_local<LOGT>(tau, k, blo - LOGR, LOGR))] = x[k];
-                __syncthreads();
-#pragma unroll
-                for (int k = 0; k < R; k++) x[k] = lds[grp * GS + lds_pad(elem_local<LOGT>(tau, k, blo, rho))];
-                __syncthreads();
-            }
+            if (r > 0) exchange(x, lds, blo - LOGR, LOGR, blo, rho);
 #pragma unroll
             for (int s = 0; s < rho; s++) {
                 const int bit = s;
                 const int lb = blo + bit;
-                const uint32_t sigma = sigma0 + (uint32_t)(LOGG - 1 - lb);
                 const bool fold_ninv = LASTSTAGE && (lb == LOGG - 1);
+                const double *tws = tw_stage(tw, sigma0, lb, blo, rho);
 #pragma unroll
                 for (int k = 0; k < R; k++) {
                     if (k & (1 << bit)) continue;
                     const int kt = k & ~((2 << bit) - 1);
-                    const uint32_t j = gidx(elem_local<LOGT>(tau, kt, blo, rho));
-                    double W = tw[(1u << sigma) + (j >> (logN - sigma))];
+                    double W = tws[lk(kt, blo, rho) >> (lb + 1)];
                     const double U = x[k], V = x[k | (1 << bit)];
                     if (fold_ninv) {
                         W = canon(mulmod(W, ninv, q, qinv), q, qinv);

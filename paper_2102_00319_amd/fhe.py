@@ -94,6 +94,7 @@ _sig = {
     "fhe_keyswitch": [_P, C.POINTER(fhe_evk), _P, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_keyswitch_batch": [_P, C.POINTER(fhe_evk), _P, C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_ctx_set_allocator": [_P, _P, _P, _P],
+    "fhe_ctx_release_buffers": [_P],
     "fhe_rotate_batch": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), _P, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_profile_enable": [_P, C.c_char_p],
     "fhe_op_counts": [_P, _P],
@@ -340,6 +341,10 @@ class Context:
     def library_bytes(self):
         """Device memory the context's growable buffers hold (scratch and layer workspace)."""
         return int(_lib.fhe_scratch_bytes(self._h)) + int(_lib.fhe_workspace_bytes(self._h))
+
+    def release_buffers(self):
+        """Give back the context's scratch and layer workspace (fhe_ctx_release_buffers)."""
+        _check(_lib.fhe_ctx_release_buffers(self._h))
 
     def use_torch_allocator(self):
         """Take the context's scratch and layer workspace from torch's caching allocator

@@ -10,6 +10,9 @@ sequences.  The schedule has four knobs, chosen by measurement:
                 the GPU) or all on one stream;
   * chunk:      most items per ragged launch sequence (0 = all of a stage);
   * order:      the order in which the contexts' lists are issued.
+The library's kernel knobs (fhe_ctx_set_tuning: the fused row pass and key inner
+product, the tensor-MAC tile width and two-group tiles, the rescale's row-pass
+workgroup) are tuned the same way, on the workload itself (tune_knobs).
 """
 import json
 import os
@@ -144,6 +147,49 @@ class UnevenBatch:
             lv = sorted(op.a.limbs for op in self.ops[n] if op.kind == OP_MUL_RELIN_RESCALE)
             parts.append("%s:%s" % (n, ",".join(map(str, lv))))
         return "uneven|" + "|".join(parts) + "|" + torch.cuda.get_device_name(0)
+
+
+# kernel knobs of the library (fhe_ctx_set_tuning) and the values tried
+KNOB_VALUES = {"ks_fuse_row_inner": (1, 0), "row_wg": (128, 256)}
+
+
+def knob_candidates(names):
+    """Every combination of the listed knobs' values, the library defaults first."""
+    out = [{}]
+    for n in names:
+        out = [dict(c, **{n: v}) for c in out for v in KNOB_VALUES[n]]
+    return out
+
+
+def apply_knobs(ctxs, knobs):
+    for c in ctxs:
+        for k, v in knobs.items():
+            c.set_tuning(k, v)
+
+
+def tune_knobs(tuner, key, ctxs, run, names, reps=3):
+    """Measure run() (a whole workload step, asynchronous) under every combination of
+    the named kernel knobs, applied to every context in ctxs; keep the fastest (cached
+    under key by the tuner) and leave it applied.  Returns (best, {candidate: seconds})."""
+    def measure(knobs):
+        apply_knobs(ctxs, knobs)
+        run()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        return ts[len(ts) // 2]
+    key = "%s|knobs=%s" % (key, ",".join(names))
+    best = tuner.lookup(key)
+    times = None
+    if best is None or set(best) != set(names):
+        best, times = tuner.tune(key, knob_candidates(names), measure)
+    apply_knobs(ctxs, best)
+    return best, times
 
 
 class GraphedForward:

@@ -142,6 +142,10 @@ class Lane:
         """Device memory the lane's contexts hold for their scratch and workspaces."""
         return sum(ctx.library_bytes() for ctx in self.ctx.values())
 
+    def release_buffers(self):
+        for ctx in self.ctx.values():
+            ctx.release_buffers()
+
 
 class Server:
     def __init__(self, set_names, lanes=4, hbm_budget=250e9, merge=True, max_merge=64, scratch_bytes=4 << 30,
@@ -169,6 +173,9 @@ class Server:
         self.mirror_error = None
         self.clients = []
         self.stats = collections.Counter()
+        # the most library memory (scratch and workspace) a batch of each network kind
+        # has held, measured when its lane finished
+        self.library_peak = {}
 
     # ------------------------------------------------------------ memory
     def add_client(self, client):
@@ -204,31 +211,32 @@ class Server:
         return done
 
     def resident_bytes(self):
-        """Client state on the device, plus per lane the larger of its running batch's
-        working set (which reserves the scratch the batch may grow to) and the library
-        memory its contexts hold."""
-        return sum(c.nbytes for c in self.clients if c.resident) + sum(
-            max(l.ws, self._library_bytes(l)) for l in self.lanes)
-
-    @staticmethod
-    def _library_bytes(lane):
-        f = getattr(lane, "library_bytes", None)
-        return f() if f else 0
+        """Client state on the device plus the working sets of the running batches (a
+        lane gives its library buffers back when its batch ends)."""
+        return sum(c.nbytes for c in self.clients if c.resident) + sum(l.ws for l in self.lanes)
 
     def host_bytes(self):
         return sum(c.host_bytes() for c in self.clients)
 
     def working_set(self, req, lane):
-        """Device bytes of one batch of `req`'s network beyond the client state:
-        inputs, layer outputs and the lane's scratch (an estimate)."""
+        """Device bytes of one batch of `req`'s network beyond the client state: inputs
+        and layer outputs (an estimate), plus the library buffers the batch's contexts
+        grow to: the most measured for that kind of network so far, at least the
+        configured scratch reservation."""
         ctx = lane.ctx[req.client.set_name]
         ct = 2 * ctx.L * ctx.N * 8
+        lib = max(self.scratch, self.library_peak.get(req.client.kind, 0))
         if req.client.kind == "slot":
             net = req.client.net
             n_conv = net.Cout * net.Ho * net.Wo
-            return int(net.H * net.W * ct * 2 + 3 * n_conv * ct + self.scratch)
+            return int(net.H * net.W * ct * 2 + 3 * n_conv * ct + lib)
         net = req.client.net
-        return int(len(req.payload) * ct * (4 + 2 * net.c2 + net.c1 * net.k * net.k) + self.scratch)
+        return int(len(req.payload) * ct * (4 + 2 * net.c2 + net.c1 * net.k * net.k) + lib)
+
+    @staticmethod
+    def _library_bytes(lane):
+        f = getattr(lane, "library_bytes", None)
+        return f() if f else 0
 
     def _make_room(self, need, keep, queue=()):
         """Evict idle clients other than `keep` until `need` more bytes fit, keeping the
@@ -395,6 +403,13 @@ class Server:
             lane.thread.join()
             if lane.error is not None:
                 raise lane.error
+            held = self._library_bytes(lane)
+            if held:
+                kind = lane.group[0].client.kind
+                self.library_peak[kind] = max(self.library_peak.get(kind, 0), held)
+                if held > self.stats["library_peak_bytes"]:
+                    self.stats["library_peak_bytes"] = held
+                lane.release_buffers()
             lane.group[0].client.inflight -= 1
             done += len(lane.group)
             lane.group, lane.thread, lane.ws = None, None, 0

@@ -22,3 +22,45 @@ def test_autotuner_picks_fastest_and_caches(tmp_path):
     data = json.loads(path.read_text())
     assert set(data) == {"k1"} and data["k1"]["best"] == best
     assert runtime.Autotuner(str(path)).lookup("missing") is None
+
+
+def test_kernel_knobs_tuned_on_the_workload(tmp_path):
+    """tune_knobs measures every combination of the named knobs (defaults first),
+    applies the fastest to every context, and takes a cached choice without measuring."""
+    class Ctx:
+        def __init__(self):
+            self.knobs = {}
+
+        def set_tuning(self, k, v):
+            self.knobs[k] = v
+
+    assert runtime.knob_candidates(["ks_fuse_row_inner", "row_wg"]) == [
+        {"ks_fuse_row_inner": 1, "row_wg": 128}, {"ks_fuse_row_inner": 1, "row_wg": 256},
+        {"ks_fuse_row_inner": 0, "row_wg": 128}, {"ks_fuse_row_inner": 0, "row_wg": 256}]
+    ctxs = [Ctx(), Ctx()]
+    runs = []
+
+    def run():
+        runs.append(dict(ctxs[0].knobs))
+
+    import torch
+    sync = torch.cuda.synchronize
+    torch.cuda.synchronize = lambda *a, **k: None   # no device here
+    clock = iter(range(10 ** 6))
+    real = runtime.time.perf_counter
+    try:
+        # the fourth candidate runs fastest: its run() calls take 1 tick, the others 5
+        def fake_clock():
+            return next(clock) * (1 if runs and runs[-1] == {"ks_fuse_row_inner": 0, "row_wg": 256} else 5)
+        runtime.time.perf_counter = fake_clock
+        t = runtime.Autotuner(str(tmp_path / "t.json"))
+        best, times = runtime.tune_knobs(t, "w", ctxs, run, ["ks_fuse_row_inner", "row_wg"], reps=1)
+    finally:
+        runtime.time.perf_counter = real
+        torch.cuda.synchronize = sync
+    assert best == {"ks_fuse_row_inner": 0, "row_wg": 256} and len(times) == 4
+    assert all(c.knobs == best for c in ctxs)
+    n = len(runs)
+    best2, times2 = runtime.tune_knobs(runtime.Autotuner(str(tmp_path / "t.json")), "w", ctxs, run,
+                                       ["ks_fuse_row_inner", "row_wg"])
+    assert best2 == best and times2 is None and len(runs) == n

@@ -132,6 +132,56 @@ def test_config2_cnn_logits_reduced_fc1():
     assert np.array_equal(g.export_ct(Y[0]), y0.data)
 
 
+def test_config2_cnn_full_fc1_100(capsys):
+    """Config 2 as configured: N = 2^14, 8 limbs, 8192 images per ciphertext, conv 5x5
+    stride 2 x 5 channels, x^2, FC 845 -> 100 (84,500 weight ciphertexts, 124 GiB), x^2,
+    FC 100 -> 10: the scores within 1e-3 of FP64; and the FC1 layer on the network's
+    own activations bit-exact against the oracle for one output over its first 8
+    inputs (the whole 845-input sum is out of the oracle's reach in test time)."""
+    P = _P()
+    g = P.Context.from_set("c2_n14")
+    D = g.scale
+    B, H, W, K, Cout = g.N // 2, 28, 28, 5, 5
+    Ho = Wo = 13
+    n1, n2 = 100, 10
+    imgs = workloads.images(workloads.SEED_DATA, B, H, W)
+    cw = workloads.weights(workloads.SEED_DATA + 1, (Cout, 1, K, K))
+    f1 = workloads.weights(workloads.SEED_DATA + 2, (n1, Cout * Ho * Wo))
+    f2 = workloads.weights(workloads.SEED_DATA + 3, (n2, n1))
+    s = g.keygen_secret(workloads.SEED_SECRET)
+    pk = g.keygen_pk(s, workloads.SEED_PK)
+    rlk = g.keygen_relin(s, workloads.SEED_EVK)
+    L = g.L
+    X = P.CtArray(encrypt_images_gpu(g, pk, imgs, D))
+    Wc = P.CtArray(g.encrypt_const_batch(pk, cw.ravel(), D, [workloads.SEED_ENC + S_CONV + t for t in range(cw.size)], L))
+    W1 = P.CtArray(g.encrypt_const_batch(pk, f1.ravel(), D, [workloads.SEED_ENC + S_FC1 + t for t in range(f1.size)],
+                                         L - 2))
+    W2 = P.CtArray(g.encrypt_const_batch(pk, f2.ravel(), D, [workloads.SEED_ENC + S_FC2 + t for t in range(f2.size)],
+                                         L - 4))
+    Y = g.conv2d_slot(rlk, X, H, W, 1, Wc, Cout, K, K, 2, 1, 1, Ho, Wo)
+    A = g.square_act(rlk, Y)
+    Z = g.fc_slot(rlk, A, W1, n1)
+    out = g.fc_slot(rlk, g.square_act(rlk, Z), W2, n2)
+    ref = cnn.slot_cnn_fp64(imgs, cw, f1, f2, 2, 1, 1, Ho, Wo)
+    worst = 0.0
+    for r in range(n2):
+        got, _ = g.decode(g.decrypt(s, out[r]), n=B)
+        worst = max(worst, float(np.abs(got - ref[:, r]).max()))
+    with capsys.disabled():
+        print("config-2 (FC1 = 100) logits: max |encrypted - FP64| = %.3e" % worst, flush=True)
+    assert worst < 1e-3
+    # FC1 output 0 over the first 8 activations, on the GPU and on the oracle
+    z8 = g.fc_slot(rlk, A[:8], [W1[i] for i in range(8)], 1)[0]
+    o = OracleCtx.from_set("c2_n14")
+    so = s.astype(np.int64)
+    rlko = o.keygen_relin(so, workloads.SEED_EVK)
+    from oracle.ckks import Ct
+    pairs = [(Ct(g.export_ct(A[i]), A[i].scale), Ct(g.export_ct(W1[i]), D)) for i in range(8)]
+    zo = cnn._mac_relin_rescale(o, rlko, pairs, cnn.Counter())
+    assert np.array_equal(g.export_ct(z8), zo.data)
+    assert z8.scale == zo.scale
+
+
 @pytest.mark.parametrize("H,W,Cin,Cout,K,stride,pad", [(3, 4, 2, 9, 2, 1, 0), (6, 6, 1, 3, 3, 2, 1)])
 def test_conv_tiles_bit_exact(H, W, Cin, Cout, K, stride, pad):
     """Conv shapes whose outputs fill the multiply-accumulate tiles in every way:

@@ -410,3 +410,33 @@ def test_rotation_batch_as_benchmarked(sets):
         assert np.array_equal(g.export_evk(gks[b]), gko)
         ref = o.rotate(ckks.Ct(g.export_ct(cts[b]), cts[b].scale), steps[b], gko)
         eq(g.export_ct(outs[b]), ref.data)
+
+
+def test_keyswitch_knobs_give_the_same_bits(sets):
+    """The key switch's kernel knob (the forward row pass fused with the key inner
+    product, or the two as separate kernels) gives the same bits either way, for
+    rotations with distinct keys and for relinearisations that share one key."""
+    import torch
+    g, _ = sets("c3_n15")
+    s = g.keygen_secret(workloads.SEED_SECRET)
+    pk = g.keygen_pk(s, workloads.SEED_PK)
+    rlk = g.keygen_relin(s, workloads.SEED_EVK)
+    steps = [1, -1, 28, 5, 7]
+    gks = [g.keygen_rot(s, r, workloads.SEED_EVK + 1 + i) for i, r in enumerate(steps)]
+    cts = [g.encrypt(pk, g.encode(workloads.slot_messages(workloads.SEED_DATA + b, 64), scale=g.scale,
+                                  limbs=9 + b), workloads.SEED_ENC + b) for b in range(len(steps))]
+    c3 = [g.mul(c, c) for c in cts]
+
+    def run():
+        rot = g.rotate_batch(gks, [cts[0]] * len(steps), steps)
+        rel = [g.relin(rlk, c) for c in c3]
+        rel += g.relin_batch(rlk, c3[:1] * 3)
+        torch.cuda.synchronize()
+        return [x.data.clone() for x in rot + rel]
+    ref = run()
+    for fuse in (0, 1):
+        g.set_tuning("ks_fuse_row_inner", fuse)
+        got = run()
+        for i, (a, b) in enumerate(zip(got, ref)):
+            assert torch.equal(a, b), (fuse, i)
+    g.set_tuning("ks_fuse_row_inner", 1)

@@ -37,8 +37,10 @@ def _setup(merge, budget_frac, cold_wait=None):
         clients.append(serving.Client(cid, net, g, sets[kind], w, seeds))
         plain.append(w)
     total = sum(c.nbytes for c in clients)
-    srv = serving.Server(list(sets.values()), lanes=2, hbm_budget=budget_frac * total + 2 * (64 << 20),
-                         merge=merge, scratch_bytes=32 << 20, cold_wait=cold_wait)
+    # the lanes' library buffers (scratch and workspace, from torch's allocator) are
+    # reserved at 256 MiB per batch: more than these N = 2^12 networks use
+    srv = serving.Server(list(sets.values()), lanes=2, hbm_budget=budget_frac * total + 2 * (288 << 20),
+                         merge=merge, scratch_bytes=256 << 20, cold_wait=cold_wait)
     for c in clients:
         srv.add_client(c)
     if not merge:   # pinned host mirrors for the two smallest clients, a pageable one for a third
@@ -96,9 +98,13 @@ def test_serving_mix_equals_alone(merge, cold_wait):
     from paper_2102_00319_amd import serving
     srv, clients, plain, pools = _setup(merge, 0.6, cold_wait)
     assert srv.async_loads == (cold_wait is not None)
-    reqs = _requests(serving, clients, pools, burst=merge)
+    # all requests at once: both lanes start at the same time, so the client state that
+    # fits beside two working sets is budget_frac of the total and admission must evict
+    reqs = _requests(serving, clients, pools, burst=True)
     srv.run(reqs, time_limit=120)
     assert srv.stats["evictions"] > 0 and srv.stats["cold_loads"] > 0
+    # the library's buffers stayed within the reservation the admission counted
+    assert 0 < srv.stats["library_peak_bytes"] <= srv.scratch
     if merge:
         assert max(r.merged for r in reqs) > 1
     for r in reqs:

@@ -287,19 +287,19 @@ def test_async_loads_serve_every_request():
 
 
 def test_library_memory_of_lanes_counts_against_the_budget():
-    """Memory a lane's contexts hold for their scratch and workspace (from torch's
-    allocator) is resident: an idle lane counts what it holds, a running one the
-    larger of that and its batch's working set."""
-    srv = FakeServer(hbm_budget=1000)
-    held = {"bytes": 0}
+    """A lane gives its library buffers back when its batch ends; the most a batch of a
+    network kind held becomes that kind's reservation in later working sets."""
+    srv = FakeServer(hbm_budget=10 ** 9)
+    held, released = {"bytes": 0}, []
     for lane in srv.lanes:
         lane.library_bytes = lambda: held["bytes"]
+        lane.release_buffers = lambda: released.append(1)
     c = FakeClient(0, "slot", 300)
     srv.add_client(c)
-    base = srv.resident_bytes()
-    held["bytes"] = 50
-    assert srv.resident_bytes() == base + 50 * len(srv.lanes)
-    srv.lanes[0].ws = 120
-    assert srv.resident_bytes() == base + 120 + 50 * (len(srv.lanes) - 1)
-    srv.lanes[0].ws = 20
-    assert srv.resident_bytes() == base + 50 * len(srv.lanes)
+    req = serving.Request(0, c, None, 1, 0, 0.0, 0)
+    before = _ws(srv, req)
+    held["bytes"] = 5000
+    srv.run([req])
+    assert released and srv.library_peak["slot"] == 5000
+    assert _ws(srv, req) == before + 5000      # the reservation of the FakeServer is 0
+    assert srv.resident_bytes() == 300          # nothing held once the lanes are idle
