@@ -205,6 +205,22 @@ fhe_status fhe_keyswitch(fhe_ctx *ctx, const fhe_evk *evk, const uint64_t *d, ui
 fhe_status fhe_keyswitch_batch(fhe_ctx *ctx, const fhe_evk *evk, const uint64_t *const *d, uint32_t limbs,
                                uint32_t n, fhe_ct *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): fhe_keyswitch_batch with
+ * its scratch in a library-owned static device array of FHE_STATIC_SCRATCH_BYTES on
+ * each GPU (held until the process ends) instead of the context's growable scratch.
+ * Same arguments, layout, results and errors as fhe_keyswitch_batch, plus FHE_ENOMEM
+ * (nothing enqueued) when the batch needs more than FHE_STATIC_SCRATCH_BYTES of
+ * scratch (a key switch at N = 2^16 and 24 limbs with 8 special primes and dnum 3
+ * takes 104 MiB, so two fit; at N = 2^15 and 16 limbs, seven) or more pointer-table
+ * space than the context's table ring.  The call allocates nothing: the ring and
+ * its events are made when the context is created.  Every call on one GPU shares
+ * that GPU's array and leaves its last contents there (the key switch writes every
+ * scratch word it reads, so nothing needs clearing); calls that overlap on one GPU
+ * (on different streams or host threads) race and must be serialised by the caller. */
+#define FHE_STATIC_SCRATCH_BYTES (256ull << 20)
+fhe_status fhe_keyswitch_batch_static(fhe_ctx *ctx, const fhe_evk *evk, const uint64_t *const *d, uint32_t limbs,
+                                      uint32_t n, fhe_ct *out);
 
 /* Work list of independent or chained operations at mixed levels (one ring).
  * Operations run as if in list order; those whose inputs are ready are grouped

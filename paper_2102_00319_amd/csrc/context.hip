@@ -201,6 +201,26 @@ static void ctx_free_all(fhe_ctx *c)
     delete c;
 }
 
+// Scratch of fhe_keyswitch_batch_static: one array per GPU, in the code object's
+// device globals.  Host code must not use its name as an address (it names a host-side
+// stand-in); static_scratch_ptr() resolves this device's address once.
+static __device__ __align__(256) uint8_t scratch[FHE_STATIC_SCRATCH_BYTES];
+
+static fhe_status static_scratch_ptr(int device, uint8_t **out)
+{
+    static std::mutex mu;
+    static std::map<int, uint8_t *> addr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+        void *ptr = nullptr;   // the caller has made `device` current
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        it = addr.emplace(device, (uint8_t *)ptr).first;
+    }
+    *out = it->second;
+    return FHE_OK;
+}
+
 extern "C" fhe_status fhe_ctx_create(const fhe_params *pp, void *hip_stream, uint64_t hbm_budget, fhe_ctx **out)
 {
     if (!pp || !out || !pp->q || (pp->n_p && !pp->p) || (pp->n_cdt && !pp->cdt))
@@ -233,6 +253,10 @@ extern "C" fhe_status fhe_ctx_create(const fhe_params *pp, void *hip_stream, uin
         }
     }
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return fhe_fail(FHE_EDEVICE, "no HIP device"); }
+    if (fhe_status e = static_scratch_ptr(c->device, &c->static_scr)) {
+        delete c;
+        return e;
+    }
 
     fhe_status st = FHE_OK;
     // per-modulus constants and twiddles
@@ -341,6 +365,23 @@ extern "C" fhe_status fhe_ctx_create(const fhe_params *pp, void *hip_stream, uin
         ctx_free_all(c);
         return st;
     }
+    // the pointer-table ring and a few of its events are made here, so that calls that
+    // may not allocate (fhe_keyswitch_batch_static) find them
+    if (hipMalloc((void **)&c->tbl_dev, TBL_ARENA_BYTES) != hipSuccess ||
+        hipHostMalloc((void **)&c->tbl_host, TBL_ARENA_BYTES) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx_free_all(c);
+        return fhe_fail(FHE_EDEVICE, "fhe_ctx_create: pointer-table ring allocation failed");
+    }
+    for (int i = 0; i < 8; ++i) {
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx_free_all(c);
+            return fhe_fail(FHE_EDEVICE, "fhe_ctx_create: event creation failed");
+        }
+        c->tbl_pool.push_back(ev);
+    }
     *out = c;
     return FHE_OK;
 }
@@ -420,6 +461,7 @@ static fhe_status ctx_grow(fhe_ctx *c, uint8_t **buf, size_t *held, size_t bytes
 {
     bytes = (bytes + 255) & ~(size_t)255;
     if (bytes <= *held) return FHE_OK;
+    if (c->no_alloc) return fhe_fail(FHE_ENOMEM, std::string(what) + " growth in a call that may not allocate");
     if (c->capturing) {
         c->cap_error = FHE_ENOMEM;
         return fhe_fail(FHE_ENOMEM, "graph capture: device memory must be sized by an eager run first");
@@ -507,6 +549,7 @@ fhe_status ctx_ptr_table(fhe_ctx *c, const std::vector<uint64_t *> &ptrs, uint64
     }
     const size_t bytes = (n * sizeof(uint64_t *) + 255) & ~(size_t)255;
     if (bytes > TBL_ARENA_BYTES) {
+        if (c->no_alloc) return fhe_fail(FHE_ENOMEM, "pointer table larger than the context's table ring");
         HIPCHK(hipStreamSynchronize(c->stream));
         if (n > c->d_big_cap) {
             if (c->d_big) HIPCHK(hipFree(c->d_big));
@@ -519,6 +562,7 @@ fhe_status ctx_ptr_table(fhe_ctx *c, const std::vector<uint64_t *> &ptrs, uint64
         return FHE_OK;
     }
     if (!c->tbl_dev) {
+        if (c->no_alloc) return fhe_fail(FHE_ENOMEM, "pointer-table ring missing in a call that may not allocate");
         HIPCHK(hipMalloc((void **)&c->tbl_dev, TBL_ARENA_BYTES));
         HIPCHK(hipHostMalloc((void **)&c->tbl_host, TBL_ARENA_BYTES));
     }
@@ -558,7 +602,15 @@ fhe_status ctx_ptr_table(fhe_ctx *c, const std::vector<uint64_t *> &ptrs, uint64
     if (!c->tbl_pool.empty()) {
         ev = c->tbl_pool.back();
         c->tbl_pool.pop_back();
+    } else if (c->no_alloc && !c->tbl_live.empty()) {
+        // no new event in a call that may not allocate: retire the oldest table
+        // (its release point is the oldest in the stream) and take over its event
+        fhe_ctx::TblAlloc a = c->tbl_live.front();
+        HIPCHK(hipEventSynchronize(a.ev));
+        c->tbl_live.pop_front();
+        ev = a.ev;
     } else {
+        if (c->no_alloc) return fhe_fail(FHE_ENOMEM, "pointer-table events exhausted in a call that may not allocate");
         HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     }
     std::memcpy(c->tbl_host + off, ptrs.data(), ptrs.size() * sizeof(uint64_t *));

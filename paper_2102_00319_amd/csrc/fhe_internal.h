@@ -181,6 +181,8 @@ struct fhe_ctx {
     fhe_alloc_fn alloc_fn;   // caller's allocator for scratch and workspace (null: hipMalloc)
     fhe_free_fn free_fn;
     void *alloc_user;
+    uint8_t *static_scr;     // this device's static scratch array (fhe_keyswitch_batch_static)
+    bool no_alloc;           // set while a call that may not allocate runs: growth paths fail instead
     uint32_t tune_chunk;     // most items per ragged launch sequence (0: no limit)
     uint32_t tune_fuse_row_inner;   // key switch: fuse the converted limbs' row pass into the inner product
     uint32_t tune_row_wg;    // rescale: row-pass workgroup cap (128 or 256)

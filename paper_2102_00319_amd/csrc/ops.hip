@@ -301,6 +301,36 @@ fhe_status fhe_keyswitch_batch(fhe_ctx *c, const fhe_evk *evk, const uint64_t *c
     }
     return ks_run(c, limbs, n, dd.data(), nullptr, ek.data(), oo.data(), nullptr, nullptr);
 }
+// The same key switches with the scratch in this GPU's static array: nothing is
+// allocated (the pointer table goes through the ring made with the context).
+fhe_status fhe_keyswitch_batch_static(fhe_ctx *c, const fhe_evk *evk, const uint64_t *const *d, uint32_t limbs,
+                                      uint32_t n, fhe_ct *out)
+{
+    fhe_status s;
+    if (!c || !evk || !d || !out || !n) return fhe_fail(FHE_EINVAL, "fhe_keyswitch_batch_static: null or empty");
+    if (!c->static_scr) return fhe_fail(FHE_EDEVICE, "fhe_keyswitch_batch_static: static scratch not resolved");
+    if (limbs < 1 || limbs > c->L) return fhe_fail(FHE_ELEVEL, "fhe_keyswitch_batch_static: limb count out of range");
+    std::vector<const uint64_t *> dd(n), ek(n);
+    std::vector<uint64_t *> oo(n);
+    for (uint32_t b = 0; b < n; ++b) {
+        if (!evk[b].d || !d[b]) return fhe_fail(FHE_EINVAL, "fhe_keyswitch_batch_static: null entry");
+        if ((s = chk_ct(c, &out[b], "fhe_keyswitch_batch_static"))) return s;
+        if (out[b].limbs != limbs || out[b].polys != 2)
+            return fhe_fail(FHE_EINVAL, "fhe_keyswitch_batch_static: bad output");
+        dd[b] = d[b]; ek[b] = evk[b].d; oo[b] = out[b].d;
+    }
+    const size_t need = ks_scratch_bytes(c, limbs, n);
+    if (need > FHE_STATIC_SCRATCH_BYTES)
+        return fhe_fail(FHE_ENOMEM, "fhe_keyswitch_batch_static: the batch needs " + std::to_string(need) +
+                                        " bytes of scratch, the static array holds " +
+                                        std::to_string(FHE_STATIC_SCRATCH_BYTES) + " (split the batch)");
+    struct NoAlloc {
+        fhe_ctx *c;
+        explicit NoAlloc(fhe_ctx *cc) : c(cc) { c->no_alloc = true; }
+        ~NoAlloc() { c->no_alloc = false; }
+    } guard(c);
+    return ks_run(c, limbs, n, dd.data(), nullptr, ek.data(), oo.data(), nullptr, c->static_scr);
+}
 fhe_status fhe_relin(fhe_ctx *c, const fhe_evk *rlk, const fhe_ct *in3, fhe_ct *out2)
 {
     fhe_status s;

@@ -93,6 +93,7 @@ _sig = {
     "fhe_rotate": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), C.c_int32, C.POINTER(fhe_ct)],
     "fhe_keyswitch": [_P, C.POINTER(fhe_evk), _P, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_keyswitch_batch": [_P, C.POINTER(fhe_evk), _P, C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
+    "fhe_keyswitch_batch_static": [_P, C.POINTER(fhe_evk), _P, C.c_uint32, C.c_uint32, C.POINTER(fhe_ct)],
     "fhe_ctx_set_allocator": [_P, _P, _P, _P],
     "fhe_ctx_release_buffers": [_P],
     "fhe_rotate_batch": [_P, C.POINTER(fhe_evk), C.POINTER(fhe_ct), _P, C.c_uint32, C.POINTER(fhe_ct)],
@@ -585,6 +586,16 @@ class Context:
         D = (C.c_void_p * n)(*[d.data_ptr() for d in ds])
         O = (fhe_ct * n)(*[o.s() for o in outs])
         _check(_lib.fhe_keyswitch_batch(self._h, K, D, limbs, n, O))
+        return outs
+
+    def keyswitch_batch_static(self, evks, ds, outs):
+        """fhe_keyswitch_batch_static: the outputs must be allocated by the caller."""
+        n = len(ds)
+        limbs = ds[0].shape[0]
+        K = (fhe_evk * n)(*[e.s() for e in evks])
+        D = (C.c_void_p * n)(*[d.data_ptr() for d in ds])
+        O = (fhe_ct * n)(*[o.s() for o in outs])
+        _check(_lib.fhe_keyswitch_batch_static(self._h, K, D, limbs, n, O))
         return outs
 
     def rotate_batch(self, gks, cts, steps, outs=None):
