@@ -165,7 +165,7 @@ def _oracle_units(arg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=8, help="rotations (distinct keys) per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -181,6 +181,8 @@ def parse():
     ap.add_argument("--ks-fuse", type=int, default=None, choices=[0, 1],
                     help="keyswitch: fuse the converted limbs' row pass into the key inner product (1) or not "
                          "(0); default: chosen by the autotuner on the step")
+    ap.add_argument("--ks-nt", type=int, default=1, choices=[0, 1],
+                    help="keyswitch with --ks-fuse given: non-temporal loads and stores of data used once (1)")
     ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "kssweep", "cnn2", "cnn4", "batch3", "serve", "fig3", "paper",
                                                            "latency"],
                     help="keyswitch: the headline metric; cnn2: slot-packed encrypted CNN images/s; "
@@ -216,11 +218,14 @@ def ks_shape(logN):
 def kernel_model(cat, N, l, K, alpha, B, dnum, L, fused=False):
     """Algorithmic work of one step (B key switches, each with its own key) per kernel
     category: (bytes moved to and from HBM by the algorithm, FP64 flops).  fused: the
-    row pass of the converted digits runs inside the key inner product."""
+    row passes of the converted digits run inside the key inner product, split by
+    target: the special-prime limbs with the inverse row pass of uP ("ks_inner"), the
+    Q limbs with the forward row pass of z and the ModDown finish ("ks_moddown_final")."""
     limb = N * 8
     logN = N.bit_length() - 1
     nd = (l + alpha - 1) // alpha
     ups = sum(l + K - min(alpha, l - j * alpha) for j in range(nd))
+    ups_q = ups - nd * K                      # converted limbs of Q_l (the rest: of P)
     logA, logB = ks_shape(logN)
     bfly = (N // 2) * FLOPS_PER_BUTTERFLY     # flops of one stage over one limb
     if cat == "ntt_fwd_row":   # the converted ModUp limbs (split form)
@@ -229,6 +234,8 @@ def kernel_model(cat, N, l, K, alpha, B, dnum, L, fused=False):
         n = B * ups
         return 2 * n * limb, n * logB * bfly
     if cat == "ntt_inv_row":   # the P limbs of u
+        if fused:
+            return 0, 0
         n = B * 2 * K
         return 2 * n * limb, n * logB * bfly
     if cat == "ks_intt_first":
@@ -236,14 +243,21 @@ def kernel_model(cat, N, l, K, alpha, B, dnum, L, fused=False):
         return 2 * n * limb, n * logB * bfly
     if cat == "ks_moddown_final":
         n = B * 2 * l
+        if fused:
+            # per Q limb: D_j of every digit and both key polynomials in, z in, the
+            # rotation addend sigma_g(c0) in, out; the converted limbs' and z's row passes
+            return (B * (3 * nd * l + 5 * l) * limb,
+                    B * 2 * nd * l * N * 9 + (B * ups_q + n) * logB * bfly + n * N * 8)
         # z in, u in, out; the rotation addend sigma_g(c0); one exact product per element
         return (3 * n + B * l) * limb, n * logB * bfly + n * N * 8
     if cat == "ks_inner":
-        # D_j and both key polynomials per digit in, u out (2 products per element per
-        # digit); fused: D_j of the converted limbs enters in column-stage form and gets
-        # its row pass here
-        return (B * (3 * nd * (l + K) + 2 * (l + K)) * limb,
-                B * 2 * nd * (l + K) * N * 9 + (B * ups * logB * bfly if fused else 0))
+        if fused:
+            # per special prime: D_j of every digit in (column-stage form) and both key
+            # polynomials, uP out; forward row passes of the digits, inverse ones of uP
+            return (B * (3 * nd * K + 2 * K) * limb,
+                    B * 2 * nd * K * N * 9 + B * (nd * K + 2 * K) * logB * bfly)
+        # D_j and both key polynomials per digit in, u out (2 products per element per digit)
+        return B * (3 * nd * (l + K) + 2 * (l + K)) * limb, B * 2 * nd * (l + K) * N * 9
     if cat == "bconv_up":
         # the row-inverted digit limbs in, the converted limbs out (alpha products per
         # target element), with the sources' last 3 inverse stages and the targets' first 3
@@ -334,7 +348,7 @@ def run_cnn4(args):
     key = "cnn4|%s|%s" % (args.act, torch.cuda.get_device_name(0))
     say("cnn4: keys, images and weights ready (%.1f s)" % t_setup)
     tuned, _ = runtime.tune_knobs(runtime.Autotuner(), key, [g], lambda: net.forward(g, rlk, gks, X, Wt),
-                                  ["ks_fuse_row_inner"], reps=2)
+                                  ["ks_fuse_row_inner", "ks_nt"], reps=2)
     say("cnn4: knobs %s" % tuned)
     g.op_counts()
     out = net.forward(g, rlk, gks, X, Wt)
@@ -477,7 +491,7 @@ def batch3(args):
     # the kernel knobs first (on the eager schedule), then the schedule with them applied
     knobs, _ = runtime.tune_knobs(tuner, ub.signature() + "|knobs", list(ctxs.values()),
                                   lambda: ub.run({"graph": False, "concurrent": True, "chunk": 0}),
-                                  ["ks_fuse_row_inner", "row_wg"], reps=2)
+                                  ["ks_fuse_row_inner", "ks_nt", "row_wg"], reps=2)
     best, times = tuner.tune(ub.signature(), ub.candidates(), lambda c: ub.time(c, reps=3))
     for _ in range(args.warmup):
         ub.run(best)
@@ -518,6 +532,10 @@ def batch3(args):
 
 
 def serve(args):
+    print(json.dumps(run_serve(args)))
+
+
+def run_serve(args):
     """Serving: Poisson arrivals of encrypted inference requests, half for the
     slot-packed CNN (N=2^14, one client, FC1 width --fc1) and half for the deep
     within-image CNN (N=2^16, --packed-clients clients), 1-64 images each;
@@ -599,7 +617,7 @@ def serve(args):
         s.update({"rate_req_s": rate, "evictions": srv.stats["evictions"], "cold_loads": srv.stats["cold_loads"],
                   "cold_load_s": round(srv.stats["cold_load_s"], 2), "evict_s": round(srv.stats["evict_s"], 2),
                   "library_gib_held": round(sum(l.library_bytes() for l in srv.lanes) / 2 ** 30, 2)})
-        print(json.dumps({"serve_rate": s}), flush=True)
+        say(json.dumps({"serve_rate": s}))
         per_rate.append(s)
     rec = {"metric": "encrypted inference serving: p50/p99 latency and images/s per arrival rate",
            "unit": "ms / images/s", "per_rate": per_rate, "lanes": args.lanes, "hbm_budget_gb": args.budget_gb,
@@ -610,7 +628,7 @@ def serve(args):
            "config": {"workload": "Poisson arrivals, 50/50 slot-packed CNN (N=2^14, FC1 %d) and deep within-image "
                                   "CNN (N=2^16), 1-64 images per request" % args.fc1,
                       "clients": {"slot": 1, "packed": args.packed_clients}}}
-    print(json.dumps(rec))
+    return rec
 
 
 FIG3_SET = "c3_n15"   # N = 2^15 (the paper's m = 2^16), 16 limbs
@@ -901,7 +919,8 @@ def run_cnn2(args):
     from paper_2102_00319_amd import runtime
     key = "cnn2|fc1=%d|%s" % (n1, torch.cuda.get_device_name(0))
     say("cnn2: keys, images and weights ready (%.1f s)" % t_setup)
-    tuned, _ = runtime.tune_knobs(runtime.Autotuner(), key, [g], forward, ["ks_fuse_row_inner", "row_wg"], reps=2)
+    tuned, _ = runtime.tune_knobs(runtime.Autotuner(), key, [g], forward,
+                                  ["ks_fuse_row_inner", "ks_nt", "row_wg"], reps=2)
     say("cnn2: knobs %s" % tuned)
 
     out = forward()
@@ -1066,14 +1085,15 @@ def main():
     if args.ks_fuse is None:
         tuner = runtime.Autotuner()
         key = "keyswitch|%s|B%d|%s" % (args.param_set, B, torch.cuda.get_device_name(0))
-        best, times = runtime.tune_knobs(tuner, key, [g], step, ["ks_fuse_row_inner"], reps=5)
-        args.ks_fuse = best["ks_fuse_row_inner"]
+        best, times = runtime.tune_knobs(tuner, key, [g], step, ["ks_fuse_row_inner", "ks_nt"], reps=25)
+        args.ks_fuse, args.ks_nt = best["ks_fuse_row_inner"], best["ks_nt"]
         tuned = {"choice": best, "ms_per_step": None if times is None else
                  {k: round(v * 1e3, 4) for k, v in times.items()}}
     else:
         g.set_tuning("ks_fuse_row_inner", args.ks_fuse)
+        g.set_tuning("ks_nt", args.ks_nt)
 
-    say("keyswitch: ks_fuse_row_inner %d%s" % (args.ks_fuse, " (tuned)" if tuned else ""))
+    say("keyswitch: ks_fuse_row_inner %d, ks_nt %d%s" % (args.ks_fuse, args.ks_nt, " (tuned)" if tuned else ""))
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -1146,7 +1166,7 @@ def main():
         "config": {"workload": "rotation key switch, N=2^16, l=24 limbs (~49-bit), K=8 special primes, dnum=3, "
                                "%d distinct Galois keys per step" % B,
                    "batch": B, "ring_degree": N, "limbs": l, "special_primes": K, "dnum": g.dnum,
-                   "ks_fuse_row_inner": args.ks_fuse, "autotuned": tuned},
+                   "ks_fuse_row_inner": args.ks_fuse, "ks_nt": args.ks_nt, "autotuned": tuned},
         "hbm_frac_compulsory": round(hbm_frac, 4),
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -1194,9 +1214,26 @@ def cnn_extras(args):
         keep["wall_s"] = round(time.perf_counter() - t0, 1)
         keep["workload"] = r["config"]["workload"]
         out[name] = keep
-        print("extras: %s %s images/s (%.1f s)" % (name, r["value"], keep["wall_s"]), file=sys.stderr, flush=True)
+        say("extras: %s %s images/s (%.1f s)" % (name, r["value"], keep["wall_s"]))
         del r
         free()
+    # one serving rate: latency percentiles from arrival to decrypted scores
+    say("extras: serving")
+    t0 = time.perf_counter()
+    a = types.SimpleNamespace(rates="10", requests=40, budget_gb=250.0, lanes=4, host_budget_gb=0.0, cold_wait=2.0,
+                              packed_clients=1, fc1=10)
+    try:
+        r = run_serve(a)
+        s = r["per_rate"][0]
+        out["serving"] = {k: s[k] for k in ("rate_req_s", "requests", "images", "images_per_s", "p50_ms", "p99_ms",
+                                            "mean_admission_wait_ms")}
+        out["serving"]["workload"] = (r["config"]["workload"] + "; one slot-CNN and one deep-CNN client, 4 lanes, "
+                                      "Poisson arrivals at 10 req/s")
+        out["serving"]["wall_s"] = round(time.perf_counter() - t0, 1)
+        say("extras: serving p50 %s ms, p99 %s ms" % (s["p50_ms"], s["p99_ms"]))
+    except Exception as e:
+        out["serving"] = {"error": "%s: %s" % (type(e).__name__, e)}
+    free()
     return out
 
 

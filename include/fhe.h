@@ -262,9 +262,13 @@ void fhe_graph_destroy(fhe_graph *g);                          /* waits for the 
 /* Tuning knobs read by the batched drivers; the Python runtime's autotuner measures
  * their combinations on a workload and keeps the fastest.  None changes a result.
  *   "chunk_items": most items per ragged launch sequence (0 = no limit);
- *   "ks_fuse_row_inner": 1 (default) fuses the forward row pass of the converted limbs
- *     into the key inner product when every item of a key switch has its own key;
- *     0 runs them as two kernels;
+ *   "ks_fuse_row_inner": 1 (default) fuses, when every item of a key switch has its
+ *     own key, the forward row passes of the converted limbs into the key inner
+ *     product, the inverse row pass of the special-prime part into the same kernel and
+ *     the Q part into the ModDown finish (five kernels); 0 runs the seven-kernel form;
+ *   "ks_nt": 1 (default) makes the loads and stores of data used once in the first
+ *     inverse pass and the fused kernels non-temporal, so that they do not evict the
+ *     twiddle rows the passes re-read; 0 makes them ordinary;
  *   "row_wg": 128 (default) or 256, the workgroup size of the rescale's row pass. */
 fhe_status fhe_ctx_set_tuning(fhe_ctx *ctx, const char *key, uint64_t value);
 

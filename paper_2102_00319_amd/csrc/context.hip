@@ -234,6 +234,7 @@ extern "C" fhe_status fhe_ctx_create(const fhe_params *pp, void *hip_stream, uin
     fhe_ctx *c = new fhe_ctx();   // value-initialised: plain fields zero, containers constructed
     c->tune_row_wg = 128;
     c->tune_fuse_row_inner = 1;
+    c->tune_ks_nt = 1;
 
     c->logN = logN; c->N = N; c->L = L; c->K = K; c->dnum = pp->dnum;
     c->alpha = (L + pp->dnum - 1) / pp->dnum;
@@ -401,6 +402,10 @@ extern "C" fhe_status fhe_ctx_set_tuning(fhe_ctx *c, const char *key, uint64_t v
     }
     if (!std::strcmp(key, "ks_fuse_row_inner")) {
         c->tune_fuse_row_inner = value ? 1u : 0u;
+        return FHE_OK;
+    }
+    if (!std::strcmp(key, "ks_nt")) {
+        c->tune_ks_nt = value ? 1u : 0u;
         return FHE_OK;
     }
     if (!std::strcmp(key, "row_wg")) {

@@ -185,6 +185,7 @@ struct fhe_ctx {
     bool no_alloc;           // set while a call that may not allocate runs: growth paths fail instead
     uint32_t tune_chunk;     // most items per ragged launch sequence (0: no limit)
     uint32_t tune_fuse_row_inner;   // key switch: fuse the converted limbs' row pass into the inner product
+    uint32_t tune_ks_nt;            // fused key switch: non-temporal loads and stores of streamed data
     uint32_t tune_row_wg;    // rescale: row-pass workgroup cap (128 or 256)
     struct Prof *prof;       // kernel timing (HIP events), null until enabled
     uint64_t ops[8];         // operation counters, see OP_* (read and reset by fhe_op_counts)

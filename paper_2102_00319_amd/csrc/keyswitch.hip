@@ -29,17 +29,22 @@
 //   2 k_conv_cols<up>   inverse column stages of the digit's limbs, times
 //                       (Q_j/q_a)^-1, conversion to every other limb of Q_l u P,
 //                       forward column stages                          -> up
-//   3 k_ks_row_inner    forward row pass of the converted limbs fused with the key
-//                       inner product (items with their own key), or k_row_fwd then
-//                       k_ks_inner (items that share a key read it once per group)
-//                                                                       -> uQ, uP
-//   4 k_row_inv         inverse row pass of uP
-//   5 k_conv_cols<down> inverse column stages, plus (P-1)/2, times (P/p_a)^-1,
+// then, for items with their own key (the default):
+//   3 k_ks_row_inner_pinv  forward row passes of the converted special-prime limbs,
+//                       key inner product, inverse row pass of the sum      -> uP
+//   4 k_conv_cols<down> inverse column stages, plus (P-1)/2, times (P/p_a)^-1,
 //                       conversion P -> Q_l minus (P-1)/2, forward column stages -> z
+//   5 k_ks_final_q      forward row passes of the converted Q limbs, key inner
+//                       product, forward row pass of z, (u - z) P^-1 + add   -> out
+// or, when items share a key (read once per group) or the fusion is off:
+//   3 k_row_fwd, k_ks_inner   forward row passes, then the inner product -> uQ, uP
+//   4 k_row_inv         inverse row pass of uP
+//   5 k_conv_cols<down> as above                                          -> z
 //   6 k_ks_moddown_final forward row pass of z fused with (u - z) P^-1 + add -> out
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <type_traits>
 
 #include "ntt_core.h"
 
@@ -93,6 +98,7 @@ static_assert(sizeof(KsGrp) == 24, "KsGrp is 3 table words");
 struct KsTab {
     uint32_t n, K, L;
     uint32_t it, la, uj, um, il, dj, fl, pl, gr;
+    uint32_t ip, iq;   // the inner list's special-prime entries, and its Q entries
 };
 __device__ __forceinline__ const KsItem &tab_item(uint64_t *const *tab, const KsTab &t, uint32_t b)
 {
@@ -103,9 +109,23 @@ __device__ __forceinline__ uint64_t tab_word(uint64_t *const *tab, uint32_t off,
     return (uint64_t)(uintptr_t)tab[off + y];
 }
 
+// Loads and stores of data read or written once (NT: non-temporal, so that they pass
+// through the caches without evicting the twiddle rows that every pass re-reads).
+template <bool NT, typename P>
+__device__ __forceinline__ uint64_t ld1(const P *p)
+{
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+template <bool NT, typename P>
+__device__ __forceinline__ void st1(P *p, uint64_t v)
+{
+    if (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 // 1. First (row) pass of the inverse transform of d_b into dc as lazy FP64 bits.
 //    blockIdx.y + y0 = entry of the la list.
-template <int LOGG, int WG>
+template <int LOGG, int WG, bool NT>
 __global__ __launch_bounds__(WG) void k_ks_intt_first(uint64_t *const *__restrict__ tab, KsTab t, uint32_t y0,
                                                       uint64_t *__restrict__ dc, const ModQ *__restrict__ mods,
                                                       const double *__restrict__ itwt, uint32_t logN,
@@ -122,12 +142,12 @@ __global__ __launch_bounds__(WG) void k_ks_intt_first(uint64_t *const *__restric
     const Gm gm(logN, blockIdx.x);
     double x[R];
 #pragma unroll
-    for (int k = 0; k < R; k++) x[k] = u64_to_f64(src[gm.coal(k)]);
+    for (int k = 0; k < R; k++) x[k] = u64_to_f64(ld1<NT>(src + gm.coal(k)));
     gm.coal_to_inv_in(x, lds);
     gm.template inv<false>(x, lds, itwt + (size_t)i * N, q, qinv, 0.0, logN, sigma0);
     uint64_t *dst = dc + (size_t)y * N;
 #pragma unroll
-    for (int k = 0; k < R; k++) dst[gm.inv_out(k)] = f64_to_bits(x[k]);
+    for (int k = 0; k < R; k++) st1<NT>(dst + gm.inv_out(k), f64_to_bits(x[k]));
 }
 
 // 4b. Key inner product, one thread per pair of coefficients (16-byte loads) of
@@ -240,29 +260,100 @@ __global__ __launch_bounds__(TPB) void k_ks_inner(uint64_t *const *__restrict__ 
 //     so the key is read at y and u stored at y; pi^-1 maps an aligned block of 64
 //     positions onto another one, so both stay coalesced.  Lazy values below 2.7 q
 //     enter the products (|v e / q| < 2^52) and three digits' products sum below 2^53
-//     (the sums are reduced every four digits).  blockIdx.y + y0 = entry of the
-//     inner list.
+//     (the sums are reduced every four digits).
+//     pi^-1 also maps the whole row of N/8 positions that a block reads onto one row
+//     (the row is fixed by the low 3 bits of the bit-reversed position, and those of
+//     pi^-1's image depend only on them), so a block holds a complete row of u: the
+//     fused forms below finish that row in the same block.
+struct InnerRow {
+    uint32_t b, x, l, nd, ginv, mx;
+    double q, qi;
+};
+// 16-byte access of the adjacent pair (p, p + 1), p even.
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) u64x2 gu64x2;
+template <bool NT>
+__device__ __forceinline__ u64x2 ld2w(const gu64 *p)
+{
+    const gu64x2 *v = reinterpret_cast<const gu64x2 *>(p);
+    if (NT) return __builtin_nontemporal_load(v);
+    return *v;
+}
+template <bool NT>
+__device__ __forceinline__ void st2w(gu64 *p, uint64_t a, uint64_t b)
+{
+    gu64x2 *v = reinterpret_cast<gu64x2 *>(p);
+    u64x2 w = {a, b};
+    if (NT) __builtin_nontemporal_store(w, v);
+    else *v = w;
+}
+// Where register k of a row sits after a forward row pass.  When the pass's last round
+// covers one bit (RL = 1), registers 2m and 2m + 1 hold the adjacent positions 2p and
+// 2p + 1 and the lanes' pairs are consecutive: the row is used in that order directly
+// (16-byte accesses; the Galois map sends the pair onto a pair, possibly swapped).
+// Otherwise the row goes through LDS into coalesced order first.
 template <int LOGG, int WG>
-__global__ __launch_bounds__(WG) void k_ks_row_inner(uint64_t *const *__restrict__ tab, KsTab t, uint32_t y0,
-                                                     const uint64_t *__restrict__ up, uint64_t *__restrict__ uQ,
-                                                     uint64_t *__restrict__ uP, const ModQ *__restrict__ mods,
-                                                     const double *__restrict__ twt, uint32_t alpha, uint32_t logN,
-                                                     uint32_t sigma0)
+struct RowOrder {
+    using Gm = Geom<LOGG, WG, false>;
+    static constexpr bool DIRECT = Gm::RL == 1;
+    static __device__ __forceinline__ uint32_t pos(const Gm &g, int k) { return DIRECT ? g.fwd_out(k) : g.coal(k); }
+    // LDS slot (in the lane's group) of register k's position
+    static __device__ __forceinline__ int slot_base(const Gm &g)
+    {
+        return DIRECT ? lds_pad(g.lt(0, Gm::RL)) : lds_pad(g.tau);
+    }
+    static constexpr int slot_k(int k) { return DIRECT ? lds_pad(Gm::lk(k, 0, Gm::RL)) : lds_pad(k << Gm::LOGT); }
+};
+template <int LOGG, int WG, bool NT>
+__device__ __forceinline__ InnerRow inner_row(uint64_t *const *__restrict__ tab, const KsTab &t, uint32_t entry,
+                                              const uint64_t *__restrict__ up, const ModQ *__restrict__ mods,
+                                              const double *__restrict__ twt, uint32_t alpha, uint32_t logN,
+                                              uint32_t sigma0, double *lds, double (&a0)[R], double (&a1)[R])
 {
     using Gm = Geom<LOGG, WG, false>;
-    __shared__ double lds[Gm::LDS];
     const uint32_t N = 1u << logN;
-    const uint64_t e = tab_word(tab, t.il, blockIdx.y + y0);
+    const uint64_t e = tab_word(tab, t.il, entry);
     const uint32_t g = (uint32_t)(e >> 16), x = (uint32_t)(e & 0xFFFF);
     const uint32_t b = reinterpret_cast<const KsGrp *>(tab + t.gr)[g].it[0];
     const KsItem &it = tab_item(tab, t, b);
-    const uint32_t l = it.l, nd = it.nd, ginv = it.ginv;
-    const uint32_t mx = x < l ? x : t.L + (x - l);
-    const double q = mods[mx].q, qi = mods[mx].qinv;
+    InnerRow r;
+    r.b = b;
+    r.x = x;
+    r.l = it.l;
+    r.nd = it.nd;
+    r.ginv = it.ginv;
+    r.mx = x < r.l ? x : t.L + (x - r.l);
+    r.q = mods[r.mx].q;
+    r.qi = mods[r.mx].qinv;
+    const uint32_t l = r.l, nd = r.nd, ginv = r.ginv, mx = r.mx;
+    const double q = r.q, qi = r.qi;
     const uint64_t *ev = tab[t.n + b];
     const size_t ML = t.L + t.K;
-    const Gm gm(logN, blockIdx.x);
-    double a0[R], a1[R];
+    using RO = RowOrder<LOGG, WG>;
+    // the row of digit jj: the item's own limb (NTT domain, in the order of RO) inside
+    // the digit, else its converted limb (column-stage form, forward-pass input order)
+    auto load_row = [&](const Gm &gj, uint32_t jj, uint64_t (&w)[R]) {
+        const uint32_t lo = jj * alpha, hi = min(lo + alpha, l);
+        if (x >= lo && x < hi) {
+            const gu64 *src = gview(tab[b] + (size_t)x * N);
+            if (RO::DIRECT) {
+#pragma unroll
+                for (int k = 0; k < R; k += 2) {
+                    const u64x2 p = ld2w<NT>(src + RO::pos(gj, k));
+                    w[k] = p.x;
+                    w[k + 1] = p.y;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < R; k++) w[k] = ld1<NT>(src + RO::pos(gj, k));
+            }
+        } else {
+            const uint32_t pos = x < lo ? x : x - (hi - lo);
+            const uint64_t *src = up + ((size_t)it.up_off + it.upoff[jj] + pos) * N;
+#pragma unroll
+            for (int k = 0; k < R; k++) w[k] = ld1<NT>(src + gj.fwd_in(k));
+        }
+    };
 #pragma unroll
     for (int k = 0; k < R; k++) a0[k] = a1[k] = 0.0;
 #pragma unroll 1
@@ -274,26 +365,36 @@ __global__ __launch_bounds__(WG) void k_ks_row_inner(uint64_t *const *__restrict
         asm volatile("" : "+v"(tid));
         const Gm gj(logN, blockIdx.x, tid);
         const uint32_t lo = j * alpha, hi = min(lo + alpha, l);
+        const bool own = x >= lo && x < hi;   // block-uniform
+        uint64_t w[R];
+        load_row(gj, j, w);
         double v[R];
-        if (x >= lo && x < hi) {   // block-uniform branch
-            const gu64 *src = gview(tab[b] + (size_t)x * N);
 #pragma unroll
-            for (int k = 0; k < R; k++) v[k] = u64_to_f64(src[gj.coal(k)]);
-        } else {
-            const uint32_t pos = x < lo ? x : x - (hi - lo);
-            const uint64_t *src = up + ((size_t)it.up_off + it.upoff[j] + pos) * N;
-#pragma unroll
-            for (int k = 0; k < R; k++) v[k] = bits_to_f64(src[gj.fwd_in(k)]);
+        for (int k = 0; k < R; k++) v[k] = own ? u64_to_f64(w[k]) : bits_to_f64(w[k]);
+        if (!own) {
             gj.fwd(v, lds, twt + (size_t)mx * N, q, qi, logN, sigma0);
-            gj.fwd_out_to_coal(v, lds);
+            if (!RO::DIRECT) gj.fwd_out_to_coal(v, lds);
         }
         const gu64 *e0 = gview(ev + (((size_t)j * 2 + 0) * ML + mx) * N);
         const gu64 *e1 = gview(ev + (((size_t)j * 2 + 1) * ML + mx) * N);
+        if (RO::DIRECT) {
 #pragma unroll
-        for (int k = 0; k < R; k++) {
-            const uint32_t y = galois_src(gj.coal(k), ginv, logN);
-            a0[k] += mulmod(v[k], u64_to_f64(e0[y]), q, qi);
-            a1[k] += mulmod(v[k], u64_to_f64(e1[y]), q, qi);
+            for (int k = 0; k < R; k += 2) {
+                const uint32_t y = galois_src(RO::pos(gj, k), ginv, logN);
+                const u64x2 p0 = ld2w<NT>(e0 + (y & ~1u)), p1 = ld2w<NT>(e1 + (y & ~1u));
+                const bool sw = y & 1u;
+                a0[k] += mulmod(v[k], u64_to_f64(sw ? p0.y : p0.x), q, qi);
+                a0[k + 1] += mulmod(v[k + 1], u64_to_f64(sw ? p0.x : p0.y), q, qi);
+                a1[k] += mulmod(v[k], u64_to_f64(sw ? p1.y : p1.x), q, qi);
+                a1[k + 1] += mulmod(v[k + 1], u64_to_f64(sw ? p1.x : p1.y), q, qi);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                const uint32_t y = galois_src(RO::pos(gj, k), ginv, logN);
+                a0[k] += mulmod(v[k], u64_to_f64(ld1<NT>(e0 + y)), q, qi);
+                a1[k] += mulmod(v[k], u64_to_f64(ld1<NT>(e1 + y)), q, qi);
+            }
         }
         if ((j & 3) == 3) {
 #pragma unroll
@@ -303,19 +404,151 @@ __global__ __launch_bounds__(WG) void k_ks_row_inner(uint64_t *const *__restrict
             }
         }
     }
-    gu64 *o0, *o1;
-    if (x < l) {
-        o0 = gview(uQ + ((size_t)it.uq_off + x) * N);
-        o1 = gview(uQ + ((size_t)it.uq_off + l + x) * N);
-    } else {
-        o0 = gview(uP + ((size_t)b * 2 * t.K + (x - l)) * N);
-        o1 = gview(uP + ((size_t)b * 2 * t.K + t.K + (x - l)) * N);
-    }
+    return r;
+}
+// This lane's place in the image of its row: the same group slot of the block (and
+// of LDS), the row's image under pi^-1 as the row index.
+template <int LOGG, int WG>
+__device__ __forceinline__ Geom<LOGG, WG, false> image_geom(uint32_t logN, uint32_t tid, uint32_t ginv)
+{
+    Geom<LOGG, WG, false> g(logN, blockIdx.x, tid);
+    g.gi = galois_src(g.gi << LOGG, ginv, logN) >> LOGG;
+    return g;
+}
+// The sums of both key polynomials, canonical, from registers (a_t[k] belongs at
+// position pi^-1(p) of the image row, p: register k's position in RowOrder) into two row buffers of LDS, each value in
+// the slot of its own position (slot: lds_pad of the offset in the row); the caller
+// reads them back in the order it needs, so the sums leave the registers before the
+// next transforms.
+template <int LOGG, int WG>
+__device__ __forceinline__ void scatter_rows(const Geom<LOGG, WG, false> &gm, const double (&a0)[R],
+                                             const double (&a1)[R], double q, double qi, double *lds0, double *lds1,
+                                             uint32_t ginv, uint32_t logN)
+{
+    constexpr uint32_t G = 1u << LOGG;
+    constexpr int GS = Geom<LOGG, WG, false>::GS;
+    double *w0 = lds0 + gm.grp * GS, *w1 = lds1 + gm.grp * GS;
 #pragma unroll
     for (int k = 0; k < R; k++) {
-        const uint32_t y = galois_src(gm.coal(k), ginv, logN);
-        o0[y] = f64_to_u64(canon(a0[k], q, qi));
-        o1[y] = f64_to_u64(canon(a1[k], q, qi));
+        const int y = (int)(galois_src(RowOrder<LOGG, WG>::pos(gm, k), ginv, logN) & (G - 1));
+        w0[lds_pad(y)] = canon(a0[k], q, qi);
+        w1[lds_pad(y)] = canon(a1[k], q, qi);
+    }
+    __syncthreads();
+}
+
+// The special-prime entries (blockIdx.y + y0 = entry of the ip list) with the inverse
+// row pass of uP in the same block: the row of u_t is gathered in LDS in its own
+// positions, read in the inverse pass's order, transformed and stored as lazy bits
+// (what k_row_inv stores from the canonical uP).
+template <int LOGG, int WG, bool NT>
+__global__ __launch_bounds__(WG) void k_ks_row_inner_pinv(uint64_t *const *__restrict__ tab, KsTab t, uint32_t y0,
+                                                          const uint64_t *__restrict__ up, uint64_t *__restrict__ uP,
+                                                          const ModQ *__restrict__ mods,
+                                                          const double *__restrict__ twt,
+                                                          const double *__restrict__ itwt, uint32_t alpha,
+                                                          uint32_t logN, uint32_t sigma0)
+{
+    using Gm = Geom<LOGG, WG, false>;
+    constexpr int r0 = LOGG < LOGR ? LOGG : LOGR;
+    __shared__ double lds[2 * Gm::LDS];
+    const uint32_t N = 1u << logN;
+    const uint32_t entry = (uint32_t)tab_word(tab, t.ip, blockIdx.y + y0);
+    InnerRow r;
+    {
+        double a0[R], a1[R];
+        r = inner_row<LOGG, WG, NT>(tab, t, entry, up, mods, twt, alpha, logN, sigma0, lds, a0, a1);
+        scatter_rows(Gm(logN, blockIdx.x), a0, a1, r.q, r.qi, lds, lds + Gm::LDS, r.ginv, logN);
+    }
+#pragma unroll 1
+    for (int tt = 0; tt < 2; ++tt) {
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const Gm go = image_geom<LOGG, WG>(logN, tid, r.ginv);
+        double *buf = lds + tt * Gm::LDS;
+        double v[R];
+        const double *rd = buf + go.grp * Gm::GS + lds_pad(go.lt(0, r0));
+#pragma unroll
+        for (int k = 0; k < R; k++) v[k] = rd[lds_pad(Gm::lk(k, 0, r0))];
+        __syncthreads();
+        go.template inv<false>(v, buf, itwt + (size_t)r.mx * N, r.q, r.qi, 0.0, logN, sigma0);
+        uint64_t *dst = uP + ((size_t)r.b * 2 * t.K + tt * t.K + (r.x - r.l)) * N;
+#pragma unroll
+        for (int k = 0; k < R; k++) st1<NT>(dst + go.inv_out(k), f64_to_bits(v[k]));
+    }
+}
+
+// The Q entries (blockIdx.y + y0 = entry of the iq list) fused with the ModDown finish:
+// the block's row of u_t (both t) is gathered in LDS in its own positions and read
+// back in coalesced order, the same row of z_t gets its forward row pass, and
+//   out_t[x] = (u_t[x] - z_t[x]) * P^-1 + add_t[x]
+// is stored; uQ is never written.
+template <int LOGG, int WG, bool NT>
+__global__ __launch_bounds__(WG) void k_ks_final_q(uint64_t *const *__restrict__ tab, KsTab t, uint32_t y0,
+                                                   const uint64_t *__restrict__ up, const uint64_t *__restrict__ z,
+                                                   const ModQ *__restrict__ mods, const double *__restrict__ twt,
+                                                   const double *__restrict__ pinv, uint32_t alpha, uint32_t logN,
+                                                   uint32_t sigma0)
+{
+    using Gm = Geom<LOGG, WG, false>;
+    __shared__ double lds[2 * Gm::LDS];
+    const uint32_t N = 1u << logN;
+    const uint32_t entry = (uint32_t)tab_word(tab, t.iq, blockIdx.y + y0);
+    InnerRow r;
+    {
+        double a0[R], a1[R];
+        r = inner_row<LOGG, WG, NT>(tab, t, entry, up, mods, twt, alpha, logN, sigma0, lds, a0, a1);
+        scatter_rows(Gm(logN, blockIdx.x), a0, a1, r.q, r.qi, lds, lds + Gm::LDS, r.ginv, logN);
+    }
+    // z_t's row of this Q limb: the item's z rows follow its uQ offset
+    const uint64_t *z0 = z + ((size_t)tab_item(tab, t, r.b).uq_off + r.x) * N;
+    const uint32_t gal = (uint32_t)tab_word(tab, 5 * t.n, r.b);
+    const double pi = pinv[r.x];
+#pragma unroll 1
+    for (int tt = 0; tt < 2; ++tt) {
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const Gm go = image_geom<LOGG, WG>(logN, tid, r.ginv);
+        double *buf = lds + tt * Gm::LDS;
+        // u_t in the order z_t's row has after its pass, then buffer t serves that pass
+        using RO = RowOrder<LOGG, WG>;
+        double u[R], v[R];
+        const double *rd = buf + go.grp * Gm::GS + RO::slot_base(go);
+#pragma unroll
+        for (int k = 0; k < R; k++) u[k] = rd[RO::slot_k(k)];
+        const uint64_t *zs = z0 + (size_t)tt * r.l * N;
+#pragma unroll
+        for (int k = 0; k < R; k++) v[k] = bits_to_f64(ld1<NT>(zs + go.fwd_in(k)));
+        const uint64_t *adp = tab[3 * t.n + 2 * r.b + tt];
+        const gu64 *ad = gview(adp) + (size_t)r.x * N;
+        __syncthreads();
+        go.fwd(v, buf, twt + (size_t)r.x * N, r.q, r.qi, logN, sigma0);
+        if (!RO::DIRECT) go.fwd_out_to_coal(v, buf);
+        gu64 *out = gview(tab[2 * t.n + r.b] + ((size_t)tt * r.l + r.x) * N);
+        double o[R];
+#pragma unroll
+        for (int k = 0; k < R; k++) o[k] = canon(mulmod(u[k] - v[k], pi, r.q, r.qi), r.q, r.qi);
+        if (RO::DIRECT) {
+#pragma unroll
+            for (int k = 0; k < R; k += 2) {
+                const uint32_t idx = RO::pos(go, k);
+                if (adp) {
+                    const uint32_t y = galois_src(idx, gal, logN);
+                    const u64x2 a = ld2w<NT>(ad + (y & ~1u));
+                    const bool sw = y & 1u;
+                    o[k] = fold(o[k] + u64_to_f64(sw ? a.y : a.x), r.q);
+                    o[k + 1] = fold(o[k + 1] + u64_to_f64(sw ? a.x : a.y), r.q);
+                }
+                st2w<NT>(out + idx, f64_to_u64(o[k]), f64_to_u64(o[k + 1]));
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                const uint32_t idx = RO::pos(go, k);
+                if (adp) o[k] = fold(o[k] + u64_to_f64(ld1<NT>(ad + galois_src(idx, gal, logN))), r.q);
+                st1<NT>(out + idx, f64_to_u64(o[k]));
+            }
+        }
     }
 }
 
@@ -683,6 +916,7 @@ struct KsPlan {
     std::vector<CvJob> upjobs, dnjobs;
     std::vector<KsGrp> groups;
     std::vector<uint64_t> la, upmods, inner, fl, pl;
+    std::vector<uint64_t> ip, iq;   // indices into inner of its special-prime and Q entries
 };
 
 // g^-1 mod 2N for odd g (the units mod 2N form a group of order N, so g^-1 = g^(N-1))
@@ -786,8 +1020,13 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
         pl.max_grp = std::max(pl.max_grp, g.m);
     }
     if (pl.groups.size() >= 65536) return fhe_fail(FHE_EINVAL, "key-switch batch too large");
-    for (uint32_t g = 0; g < pl.groups.size(); ++g)
-        for (uint32_t x = 0; x < ls[pl.groups[g].it[0]] + K; ++x) pl.inner.push_back(((uint64_t)g << 16) | x);
+    for (uint32_t g = 0; g < pl.groups.size(); ++g) {
+        const uint32_t l = ls[pl.groups[g].it[0]];
+        for (uint32_t x = 0; x < l + K; ++x) {
+            (x < l ? pl.iq : pl.ip).push_back(pl.inner.size());
+            pl.inner.push_back(((uint64_t)g << 16) | x);
+        }
+    }
     pl.sum_l = uq / 2;
     pl.sum_dc = dc;
     pl.sum_ups = up;
@@ -799,6 +1038,13 @@ fhe_status ks_plan(const fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
 }  // namespace
 
 // ---- launchers of the key-switching path
+// The fused kernels' variant from the context's knob: f(NT) as an integral constant.
+template <typename F>
+static void ks_fused_variant(const fhe_ctx *c, F f)
+{
+    if (c->tune_ks_nt) f(std::true_type{});
+    else f(std::false_type{});
+}
 static void ks_row_fwd(fhe_ctx *c, uint64_t *base, const uint64_t *lst, uint32_t nlimbs)
 {
     ProfScope ps(c, "ntt_fwd_row");
@@ -920,6 +1166,10 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
     push_words(pl.pl.data(), pl.pl.size() * 8);
     kt.gr = (uint32_t)tab.size();
     push_words(pl.groups.data(), pl.groups.size() * sizeof(KsGrp));
+    kt.ip = (uint32_t)tab.size();
+    push_words(pl.ip.data(), pl.ip.size() * 8);
+    kt.iq = (uint32_t)tab.size();
+    push_words(pl.iq.data(), pl.iq.size() * 8);
     uint64_t **dt;
     if ((s = ctx_ptr_table(c, tab, &dt))) return s;
     const uint64_t *dwords = (const uint64_t *)dt;
@@ -932,26 +1182,61 @@ fhe_status ks_run_ragged(fhe_ctx *c, uint32_t n, const uint32_t *ls, const uint6
         dispatch_row(c, [&](auto sh) {
             using S = decltype(sh);
             in_pieces(pl.sum_dc, [&](uint32_t y0, uint32_t cnt) {
-                hipLaunchKernelGGL((k_ks_intt_first<S::LOGW, S::WG>), dim3(S::GB, cnt), dim3(S::WG), 0, st,
-                                   (uint64_t *const *)dt, kt, y0, dc, (const ModQ *)c->d_mod, (const double *)c->d_itw,
-                                   c->logN, 3u);
+                if (c->tune_ks_nt)
+                    hipLaunchKernelGGL((k_ks_intt_first<S::LOGW, S::WG, true>), dim3(S::GB, cnt), dim3(S::WG), 0, st,
+                                       (uint64_t *const *)dt, kt, y0, dc, (const ModQ *)c->d_mod,
+                                       (const double *)c->d_itw, c->logN, 3u);
+                else
+                    hipLaunchKernelGGL((k_ks_intt_first<S::LOGW, S::WG, false>), dim3(S::GB, cnt), dim3(S::WG), 0,
+                                       st, (uint64_t *const *)dt, kt, y0, dc, (const ModQ *)c->d_mod,
+                                       (const double *)c->d_itw, c->logN, 3u);
             });
         });
     }
     // 2. ModUp: column stages and conversion of every digit
     ks_conv<false>(c, dc, up, dwords + kt.uj, pl.sum_nd, pl.up_ns, pl.up_max, "bconv_up");
-    // 3. forward row pass of the converted limbs and the key inner product
     if (pl.max_grp == 1 && c->tune_fuse_row_inner) {
-        ProfScope ps(c, "ks_inner");
-        dispatch_row(c, [&](auto sh) {
-            using S = decltype(sh);
-            in_pieces(pl.sum_inner, [&](uint32_t y0, uint32_t cnt) {
-                hipLaunchKernelGGL((k_ks_row_inner<S::LOGW, S::WG>), dim3(S::GB, cnt), dim3(S::WG), 0, st,
-                                   (uint64_t *const *)dt, kt, y0, (const uint64_t *)up, uQ, uP, (const ModQ *)c->d_mod,
-                                   (const double *)c->d_tw, c->alpha, c->logN, 3u);
+        // items with their own keys: 3+4. forward row passes and the key inner product
+        // of the special-prime limbs with the inverse row pass of uP, 5. ModDown's
+        // conversion, 6. forward row passes and the inner product of the Q limbs with
+        // the ModDown finish (uQ stays on chip)
+        {
+            ProfScope ps(c, "ks_inner");
+            dispatch_row(c, [&](auto sh) {
+                using S = decltype(sh);
+                in_pieces((uint32_t)pl.ip.size(), [&](uint32_t y0, uint32_t cnt) {
+                    auto go = [&](auto nt) {
+                        hipLaunchKernelGGL((k_ks_row_inner_pinv<S::LOGW, S::WG, decltype(nt)::value>),
+                                           dim3(S::GB, cnt), dim3(S::WG), 0, st, (uint64_t *const *)dt, kt, y0,
+                                           (const uint64_t *)up, uP, (const ModQ *)c->d_mod,
+                                           (const double *)c->d_tw, (const double *)c->d_itw, c->alpha, c->logN, 3u);
+                    };
+                    ks_fused_variant(c, go);
+                });
             });
-        });
-    } else {
+        }
+        ks_conv<true>(c, uP, z, dwords + kt.dj, 2 * n, pl.dn_ns, pl.dn_max, "bconv_down");
+        {
+            ProfScope ps(c, "ks_moddown_final");
+            dispatch_row(c, [&](auto sh) {
+                using S = decltype(sh);
+                in_pieces((uint32_t)pl.iq.size(), [&](uint32_t y0, uint32_t cnt) {
+                    auto go = [&](auto nt) {
+                        hipLaunchKernelGGL((k_ks_final_q<S::LOGW, S::WG, decltype(nt)::value>),
+                                           dim3(S::GB, cnt),
+                                           dim3(S::WG), 0, st, (uint64_t *const *)dt, kt, y0, (const uint64_t *)up,
+                                           (const uint64_t *)z, (const ModQ *)c->d_mod, (const double *)c->d_tw,
+                                           (const double *)c->d_pinv, c->alpha, c->logN, 3u);
+                    };
+                    ks_fused_variant(c, go);
+                });
+            });
+        }
+        HIPCHK(hipGetLastError());
+        return FHE_OK;
+    }
+    // 3. forward row pass of the converted limbs and the key inner product
+    {
         ks_row_fwd(c, up, dwords + kt.um, pl.sum_ups);
         ProfScope ps(c, "ks_inner");
         in_pieces(pl.sum_inner, [&](uint32_t y0, uint32_t cnt) {

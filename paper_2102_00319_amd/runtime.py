@@ -150,7 +150,7 @@ class UnevenBatch:
 
 
 # kernel knobs of the library (fhe_ctx_set_tuning) and the values tried
-KNOB_VALUES = {"ks_fuse_row_inner": (1, 0), "row_wg": (128, 256)}
+KNOB_VALUES = {"ks_fuse_row_inner": (1, 0), "ks_nt": (1, 0), "row_wg": (128, 256)}
 
 
 def knob_candidates(names):

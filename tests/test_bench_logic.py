@@ -18,13 +18,26 @@ def test_inner_product_bytes_per_key_switch():
     assert b == 8 * (3 * 3 * 32 + 2 * 32) * limb == 1476395008
 
 
-def test_fused_row_pass_moves_no_bytes_of_its_own():
+def test_fused_path_bytes_per_key_switch():
+    """The fused path (row passes inside the inner products, uQ kept on chip, uP's inverse
+    row pass inside the special-prime inner product) against the split path, in limbs
+    per key switch at N = 2^16, l = 24, K = 8, dnum 3 (the rotation addend included)."""
     args = (1 << 16, 24, 8, 8, 8, 3, 24)
-    assert bench.kernel_model("ntt_fwd_row", *args, fused=True) == (0, 0)
-    b_split, f_split = bench.kernel_model("ntt_fwd_row", *args, fused=False)
-    b_in0, f_in0 = bench.kernel_model("ks_inner", *args, fused=False)
-    b_in1, f_in1 = bench.kernel_model("ks_inner", *args, fused=True)
-    assert b_in1 == b_in0 and f_in1 == f_in0 + f_split and b_split > 0
+    limb = (1 << 16) * 8
+    cats = ["ks_intt_first", "bconv_up", "ntt_fwd_row", "ks_inner", "ntt_inv_row", "bconv_down", "ks_moddown_final"]
+
+    def limbs(fused):
+        return {c: bench.kernel_model(c, *args, fused=fused)[0] // (8 * limb) for c in cats}
+    f, s = limbs(True), limbs(False)
+    assert f["ntt_fwd_row"] == f["ntt_inv_row"] == 0 and s["ntt_fwd_row"] == 2 * 72 and s["ntt_inv_row"] == 32
+    # special primes: 3 digits of D_j, both key polynomials, uP out
+    assert f["ks_inner"] == 3 * 8 + 3 * 2 * 8 + 2 * 8 == 88
+    # Q limbs: 3 digits of D_j and both keys, z in, addend in, out
+    assert f["ks_moddown_final"] == 3 * 3 * 24 + 2 * 24 + 24 + 2 * 24 == 336
+    assert sum(f.values()) == 632 and sum(s.values()) == 48 + 96 + 144 + 352 + 32 + 64 + 168
+    # the same flops for the transforms: every converted limb still gets its row pass
+    fl = lambda fused, c: bench.kernel_model(c, *args, fused=fused)[1]
+    assert sum(fl(True, c) for c in cats) == sum(fl(False, c) for c in cats)
 
 
 def test_conversion_targets():

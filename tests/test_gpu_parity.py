@@ -413,9 +413,10 @@ def test_rotation_batch_as_benchmarked(sets):
 
 
 def test_keyswitch_knobs_give_the_same_bits(sets):
-    """The key switch's kernel knob (the forward row pass fused with the key inner
-    product, or the two as separate kernels) gives the same bits either way, for
-    rotations with distinct keys and for relinearisations that share one key."""
+    """The key switch's kernel knobs (the five-kernel fused form or the seven-kernel
+    one; data used once loaded and stored non-temporally or not) give the
+    same bits every way, for rotations with distinct keys and for relinearisations
+    that share one key."""
     import torch
     g, _ = sets("c3_n15")
     s = g.keygen_secret(workloads.SEED_SECRET)
@@ -434,9 +435,11 @@ def test_keyswitch_knobs_give_the_same_bits(sets):
         torch.cuda.synchronize()
         return [x.data.clone() for x in rot + rel]
     ref = run()
-    for fuse in (0, 1):
+    for fuse, nt in ((0, 0), (0, 1), (1, 0), (1, 1)):
         g.set_tuning("ks_fuse_row_inner", fuse)
+        g.set_tuning("ks_nt", nt)
         got = run()
         for i, (a, b) in enumerate(zip(got, ref)):
-            assert torch.equal(a, b), (fuse, i)
+            assert torch.equal(a, b), (fuse, nt, i)
     g.set_tuning("ks_fuse_row_inner", 1)
+    g.set_tuning("ks_nt", 1)
