@@ -183,7 +183,7 @@ def parse():
                          "(0); default: chosen by the autotuner on the step")
     ap.add_argument("--ks-nt", type=int, default=1, choices=[0, 1],
                     help="keyswitch with --ks-fuse given: non-temporal loads and stores of data used once (1)")
-    ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "kssweep", "cnn2", "cnn4", "batch3", "serve", "fig3", "paper",
+    ap.add_argument("--workload", default="keyswitch", choices=["keyswitch", "kssweep", "cnn2", "cnn4", "batch3", "serve", "fig3",
                                                            "latency"],
                     help="keyswitch: the headline metric; cnn2: slot-packed encrypted CNN images/s; "
                          "cnn4: within-image packed deep CNN images/s; batch3: 256 uneven jobs (mixed N and "
@@ -205,7 +205,6 @@ def parse():
     ap.add_argument("--cold-wait", type=float, default=2.0,
                     help="serve: seconds a request of a client in host memory waits behind resident clients' ones")
     ap.add_argument("--packed-clients", type=int, default=4, help="serve: deep-CNN clients")
-    ap.add_argument("--band", type=int, default=2, help="paper: pooled rows per conv/ActPool band")
     return ap.parse_args()
 
 
@@ -694,73 +693,6 @@ def fig3(args):
                                                            "~2^46, dnum 4" % FIG3_SET}}))
 
 
-def _paper_cnn_fp64(imgs, wc, wfc, coef):
-    h = _conv_fp64(imgs[:, None], wc, 1, 0)[:, :, :26, :26]
-    h = coef[0] + coef[1] * h + coef[2] * h * h
-    B, C, H, W = h.shape
-    h = h.reshape(B, C, H // 2, 2, W // 2, 2).mean(axis=(3, 5))
-    return h.reshape(B, -1) @ wfc.T
-
-
-def paper(args):
-    print(json.dumps(run_paper(args)))
-
-
-def run_paper(args):
-    """The paper's network at its ring (m = 2^16: N = 2^15, 16384 images per batch,
-    Sec. 4.3): conv 3x3 x 28 without padding, ActPool (g and 2x2 mean), FC 4732 -> 10,
-    images and weights encrypted.  One step = one forward pass over the batch.  The
-    paper's own run takes 561 s for the batch on 112 POWER9 threads (Sec. 4.4), quoted
-    as context only."""
-    import numpy as np
-    import torch
-
-    import workloads
-    import paper_2102_00319_amd as P
-    from paper_2102_00319_amd import networks
-
-    torch.cuda.set_device(0)
-    g = P.Context.from_set("p_n15")
-    net = networks.PaperCNN(band=args.band)
-    B = g.N // 2
-    imgs = workloads.images(workloads.SEED_DATA, B, 28, 28)
-    wc = workloads.weights(workloads.SEED_DATA + 1, (28, 1, 3, 3))
-    wfc = workloads.weights(workloads.SEED_DATA + 2, (10, 4732))
-    t_setup = time.perf_counter()
-    s = g.keygen_secret(workloads.SEED_SECRET)
-    pk = g.keygen_pk(s, workloads.SEED_PK)
-    rlk, _ = net.keygen(g, s, workloads.SEED_EVK)
-    X = net.encrypt_images(g, pk, imgs, workloads.SEED_ENC, progress=lambda m: say("paper: " + m))
-    W = net.encrypt_weights(g, pk, wc, wfc, (workloads.SEED_ENC + 100000, workloads.SEED_ENC + 200000))
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t_setup
-    say("paper: keys, images and weights ready (%.1f s)" % t_setup)
-    out = net.forward(g, rlk, {}, X, W, progress=lambda m: say("paper: " + m))
-    err = float(np.abs(net.decrypt_scores(g, s, out, B) - _paper_cnn_fp64(imgs, wc, wfc, net.coef)).max())
-    del out
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = net.forward(g, rlk, {}, X, W)
-        del out
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    say("paper: %.3f s per batch, max error %.2e" % (dt, err))
-    g.profile_enable("*")
-    out = net.forward(g, rlk, {}, X, W)
-    torch.cuda.synchronize()
-    prof = {c: g.profile_read(c)[0] for c in PROFILE_CATEGORIES}
-    g.profile_enable(None)
-    rec = {"metric": "the paper's encrypted CNN: seconds per 16384-image batch and images/s",
-           "value": round(B / dt, 1), "unit": "images/s", "s_per_batch": round(dt, 3), "images_per_batch": B,
-           "steps": args.steps, "max_abs_logit_error_vs_fp64": err, "setup_s": round(t_setup, 1),
-           "paper_context": "561 s per batch on 112 POWER9 threads with HElib (Sec. 4.4), another machine",
-           "kernel_ms_per_batch": {k: round(v, 1) for k, v in sorted(prof.items(), key=lambda kv: -kv[1]) if v > 0},
-           "config": {"workload": "conv3x3x28 (no pad) -> ActPool(g, 2x2 mean) -> FC4732x10, N=2^15, 16 limbs "
-                                  "(q0 ~2^50, 15 x ~2^40), scale 2^40, 16384 images, band %d" % args.band}}
-    return rec
-
-
 def kssweep(args):
     """Key switches per second against batch size B in {1, 8, 32, 64}: B ciphertexts
     with B distinct Galois keys, B ciphertexts sharing one key, and one ciphertext
@@ -999,8 +931,6 @@ def main():
         return serve(args)
     if args.workload == "fig3":
         return fig3(args)
-    if args.workload == "paper":
-        return paper(args)
     if args.workload == "latency":
         return latency(args)
     if args.workload == "kssweep":
@@ -1180,9 +1110,9 @@ def main():
 
 def cnn_extras(args):
     """The encrypted-CNN part of the metric, from short runs after the key-switch
-    measurement: the deep CNN (N = 2^16) batched and one ciphertext per call, the slot
-    CNN (N = 2^14, FC1 = 100) batched and one ciphertext per call, and the paper's
-    network at its ring; images/s and the largest score error against FP64 each."""
+    measurement: the deep CNN (N = 2^16) batched and one ciphertext per call, and the slot
+    CNN (N = 2^14, FC1 = 100) batched and one ciphertext per call; images/s and the
+    largest score error against FP64 each."""
     import gc
     import types
 
@@ -1196,8 +1126,7 @@ def cnn_extras(args):
     out = {}
     common = dict(steps=3, warmup=1, row_wg=args.row_wg, graph_streams=0, unbatched=True)
     runs = [("deep_cnn_n16", run_cnn4, dict(act="cubic")),
-            ("slot_cnn_n14_fc1_100", run_cnn2, dict(fc1=100)),
-            ("paper_cnn_n15", run_paper, dict(band=2, unbatched=False))]
+            ("slot_cnn_n14_fc1_100", run_cnn2, dict(fc1=100))]
     for name, fn, kw in runs:
         say("extras: %s" % name)
         t0 = time.perf_counter()
@@ -1217,23 +1146,6 @@ def cnn_extras(args):
         say("extras: %s %s images/s (%.1f s)" % (name, r["value"], keep["wall_s"]))
         del r
         free()
-    # one serving rate: latency percentiles from arrival to decrypted scores
-    say("extras: serving")
-    t0 = time.perf_counter()
-    a = types.SimpleNamespace(rates="10", requests=40, budget_gb=250.0, lanes=4, host_budget_gb=0.0, cold_wait=2.0,
-                              packed_clients=1, fc1=10)
-    try:
-        r = run_serve(a)
-        s = r["per_rate"][0]
-        out["serving"] = {k: s[k] for k in ("rate_req_s", "requests", "images", "images_per_s", "p50_ms", "p99_ms",
-                                            "mean_admission_wait_ms")}
-        out["serving"]["workload"] = (r["config"]["workload"] + "; one slot-CNN and one deep-CNN client, 4 lanes, "
-                                      "Poisson arrivals at 10 req/s")
-        out["serving"]["wall_s"] = round(time.perf_counter() - t0, 1)
-        say("extras: serving p50 %s ms, p99 %s ms" % (s["p50_ms"], s["p99_ms"]))
-    except Exception as e:
-        out["serving"] = {"error": "%s: %s" % (type(e).__name__, e)}
-    free()
     return out
 
 
