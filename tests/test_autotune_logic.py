@@ -64,3 +64,32 @@ def test_kernel_knobs_tuned_on_the_workload(tmp_path):
     best2, times2 = runtime.tune_knobs(runtime.Autotuner(str(tmp_path / "t.json")), "w", ctxs, run,
                                        ["ks_fuse_row_inner", "row_wg"])
     assert best2 == best and times2 is None and len(runs) == n
+
+
+def test_cached_choice_is_per_knob_set(tmp_path):
+    """A choice cached for one set of knobs is not taken for another set: the workload
+    key carries the knob names, so adding a knob measures again."""
+    class Ctx:
+        def __init__(self):
+            self.knobs = {}
+
+        def set_tuning(self, k, v):
+            self.knobs[k] = v
+
+    import torch
+    sync = torch.cuda.synchronize
+    torch.cuda.synchronize = lambda *a, **k: None   # no device here
+    try:
+        ctx = Ctx()
+        calls = []
+        t = runtime.Autotuner(str(tmp_path / "t.json"))
+        best1, times1 = runtime.tune_knobs(t, "w", [ctx], lambda: calls.append(1), ["ks_fuse_row_inner"], reps=1)
+        n1 = len(calls)
+        best2, times2 = runtime.tune_knobs(runtime.Autotuner(str(tmp_path / "t.json")), "w", [ctx],
+                                           lambda: calls.append(1), ["ks_fuse_row_inner", "ks_nt"], reps=1)
+    finally:
+        torch.cuda.synchronize = sync
+    assert times1 is not None and times2 is not None and len(calls) > n1
+    assert set(best1) == {"ks_fuse_row_inner"} and set(best2) == {"ks_fuse_row_inner", "ks_nt"}
+    assert set(json.loads((tmp_path / "t.json").read_text())) == {"w|knobs=ks_fuse_row_inner",
+                                                                  "w|knobs=ks_fuse_row_inner,ks_nt"}
