@@ -51,26 +51,27 @@ def source_digest(path):
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None when
-    there is none or the kernel's source code changed since the counters were taken."""
+def measured_traffic(kernel, form):
+    """HBM bytes per launch of `kernel` (category) in the key switch's `form` ("fused" or
+    "split") from the committed counter summary, or None when there is none for that form
+    or the kernel's source code changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "%s_n16_l24_hbm_counters.md" % kernel)
     try:
         fields = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line
-                      and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel", "source"))
+                      and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel", "form", "source"))
         src, digest = fields["source"].split(" code-sha256[:16] ")
         now = source_digest(os.path.join(ROOT, src))
-        if fields["kernel"].strip() != kernel or now != digest.strip():
+        if fields["kernel"].strip() != kernel or fields["form"].strip() != form or now != digest.strip():
             return None
         return int(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
 
 
-def measured_step_traffic(param_set, batch):
-    """HBM bytes of one step (all kernels of `batch` key switches) from the committed
-    per-kernel counter summary, or None when there is none for this shape or the
-    key-switch source changed since the counters were taken."""
+def measured_step_traffic(param_set, batch, form):
+    """HBM bytes of one step (all kernels of `batch` key switches in the key switch's
+    `form`) from the committed per-kernel counter summary, or None when there is none for
+    this shape and form or the key-switch source changed since the counters were taken."""
     if param_set != "c4_n16":
         return None
     path = os.path.join(ROOT, "profiles", "keyswitch_n16_l24_step_hbm_counters.md")
@@ -80,7 +81,7 @@ def measured_step_traffic(param_set, batch):
             name, digest = src.strip().split(" code-sha256[:16] ")
             if source_digest(os.path.join(ROOT, name)) != digest.strip():
                 return None
-        if int(fields["batch"]) != batch:
+        if int(fields["batch"]) != batch or fields["form"].strip() != form:
             return None
         return int(fields["traffic_bytes_per_step"])
     except (OSError, KeyError, ValueError):
@@ -1059,9 +1060,10 @@ def main():
 
     # Roofline of the whole key switch: the compulsory bytes counted per key switch
     # (input, key, output) times the key switches of a step, over the timed step.
+    form = "fused" if args.ks_fuse else "split"
     step_gbs = B * ks_bytes / (ms_per_step * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(step_gbs / HBM_PEAK_GBS, 4), "traffic": measured_step_traffic(args.param_set, B),
+            "frac": round(step_gbs / HBM_PEAK_GBS, 4), "traffic": measured_step_traffic(args.param_set, B, form),
             "scope": "whole key switch: %d key switches per step, all kernels, step time" % B,
             "algorithmic_bytes_per_step": int(B * ks_bytes)}
     # the dominant kernel on its own, live-timed with HIP events on the library's stream
@@ -1077,7 +1079,7 @@ def main():
         "frac_compulsory": round(compulsory_gbs / HBM_PEAK_GBS, 4),
         "frac_own_io": round(own_gbs / HBM_PEAK_GBS, 4),
         "own_io_bytes_per_launch": int(per_launch_b),
-        "own_io_traffic": measured_traffic(dominant),
+        "own_io_traffic": measured_traffic(dominant, form),
         "tflops": round(per_launch_f / (avg_ms * 1e-3) / 1e12, 2)}
 
     rec = {

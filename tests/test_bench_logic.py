@@ -54,7 +54,9 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_counter_lookup_needs_matching_source():
-    assert bench.measured_traffic("no_such_kernel") is None
+    assert bench.measured_traffic("no_such_kernel", "fused") is None
+    # the committed counters are those of the fused form
+    assert bench.measured_traffic("ks_moddown_final", "split") is None
 
 
 def test_source_digest_ignores_comments(tmp_path):
