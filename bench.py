@@ -53,7 +53,7 @@ def source_digest(path):
 
 def measured_traffic(kernel, form):
     """HBM bytes per launch of `kernel` (category) in the key switch's `form` ("fused" or
-    "split") from the committed counter summary, or None when there is none for that form
+    "split", "-nt" appended with non-temporal streams) from the committed counter summary, or None when there is none for that form
     or the kernel's source code changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "%s_n16_l24_hbm_counters.md" % kernel)
     try:
@@ -1060,7 +1060,7 @@ def main():
 
     # Roofline of the whole key switch: the compulsory bytes counted per key switch
     # (input, key, output) times the key switches of a step, over the timed step.
-    form = "fused" if args.ks_fuse else "split"
+    form = ("fused" if args.ks_fuse else "split") + ("-nt" if args.ks_nt else "")
     step_gbs = B * ks_bytes / (ms_per_step * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(step_gbs / HBM_PEAK_GBS, 4), "traffic": measured_step_traffic(args.param_set, B, form),

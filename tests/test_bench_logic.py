@@ -57,6 +57,7 @@ def test_counter_lookup_needs_matching_source():
     assert bench.measured_traffic("no_such_kernel", "fused") is None
     # the committed counters are those of the fused form
     assert bench.measured_traffic("ks_moddown_final", "split") is None
+    assert bench.measured_traffic("ks_moddown_final", "fused") is None   # taken with non-temporal streams
 
 
 def test_source_digest_ignores_comments(tmp_path):
