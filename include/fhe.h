@@ -100,6 +100,7 @@ const char *fhe_last_error(void);
 uint32_t fhe_ring_degree(const fhe_ctx *ctx);
 uint64_t fhe_modulus(const fhe_ctx *ctx, uint32_t idx);          /* 0..n_q-1: q_i; n_q..: p_j */
 size_t fhe_evk_bytes(const fhe_ctx *ctx);
+size_t fhe_ct_bytes(const fhe_ctx *ctx, uint32_t limbs, uint32_t polys);   /* device bytes of a ciphertext (0: null ctx) */
 uint64_t fhe_galois_elt(const fhe_ctx *ctx, int32_t step);        /* 5^(step mod N/2) mod 2N */
 uint64_t fhe_scratch_bytes(const fhe_ctx *ctx);                   /* scratch currently held */
 uint64_t fhe_workspace_bytes(const fhe_ctx *ctx);                 /* layer workspace currently held */
@@ -121,9 +122,10 @@ fhe_status fhe_ctx_set_allocator(fhe_ctx *ctx, fhe_alloc_fn alloc_fn, fhe_free_f
 fhe_status fhe_ctx_release_buffers(fhe_ctx *ctx);
 
 /* Kernel timing for measurement: after fhe_profile_enable(ctx, cat) every
- * launch of kernel category cat ("*" = all; categories: ntt_fwd, ntt_inv,
- * bconv_up, bconv_down, ks_inner, ks_final, ks_copy, automorph, rescale,
- * tensor, elementwise) is bracketed by HIP events on the context's stream.
+ * launch of kernel category cat ("*" = all; categories: ntt_fwd, ntt_fwd_col,
+ * ntt_fwd_row, ntt_inv, ntt_inv_col, ntt_inv_row, bconv_up, bconv_down,
+ * ks_intt_first, ks_inner, ks_moddown_final, automorph, rescale, tensor,
+ * elementwise) is bracketed by HIP events on the context's stream.
  * fhe_profile_read synchronises the stream and returns the summed event time
  * and launch count of a category since enabling.  fhe_profile_enable(ctx,
  * NULL) switches timing off. */

@@ -428,6 +428,10 @@ extern "C" size_t fhe_evk_bytes(const fhe_ctx *c)
 {
     return c ? (size_t)c->dnum * 2 * (c->L + c->K) * c->N * sizeof(uint64_t) : 0;
 }
+extern "C" size_t fhe_ct_bytes(const fhe_ctx *c, uint32_t limbs, uint32_t polys)
+{
+    return c ? (size_t)polys * limbs * c->N * sizeof(uint64_t) : 0;
+}
 extern "C" uint64_t fhe_galois_elt(const fhe_ctx *c, int32_t step)
 {
     if (!c) return 0;

@@ -139,12 +139,14 @@ _lib.fhe_last_error.restype = C.c_char_p
 _lib.fhe_graph_destroy.argtypes = [_P]
 _lib.fhe_graph_destroy.restype = None
 for _n, _r in [("fhe_ring_degree", C.c_uint32), ("fhe_modulus", C.c_uint64), ("fhe_evk_bytes", C.c_size_t),
+               ("fhe_ct_bytes", C.c_size_t),
                ("fhe_galois_elt", C.c_uint64), ("fhe_scratch_bytes", C.c_uint64), ("fhe_workspace_bytes", C.c_uint64)]:
     getattr(_lib, _n).restype = _r
 _lib.fhe_workspace_bytes.argtypes = [_P]
 _lib.fhe_ring_degree.argtypes = [_P]
 _lib.fhe_modulus.argtypes = [_P, C.c_uint32]
 _lib.fhe_evk_bytes.argtypes = [_P]
+_lib.fhe_ct_bytes.argtypes = [_P, C.c_uint32, C.c_uint32]
 _lib.fhe_galois_elt.argtypes = [_P, C.c_int32]
 _lib.fhe_scratch_bytes.argtypes = [_P]
 
@@ -167,6 +169,7 @@ def lib():
 
 def exported_symbols():
     return sorted(_sig) + ["fhe_ctx_destroy", "fhe_last_error", "fhe_ring_degree", "fhe_modulus", "fhe_evk_bytes",
+                           "fhe_ct_bytes",
                            "fhe_galois_elt", "fhe_scratch_bytes", "fhe_workspace_bytes", "fhe_graph_destroy"]
 
 

@@ -63,3 +63,10 @@ def test_invalid_parameters_refused_before_any_device_call():
         rc, msg = _create(fhe, log_n, qq, pp, dnum)
         assert rc == fhe.FHE_EPARAM, (log_n, dnum, msg)
         assert what in msg, msg
+
+
+def test_size_helpers_without_a_context():
+    """The sizing helpers are host-only and answer 0 for a null context."""
+    from paper_2102_00319_amd import fhe
+    assert fhe.lib().fhe_ct_bytes(None, 24, 2) == 0
+    assert fhe.lib().fhe_evk_bytes(None) == 0
